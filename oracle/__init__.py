@@ -107,8 +107,9 @@ def lattice():
 
 
 def feq_dev(rho, rho0, u):
+    """f^eq(rho, u) - w rho0."""
     out = np.zeros(Q)
-    lib().lbo_feq_dev(float(rho), float(rho0), _f64(u), out)
+    lib().lbo_feq_dev(float(rho) - float(rho0), float(rho), _f64(u), out)
     return out
 
 

@@ -112,14 +112,15 @@ static inline long nsites(const lbo_cfg *g) { return (long)g->nx * g->ny * g->nz
 /* ------------------------------------------------------------------------ */
 
 /* f^eq_i(rho,u) - w_i rho0 with f^eq = w rho [1 + c.u/cs2 + (c.u)^2/(2 cs4)
- * - u.u/(2 cs2)], cs2 = 1/3, written so that the rest part w(rho - rho0) is
- * separated from the velocity part. */
-void lbo_feq_dev(double rho, double rho0, const double u[3], double out[LBO_Q]) {
+ * - u.u/(2 cs2)], cs2 = 1/3, written so that the rest part w drho,
+ * drho = rho - rho0, is separated from the velocity part.  drho is passed in
+ * directly (R10): forming it as (rho0 + sum df) - rho0 would drop its low bits. */
+void lbo_feq_dev(double drho, double rho, const double u[3], double out[LBO_Q]) {
   lattice_init();
   const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   for (int i = 0; i < LBO_Q; ++i) {
     const double cu = C[i][0] * u[0] + C[i][1] * u[1] + C[i][2] * u[2];
-    out[i] = W[i] * (rho - rho0) + W[i] * rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+    out[i] = W[i] * drho + W[i] * rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
   }
 }
 
@@ -179,7 +180,8 @@ void lbo_rates(const lbo_cfg *cfg, double lam[LBO_Q]) {
   }
 }
 
-static void site_rho_u(const lbo_cfg *cfg, const double df[LBO_Q], double *rho, double u[3]) {
+static void site_rho_u(const lbo_cfg *cfg, const double df[LBO_Q], double *drho, double *rho,
+                       double u[3]) {
   double d = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
   for (int i = 0; i < LBO_Q; ++i) {
     d += df[i];
@@ -187,6 +189,7 @@ static void site_rho_u(const lbo_cfg *cfg, const double df[LBO_Q], double *rho, 
     jy += df[i] * C[i][1];
     jz += df[i] * C[i][2];
   }
+  *drho = d;
   *rho = cfg->rho0 + d;
   u[0] = jx / *rho;
   u[1] = jy / *rho;
@@ -199,9 +202,9 @@ static void site_rho_u(const lbo_cfg *cfg, const double df[LBO_Q], double *rho, 
  * followed by f_i = w_i sum_k E_ki m_k / b_k. */
 static void collide_site_with(const lbo_cfg *cfg, double df[LBO_Q], const double *E,
                               const double *b, const double *lam) {
-  double rho, u[3], feq[LBO_Q];
-  site_rho_u(cfg, df, &rho, u);
-  lbo_feq_dev(rho, cfg->rho0, u, feq);
+  double drho, rho, u[3], feq[LBO_Q];
+  site_rho_u(cfg, df, &drho, &rho, u);
+  lbo_feq_dev(drho, rho, u, feq);
   if (cfg->collision == LBO_BGK) {
     const double om = 1.0 - 1.0 / cfg->tau;
     for (int i = 0; i < LBO_Q; ++i) df[i] = feq[i] + om * (df[i] - feq[i]);
@@ -248,7 +251,7 @@ void lbo_init_fluid(const lbo_cfg *cfg, double *df, const double *rho, const dou
       uu[2] = u[2 * N + s];
     }
     const double r = rho ? rho[s] : cfg->rho0;
-    lbo_feq_dev(r, cfg->rho0, uu, feq);
+    lbo_feq_dev(r - cfg->rho0, r, uu, feq);
     for (int i = 0; i < LBO_Q; ++i) df[i * N + s] = feq[i];
   }
 }
@@ -260,9 +263,9 @@ void lbo_moments(const lbo_cfg *cfg, const double *df, double *rho, double *u) {
   const long N = nsites(cfg);
 #pragma omp parallel for schedule(static)
   for (long s = 0; s < N; ++s) {
-    double f[LBO_Q], r, uu[3];
+    double f[LBO_Q], d, r, uu[3];
     for (int i = 0; i < LBO_Q; ++i) f[i] = df[i * N + s];
-    site_rho_u(cfg, f, &r, uu);
+    site_rho_u(cfg, f, &d, &r, uu);
     rho[s] = r;
     u[s] = uu[0];
     u[N + s] = uu[1];
@@ -277,10 +280,10 @@ void lbo_force_half(const lbo_cfg *cfg, double *df, const double *Fc) {
   const long N = nsites(cfg);
 #pragma omp parallel for schedule(static)
   for (long s = 0; s < N; ++s) {
-    double f[LBO_Q], r, uu[3], F[3], G[LBO_Q];
+    double f[LBO_Q], d, r, uu[3], F[3], G[LBO_Q];
     for (int i = 0; i < LBO_Q; ++i) f[i] = df[i * N + s];
     for (int a = 0; a < 3; ++a) F[a] = cfg->fext[a] + (Fc ? Fc[a * N + s] : 0.0);
-    site_rho_u(cfg, f, &r, uu);
+    site_rho_u(cfg, f, &d, &r, uu);
     double um[3];
     for (int a = 0; a < 3; ++a) um[a] = uu[a] + 0.25 * F[a] / r;
     lbo_force_term(um, F, G);

@@ -52,7 +52,7 @@ typedef struct lbo_cfg {
 
 /* lattice and local operators */
 int lbo_d3q19(int32_t c[LBO_Q * 3], double w[LBO_Q], int32_t opp[LBO_Q]);
-void lbo_feq_dev(double rho, double rho0, const double u[3], double out[LBO_Q]);
+void lbo_feq_dev(double drho, double rho, const double u[3], double out[LBO_Q]);
 void lbo_force_term(const double u[3], const double F[3], double G[LBO_Q]);
 void lbo_mrt_basis(double E[LBO_Q * LBO_Q], double b[LBO_Q]);
 void lbo_rates(const lbo_cfg *cfg, double lam[LBO_Q]);
