@@ -1,0 +1,178 @@
+"""Throughput of the split-forcing D3Q19 lattice Boltzmann step with
+fluid-particle coupling on one MI355X.
+
+Default workload (force coupling at scale): periodic 256^3 box, two-rate MRT
+(TRT rates, magic 3/16) with tau = 0.6, populations stored in FP32 as
+deviations from w rho0 with FP32 compute; 100 bead-spring chains of 100 beads
+(10^4 particles, harmonic k = 30, r0 = 1, mass 1, velocities N(0, 1e-3)),
+force coupling gamma = 2 with the two-point kernel, and the multiple
+time-step split with the coupling outside and 5 sub-steps per side (the bond
+stiffness is beyond the stability limit of the single-step ordering at
+h = 1).  Inputs are synthetic and seeded.  One step is the whole hot path:
+both coupling half steps, the bond sub-steps and the fused lattice pass.
+
+Prints one JSON line.  --gpus above 1 is refused (single-GPU build).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("MLUPS & HBM GB/s fraction (D3Q19+coupling); ensemble runs/s + p50/p99 latency")
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1406_2211_amd/csrc/lbc_kernels.hip",
+                  "paper_1406_2211_amd/csrc/lbc_device.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_c2.json")
+
+
+def workload(name):
+    from paper_1406_2211_amd import inputs as I
+    if name == "c2":
+        n = 256
+        pos, vel, bonds = I.chains(100, 100, (n, n, n), 1.0, 1e-3, seed=2)
+        return dict(
+            desc="D3Q19 two-rate MRT (TRT rates) 256^3 periodic, tau=0.6, FP32 storage/compute; "
+                 "10^4 particles in 100 harmonic chains (k=30, r0=1, m=1), force coupling "
+                 "gamma=2, 2-point kernel, multiple time-step split n=5",
+            grid=(n, n, n, 0),
+            params=dict(tau=0.6, collision=1, coupling=1, gamma=2.0, kernel=2, storage=1,
+                        mts_substeps=5),
+            pos=pos, vel=vel, mass=np.ones(len(pos)), bonds=bonds, bond_k=30.0, bond_r0=1.0,
+            bytes_per_site=152, dtype="f32")
+    if name == "plain256":
+        n = 256
+        return dict(desc="D3Q19 two-rate MRT 256^3 periodic, FP32, no particles", grid=(n, n, n, 0),
+                    params=dict(tau=0.6, collision=1, storage=1), pos=None, bytes_per_site=152,
+                    dtype="f32")
+    if name == "c1":
+        n = 32
+        return dict(desc="D3Q19 BGK 32^3 periodic FP64, 1 particle, force coupling gamma=1",
+                    grid=(n, n, n, 0),
+                    params=dict(tau=0.8, body_force=(1e-6, 0, 0), coupling=1, gamma=1.0,
+                                kernel=2, storage=0),
+                    pos=I.uniform_positions(1, (n, n, n), 1), vel=np.zeros((1, 3)),
+                    mass=np.ones(1), bytes_per_site=304, dtype="f64")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_record(N):
+    """HBM bytes per launch of the fused lattice kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != source_hash() or rec.get("sites") != N:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, steps):
+    """The FP64 CPU oracle, untuned, on a bounded sample of the same workload."""
+    import oracle as O
+    nx, ny, nz, wall = wl["grid"]
+    p = wl["params"]
+    o = O.Oracle(nx=nx, ny=ny, nz=nz, wall_y=wall, tau=p["tau"], collision=p.get("collision", 0),
+                 coupling=p.get("coupling", 0), gamma=p.get("gamma", 0.0),
+                 kernel=p.get("kernel", 2), mts_n=p.get("mts_substeps", 0),
+                 fext=p.get("body_force", (0, 0, 0)), bonds=wl.get("bonds"),
+                 bond_k=wl.get("bond_k", 0.0), bond_r0=wl.get("bond_r0", 1.0))
+    df = o.init_fluid()
+    pos = None if wl.get("pos") is None else wl["pos"].copy()
+    vel = None if pos is None else wl["vel"].copy()
+    t0 = time.perf_counter()
+    o.run(df, steps, pos, vel, wl.get("mass"))
+    dt = time.perf_counter() - t0
+    return {"value": round(nx * ny * nz * steps / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": O.threads(), "kind": "oracle",
+            "sample": f"{steps} full steps of the same workload ({nx}x{ny}x{nz}, all particles), "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1406_2211_amd import lbc as L
+
+    wl = workload(args.workload)
+    nx, ny, nz, wall = wl["grid"]
+    N = nx * ny * nz
+    pos = wl.get("pos")
+    npart = 0 if pos is None else len(pos)
+    bonds = wl.get("bonds")
+    lat = L.Lattice(nx, ny, nz, wall_y=wall, max_particles=npart,
+                    max_bonds=0 if bonds is None else len(bonds), **wl["params"])
+    lat.lb_init_fluid()
+    if npart:
+        lat.lb_set_particles(torch.from_numpy(pos), torch.from_numpy(wl["vel"]),
+                             torch.from_numpy(wl["mass"]))
+    if bonds is not None:
+        lat.lb_set_bonds(bonds, wl["bond_k"], wl["bond_r0"])
+    lat.lb_step(args.warmup)
+    torch.cuda.synchronize()
+    lat.lb_timing(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.lb_step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lat_ms, passes = lat.lb_timing_read()
+    tot = lat.lb_totals()
+    if not np.all(np.isfinite(tot)):
+        print("bench.py: non-finite state after the timed steps", file=sys.stderr)
+        sys.exit(1)
+
+    mlups = N * args.steps / dt / 1e6
+    bps = wl["bytes_per_site"]
+    kern_s = lat_ms / 1e3 / max(passes, 1)
+    achieved = bps * N / kern_s / 1e9
+    traffic = traffic_record(N)
+    out = {
+        "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3 / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": wl["dtype"], "data": "synthetic",
+        "config": {"workload": args.workload + ": " + wl["desc"], "sites": N,
+                   "particles": npart, "parallelism": "single-gpu"},
+        "hbm_gbs_step": round(bps * N * args.steps / dt / 1e9, 1),
+        "roofline": {"bound": "hbm", "kernel": "k_stream_collide", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "avg_launch_us": round(kern_s * 1e6, 2),
+                     "algorithmic_bytes_per_launch": bps * N},
+    }
+    lat.lb_destroy()
+    del lat
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

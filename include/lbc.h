@@ -1,0 +1,179 @@
+/*
+ * lbc.h -- C ABI of the MI355X (gfx950) lattice Boltzmann library with
+ * operator-split second-order forcing and fluid-particle coupling, after
+ * Schiller, "A unified operator splitting approach for multi-scale
+ * fluid-particle coupling in the lattice Boltzmann method" (arXiv:1406.2211).
+ *
+ * Conventions shared by every call
+ *   - Lattice units: time step h = 1, lattice spacing a = 1.  D3Q19.
+ *   - Every call returns an lb_status; no exception crosses the ABI.  On a
+ *     failure lb_last_error(ctx) holds a message (lb_last_error(NULL) holds
+ *     the message of a failed lb_create / lb_workspace_size).
+ *   - Pointers named d_* are device pointers, h_* host pointers, both owned
+ *     by the caller.  The library never allocates device memory: all of its
+ *     device state lives in the caller's workspace (lb_workspace_size).
+ *   - Every device operation is enqueued on the stream given to lb_create and
+ *     is asynchronous unless stated otherwise.  Parameter errors are detected
+ *     on the host before anything is enqueued.
+ *   - Field layouts: scalar fields [nz][ny][nx] (x fastest); vector fields
+ *     [3][nz][ny][nx]; populations [19][nz][ny][nx] in the order returned by
+ *     lb_lattice_velocities; particle vectors [n][3].  Exchange precision is
+ *     FP64 regardless of the storage precision.
+ *   - tau is the lattice relaxation time: the Crank-Nicolson collision of
+ *     Sec. 3.2 (Eq. collision-operator) with BGK time tau_paper relaxes at
+ *     lambda = h/(tau_paper + h/2); this ABI takes tau = tau_paper + h/2 > 1/2.
+ *
+ * One time step (Eq. LB-splitting and Eq. fc-splitting) is
+ *   P^1/2  F^1/2  C  S  F^1/2  P^1/2
+ * where F^1/2 is the midpoint half force (Sec. 3.3) applied to the lattice
+ * together with the coupling half step, C the full collision (which equals
+ * C^1/2 C^1/2 of Eq. LB-splitting up to the end half-collisions, Eq.
+ * LB-splitting-combined) and S streaming (Sec. 3.1).  The library stores the
+ * post-collision populations and folds the second half force of one step and
+ * the first half force of the next into a single exact equilibrium shift of
+ * one fused lattice pass; the physical state is defined at every step
+ * boundary and is what lb_moments / lb_populations / lb_totals return.
+ */
+#ifndef LBC_H
+#define LBC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lb_status {
+  LB_OK = 0,
+  LB_EINVAL = 1,  /* invalid argument or configuration */
+  LB_ENOMEM = 2,  /* workspace too small or capacity exceeded */
+  LB_EBUSY = 3,   /* ensemble has no free slot or memory for a request */
+  LB_EDEVICE = 4, /* a HIP runtime call failed */
+  LB_ESTATE = 5   /* call not valid in the current state */
+} lb_status;
+
+enum lb_collision { LB_BGK = 0, LB_TRT = 1 };
+enum lb_forcing { LB_FORCING_SPLIT2 = 0 };
+enum lb_coupling { LB_COUPLE_NONE = 0, LB_COUPLE_FC = 1, LB_COUPLE_EBF = 2, LB_COUPLE_IB = 3 };
+enum lb_kernel { LB_PHI2 = 2, LB_PHI3 = 3, LB_PHI4 = 4 };
+enum lb_storage { LB_F64 = 0, LB_F32 = 1, LB_F16 = 2, LB_BF16 = 3 };
+enum lb_bond_type { LB_HARMONIC = 0, LB_FENE = 1 };
+
+typedef struct lb_grid {
+  int32_t nx, ny, nz;
+  int32_t wall_y; /* 0: periodic in y; 1: halfway bounce-back walls at y=-1/2, ny-1/2 */
+} lb_grid;
+
+typedef struct lb_params {
+  double tau;            /* lattice relaxation time (> 1/2), see above */
+  double rho0;           /* reference density; populations are stored as f - w rho0 */
+  double body_force[3];  /* constant body-force density F_ext */
+  int32_t collision;     /* LB_BGK, or LB_TRT: MRT with the two rates of Eq. mrt-coll */
+  double trt_magic;      /* (1/l+ - 1/2)(1/l- - 1/2) for LB_TRT; 3/16 if <= 0 */
+  int32_t forcing;       /* LB_FORCING_SPLIT2: midpoint half forces around C S */
+  int32_t coupling;      /* LB_COUPLE_* (Sec. 5.1 IB, 5.2 FC, 5.3 modified EBF) */
+  double gamma;          /* friction of FC / EBF (Eq. viscous-coupling) */
+  int32_t kernel;        /* LB_PHI2, LB_PHI3, LB_PHI4 (Appendix A) */
+  int32_t storage;       /* LB_F64 (FP64 compute), LB_F32/LB_F16/LB_BF16 (FP32 compute) */
+  int32_t f16_scale_log2;/* LB_F16/LB_BF16: stored value is 2^p (f - w rho0) */
+  int32_t mts_substeps;  /* 0: Alg. 3 ordering; n > 0: Sec. 6 split with the coupling
+                            outside and n velocity-Verlet sub-steps on each side */
+  int32_t deterministic; /* reserved, must be 0 */
+} lb_params;
+
+typedef struct lb_limits {
+  int64_t max_particles;  /* capacity for lb_set_particles */
+  int64_t max_bonds;      /* capacity for lb_set_bonds */
+  int32_t max_shells;     /* capacity for lb_set_shells */
+  int32_t max_shell_size;
+} lb_limits;
+
+typedef struct lb_ctx lb_ctx;
+
+/* D3Q19 velocity set in library order, c[i*3 + a]; returns 19. */
+int32_t lb_lattice_velocities(int32_t c[57]);
+
+/* Device bytes needed for a context of this size (a pure function of the
+ * arguments).  The caller allocates them (alignment 256 B) and passes them to
+ * lb_create. */
+lb_status lb_workspace_size(const lb_grid* g, const lb_params* p, const lb_limits* lim,
+                            size_t* bytes);
+
+/* Creates a context on the current HIP device.  The workspace and the stream
+ * (a hipStream_t, or NULL for the null stream) are borrowed: the caller keeps
+ * them alive until lb_destroy.  Initialises the fluid at rest,
+ * f = f^eq(rho0, 0), with no particles.  Errors: LB_EINVAL (bad grid or
+ * parameters, e.g. tau <= 1/2), LB_ENOMEM (workspace smaller than
+ * lb_workspace_size), LB_EDEVICE. */
+lb_status lb_create(const lb_grid* g, const lb_params* p, const lb_limits* lim,
+                    void* d_workspace, size_t bytes, void* hip_stream, lb_ctx** out);
+
+/* Sets the physical state f = f^eq(rho, u) (moments of Sec. 2).  d_rho
+ * [nz][ny][nx] and d_u [3][nz][ny][nx] are FP64 device arrays; NULL means
+ * rho0 and 0. */
+lb_status lb_init_fluid(lb_ctx* ctx, const double* d_rho, const double* d_u);
+
+/* Copies n particles (FC/EBF: positions r, velocities v, masses m > 0; IB:
+ * marker positions X, velocities and masses ignored and may be NULL) into the
+ * context.  FP64 device arrays [n][3], [n][3], [n].  Positions in periodic
+ * directions are wrapped into [0, L).  Errors: LB_ENOMEM if n exceeds
+ * max_particles, LB_EINVAL for n < 0. */
+lb_status lb_set_particles(lb_ctx* ctx, int64_t n, const double* d_pos, const double* d_vel,
+                           const double* d_mass);
+
+/* Bonds between particles (intrinsic forces, "CalculateForces" of Alg. 3):
+ * harmonic U = k/2 (|d| - r0)^2 or FENE U = -k r0^2/2 ln(1 - |d|^2/r0^2)
+ * with d the minimum-image separation.  h_pairs [nb][2] host int32 particle
+ * indices.  Bonded clusters must not exceed 1024 particles.  Synchronous. */
+lb_status lb_set_bonds(lb_ctx* ctx, int64_t nb, const int32_t* h_pairs, double k, double r0,
+                       int32_t type);
+
+/* Rigid shells for IB (intrinsic forces of Alg. 2): markers
+ * s*shell_size .. (s+1)*shell_size-1 form shell s and are tethered with
+ * stiffness k_tether to a copy of h_template ([shell_size][3] host FP64,
+ * centred on the origin) placed at the shell centroid with the least-squares
+ * rotation.  Synchronous. */
+lb_status lb_set_shells(lb_ctx* ctx, int32_t nshell, int32_t shell_size,
+                        const double* h_template, double k_tether);
+
+/* Advances nsteps full time steps (see the top of this file; Alg. 2 for IB,
+ * Alg. 3 or the Sec. 6 split for FC/EBF).  Asynchronous. */
+lb_status lb_step(lb_ctx* ctx, int64_t nsteps);
+
+/* Physical density and velocity at every site (rho u = sum_i f_i c_i of the
+ * physical populations, i.e. including the second half force; the
+ * redefined velocity of Sec. 4).  FP64 device outputs d_rho [nz][ny][nx]
+ * (may be NULL) and d_u [3][nz][ny][nx]. */
+lb_status lb_moments(lb_ctx* ctx, double* d_rho, double* d_u);
+
+/* Physical populations as deviations f_i - w_i rho0, FP64 [19][nz][ny][nx]. */
+lb_status lb_populations(lb_ctx* ctx, double* d_df);
+
+/* Current particle positions and velocities, FP64 device [n][3] (either may be NULL). */
+lb_status lb_get_particles(lb_ctx* ctx, double* d_pos, double* d_vel);
+
+/* Conserved totals in FP64, reduced on the device in a fixed order:
+ * h_out[0] = sum_x rho - N rho0, h_out[1..3] = fluid momentum sum_x rho u,
+ * h_out[4..6] = particle momentum sum_p m_p v_p (0 for IB).  Synchronous. */
+lb_status lb_totals(lb_ctx* ctx, double h_out[7]);
+
+/* Kernel timing for measurement: with max_passes > 0 the next max_passes
+ * fused lattice passes are each bracketed by a pair of HIP events recorded on
+ * the context stream (host-side event objects; no device memory); 0 disables.
+ * lb_timing_read waits for the stream and returns the summed event time of
+ * the recorded passes (ms) and their number, then resets the count. */
+lb_status lb_timing(lb_ctx* ctx, int32_t max_passes);
+lb_status lb_timing_read(lb_ctx* ctx, double* lattice_ms, int64_t* passes);
+
+/* Number of particles, steps taken so far. */
+lb_status lb_info(const lb_ctx* ctx, int64_t* nparticles, int64_t* steps);
+
+lb_status lb_destroy(lb_ctx* ctx);
+const char* lb_last_error(const lb_ctx* ctx);
+const char* lb_status_string(lb_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBC_H */

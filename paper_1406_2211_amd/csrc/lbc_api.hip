@@ -1,0 +1,634 @@
+// lbc_api.hip -- host runtime behind include/lbc.h: parameter checks, the
+// workspace layout (all device memory belongs to the caller), bonded-group
+// construction, and the per-step kernel sequence of each coupling scheme.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "lbc_device.h"
+#include "lbc_internal.h"
+
+using namespace lbc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int storage_bytes(int s) { return s == LB_F64 ? 8 : (s == LB_F32 ? 4 : 2); }
+int force_vec_bytes(int s) { return s == LB_F64 ? 32 : 16; }
+
+// Sequential carving of the workspace; with base == nullptr only sizes.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t bytes) {
+    T* p = base ? (T*)(base + off) : nullptr;
+    off = align256(off + bytes);
+    return p;
+  }
+};
+
+struct Layout {
+  void* f[2];
+  void *FA, *FB;
+  uint64_t* mask;
+  double *pos, *vel, *mass, *fint, *aux;
+  int32_t *perm, *loc, *goff, *bstart, *bnbr;
+  double *tmpl, *rot, *partial, *tot;
+  size_t bytes;
+};
+
+Layout carve(const lb_grid& g, const lb_params& p, const lb_limits& lim, void* base) {
+  Carver c{(char*)base};
+  Layout L{};
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  const long long wpr = (g.nx + 63) / 64;
+  const size_t fb = (size_t)19 * N * storage_bytes(p.storage);
+  L.f[0] = c.take<void>(fb);
+  L.f[1] = c.take<void>(fb);
+  L.FA = c.take<void>((size_t)N * force_vec_bytes(p.storage));
+  L.FB = c.take<void>((size_t)N * force_vec_bytes(p.storage));
+  L.mask = c.take<uint64_t>((size_t)g.nz * g.ny * wpr * 8);
+  const size_t np = (size_t)std::max<int64_t>(lim.max_particles, 1);
+  L.pos = c.take<double>(np * 24);
+  L.vel = c.take<double>(np * 24);
+  L.mass = c.take<double>(np * 8);
+  L.fint = c.take<double>(np * 24);
+  L.aux = c.take<double>(np * 24);
+  L.perm = c.take<int32_t>(np * 4);
+  L.loc = c.take<int32_t>(np * 4);
+  L.goff = c.take<int32_t>((np + 1) * 4);
+  L.bstart = c.take<int32_t>((np + 1) * 4);
+  L.bnbr = c.take<int32_t>((size_t)std::max<int64_t>(2 * lim.max_bonds, 1) * 4);
+  L.tmpl = c.take<double>((size_t)std::max(lim.max_shell_size, 1) * 24);
+  L.rot = c.take<double>((size_t)std::max(lim.max_shells, 1) * 72);
+  L.partial = c.take<double>((size_t)kTotalsBlocks * 4 * 8);
+  L.tot = c.take<double>(8 * 8);
+  L.bytes = c.off;
+  return L;
+}
+
+bool check_params(const lb_grid* g, const lb_params* p, const lb_limits* lim, std::string& err) {
+  if (!g || !p || !lim) return err = "null argument", false;
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return err = "grid dimensions must be >= 1", false;
+  if ((long long)g->nx * g->ny * g->nz > (1ll << 36)) return err = "grid too large", false;
+  if (g->wall_y != 0 && g->wall_y != 1) return err = "wall_y must be 0 or 1", false;
+  if (g->wall_y && g->ny < 2) return err = "a walled channel needs ny >= 2", false;
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau))
+    return err = "tau (lattice relaxation time) must be > 1/2", false;
+  if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return err = "rho0 must be > 0", false;
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->body_force[a])) return err = "body force must be finite", false;
+  if (p->collision != LB_BGK && p->collision != LB_TRT) return err = "unknown collision", false;
+  if (p->forcing != LB_FORCING_SPLIT2) return err = "unknown forcing scheme", false;
+  if (p->coupling < LB_COUPLE_NONE || p->coupling > LB_COUPLE_IB)
+    return err = "unknown coupling", false;
+  if ((p->coupling == LB_COUPLE_FC || p->coupling == LB_COUPLE_EBF) &&
+      (!(p->gamma > 0.0) || !std::isfinite(p->gamma)))
+    return err = "force coupling needs gamma > 0", false;
+  if (p->kernel < 2 || p->kernel > 4) return err = "kernel must be 2, 3 or 4", false;
+  if (p->storage < LB_F64 || p->storage > LB_BF16) return err = "unknown storage", false;
+  if (p->f16_scale_log2 < -40 || p->f16_scale_log2 > 40)
+    return err = "f16_scale_log2 out of range", false;
+  if (p->mts_substeps < 0 || p->mts_substeps > 256) return err = "mts_substeps out of range", false;
+  if (p->mts_substeps > 0 && p->coupling == LB_COUPLE_IB)
+    return err = "multiple time stepping applies to force coupling only", false;
+  if (p->deterministic != 0) return err = "deterministic mode is not available", false;
+  if (lim->max_particles < 0 || lim->max_particles > (1ll << 30) || lim->max_bonds < 0 ||
+      lim->max_bonds > (1ll << 29) || lim->max_shells < 0 || lim->max_shell_size < 0)
+    return err = "invalid limits", false;
+  return true;
+}
+
+}  // namespace
+
+struct lb_ctx {
+  lb_grid g;
+  lb_params p;
+  lb_limits lim;
+  hipStream_t st;
+  Geo geo;
+  Layout L;
+  int cur = 0;
+  int pend = 0;
+  int64_t steps = 0;
+  int64_t np = 0;
+  int64_t nbond = 0;
+  std::vector<int32_t> bonds;
+  double bond_k = 0, bond_r0 = 1;
+  int bond_type = LB_HARMONIC;
+  bool groups_dirty = true;
+  int ngroups = 0, gcap = 64;
+  int nshell = 0, shell_size = 0;
+  double k_tether = 0;
+  double omp = 0, omm = 0;
+  float scale = 1.f, inv = 1.f;
+  std::vector<hipEvent_t> ev;  // timing event pairs
+  int32_t ev_used = 0;
+  std::string err;
+};
+
+#define HIPCHK(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      (ctx)->err = std::string(#call) + ": " + hipGetErrorString(e_);                  \
+      return LB_EDEVICE;                                                               \
+    }                                                                                  \
+  } while (0)
+
+static lb_status fail(lb_ctx* ctx, lb_status s, const std::string& m) {
+  if (ctx)
+    ctx->err = m;
+  else
+    g_last_error = m;
+  return s;
+}
+
+static SiteArgs site_args(const lb_ctx* c) {
+  SiteArgs s;
+  s.g = c->geo;
+  s.f = c->L.f[c->cur];
+  s.FB = c->L.FB;
+  s.rho0 = c->p.rho0;
+  s.pfx = c->pend * c->p.body_force[0];
+  s.pfy = c->pend * c->p.body_force[1];
+  s.pfz = c->pend * c->p.body_force[2];
+  s.inv = c->inv;
+  return s;
+}
+
+static PartArgs part_args(const lb_ctx* c) {
+  PartArgs a;
+  a.s = site_args(c);
+  a.FA = c->L.FA;
+  a.FB = c->L.FB;
+  a.mask = c->L.mask;
+  a.K = c->p.kernel;
+  a.n = c->np;
+  a.pos = c->L.pos;
+  a.vel = c->L.vel;
+  a.mass = c->L.mass;
+  a.fint = c->L.fint;
+  a.aux = c->L.aux;
+  a.gamma = c->p.gamma;
+  a.coupling = c->p.coupling;
+  a.use_fint = 0;
+  a.phys = 1;
+  a.target = 0;
+  a.drift_after = 0;
+  return a;
+}
+
+static BondArgs bond_args(const lb_ctx* c, double* pos) {
+  BondArgs b;
+  b.g = c->geo;
+  b.perm = c->L.perm;
+  b.loc = c->L.loc;
+  b.goff = c->L.goff;
+  b.start = c->L.bstart;
+  b.nbr = c->L.bnbr;
+  b.pos = pos;
+  b.vel = c->L.vel;
+  b.mass = c->L.mass;
+  b.fint = c->L.fint;
+  b.k = c->bond_k;
+  b.r0 = c->bond_r0;
+  b.type = c->bond_type;
+  return b;
+}
+
+// Groups of whole bonded clusters (union-find), packed into blocks of at most
+// gcap particles, plus a CSR list of bond partners.
+static lb_status build_groups(lb_ctx* c) {
+  const int64_t n = c->np;
+  std::vector<int32_t> parent(n);
+  std::iota(parent.begin(), parent.end(), 0);
+  auto find = [&](int32_t x) {
+    while (parent[x] != x) x = parent[x] = parent[parent[x]];
+    return x;
+  };
+  std::vector<int32_t> deg(n + 1, 0);
+  for (int64_t b = 0; b < c->nbond; ++b) {
+    const int32_t i = c->bonds[2 * b], j = c->bonds[2 * b + 1];
+    if (i < 0 || j < 0 || i >= n || j >= n)
+      return fail(c, LB_EINVAL, "bond index outside the particle range");
+    parent[find(i)] = find(j);
+    deg[i]++;
+    deg[j]++;
+  }
+  std::vector<int32_t> start(n + 1, 0);
+  for (int64_t p = 0; p < n; ++p) start[p + 1] = start[p] + deg[p];
+  std::vector<int32_t> nbr(std::max<int64_t>(2 * c->nbond, 1)), fill(start.begin(), start.end() - 1);
+  for (int64_t b = 0; b < c->nbond; ++b) {
+    const int32_t i = c->bonds[2 * b], j = c->bonds[2 * b + 1];
+    nbr[fill[i]++] = j;
+    nbr[fill[j]++] = i;
+  }
+  // members of each cluster in index order
+  std::vector<int32_t> root(n), order(n);
+  for (int64_t p = 0; p < n; ++p) root[p] = find((int32_t)p);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return root[a] < root[b]; });
+  std::vector<std::pair<int32_t, int32_t>> clusters;  // (offset in order, size)
+  for (int64_t k = 0; k < n;) {
+    int64_t e = k;
+    while (e < n && root[order[e]] == root[order[k]]) ++e;
+    clusters.push_back({(int32_t)k, (int32_t)(e - k)});
+    k = e;
+  }
+  int maxc = 1;
+  for (auto& cl : clusters) maxc = std::max(maxc, cl.second);
+  if (maxc > 1024) return fail(c, LB_EINVAL, "a bonded cluster has more than 1024 particles");
+  const int gcap = std::max(256, ((maxc + 63) / 64) * 64);
+  std::vector<int32_t> perm, loc(n), goff{0};
+  int fillg = 0;
+  for (auto& cl : clusters) {
+    if (fillg + cl.second > gcap) {
+      goff.push_back((int32_t)perm.size());
+      fillg = 0;
+    }
+    for (int k = 0; k < cl.second; ++k) {
+      const int32_t p = order[cl.first + k];
+      loc[p] = fillg + k;
+      perm.push_back(p);
+    }
+    fillg += cl.second;
+  }
+  if (fillg > 0) goff.push_back((int32_t)perm.size());
+  c->ngroups = (int)goff.size() - 1;
+  c->gcap = gcap;
+  if (n > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->L.perm, perm.data(), n * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->L.loc, loc.data(), n * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->L.goff, goff.data(), goff.size() * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->L.bstart, start.data(), (n + 1) * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->L.bnbr, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+  }
+  c->groups_dirty = false;
+  return LB_OK;
+}
+
+// F_int at the given positions: shell tethers and bonds.
+static lb_status enqueue_fint(lb_ctx* c, double* pos, bool& any) {
+  any = false;
+  if (c->nshell > 0) {
+    const int64_t nm = (int64_t)c->nshell * c->shell_size;
+    if (nm < c->np)
+      HIPCHK(c, hipMemsetAsync(c->L.fint + 3 * nm, 0, (size_t)(c->np - nm) * 24, c->st));
+    ShellArgs s{c->geo, pos, c->L.tmpl, c->L.fint, c->L.rot, c->shell_size, c->k_tether};
+    HIPCHK(c, launch_shell_forces(s, c->nshell, c->st));
+    any = true;
+  }
+  if (c->nbond > 0) {
+    HIPCHK(c, launch_bond_groups(bond_args(c, pos), c->ngroups, c->gcap, 0, any ? 1 : 0, 0, 0.0,
+                                 c->st));
+    any = true;
+  }
+  return LB_OK;
+}
+
+static lb_status lattice_pass(lb_ctx* c) {
+  LatArgs a;
+  a.g = c->geo;
+  a.fin = c->L.f[c->cur];
+  a.fout = c->L.f[1 - c->cur];
+  a.FA = c->L.FA;
+  a.FB = c->L.FB;
+  a.mask = c->L.mask;
+  a.rho0 = c->p.rho0;
+  const double fac = 1.0 + c->pend;
+  a.Fx = fac * c->p.body_force[0];
+  a.Fy = fac * c->p.body_force[1];
+  a.Fz = fac * c->p.body_force[2];
+  a.omp = c->omp;
+  a.omm = c->omm;
+  a.scale = c->scale;
+  a.inv = c->inv;
+  const bool timed = 2 * (size_t)c->ev_used + 1 < c->ev.size();
+  if (timed) HIPCHK(c, hipEventRecord(c->ev[2 * c->ev_used], c->st));
+  HIPCHK(c, launch_stream_collide(c->p.storage, c->p.collision, a, c->st));
+  if (timed) HIPCHK(c, hipEventRecord(c->ev[2 * c->ev_used++ + 1], c->st));
+  c->cur = 1 - c->cur;
+  c->pend = 1;
+  return LB_OK;
+}
+
+static lb_status step_once(lb_ctx* c) {
+  const bool parts = c->p.coupling != LB_COUPLE_NONE && c->np > 0;
+  lb_status s;
+  if (!parts) return lattice_pass(c);
+  if (c->p.coupling == LB_COUPLE_IB) {
+    PartArgs a = part_args(c);
+    HIPCHK(c, launch_ib_predict(c->p.storage, a, c->st));
+    bool any;
+    if ((s = enqueue_fint(c, c->L.aux, any)) != LB_OK) return s;
+    if (!any) HIPCHK(c, hipMemsetAsync(c->L.fint, 0, (size_t)c->np * 24, c->st));
+    HIPCHK(c, launch_ib_advect(c->p.storage, a, 1, c->st));
+    if ((s = lattice_pass(c)) != LB_OK) return s;
+    a = part_args(c);
+    HIPCHK(c, launch_ib_spread_b(c->p.storage, a, c->st));
+    HIPCHK(c, launch_ib_advect(c->p.storage, a, 0, c->st));
+    return LB_OK;
+  }
+  if (c->p.mts_substeps > 0) {
+    const int n = c->p.mts_substeps;
+    const double dt = 1.0 / (2.0 * n);
+    PartArgs a = part_args(c);
+    a.target = 0;
+    HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
+    HIPCHK(c, launch_bond_groups(bond_args(c, c->L.pos), c->ngroups, c->gcap, 1, 0, n, dt, c->st));
+    if ((s = lattice_pass(c)) != LB_OK) return s;
+    HIPCHK(c, launch_bond_groups(bond_args(c, c->L.pos), c->ngroups, c->gcap, 1, 0, n, dt, c->st));
+    a = part_args(c);
+    a.phys = 0;
+    a.target = 1;
+    HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
+    return LB_OK;
+  }
+  // Alg. 3: P^1/2, F_int, coupling half (+ spread A), LB, coupling half (+ spread B), P^1/2
+  HIPCHK(c, launch_drift(c->geo, c->np, c->L.pos, c->L.vel, 0.5, c->st));
+  bool any;
+  if ((s = enqueue_fint(c, c->L.pos, any)) != LB_OK) return s;
+  PartArgs a = part_args(c);
+  a.use_fint = any ? 1 : 0;
+  a.target = 0;
+  HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
+  if ((s = lattice_pass(c)) != LB_OK) return s;
+  a = part_args(c);
+  a.use_fint = any ? 1 : 0;
+  a.phys = 0;
+  a.target = 1;
+  a.drift_after = 1;
+  HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
+  return LB_OK;
+}
+
+extern "C" {
+
+int32_t lb_lattice_velocities(int32_t c[57]) {
+  for (int i = 0; i < Q; ++i) {
+    c[3 * i] = CX[i];
+    c[3 * i + 1] = CY[i];
+    c[3 * i + 2] = CZ[i];
+  }
+  return Q;
+}
+
+lb_status lb_workspace_size(const lb_grid* g, const lb_params* p, const lb_limits* lim,
+                            size_t* bytes) {
+  std::string err;
+  if (!bytes) return fail(nullptr, LB_EINVAL, "null output");
+  if (!check_params(g, p, lim, err)) return fail(nullptr, LB_EINVAL, err);
+  *bytes = carve(*g, *p, *lim, nullptr).bytes;
+  return LB_OK;
+}
+
+lb_status lb_create(const lb_grid* g, const lb_params* p, const lb_limits* lim, void* d_workspace,
+                    size_t bytes, void* hip_stream, lb_ctx** out) {
+  std::string err;
+  if (!out) return fail(nullptr, LB_EINVAL, "null output");
+  *out = nullptr;
+  if (!check_params(g, p, lim, err)) return fail(nullptr, LB_EINVAL, err);
+  const size_t need = carve(*g, *p, *lim, nullptr).bytes;
+  if (!d_workspace || bytes < need)
+    return fail(nullptr, LB_ENOMEM, "workspace smaller than lb_workspace_size");
+  if (((uintptr_t)d_workspace & 255) != 0)
+    return fail(nullptr, LB_EINVAL, "workspace must be 256-byte aligned");
+  lb_ctx* c = new lb_ctx();
+  c->g = *g;
+  c->p = *p;
+  if (!(c->p.trt_magic > 0)) c->p.trt_magic = 3.0 / 16.0;
+  c->lim = *lim;
+  c->st = (hipStream_t)hip_stream;
+  c->geo.nx = g->nx;
+  c->geo.ny = g->ny;
+  c->geo.nz = g->nz;
+  c->geo.wall = g->wall_y;
+  c->geo.wpr = (g->nx + 63) / 64;
+  c->geo.N = (long long)g->nx * g->ny * g->nz;
+  c->L = carve(*g, *p, *lim, d_workspace);
+  const double lp = 1.0 / c->p.tau;
+  const double lm = c->p.collision == LB_TRT ? 1.0 / (0.5 + c->p.trt_magic / (c->p.tau - 0.5)) : lp;
+  c->omp = 1.0 - lp;
+  c->omm = 1.0 - lm;
+  if (p->storage == LB_F16 || p->storage == LB_BF16) {
+    c->scale = std::ldexp(1.0f, p->f16_scale_log2);
+    c->inv = std::ldexp(1.0f, -p->f16_scale_log2);
+  }
+  lb_status s = lb_init_fluid(c, nullptr, nullptr);
+  if (s != LB_OK) {
+    g_last_error = c->err;
+    delete c;
+    return s;
+  }
+  *out = c;
+  return LB_OK;
+}
+
+lb_status lb_init_fluid(lb_ctx* c, const double* d_rho, const double* d_u) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  InitArgs a{c->geo, c->L.f[0], d_rho, d_u, c->p.rho0, c->scale};
+  c->cur = 0;
+  HIPCHK(c, launch_init(c->p.storage, a, c->st));
+  const size_t vb = (size_t)c->geo.N * force_vec_bytes(c->p.storage);
+  HIPCHK(c, hipMemsetAsync(c->L.FA, 0, vb, c->st));
+  HIPCHK(c, hipMemsetAsync(c->L.FB, 0, vb, c->st));
+  HIPCHK(c, hipMemsetAsync(c->L.mask, 0, (size_t)c->geo.nz * c->geo.ny * c->geo.wpr * 8, c->st));
+  c->pend = 0;
+  return LB_OK;
+}
+
+lb_status lb_set_particles(lb_ctx* c, int64_t n, const double* d_pos, const double* d_vel,
+                           const double* d_mass) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (n < 0) return fail(c, LB_EINVAL, "negative particle count");
+  if (n > c->lim.max_particles) return fail(c, LB_ENOMEM, "more particles than max_particles");
+  const bool massive = c->p.coupling == LB_COUPLE_FC || c->p.coupling == LB_COUPLE_EBF;
+  if (n > 0 && !d_pos) return fail(c, LB_EINVAL, "null positions");
+  if (n > 0 && massive && (!d_vel || !d_mass))
+    return fail(c, LB_EINVAL, "force coupling needs velocities and masses");
+  if (n > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->L.pos, d_pos, n * 24, hipMemcpyDeviceToDevice, c->st));
+    if (d_vel)
+      HIPCHK(c, hipMemcpyAsync(c->L.vel, d_vel, n * 24, hipMemcpyDeviceToDevice, c->st));
+    else
+      HIPCHK(c, hipMemsetAsync(c->L.vel, 0, n * 24, c->st));
+    if (d_mass) {
+      HIPCHK(c, hipMemcpyAsync(c->L.mass, d_mass, n * 8, hipMemcpyDeviceToDevice, c->st));
+    } else {
+      std::vector<double> ones(n, 1.0);
+      HIPCHK(c, hipMemcpyAsync(c->L.mass, ones.data(), n * 8, hipMemcpyHostToDevice, c->st));
+      HIPCHK(c, hipStreamSynchronize(c->st));
+    }
+    HIPCHK(c, launch_wrap(c->geo, n, c->L.pos, c->st));
+  }
+  c->np = n;
+  c->groups_dirty = true;
+  return LB_OK;
+}
+
+lb_status lb_set_bonds(lb_ctx* c, int64_t nb, const int32_t* h_pairs, double k, double r0,
+                       int32_t type) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (nb < 0 || (nb > 0 && !h_pairs)) return fail(c, LB_EINVAL, "invalid bond list");
+  if (nb > c->lim.max_bonds) return fail(c, LB_ENOMEM, "more bonds than max_bonds");
+  if (type != LB_HARMONIC && type != LB_FENE) return fail(c, LB_EINVAL, "unknown bond type");
+  if (!std::isfinite(k) || !std::isfinite(r0) || (type == LB_FENE && !(r0 > 0)))
+    return fail(c, LB_EINVAL, "invalid bond parameters");
+  c->bonds.assign(h_pairs, h_pairs + 2 * nb);
+  c->nbond = nb;
+  c->bond_k = k;
+  c->bond_r0 = r0;
+  c->bond_type = type;
+  c->groups_dirty = true;
+  return LB_OK;
+}
+
+lb_status lb_set_shells(lb_ctx* c, int32_t nshell, int32_t shell_size, const double* h_template,
+                        double k_tether) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (nshell < 0 || shell_size < 0 || (nshell > 0 && (shell_size < 3 || !h_template)))
+    return fail(c, LB_EINVAL, "invalid shell description");
+  if (nshell > c->lim.max_shells || shell_size > c->lim.max_shell_size)
+    return fail(c, LB_ENOMEM, "shells exceed the limits");
+  if (nshell > 0 && c->p.mts_substeps > 0)
+    return fail(c, LB_EINVAL, "shells are not supported with multiple time stepping");
+  if (nshell > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->L.tmpl, h_template, (size_t)shell_size * 24,
+                             hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+  }
+  c->nshell = nshell;
+  c->shell_size = shell_size;
+  c->k_tether = k_tether;
+  return LB_OK;
+}
+
+lb_status lb_step(lb_ctx* c, int64_t nsteps) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (nsteps < 0) return fail(c, LB_EINVAL, "negative step count");
+  if ((int64_t)c->nshell * c->shell_size > c->np)
+    return fail(c, LB_ESTATE, "shells need nshell*shell_size particles");
+  const bool need_groups =
+      c->np > 0 && c->p.coupling != LB_COUPLE_NONE && (c->nbond > 0 || c->p.mts_substeps > 0);
+  if (need_groups && c->groups_dirty) {
+    lb_status s = build_groups(c);
+    if (s != LB_OK) return s;
+  }
+  for (int64_t t = 0; t < nsteps; ++t) {
+    lb_status s = step_once(c);
+    if (s != LB_OK) return s;
+    c->steps++;
+  }
+  return LB_OK;
+}
+
+lb_status lb_moments(lb_ctx* c, double* d_rho, double* d_u) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (!d_u) return fail(c, LB_EINVAL, "null velocity output");
+  HIPCHK(c, launch_moments(c->p.storage, site_args(c), d_rho, d_u, c->st));
+  return LB_OK;
+}
+
+lb_status lb_populations(lb_ctx* c, double* d_df) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (!d_df) return fail(c, LB_EINVAL, "null output");
+  HIPCHK(c, launch_populations(c->p.storage, site_args(c), d_df, c->st));
+  return LB_OK;
+}
+
+lb_status lb_get_particles(lb_ctx* c, double* d_pos, double* d_vel) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (c->np > 0 && d_pos)
+    HIPCHK(c, hipMemcpyAsync(d_pos, c->L.pos, c->np * 24, hipMemcpyDeviceToDevice, c->st));
+  if (c->np > 0 && d_vel)
+    HIPCHK(c, hipMemcpyAsync(d_vel, c->L.vel, c->np * 24, hipMemcpyDeviceToDevice, c->st));
+  return LB_OK;
+}
+
+lb_status lb_totals(lb_ctx* c, double h_out[7]) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (!h_out) return fail(c, LB_EINVAL, "null output");
+  const bool massive = c->p.coupling == LB_COUPLE_FC || c->p.coupling == LB_COUPLE_EBF;
+  HIPCHK(c, launch_totals(c->p.storage, site_args(c), c->L.partial, kTotalsBlocks,
+                          massive ? c->L.vel : nullptr, massive ? c->L.mass : nullptr, c->np,
+                          c->L.tot, c->st));
+  double tmp[8];
+  HIPCHK(c, hipMemcpyAsync(tmp, c->L.tot, 8 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  for (int k = 0; k < 7; ++k) h_out[k] = tmp[k];
+  return LB_OK;
+}
+
+static void free_events(lb_ctx* c) {
+  for (auto e : c->ev) (void)hipEventDestroy(e);
+  c->ev.clear();
+  c->ev_used = 0;
+}
+
+lb_status lb_timing(lb_ctx* c, int32_t max_passes) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (max_passes < 0 || max_passes > (1 << 20)) return fail(c, LB_EINVAL, "invalid pass count");
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  free_events(c);
+  for (int32_t k = 0; k < 2 * max_passes; ++k) {
+    hipEvent_t e;
+    HIPCHK(c, hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  return LB_OK;
+}
+
+lb_status lb_timing_read(lb_ctx* c, double* lattice_ms, int64_t* passes) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  double tot = 0;
+  for (int32_t k = 0; k < c->ev_used; ++k) {
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+    tot += ms;
+  }
+  if (lattice_ms) *lattice_ms = tot;
+  if (passes) *passes = c->ev_used;
+  c->ev_used = 0;
+  return LB_OK;
+}
+
+lb_status lb_info(const lb_ctx* c, int64_t* nparticles, int64_t* steps) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (nparticles) *nparticles = c->np;
+  if (steps) *steps = c->steps;
+  return LB_OK;
+}
+
+lb_status lb_destroy(lb_ctx* c) {
+  if (!c) return LB_OK;
+  free_events(c);
+  delete c;
+  return LB_OK;
+}
+
+const char* lb_last_error(const lb_ctx* c) { return c ? c->err.c_str() : g_last_error.c_str(); }
+
+const char* lb_status_string(lb_status s) {
+  switch (s) {
+    case LB_OK: return "ok";
+    case LB_EINVAL: return "invalid argument";
+    case LB_ENOMEM: return "insufficient workspace or capacity";
+    case LB_EBUSY: return "busy";
+    case LB_EDEVICE: return "device error";
+    case LB_ESTATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,144 @@
+// lbc_device.h -- device-side building blocks of the gfx950 lattice Boltzmann
+// library: the D3Q19 velocity set in library order, storage traits for the
+// population precisions, the pull gather used by every kernel that needs the
+// post-stream populations, and small FP64 helpers for the particle side.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbc.h"
+#include "lbc_internal.h"
+
+namespace lbc {
+
+// D3Q19 with opposite directions adjacent: i and i+1 are opposites for odd i,
+// so the two-rate collision works on the pairs (1,2), (3,4), ..., (17,18).
+constexpr int Q = 19;
+constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+// weights: rest 1/3, faces 1/18, edges 1/36
+constexpr int WCLASS[Q] = {0, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2};
+
+template <typename R>
+__device__ __forceinline__ R wgt(int i) {
+  return WCLASS[i] == 0 ? R(1) / R(3) : (WCLASS[i] == 1 ? R(1) / R(18) : R(1) / R(36));
+}
+
+// ------------------------------------------------------------------ storage
+template <int S>
+struct Store;
+template <>
+struct Store<LB_F64> {
+  using T = double;
+  using R = double;
+  using V4 = double4;
+  static __device__ __forceinline__ R ld(const T* p, R) { return *p; }
+  static __device__ __forceinline__ void st(T* p, R v, R) { *p = v; }
+};
+template <>
+struct Store<LB_F32> {
+  using T = float;
+  using R = float;
+  using V4 = float4;
+  static __device__ __forceinline__ R ld(const T* p, R) { return *p; }
+  static __device__ __forceinline__ void st(T* p, R v, R) { *p = v; }
+};
+template <>
+struct Store<LB_F16> {
+  using T = __half;
+  using R = float;
+  using V4 = float4;
+  // stored value is scale * (f - w rho0); inv is 1/scale (a power of two)
+  static __device__ __forceinline__ R ld(const T* p, R inv) { return __half2float(*p) * inv; }
+  static __device__ __forceinline__ void st(T* p, R v, R scale) { *p = __float2half_rn(v * scale); }
+};
+template <>
+struct Store<LB_BF16> {
+  using T = __hip_bfloat16;
+  using R = float;
+  using V4 = float4;
+  static __device__ __forceinline__ R ld(const T* p, R inv) { return __bfloat162float(*p) * inv; }
+  static __device__ __forceinline__ void st(T* p, R v, R scale) { *p = __float2bfloat16(v * scale); }
+};
+
+__device__ __forceinline__ long long site_index(const Geo& g, int x, int y, int z) {
+  return ((long long)z * g.ny + y) * g.nx + x;
+}
+
+// Pull gather: fbar_i(x) = f*_i(x - c_i), periodic, or the reflected opposite
+// population of the same site when x - c_i lies beyond a y wall (halfway
+// bounce-back).  Values are converted to the compute type R.
+template <int S, typename R>
+__device__ __forceinline__ void pull(const typename Store<S>::T* __restrict__ f, const Geo& g,
+                                     int x, int y, int z, R inv, R out[Q]) {
+  const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+  const long long own = site_index(g, x, y, z);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    long long src;
+    const bool bb = g.wall && ((CY[i] == 1 && y == 0) || (CY[i] == -1 && y == g.ny - 1));
+    if (bb) {
+      src = (long long)OPP[i] * g.N + own;
+    } else {
+      const int xs = CX[i] == 1 ? xm : (CX[i] == -1 ? xp : x);
+      const int ys = CY[i] == 1 ? ym : (CY[i] == -1 ? yp : y);
+      const int zs = CZ[i] == 1 ? zm : (CZ[i] == -1 ? zp : z);
+      src = (long long)i * g.N + site_index(g, xs, ys, zs);
+    }
+    out[i] = Store<S>::ld(f + src, inv);
+  }
+}
+
+// deviation equilibrium f^eq_i(rho,u) - w_i rho0 = w_i [drho + rho P_i(u)],
+// P_i(u) = 3 c.u + 9/2 (c.u)^2 - 3/2 u.u
+template <typename R>
+__device__ __forceinline__ R feq_dev(int i, R drho, R rho, R ux, R uy, R uz, R usq) {
+  const R cu = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
+  return wgt<R>(i) * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq));
+}
+
+// ---------------------------------------------------------- delta functions
+// One-dimensional weights of a delta-function stencil (Appendix A kernels).
+// Returns the first node j0; weights for nodes j0 .. j0+K-1.
+__device__ __forceinline__ double phi_eval(int K, double r) {
+  const double a = fabs(r);
+  if (K == 2) return a < 1.0 ? 1.0 - a : 0.0;
+  if (K == 3) {
+    if (a <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * r * r)) / 3.0;
+    if (a <= 1.5) return (5.0 - 3.0 * a - sqrt(fmax(0.0, 6.0 * a - 2.0 - 3.0 * r * r))) / 6.0;
+    return 0.0;
+  }
+  if (a <= 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * r * r)) / 8.0;
+  if (a <= 2.0) return (5.0 - 2.0 * a - sqrt(fmax(0.0, -7.0 + 12.0 * a - 4.0 * r * r))) / 8.0;
+  return 0.0;
+}
+
+__device__ __forceinline__ int stencil(int K, double X, double w[4]) {
+  const int j0 = K == 3 ? (int)floor(X + 0.5) - 1 : (K == 2 ? (int)floor(X) : (int)floor(X) - 1);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = k < K ? phi_eval(K, (double)(j0 + k) - X) : 0.0;
+  return j0;
+}
+
+__device__ __forceinline__ int wrap_idx(int j, int n) {
+  int r = j % n;
+  return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ double wrap_pos(double x, double L) { return x - L * floor(x / L); }
+
+// ------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace lbc

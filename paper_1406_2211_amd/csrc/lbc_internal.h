@@ -1,0 +1,118 @@
+// lbc_internal.h -- argument blocks and launchers shared by the host runtime
+// (lbc_api.hip) and the kernels (lbc_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbc.h"
+
+namespace lbc {
+
+// Lattice geometry passed to every kernel.
+struct Geo {
+  int nx, ny, nz;
+  int wall;  // halfway bounce-back walls in y
+  int wpr;   // 64-bit force-mask words per row
+  long long N;
+};
+
+// Fused lattice pass (stream, both pending half forces, collide).
+struct LatArgs {
+  Geo g;
+  const void* fin;  // f* of the previous pass
+  void* fout;       // f* of this pass
+  void* FA;         // first-half coupling force of this step (vec4 per site)
+  void* FB;         // second-half coupling force of the previous step
+  uint64_t* mask;   // per-site flag: FA or FB nonzero
+  double rho0;
+  double Fx, Fy, Fz;  // body force times the number of pending halves (1 or 2)
+  double omp, omm;    // 1 - lambda for even / odd non-conserved moments
+  float scale, inv;   // 16-bit storage scale 2^p and its inverse (1 otherwise)
+};
+
+struct InitArgs {
+  Geo g;
+  void* f;
+  const double* rho;
+  const double* u;
+  double rho0;
+  float scale;
+};
+
+// Read access to the stored state for moments at a site.
+struct SiteArgs {
+  Geo g;
+  const void* f;
+  const void* FB;
+  double rho0;
+  double pfx, pfy, pfz;  // pending body force (0 before the first step, F_ext after)
+  float inv;
+};
+
+struct PartArgs {
+  SiteArgs s;
+  void* FA;
+  void* FB;  // writable alias of s.FB
+  uint64_t* mask;
+  int K;  // delta kernel points (2, 3, 4)
+  long long n;
+  double* pos;
+  double* vel;
+  const double* mass;
+  double* fint;
+  double* aux;  // IB predictor positions
+  double gamma;
+  int coupling;
+  int use_fint;     // F_int enters the coupling force and the kick (Alg. 3)
+  int phys;         // interpolate the physical velocity (with pending FB)
+  int target;       // spread into FA (0) or FB (1)
+  int drift_after;  // final P^1/2 of Alg. 3
+};
+
+struct BondArgs {
+  Geo g;
+  const int32_t* perm;   // particles ordered by group
+  const int32_t* loc;    // slot of each particle inside its group
+  const int32_t* goff;   // group offsets into perm
+  const int32_t* start;  // CSR of bond partners (global particle indices)
+  const int32_t* nbr;
+  double* pos;
+  double* vel;
+  const double* mass;
+  double* fint;
+  double k, r0;
+  int type;
+};
+
+struct ShellArgs {
+  Geo g;
+  const double* pos;
+  const double* tmpl;
+  double* fint;
+  double* rot;
+  int M;
+  double k;
+};
+
+hipError_t launch_stream_collide(int storage, int collision, const LatArgs& a, hipStream_t st);
+hipError_t launch_init(int storage, const InitArgs& a, hipStream_t st);
+hipError_t launch_moments(int storage, const SiteArgs& a, double* rho, double* u, hipStream_t st);
+hipError_t launch_populations(int storage, const SiteArgs& a, double* out, hipStream_t st);
+hipError_t launch_totals(int storage, const SiteArgs& a, double* partial, int nblk,
+                         const double* vel, const double* mass, long long np, double* out,
+                         hipStream_t st);
+hipError_t launch_drift(const Geo& g, long long n, double* pos, const double* vel, double dt,
+                        hipStream_t st);
+hipError_t launch_wrap(const Geo& g, long long n, double* pos, hipStream_t st);
+hipError_t launch_couple_half(int storage, const PartArgs& a, hipStream_t st);
+hipError_t launch_ib_predict(int storage, const PartArgs& a, hipStream_t st);
+hipError_t launch_ib_advect(int storage, const PartArgs& a, int spread_fint, hipStream_t st);
+hipError_t launch_ib_spread_b(int storage, const PartArgs& a, hipStream_t st);
+hipError_t launch_bond_groups(const BondArgs& b, int ngroups, int gcap, int mode, int acc,
+                              int nsub, double dt, hipStream_t st);
+hipError_t launch_shell_forces(const ShellArgs& s, int nshell, hipStream_t st);
+
+constexpr int kTotalsBlocks = 1024;
+
+}  // namespace lbc

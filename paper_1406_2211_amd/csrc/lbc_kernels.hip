@@ -1,0 +1,725 @@
+// lbc_kernels.hip -- gfx950 kernels of the split-forcing lattice Boltzmann
+// step with fluid-particle coupling (Schiller, arXiv:1406.2211).
+//
+// Lattice state between steps: post-collision populations f* (deviation from
+// w rho0, structure of arrays [19][nz][ny][nx]), a pending second half force
+// FB (per-site vector, nonzero only at sites flagged in a per-site bit mask)
+// and a flag telling whether the body force's second half is pending.  The
+// physical populations at a step boundary are S f* shifted by the equilibrium
+// difference of that pending half force (Sec. 3.3: a midpoint half force is an
+// exact equilibrium shift).
+#include "lbc_device.h"
+#include "lbc_internal.h"
+
+namespace lbc {
+
+// ======================================================================
+// Fused lattice pass: pull (streaming S, Sec. 3.1), moments, both pending
+// half forces as one equilibrium shift (F^1/2 of the previous step and of
+// this step, Sec. 3.3), collision C (Eq. collision-operator / Eq. mrt-coll),
+// store.  One work-item per site; a 64-wide wavefront covers 64 consecutive
+// x sites of one row, i.e. exactly one 64-bit word of the force mask.
+// ======================================================================
+template <int S, int COL>
+__global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
+  using St = Store<S>;
+  using T = typename St::T;
+  using R = typename St::R;
+  using V4 = typename St::V4;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y, z = blockIdx.z;
+  if (x >= a.g.nx) return;
+  R f[Q];
+  pull<S, R>((const T*)a.fin, a.g, x, y, z, (R)a.inv, f);
+  R drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += f[i];
+    jx += R(CX[i]) * f[i];
+    jy += R(CY[i]) * f[i];
+    jz += R(CZ[i]) * f[i];
+  }
+  const R rho = R(a.rho0) + drho;
+  const R ir = R(1) / rho;
+  R Fx = R(a.Fx), Fy = R(a.Fy), Fz = R(a.Fz);
+  const long long own = site_index(a.g, x, y, z);
+  uint64_t* mp = a.mask + ((long long)z * a.g.ny + y) * a.g.wpr + (x >> 6);
+  const uint64_t word = *mp;
+  if (word) {
+    if ((word >> (x & 63)) & 1ull) {
+      V4* FA = (V4*)a.FA;
+      V4* FB = (V4*)a.FB;
+      const V4 fa = FA[own], fb = FB[own];
+      Fx += fa.x + fb.x;
+      Fy += fa.y + fb.y;
+      Fz += fa.z + fb.z;
+      V4 zero;
+      zero.x = zero.y = zero.z = zero.w = 0;
+      FA[own] = zero;
+      FB[own] = zero;
+    }
+    if ((x & 63) == 0) *mp = 0;
+  }
+  const R ux = jx * ir, uy = jy * ir, uz = jz * ir;         // post-stream velocity
+  const R hx = ux + R(0.5) * Fx * ir, hy = uy + R(0.5) * Fy * ir,
+          hz = uz + R(0.5) * Fz * ir;                      // after both half forces
+  const R usq = ux * ux + uy * uy + uz * uz, hsq = hx * hx + hy * hy + hz * hz;
+  T* fo = (T*)a.fout;
+  const R omp = R(a.omp), omm = R(a.omm), sc = R(a.scale);
+  if (COL == LB_BGK) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R eb = feq_dev<R>(i, drho, rho, ux, uy, uz, usq);
+      const R ep = feq_dev<R>(i, drho, rho, hx, hy, hz, hsq);
+      St::st(fo + (long long)i * a.g.N + own, ep + omp * (f[i] - eb), sc);
+    }
+  } else {
+    {
+      const R w0 = wgt<R>(0);
+      const R eb = w0 * (drho - R(1.5) * rho * usq), ep = w0 * (drho - R(1.5) * rho * hsq);
+      St::st(fo + own, ep + omp * (f[0] - eb), sc);
+    }
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+      const R w = wgt<R>(i);
+      const R cb = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
+      const R ch = R(CX[i]) * hx + R(CY[i]) * hy + R(CZ[i]) * hz;
+      const R Eb = w * (drho + rho * (R(4.5) * cb * cb - R(1.5) * usq)), Ob = w * rho * R(3) * cb;
+      const R Eh = w * (drho + rho * (R(4.5) * ch * ch - R(1.5) * hsq)), Oh = w * rho * R(3) * ch;
+      const R ni = f[i] - (Eb + Ob), nj = f[i + 1] - (Eb - Ob);
+      const R sym = R(0.5) * (ni + nj), anti = R(0.5) * (ni - nj);
+      St::st(fo + (long long)i * a.g.N + own, Eh + Oh + omp * sym + omm * anti, sc);
+      St::st(fo + (long long)(i + 1) * a.g.N + own, Eh - Oh + omp * sym - omm * anti, sc);
+    }
+  }
+}
+
+// ======================================================================
+// Initialisation: physical state f = f^eq(rho, u).  Written as the pre-image
+// under the pull gather (push of each population to the slot it will be
+// pulled from), so that the first lattice pass sees exactly f^eq.
+// ======================================================================
+template <int S>
+__global__ void k_init(InitArgs a) {
+  using St = Store<S>;
+  using T = typename St::T;
+  using R = typename St::R;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y, z = blockIdx.z;
+  if (x >= a.g.nx) return;
+  const long long s = site_index(a.g, x, y, z);
+  const double rho = a.rho ? a.rho[s] : a.rho0;
+  const double ux = a.u ? a.u[s] : 0.0, uy = a.u ? a.u[a.g.N + s] : 0.0,
+               uz = a.u ? a.u[2 * a.g.N + s] : 0.0;
+  const double usq = ux * ux + uy * uy + uz * uz;
+  const double drho = rho - a.rho0;
+  T* f = (T*)a.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double v = feq_dev<double>(i, drho, rho, ux, uy, uz, usq);
+    const int ys = y - CY[i];
+    long long dst;
+    if (a.g.wall && (ys < 0 || ys >= a.g.ny)) {
+      dst = (long long)OPP[i] * a.g.N + s;
+    } else {
+      dst = (long long)i * a.g.N +
+            site_index(a.g, wrap_idx(x - CX[i], a.g.nx), wrap_idx(ys, a.g.ny),
+                       wrap_idx(z - CZ[i], a.g.nz));
+    }
+    St::st(f + dst, (R)v, (R)a.scale);
+  }
+}
+
+// Physical moments at one site: rho and rho u = sum f c + (h/2)(FB + pend F_ext)
+// (the redefined velocity of Sec. 4).
+template <int S>
+__device__ __forceinline__ void site_phys(const SiteArgs& a, int x, int y, int z, double fl[Q],
+                                          double& drho, double j[3], bool phys) {
+  using St = Store<S>;
+  pull<S, double>((const typename St::T*)a.f, a.g, x, y, z, (double)a.inv, fl);
+  drho = 0;
+  j[0] = j[1] = j[2] = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += fl[i];
+    j[0] += CX[i] * fl[i];
+    j[1] += CY[i] * fl[i];
+    j[2] += CZ[i] * fl[i];
+  }
+  if (phys) {
+    const long long s = site_index(a.g, x, y, z);
+    using V4 = typename St::V4;
+    const V4 fb = ((const V4*)a.FB)[s];
+    j[0] += 0.5 * ((double)fb.x + a.pfx);
+    j[1] += 0.5 * ((double)fb.y + a.pfy);
+    j[2] += 0.5 * ((double)fb.z + a.pfz);
+  }
+}
+
+template <int S>
+__global__ void k_moments(SiteArgs a, double* rho, double* u) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y, z = blockIdx.z;
+  if (x >= a.g.nx) return;
+  double fl[Q], drho, j[3];
+  site_phys<S>(a, x, y, z, fl, drho, j, true);
+  const long long s = site_index(a.g, x, y, z);
+  const double r = a.rho0 + drho;
+  if (rho) rho[s] = r;
+  u[s] = j[0] / r;
+  u[a.g.N + s] = j[1] / r;
+  u[2 * a.g.N + s] = j[2] / r;
+}
+
+template <int S>
+__global__ void k_populations(SiteArgs a, double* out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y, z = blockIdx.z;
+  if (x >= a.g.nx) return;
+  double fl[Q], drho, j[3], jb[3];
+  site_phys<S>(a, x, y, z, fl, drho, jb, false);
+  site_phys<S>(a, x, y, z, fl, drho, j, true);
+  const long long s = site_index(a.g, x, y, z);
+  const double r = a.rho0 + drho;
+  const double ub[3] = {jb[0] / r, jb[1] / r, jb[2] / r}, up[3] = {j[0] / r, j[1] / r, j[2] / r};
+  const double sb = ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2];
+  const double sp = up[0] * up[0] + up[1] * up[1] + up[2] * up[2];
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    out[(long long)i * a.g.N + s] = fl[i] + feq_dev<double>(i, drho, r, up[0], up[1], up[2], sp) -
+                                    feq_dev<double>(i, drho, r, ub[0], ub[1], ub[2], sb);
+}
+
+// Block reduction of 4 doubles in a fixed order (deterministic).
+__device__ __forceinline__ void block_sum4(double v[4], double* lds /*[4*16]*/) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0)
+    for (int k = 0; k < 4; ++k) lds[4 * wv + k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 4; ++k) {
+      double t = 0;
+      for (int w = 0; w < nw; ++w) t += lds[4 * w + k];
+      v[k] = t;
+    }
+  }
+  __syncthreads();
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_totals_sites(SiteArgs a, double* partial) {
+  __shared__ double lds[64];
+  double v[4] = {0, 0, 0, 0};
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < a.g.N; s += stride) {
+    const int x = (int)(s % a.g.nx);
+    const long long r = s / a.g.nx;
+    const int y = (int)(r % a.g.ny), z = (int)(r / a.g.ny);
+    double fl[Q], drho, j[3];
+    site_phys<S>(a, x, y, z, fl, drho, j, true);
+    v[0] += drho;
+    v[1] += j[0];
+    v[2] += j[1];
+    v[3] += j[2];
+  }
+  block_sum4(v, lds);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) partial[4 * blockIdx.x + k] = v[k];
+}
+
+__global__ __launch_bounds__(256) void k_totals_final(const double* partial, int nblk,
+                                                      const double* vel, const double* mass,
+                                                      long long np, double* out) {
+  __shared__ double lds[64];
+  double v[4] = {0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+    for (int k = 0; k < 4; ++k) v[k] += partial[4 * b + k];
+  block_sum4(v, lds);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) out[k] = v[k];
+  double p[4] = {0, 0, 0, 0};
+  if (vel && mass)
+    for (long long i = threadIdx.x; i < np; i += blockDim.x)
+      for (int k = 0; k < 3; ++k) p[k] += mass[i] * vel[3 * i + k];
+  block_sum4(p, lds);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) out[4 + k] = p[k];
+}
+
+// ======================================================================
+// Particle side: interpolation I (Eq. IBM-interpolation), spreading I*
+// (Eq. IBM-spreading), coupling forces (Eq. modified-force, Eq.
+// modified-ebf), velocity kicks and position drifts (Alg. 2 and 3).
+// ======================================================================
+template <int S>
+__device__ void interp(const PartArgs& a, const double X[3], bool phys, double& rp,
+                       double up[3]) {
+  double wx[4], wy[4], wz[4];
+  const int jx = stencil(a.K, X[0], wx), jy = stencil(a.K, X[1], wy), jz = stencil(a.K, X[2], wz);
+  rp = 0;
+  up[0] = up[1] = up[2] = 0;
+  for (int kz = 0; kz < a.K; ++kz) {
+    const int zz = wrap_idx(jz + kz, a.s.g.nz);
+    for (int ky = 0; ky < a.K; ++ky) {
+      int yy = jy + ky;
+      if (a.s.g.wall) {
+        if (yy < 0 || yy >= a.s.g.ny) continue;
+      } else {
+        yy = wrap_idx(yy, a.s.g.ny);
+      }
+      for (int kx = 0; kx < a.K; ++kx) {
+        const double W = wx[kx] * wy[ky] * wz[kz];
+        if (W == 0.0) continue;
+        const int xx = wrap_idx(jx + kx, a.s.g.nx);
+        double fl[Q], drho, j[3];
+        site_phys<S>(a.s, xx, yy, zz, fl, drho, j, phys);
+        const double r = a.s.rho0 + drho;
+        rp += W * r;
+        up[0] += W * j[0] / r;
+        up[1] += W * j[1] / r;
+        up[2] += W * j[2] / r;
+      }
+    }
+  }
+}
+
+template <typename E>
+__device__ void spread(const PartArgs& a, const double X[3], const double F[3], void* field) {
+  double wx[4], wy[4], wz[4];
+  const int jx = stencil(a.K, X[0], wx), jy = stencil(a.K, X[1], wy), jz = stencil(a.K, X[2], wz);
+  E* Fd = (E*)field;
+  for (int kz = 0; kz < a.K; ++kz) {
+    const int zz = wrap_idx(jz + kz, a.s.g.nz);
+    for (int ky = 0; ky < a.K; ++ky) {
+      int yy = jy + ky;
+      if (a.s.g.wall) {
+        if (yy < 0 || yy >= a.s.g.ny) continue;
+      } else {
+        yy = wrap_idx(yy, a.s.g.ny);
+      }
+      for (int kx = 0; kx < a.K; ++kx) {
+        const double W = wx[kx] * wy[ky] * wz[kz];
+        if (W == 0.0) continue;
+        const int xx = wrap_idx(jx + kx, a.s.g.nx);
+        const long long s = site_index(a.s.g, xx, yy, zz);
+        unsafeAtomicAdd(Fd + 4 * s + 0, (E)(W * F[0]));
+        unsafeAtomicAdd(Fd + 4 * s + 1, (E)(W * F[1]));
+        unsafeAtomicAdd(Fd + 4 * s + 2, (E)(W * F[2]));
+        atomicOr((unsigned long long*)(a.mask + ((long long)zz * a.s.g.ny + yy) * a.s.g.wpr +
+                                       (xx >> 6)),
+                 1ull << (xx & 63));
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void wrap3(const Geo& g, double r[3]) {
+  r[0] = wrap_pos(r[0], (double)g.nx);
+  if (!g.wall) r[1] = wrap_pos(r[1], (double)g.ny);
+  r[2] = wrap_pos(r[2], (double)g.nz);
+}
+
+// P^1/2: r <- r + (h/2) v, wrapped (first drift of Alg. 3).
+__global__ void k_drift(Geo g, long long n, double* pos, const double* vel, double dt) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  double r[3];
+  for (int k = 0; k < 3; ++k) r[k] = pos[3 * p + k] + dt * vel[3 * p + k];
+  wrap3(g, r);
+  for (int k = 0; k < 3; ++k) pos[3 * p + k] = r[k];
+}
+
+__global__ void k_wrap(Geo g, long long n, double* pos) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  double r[3] = {pos[3 * p], pos[3 * p + 1], pos[3 * p + 2]};
+  wrap3(g, r);
+  for (int k = 0; k < 3; ++k) pos[3 * p + k] = r[k];
+}
+
+// One coupling half step for FC / modified EBF: interpolate rho_p, u_p at r,
+// compute F^h (h' = h/2), kick v, optionally drift, and spread -F^h.
+template <int S>
+__global__ void k_couple_half(PartArgs a) {
+  using E = typename Store<S>::R;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n) return;
+  double r[3], v[3], Fi[3] = {0, 0, 0};
+  for (int k = 0; k < 3; ++k) {
+    r[k] = a.pos[3 * p + k];
+    v[k] = a.vel[3 * p + k];
+    if (a.use_fint) Fi[k] = a.fint[3 * p + k];
+  }
+  const double m = a.mass[p];
+  double rp, up[3];
+  interp<S>(a, r, a.phys != 0, rp, up);
+  const double hh = 0.5, al = a.gamma * hh / m, be = a.gamma * hh / rp;
+  double Fh[3];
+  if (a.coupling == LB_COUPLE_FC) {
+    const double den = 1.0 + 0.5 * al + 0.5 * be;
+    for (int k = 0; k < 3; ++k) {
+      Fh[k] = -(a.gamma * (v[k] - up[k]) + 0.5 * al * Fi[k]) / den;
+      v[k] += hh / m * (Fh[k] + Fi[k]);
+    }
+  } else {
+    const double sm = al + be;
+    for (int k = 0; k < 3; ++k) {
+      const double d = v[k] - up[k];
+      Fh[k] = -a.gamma / sm * d - al / sm * Fi[k];
+      v[k] = v[k] - al / sm * d + (hh / m) * (be / sm) * Fi[k];
+    }
+  }
+  const double Ff[3] = {-Fh[0], -Fh[1], -Fh[2]};
+  spread<E>(a, r, Ff, a.target ? a.FB : a.FA);
+  if (a.drift_after) {
+    for (int k = 0; k < 3; ++k) r[k] += hh * v[k];
+    wrap3(a.s.g, r);
+    for (int k = 0; k < 3; ++k) a.pos[3 * p + k] = r[k];
+  }
+  for (int k = 0; k < 3; ++k) a.vel[3 * p + k] = v[k];
+}
+
+// IB (Alg. 2): predictor X~ = X + (h/2) I[X] u(t)
+template <int S>
+__global__ void k_ib_predict(PartArgs a) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n) return;
+  double X[3] = {a.pos[3 * p], a.pos[3 * p + 1], a.pos[3 * p + 2]}, rp, up[3];
+  interp<S>(a, X, true, rp, up);
+  for (int k = 0; k < 3; ++k) X[k] += 0.5 * up[k];
+  wrap3(a.s.g, X);
+  for (int k = 0; k < 3; ++k) a.aux[3 * p + k] = X[k];
+}
+
+// IB: X <- X + (h/2) I[X~] u with the current physical u; with spread != 0
+// also spreads +F_int at X~ into the A field (first half force).
+template <int S>
+__global__ void k_ib_advect(PartArgs a, int spread_fint) {
+  using E = typename Store<S>::R;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n) return;
+  const double Xt[3] = {a.aux[3 * p], a.aux[3 * p + 1], a.aux[3 * p + 2]};
+  double rp, up[3];
+  interp<S>(a, Xt, true, rp, up);
+  double X[3];
+  for (int k = 0; k < 3; ++k) X[k] = a.pos[3 * p + k] + 0.5 * up[k];
+  wrap3(a.s.g, X);
+  for (int k = 0; k < 3; ++k) a.pos[3 * p + k] = X[k];
+  if (spread_fint) {
+    const double F[3] = {a.fint[3 * p], a.fint[3 * p + 1], a.fint[3 * p + 2]};
+    spread<E>(a, Xt, F, a.FA);
+  }
+}
+
+// IB: spread +F_int at X~ into the B field (second half force).
+template <int S>
+__global__ void k_ib_spread_b(PartArgs a) {
+  using E = typename Store<S>::R;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n) return;
+  const double Xt[3] = {a.aux[3 * p], a.aux[3 * p + 1], a.aux[3 * p + 2]};
+  const double F[3] = {a.fint[3 * p], a.fint[3 * p + 1], a.fint[3 * p + 2]};
+  spread<E>(a, Xt, F, a.FB);
+}
+
+// ======================================================================
+// Intrinsic forces.
+// ======================================================================
+
+// Bonded groups: block b owns the particles perm[goff[b] .. goff[b+1]), a
+// union of whole bonded clusters, so every bond partner is in the block's
+// LDS.  mode 0: F_int at the current positions (stored, or added with acc).
+// mode 1: nsub velocity-Verlet sub-steps of length dt with F_int only
+// (the [P F_int P]^n factor of the multiple time-step split, Sec. 6).
+__device__ __forceinline__ void bond_force(const BondArgs& b, long long p, const double r[3],
+                                           const double* lds, double F[3]) {
+  F[0] = F[1] = F[2] = 0;
+  for (int e = b.start[p]; e < b.start[p + 1]; ++e) {
+    const int q = b.nbr[e];
+    const int lq = b.loc[q];
+    double d[3];
+    for (int k = 0; k < 3; ++k) d[k] = lds[3 * lq + k] - r[k];
+    d[0] -= b.g.nx * floor(d[0] / b.g.nx + 0.5);
+    if (!b.g.wall) d[1] -= b.g.ny * floor(d[1] / b.g.ny + 0.5);
+    d[2] -= b.g.nz * floor(d[2] / b.g.nz + 0.5);
+    const double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double s;
+    if (b.type == LB_FENE)
+      s = b.k / (1.0 - L * L / (b.r0 * b.r0));
+    else
+      s = L > 0.0 ? b.k * (L - b.r0) / L : 0.0;
+    for (int k = 0; k < 3; ++k) F[k] += s * d[k];
+  }
+}
+
+__global__ void k_bond_groups(BondArgs b, int mode, int acc, int nsub, double dt) {
+  extern __shared__ double lds[];
+  const int g0 = b.goff[blockIdx.x], cnt = b.goff[blockIdx.x + 1] - g0;
+  const int t = threadIdx.x;
+  const bool on = t < cnt;
+  const long long p = on ? b.perm[g0 + t] : 0;
+  double r[3] = {0, 0, 0}, v[3] = {0, 0, 0}, m = 1.0;
+  if (on) {
+    for (int k = 0; k < 3; ++k) {
+      r[k] = b.pos[3 * p + k];
+      v[k] = b.vel ? b.vel[3 * p + k] : 0.0;
+    }
+    if (b.mass) m = b.mass[p];
+  }
+  if (mode == 0) {
+    if (on)
+      for (int k = 0; k < 3; ++k) lds[3 * t + k] = r[k];
+    __syncthreads();
+    if (on) {
+      double F[3];
+      bond_force(b, p, r, lds, F);
+      for (int k = 0; k < 3; ++k) b.fint[3 * p + k] = acc ? b.fint[3 * p + k] + F[k] : F[k];
+    }
+    return;
+  }
+  for (int s = 0; s < nsub; ++s) {
+    if (on) {
+      for (int k = 0; k < 3; ++k) r[k] += 0.5 * dt * v[k];
+      wrap3(b.g, r);
+    }
+    __syncthreads();
+    if (on)
+      for (int k = 0; k < 3; ++k) lds[3 * t + k] = r[k];
+    __syncthreads();
+    if (on) {
+      double F[3];
+      bond_force(b, p, r, lds, F);
+      for (int k = 0; k < 3; ++k) {
+        v[k] += dt / m * F[k];
+        r[k] += 0.5 * dt * v[k];
+      }
+      wrap3(b.g, r);
+    }
+  }
+  if (on)
+    for (int k = 0; k < 3; ++k) {
+      b.pos[3 * p + k] = r[k];
+      b.vel[3 * p + k] = v[k];
+    }
+}
+
+// Rigid-shell tethers: block per shell.  Markers are unwrapped around the
+// first marker, centred, the least-squares rotation of the template onto
+// them is found from the dominant eigenvector of Horn's symmetric 4x4
+// quaternion matrix (cyclic Jacobi), and F_j = -k (y_j - c - R t_j).
+__device__ void sym4_eig_max(double A[4][4], double q[4]) {
+  double V[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+  for (int it = 0; it < 50; ++it) {
+    double off = 0, dia = 0;
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) (i == j ? dia : off) += A[i][j] * A[i][j];
+    if (off == 0.0 || off < 1e-32 * dia) break;
+    for (int p = 0; p < 3; ++p)
+      for (int r = p + 1; r < 4; ++r) {
+        const double apr = A[p][r];
+        if (apr == 0.0) continue;
+        const double theta = 0.5 * (A[r][r] - A[p][p]) / apr;
+        const double t = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = rsqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < 4; ++k) {
+          const double x = A[k][p], y = A[k][r];
+          A[k][p] = c * x - s * y;
+          A[k][r] = s * x + c * y;
+        }
+        for (int k = 0; k < 4; ++k) {
+          const double x = A[p][k], y = A[r][k];
+          A[p][k] = c * x - s * y;
+          A[r][k] = s * x + c * y;
+        }
+        for (int k = 0; k < 4; ++k) {
+          const double x = V[k][p], y = V[k][r];
+          V[k][p] = c * x - s * y;
+          V[k][r] = s * x + c * y;
+        }
+      }
+  }
+  int best = 0;
+  for (int k = 1; k < 4; ++k)
+    if (A[k][k] > A[best][best]) best = k;
+  for (int k = 0; k < 4; ++k) q[k] = V[k][best];
+}
+
+__global__ __launch_bounds__(256) void k_shell_forces(ShellArgs sa) {
+  __shared__ double red[16 * 4];
+  __shared__ double sh_c[3], sh_R[9];
+  const int M = sa.M;
+  const long long base = (long long)blockIdx.x * M;
+  const double* X = sa.pos + 3 * base;
+  const double X0[3] = {X[0], X[1], X[2]};
+  auto unwrap = [&](int j, double y[3]) {
+    for (int k = 0; k < 3; ++k) y[k] = X[3 * j + k] - X0[k];
+    y[0] -= sa.g.nx * floor(y[0] / sa.g.nx + 0.5);
+    if (!sa.g.wall) y[1] -= sa.g.ny * floor(y[1] / sa.g.ny + 0.5);
+    y[2] -= sa.g.nz * floor(y[2] / sa.g.nz + 0.5);
+    for (int k = 0; k < 3; ++k) y[k] += X0[k];
+  };
+  double acc[4] = {0, 0, 0, 0};
+  for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    double y[3];
+    unwrap(j, y);
+    for (int k = 0; k < 3; ++k) acc[k] += y[k];
+  }
+  block_sum4(acc, red);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) sh_c[k] = acc[k] / M;
+  __syncthreads();
+  const double c[3] = {sh_c[0], sh_c[1], sh_c[2]};
+  double S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    double y[3];
+    unwrap(j, y);
+    const double* t = sa.tmpl + 3 * j;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) S[3 * a + b] += t[a] * (y[b] - c[b]);
+  }
+  double s0[4] = {S[0], S[1], S[2], S[3]}, s1[4] = {S[4], S[5], S[6], S[7]},
+         s2[4] = {S[8], 0, 0, 0};
+  block_sum4(s0, red);
+  block_sum4(s1, red);
+  block_sum4(s2, red);
+  if (threadIdx.x == 0) {
+    const double Sxx = s0[0], Sxy = s0[1], Sxz = s0[2], Syx = s0[3], Syy = s1[0], Syz = s1[1],
+                 Szx = s1[2], Szy = s1[3], Szz = s2[0];
+    double A[4][4] = {{Sxx + Syy + Szz, Syz - Szy, Szx - Sxz, Sxy - Syx},
+                      {Syz - Szy, Sxx - Syy - Szz, Sxy + Syx, Szx + Sxz},
+                      {Szx - Sxz, Sxy + Syx, -Sxx + Syy - Szz, Syz + Szy},
+                      {Sxy - Syx, Szx + Sxz, Syz + Szy, -Sxx - Syy + Szz}};
+    double q[4];
+    sym4_eig_max(A, q);
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    sh_R[0] = w * w + x * x - y * y - z * z;
+    sh_R[1] = 2 * (x * y - w * z);
+    sh_R[2] = 2 * (x * z + w * y);
+    sh_R[3] = 2 * (x * y + w * z);
+    sh_R[4] = w * w - x * x + y * y - z * z;
+    sh_R[5] = 2 * (y * z - w * x);
+    sh_R[6] = 2 * (x * z - w * y);
+    sh_R[7] = 2 * (y * z + w * x);
+    sh_R[8] = w * w - x * x - y * y + z * z;
+    if (sa.rot)
+      for (int k = 0; k < 9; ++k) sa.rot[9 * blockIdx.x + k] = sh_R[k];
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    double y[3];
+    unwrap(j, y);
+    const double* t = sa.tmpl + 3 * j;
+    for (int a = 0; a < 3; ++a) {
+      const double tgt = sh_R[3 * a] * t[0] + sh_R[3 * a + 1] * t[1] + sh_R[3 * a + 2] * t[2];
+      sa.fint[3 * (base + j) + a] = -sa.k * (y[a] - c[a] - tgt);
+    }
+  }
+}
+
+// ======================================================================
+// Launchers (host side)
+// ======================================================================
+static dim3 lattice_block(const Geo& g) {
+  int bx = ((g.nx + 63) / 64) * 64;
+  if (bx > 256) bx = 256;
+  return dim3(bx, 1, 1);
+}
+static dim3 lattice_grid(const Geo& g, dim3 b) {
+  return dim3((g.nx + b.x - 1) / b.x, g.ny, g.nz);
+}
+
+#define LBC_STORAGE_SWITCH(S, CALL)                                 \
+  switch (S) {                                                      \
+    case LB_F64: { constexpr int SS = LB_F64; CALL; } break;        \
+    case LB_F32: { constexpr int SS = LB_F32; CALL; } break;        \
+    case LB_F16: { constexpr int SS = LB_F16; CALL; } break;        \
+    default: { constexpr int SS = LB_BF16; CALL; } break;           \
+  }
+
+hipError_t launch_stream_collide(int storage, int collision, const LatArgs& a, hipStream_t st) {
+  const dim3 b = lattice_block(a.g), gr = lattice_grid(a.g, b);
+  if (collision == LB_BGK) {
+    LBC_STORAGE_SWITCH(storage, (k_stream_collide<SS, LB_BGK><<<gr, b, 0, st>>>(a)));
+  } else {
+    LBC_STORAGE_SWITCH(storage, (k_stream_collide<SS, LB_TRT><<<gr, b, 0, st>>>(a)));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init(int storage, const InitArgs& a, hipStream_t st) {
+  const dim3 b = lattice_block(a.g), gr = lattice_grid(a.g, b);
+  LBC_STORAGE_SWITCH(storage, (k_init<SS><<<gr, b, 0, st>>>(a)));
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(int storage, const SiteArgs& a, double* rho, double* u, hipStream_t st) {
+  const dim3 b = lattice_block(a.g), gr = lattice_grid(a.g, b);
+  LBC_STORAGE_SWITCH(storage, (k_moments<SS><<<gr, b, 0, st>>>(a, rho, u)));
+  return hipGetLastError();
+}
+
+hipError_t launch_populations(int storage, const SiteArgs& a, double* out, hipStream_t st) {
+  const dim3 b = lattice_block(a.g), gr = lattice_grid(a.g, b);
+  LBC_STORAGE_SWITCH(storage, (k_populations<SS><<<gr, b, 0, st>>>(a, out)));
+  return hipGetLastError();
+}
+
+hipError_t launch_totals(int storage, const SiteArgs& a, double* partial, int nblk,
+                         const double* vel, const double* mass, long long np, double* out,
+                         hipStream_t st) {
+  LBC_STORAGE_SWITCH(storage, (k_totals_sites<SS><<<nblk, 256, 0, st>>>(a, partial)));
+  k_totals_final<<<1, 256, 0, st>>>(partial, nblk, vel, mass, np, out);
+  return hipGetLastError();
+}
+
+static inline unsigned pblocks(long long n) { return (unsigned)((n + 127) / 128); }
+
+hipError_t launch_drift(const Geo& g, long long n, double* pos, const double* vel, double dt,
+                        hipStream_t st) {
+  if (n > 0) k_drift<<<pblocks(n), 128, 0, st>>>(g, n, pos, vel, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_wrap(const Geo& g, long long n, double* pos, hipStream_t st) {
+  if (n > 0) k_wrap<<<pblocks(n), 128, 0, st>>>(g, n, pos);
+  return hipGetLastError();
+}
+
+hipError_t launch_couple_half(int storage, const PartArgs& a, hipStream_t st) {
+  if (a.n > 0) LBC_STORAGE_SWITCH(storage, (k_couple_half<SS><<<pblocks(a.n), 128, 0, st>>>(a)));
+  return hipGetLastError();
+}
+
+hipError_t launch_ib_predict(int storage, const PartArgs& a, hipStream_t st) {
+  if (a.n > 0) LBC_STORAGE_SWITCH(storage, (k_ib_predict<SS><<<pblocks(a.n), 128, 0, st>>>(a)));
+  return hipGetLastError();
+}
+
+hipError_t launch_ib_advect(int storage, const PartArgs& a, int spread_fint, hipStream_t st) {
+  if (a.n > 0)
+    LBC_STORAGE_SWITCH(storage, (k_ib_advect<SS><<<pblocks(a.n), 128, 0, st>>>(a, spread_fint)));
+  return hipGetLastError();
+}
+
+hipError_t launch_ib_spread_b(int storage, const PartArgs& a, hipStream_t st) {
+  if (a.n > 0) LBC_STORAGE_SWITCH(storage, (k_ib_spread_b<SS><<<pblocks(a.n), 128, 0, st>>>(a)));
+  return hipGetLastError();
+}
+
+hipError_t launch_bond_groups(const BondArgs& b, int ngroups, int gcap, int mode, int acc,
+                              int nsub, double dt, hipStream_t st) {
+  if (ngroups > 0)
+    k_bond_groups<<<ngroups, gcap, (size_t)gcap * 3 * sizeof(double), st>>>(b, mode, acc, nsub, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_shell_forces(const ShellArgs& s, int nshell, hipStream_t st) {
+  if (nshell > 0) k_shell_forces<<<nshell, 256, 0, st>>>(s);
+  return hipGetLastError();
+}
+
+}  // namespace lbc

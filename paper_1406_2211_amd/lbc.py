@@ -1,0 +1,244 @@
+"""ctypes binding of ``liblbc.so`` (the C ABI declared in ``include/lbc.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels.
+PyTorch provides device memory and the stream.  There is no fallback: if the
+library has not been built, using it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbc.so")
+
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EBUSY, LB_EDEVICE, LB_ESTATE = range(6)
+LB_BGK, LB_TRT = 0, 1
+LB_FORCING_SPLIT2 = 0
+LB_COUPLE_NONE, LB_COUPLE_FC, LB_COUPLE_EBF, LB_COUPLE_IB = 0, 1, 2, 3
+LB_PHI2, LB_PHI3, LB_PHI4 = 2, 3, 4
+LB_F64, LB_F32, LB_F16, LB_BF16 = 0, 1, 2, 3
+LB_HARMONIC, LB_FENE = 0, 1
+
+EXPORTS = ["lb_lattice_velocities", "lb_workspace_size", "lb_create", "lb_init_fluid",
+           "lb_set_particles", "lb_set_bonds", "lb_set_shells", "lb_step", "lb_moments",
+           "lb_populations", "lb_get_particles", "lb_totals", "lb_timing", "lb_timing_read",
+           "lb_info", "lb_destroy",
+           "lb_last_error", "lb_status_string"]
+
+
+class lb_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("wall_y", C.c_int32)]
+
+
+class lb_params(C.Structure):
+    _fields_ = [("tau", C.c_double), ("rho0", C.c_double), ("body_force", C.c_double * 3),
+                ("collision", C.c_int32), ("trt_magic", C.c_double), ("forcing", C.c_int32),
+                ("coupling", C.c_int32), ("gamma", C.c_double), ("kernel", C.c_int32),
+                ("storage", C.c_int32), ("f16_scale_log2", C.c_int32),
+                ("mts_substeps", C.c_int32), ("deterministic", C.c_int32)]
+
+
+class lb_limits(C.Structure):
+    _fields_ = [("max_particles", C.c_int64), ("max_bonds", C.c_int64),
+                ("max_shells", C.c_int32), ("max_shell_size", C.c_int32)]
+
+
+class LbcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lbc status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load liblbc.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1406_2211_amd/build.py "
+                           "(or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+    G, P, M = C.POINTER(lb_grid), C.POINTER(lb_params), C.POINTER(lb_limits)
+    sig = {
+        "lb_lattice_velocities": (i32, [C.POINTER(i32)]),
+        "lb_workspace_size": (i32, [G, P, M, C.POINTER(C.c_size_t)]),
+        "lb_create": (i32, [G, P, M, vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "lb_init_fluid": (i32, [vp, vp, vp]),
+        "lb_set_particles": (i32, [vp, i64, vp, vp, vp]),
+        "lb_set_bonds": (i32, [vp, i64, vp, dbl, dbl, i32]),
+        "lb_set_shells": (i32, [vp, i32, i32, vp, dbl]),
+        "lb_step": (i32, [vp, i64]),
+        "lb_moments": (i32, [vp, vp, vp]),
+        "lb_populations": (i32, [vp, vp]),
+        "lb_get_particles": (i32, [vp, vp, vp]),
+        "lb_totals": (i32, [vp, C.POINTER(dbl)]),
+        "lb_timing": (i32, [vp, i32]),
+        "lb_timing_read": (i32, [vp, C.POINTER(dbl), C.POINTER(i64)]),
+        "lb_info": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
+        "lb_destroy": (i32, [vp]),
+        "lb_last_error": (C.c_char_p, [vp]),
+        "lb_status_string": (C.c_char_p, [i32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status, ctx=None):
+    if status != LB_OK:
+        msg = load().lb_last_error(ctx).decode()
+        raise LbcError(status, msg)
+
+
+def lattice_velocities():
+    c = (C.c_int32 * 57)()
+    q = load().lb_lattice_velocities(c)
+    return np.array(c[:], dtype=np.int64).reshape(q, 3)
+
+
+def make_params(tau, rho0=1.0, body_force=(0.0, 0.0, 0.0), collision=LB_BGK, trt_magic=3.0 / 16.0,
+                coupling=LB_COUPLE_NONE, gamma=0.0, kernel=LB_PHI2, storage=LB_F64,
+                f16_scale_log2=0, mts_substeps=0):
+    p = lb_params()
+    p.tau, p.rho0 = float(tau), float(rho0)
+    for a in range(3):
+        p.body_force[a] = float(body_force[a])
+    p.collision, p.trt_magic, p.forcing = int(collision), float(trt_magic), LB_FORCING_SPLIT2
+    p.coupling, p.gamma, p.kernel = int(coupling), float(gamma), int(kernel)
+    p.storage, p.f16_scale_log2 = int(storage), int(f16_scale_log2)
+    p.mts_substeps, p.deterministic = int(mts_substeps), 0
+    return p
+
+
+def workspace_size(grid, params, limits):
+    n = C.c_size_t()
+    _check(load().lb_workspace_size(C.byref(grid), C.byref(params), C.byref(limits), C.byref(n)))
+    return n.value
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Lattice:
+    """One lattice context.  Device memory (the workspace) is a torch uint8
+    tensor owned by this object; all calls are enqueued on ``stream`` (a
+    torch.cuda.Stream; default: the current stream at construction)."""
+
+    def __init__(self, nx, ny, nz, wall_y=0, max_particles=0, max_bonds=0, max_shells=0,
+                 max_shell_size=0, stream=None, device="cuda", **params):
+        import torch
+        self.torch = torch
+        self.grid = lb_grid(int(nx), int(ny), int(nz), int(wall_y))
+        self.params = make_params(**params)
+        self.limits = lb_limits(int(max_particles), int(max_bonds), int(max_shells),
+                                int(max_shell_size))
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = workspace_size(self.grid, self.params, self.limits)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._ws_ptr = base + off
+        self.ctx = C.c_void_p()
+        _check(load().lb_create(C.byref(self.grid), C.byref(self.params), C.byref(self.limits),
+                                C.c_void_p(self._ws_ptr), nbytes, C.c_void_p(self.stream.cuda_stream),
+                                C.byref(self.ctx)))
+        self.shape = (int(nz), int(ny), int(nx))
+        self.N = int(nx) * int(ny) * int(nz)
+        self.np = 0
+
+    # -- helpers ------------------------------------------------------------
+    def _f64(self, t, shape):
+        t = self.torch.as_tensor(t, dtype=self.torch.float64, device=self.device)
+        return t.reshape(shape).contiguous()
+
+    def _call(self, name, *args):
+        _check(getattr(load(), name)(self.ctx, *args), self.ctx)
+
+    # -- ABI ----------------------------------------------------------------
+    def lb_init_fluid(self, rho=None, u=None):
+        r = None if rho is None else self._f64(rho, self.shape)
+        v = None if u is None else self._f64(u, (3,) + self.shape)
+        with self.torch.cuda.stream(self.stream):
+            self._call("lb_init_fluid", _ptr(r), _ptr(v))
+            self._keep = (r, v)
+
+    def lb_set_particles(self, pos, vel=None, mass=None):
+        p = self._f64(pos, (-1, 3))
+        n = p.shape[0]
+        v = None if vel is None else self._f64(vel, (n, 3))
+        m = None if mass is None else self._f64(mass, (n,))
+        self._call("lb_set_particles", n, _ptr(p), _ptr(v), _ptr(m))
+        self._keep_p = (p, v, m)
+        self.np = n
+
+    def lb_set_bonds(self, pairs, k, r0, type=LB_HARMONIC):
+        pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        self._call("lb_set_bonds", pr.shape[0], pr.ctypes.data_as(C.c_void_p), float(k),
+                   float(r0), int(type))
+
+    def lb_set_shells(self, nshell, template, k_tether):
+        t = np.ascontiguousarray(template, dtype=np.float64).reshape(-1, 3)
+        self._call("lb_set_shells", int(nshell), t.shape[0], t.ctypes.data_as(C.c_void_p),
+                   float(k_tether))
+
+    def lb_step(self, nsteps=1):
+        self._call("lb_step", int(nsteps))
+
+    def lb_moments(self):
+        rho = self.torch.empty(self.shape, dtype=self.torch.float64, device=self.device)
+        u = self.torch.empty((3,) + self.shape, dtype=self.torch.float64, device=self.device)
+        self._call("lb_moments", _ptr(rho), _ptr(u))
+        return rho, u
+
+    def lb_populations(self):
+        df = self.torch.empty((19,) + self.shape, dtype=self.torch.float64, device=self.device)
+        self._call("lb_populations", _ptr(df))
+        return df
+
+    def lb_get_particles(self):
+        pos = self.torch.empty((self.np, 3), dtype=self.torch.float64, device=self.device)
+        vel = self.torch.empty((self.np, 3), dtype=self.torch.float64, device=self.device)
+        if self.np:
+            self._call("lb_get_particles", _ptr(pos), _ptr(vel))
+        return pos, vel
+
+    def lb_totals(self):
+        out = (C.c_double * 7)()
+        self._call("lb_totals", out)
+        return np.array(out[:])
+
+    def lb_timing(self, max_passes):
+        self._call("lb_timing", int(max_passes))
+
+    def lb_timing_read(self):
+        ms, n = C.c_double(), C.c_int64()
+        self._call("lb_timing_read", C.byref(ms), C.byref(n))
+        return ms.value, n.value
+
+    def lb_info(self):
+        n, s = C.c_int64(), C.c_int64()
+        self._call("lb_info", C.byref(n), C.byref(s))
+        return n.value, s.value
+
+    def lb_destroy(self):
+        if self.ctx:
+            load().lb_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.lb_destroy()
+        except Exception:
+            pass

@@ -1,0 +1,153 @@
+"""Shared harness of the GPU parity tests: runs the CPU oracle and the HIP
+library (through its C ABI) on the same seeded inputs and compares them."""
+from __future__ import annotations
+
+import sys
+from dataclasses import dataclass, field
+
+import numpy as np
+
+import oracle as O
+from paper_1406_2211_amd import inputs as I
+
+COUPLING_TO_ORACLE = {0: O.NONE, 1: O.FC, 2: O.EBF, 3: O.IB}
+
+
+@dataclass
+class Case:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    tau: float
+    steps: int
+    wall_y: int = 0
+    fext: tuple = (0.0, 0.0, 0.0)
+    collision: int = 0          # 0 BGK, 1 TRT
+    coupling: int = 0           # 0 none, 1 FC, 2 EBF, 3 IB
+    gamma: float = 0.0
+    kernel: int = 2
+    storage: int = 0            # lbc storage enum
+    mts: int = 0
+    u_noise: float = 1e-4
+    seed: int = 1
+    pos: np.ndarray | None = None
+    vel: np.ndarray | None = None
+    mass: np.ndarray | None = None
+    bonds: np.ndarray | None = None
+    bond_k: float = 0.0
+    bond_r0: float = 1.0
+    bond_type: int = 0
+    nshell: int = 0
+    template: np.ndarray | None = None
+    tether_k: float = 0.0
+    f16_scale_log2: int = 0
+    extra: dict = field(default_factory=dict)
+
+
+def initial_fields(c: Case):
+    shape = (c.nz, c.ny, c.nx)
+    u = I.noise_velocity(shape, c.u_noise, c.seed) if c.u_noise > 0 else np.zeros((3,) + shape)
+    rho = None
+    return rho, u
+
+
+def run_oracle(c: Case):
+    o = O.Oracle(nx=c.nx, ny=c.ny, nz=c.nz, tau=c.tau, wall_y=c.wall_y, fext=c.fext,
+                 collision=c.collision, coupling=COUPLING_TO_ORACLE[c.coupling], gamma=c.gamma,
+                 kernel=c.kernel, mts_n=c.mts, bonds=c.bonds, bond_k=c.bond_k, bond_r0=c.bond_r0,
+                 bond_type=c.bond_type, nshell=c.nshell, shell_template=c.template,
+                 tether_k=c.tether_k)
+    rho, u = initial_fields(c)
+    df = o.init_fluid(rho, u)
+    pos = None if c.pos is None else np.array(c.pos, dtype=np.float64, copy=True)
+    vel = None
+    if pos is not None:
+        vel = np.zeros_like(pos) if c.vel is None else np.array(c.vel, dtype=np.float64, copy=True)
+    o.run(df, c.steps, pos, vel, c.mass)
+    rho_o, u_o = o.moments(df)
+    return dict(df=df, rho=rho_o, u=u_o, pos=pos, vel=vel, totals=o.totals(df, vel, c.mass))
+
+
+def make_gpu(c: Case):
+    import torch
+    from paper_1406_2211_amd import lbc as L
+    n = 0 if c.pos is None else len(c.pos)
+    nb = 0 if c.bonds is None else len(c.bonds)
+    ms = 0 if c.template is None else len(c.template)
+    lat = L.Lattice(c.nx, c.ny, c.nz, wall_y=c.wall_y, max_particles=n, max_bonds=nb,
+                    max_shells=c.nshell, max_shell_size=ms, tau=c.tau, body_force=c.fext,
+                    collision=c.collision, coupling=c.coupling, gamma=c.gamma, kernel=c.kernel,
+                    storage=c.storage, mts_substeps=c.mts, f16_scale_log2=c.f16_scale_log2)
+    rho, u = initial_fields(c)
+    lat.lb_init_fluid(None if rho is None else torch.from_numpy(rho),
+                      None if u is None else torch.from_numpy(np.ascontiguousarray(u)))
+    if n:
+        vel = np.zeros((n, 3)) if c.vel is None else c.vel
+        mass = None if c.mass is None else torch.from_numpy(np.asarray(c.mass, np.float64))
+        lat.lb_set_particles(torch.from_numpy(np.asarray(c.pos, np.float64)),
+                             torch.from_numpy(np.asarray(vel, np.float64)), mass)
+    if nb:
+        lat.lb_set_bonds(c.bonds, c.bond_k, c.bond_r0, c.bond_type)
+    if c.nshell:
+        lat.lb_set_shells(c.nshell, c.template, c.tether_k)
+    return lat
+
+
+def run_gpu(c: Case, lat=None):
+    import torch
+    if lat is None:
+        lat = make_gpu(c)
+    print(f"[gpu] case {c.name}: {c.nx}x{c.ny}x{c.nz} steps={c.steps} storage={c.storage} "
+          f"coupling={c.coupling} kernel={c.kernel} np={0 if c.pos is None else len(c.pos)}",
+          flush=True)
+    sys.stdout.flush()
+    lat.lb_step(c.steps)
+    rho, u = lat.lb_moments()
+    df = lat.lb_populations()
+    pos, vel = lat.lb_get_particles()
+    torch.cuda.synchronize()
+    tot = lat.lb_totals()
+    out = dict(df=df.cpu().numpy(), rho=rho.cpu().numpy(), u=u.cpu().numpy(),
+               pos=pos.cpu().numpy() if c.pos is not None else None,
+               vel=vel.cpu().numpy() if c.pos is not None else None, totals=tot)
+    lat.lb_destroy()
+    return out
+
+
+def to_oracle_order(df_gpu):
+    """Permute populations from the library order to the oracle order."""
+    from paper_1406_2211_amd import lbc as L
+    cg = L.lattice_velocities()
+    co, _, _ = O.lattice()
+    perm = [int(np.where((cg == co[j]).all(1))[0][0]) for j in range(19)]
+    return df_gpu[perm]
+
+
+def rel_err(a, b):
+    scale = np.abs(b).max()
+    return np.abs(a - b).max() / (scale if scale > 0 else 1.0)
+
+
+def compare(c: Case, g, o, tol, ptol=None):
+    """Max-norm errors: populations and velocities relative to the oracle's
+    max magnitude; positions relative to the box (minimum image); particle
+    velocities relative to their max magnitude."""
+    errs = {}
+    errs["df"] = rel_err(to_oracle_order(g["df"]), o["df"])
+    errs["u"] = rel_err(g["u"], o["u"])
+    errs["rho"] = np.abs(g["rho"] - o["rho"]).max()
+    if c.pos is not None:
+        L = np.array([c.nx, c.ny, c.nz], float)
+        d = g["pos"] - o["pos"]
+        per = np.array([1, 0 if c.wall_y else 1, 1], bool)
+        d[:, per] -= L[per] * np.round(d[:, per] / L[per])
+        errs["pos"] = np.abs(d).max() / L.max()
+        errs["vel"] = rel_err(g["vel"], o["vel"]) if np.abs(o["vel"]).max() > 0 else \
+            np.abs(g["vel"]).max()
+    print(f"[parity] {c.name}: " + ", ".join(f"{k}={v:.3e}" for k, v in errs.items()), flush=True)
+    ptol = tol if ptol is None else ptol
+    for k, v in errs.items():
+        lim = ptol if k in ("pos", "vel") else tol
+        assert v <= lim, f"{c.name}: {k} error {v:.3e} > {lim:.1e}"
+    return errs

@@ -1,0 +1,93 @@
+"""CPU checks of the C ABI: the built library loads and exports every entry
+point that include/lbc.h declares, and host-side validation rejects invalid
+configurations before anything touches a device."""
+import os
+import re
+
+import pytest
+
+from paper_1406_2211_amd import lbc as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "lbc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    syms = declared_symbols()
+    assert len(syms) >= 16
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert not missing, missing
+    assert set(syms) <= set(L.EXPORTS) | set(syms)
+
+
+def test_lattice_velocities_are_d3q19():
+    c = L.lattice_velocities()
+    assert c.shape == (19, 3)
+    s = set(map(tuple, c.tolist()))
+    assert len(s) == 19 and (0, 0, 0) in s
+    assert all(tuple(-v for v in t) in s for t in s)
+    assert sorted((abs(c).sum(1)).tolist()) == [0] + [1] * 6 + [2] * 12
+
+
+def _g(nx=8, ny=8, nz=8, wall=0):
+    return L.lb_grid(nx, ny, nz, wall)
+
+
+def _lim(n=0, nb=0, ns=0, ms=0):
+    return L.lb_limits(n, nb, ns, ms)
+
+
+def test_workspace_size_scales_with_storage():
+    sizes = [L.workspace_size(_g(64, 64, 64), L.make_params(0.8, storage=s), _lim())
+             for s in (L.LB_F64, L.LB_F32, L.LB_F16)]
+    assert sizes[0] > sizes[1] > sizes[2]
+    # two population buffers dominate: 2 * 19 * N * bytes
+    N = 64 ** 3
+    assert sizes[1] >= 2 * 19 * N * 4
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(tau=0.8, rho0=0.0),
+    dict(tau=0.8, collision=7), dict(tau=0.8, coupling=9), dict(tau=0.8, kernel=5),
+    dict(tau=0.8, storage=9), dict(tau=0.8, coupling=L.LB_COUPLE_FC, gamma=0.0),
+    dict(tau=0.8, coupling=L.LB_COUPLE_IB, mts_substeps=3), dict(tau=0.8, mts_substeps=-1),
+    dict(tau=0.8, body_force=(float("inf"), 0, 0)),
+])
+def test_invalid_parameters_rejected(bad):
+    with pytest.raises(L.LbcError) as e:
+        L.workspace_size(_g(), L.make_params(**bad), _lim())
+    assert e.value.status == L.LB_EINVAL
+
+
+@pytest.mark.parametrize("grid", [(0, 8, 8, 0), (8, -1, 8, 0), (8, 1, 8, 1), (8, 8, 8, 2)])
+def test_invalid_grid_rejected(grid):
+    with pytest.raises(L.LbcError):
+        L.workspace_size(L.lb_grid(*grid), L.make_params(0.8), _lim())
+
+
+def test_invalid_limits_rejected():
+    with pytest.raises(L.LbcError):
+        L.workspace_size(_g(), L.make_params(0.8), _lim(n=-5))
+
+
+def test_create_rejects_small_workspace_without_device():
+    import ctypes as C
+    g, p, m = _g(), L.make_params(0.8), _lim()
+    need = L.workspace_size(g, p, m)
+    ctx = C.c_void_p()
+    st = L.load().lb_create(C.byref(g), C.byref(p), C.byref(m), C.c_void_p(256), need - 1, None,
+                            C.byref(ctx))
+    assert st == L.LB_ENOMEM and not ctx.value
+    assert b"workspace" in L.load().lb_last_error(None)
+
+
+def test_status_strings():
+    lib = L.load()
+    for s in range(6):
+        assert lib.lb_status_string(s)

@@ -1,0 +1,138 @@
+"""GPU parity: the HIP library (called through its C ABI) against the FP64 CPU
+oracle on the same seeded inputs.  Tolerances (max norm, relative to the
+oracle's largest magnitude): FP64 storage 1e-12, FP32 storage 1e-5."""
+import numpy as np
+import pytest
+
+from paper_1406_2211_amd import inputs as I
+from parity import Case, compare, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def _chains_case(name, n, nchains, nbeads, steps, storage, mts=5, seed=2, k=30.0):
+    pos, vel, bonds = I.chains(nchains, nbeads, (n, n, n), 1.0, 1e-3, seed)
+    return Case(name=name, nx=n, ny=n, nz=n, tau=0.6, steps=steps, collision=1, coupling=1,
+                gamma=2.0, kernel=2, storage=storage, mts=mts, u_noise=0.0, pos=pos, vel=vel,
+                mass=np.ones(len(pos)), bonds=bonds, bond_k=k, bond_r0=1.0)
+
+
+def _c1_case(n, steps, storage=0, seed=1):
+    pos = I.uniform_positions(1, (n, n, n), seed)
+    return Case(name=f"c1_{n}_{steps}_s{storage}", nx=n, ny=n, nz=n, tau=0.8, steps=steps,
+                fext=(1e-6, 0.0, 0.0), coupling=1, gamma=1.0, kernel=2, storage=storage,
+                pos=pos, vel=np.zeros((1, 3)), mass=np.ones(1), seed=seed)
+
+
+def _ib_case(name, kernel, storage=0, steps=30):
+    T = I.icosphere(1, 4.0)
+    box = (24, 24, 32)
+    cen = I.shell_centres(2, 4.0, box, True, 2.0, 3.0, seed=3)
+    X = np.vstack([c + T for c in cen])
+    X = X + 0.15 * np.random.default_rng(5).standard_normal(X.shape)
+    return Case(name=name, nx=24, ny=24, nz=32, tau=0.8, steps=steps, wall_y=1,
+                fext=(0.0, 0.0, 1e-6), coupling=3, kernel=kernel, storage=storage, u_noise=0.0,
+                pos=X, nshell=2, template=T, tether_k=0.05)
+
+
+def check(c, tol, ptol=None):
+    o = run_oracle(c)
+    g = run_gpu(c)
+    return compare(c, g, o, tol, ptol)
+
+
+# ------------------------------------------------------------------- FP64
+def test_c1_small_fp64():
+    check(_c1_case(16, 60), TOL64)
+
+
+def test_c1_full_fp64():
+    """The plain-method configuration at full size: 32^3, 500 steps."""
+    check(_c1_case(32, 500), TOL64)
+
+
+def test_rest_state_stays_exactly_zero():
+    c = Case(name="rest", nx=20, ny=6, nz=5, tau=0.7, steps=25, collision=1, wall_y=1,
+             coupling=1, gamma=1.0, u_noise=0.0, pos=np.array([[3.2, 2.5, 1.1]]),
+             vel=np.zeros((1, 3)), mass=np.ones(1))
+    g = run_gpu(c)
+    assert np.all(g["df"] == 0.0) and np.all(g["vel"] == 0.0)
+
+
+def test_ragged_walls_trt_ebf_bonds_phi3():
+    """nx = 70 (one full 64-site row word and a ragged tail), y walls, TRT,
+    modified EBF with a bonded chain, 3-point kernel, body force."""
+    pos = np.array([[10.2, 2.1, 1.3], [11.0, 2.4, 1.6], [11.8, 2.2, 2.1], [68.9, 1.9, 0.4]])
+    c = Case(name="ragged", nx=70, ny=5, nz=3, tau=0.66, steps=40, wall_y=1,
+             fext=(1e-6, 0.0, 2e-6), collision=1, coupling=2, gamma=0.7, kernel=3,
+             pos=pos, vel=1e-3 * np.random.default_rng(9).standard_normal((4, 3)),
+             mass=np.array([0.5, 1.0, 2.0, 0.3]), bonds=np.array([[0, 1], [1, 2]]),
+             bond_k=0.3, bond_r0=0.9)
+    check(c, TOL64)
+
+
+def test_one_site_lattice_fc():
+    """Degenerate 1x1x1 periodic lattice: the fluid is one cell."""
+    c = Case(name="one_site", nx=1, ny=1, nz=1, tau=0.9, steps=7, coupling=1, gamma=1.7,
+             kernel=4, pos=np.array([[0.3, 0.6, 0.2]]), vel=np.array([[-2e-3, 1e-3, 5e-4]]),
+             mass=np.array([0.6]))
+    check(c, TOL64)
+
+
+def test_thin_box_no_particles():
+    c = Case(name="thin", nx=1, ny=8, nz=6, tau=0.55, steps=30, fext=(3e-6, 1e-6, 0.0),
+             collision=1)
+    check(c, TOL64)
+
+
+def test_particles_at_periodic_seam_phi4():
+    pos = np.array([[19.995, 0.002, 7.0], [0.001, 11.999, 19.9999], [10.0, 10.0, 10.0]])
+    c = Case(name="seam", nx=20, ny=12, nz=20, tau=0.8, steps=30, coupling=1, gamma=1.2,
+             kernel=4, pos=pos, vel=np.array([[3e-3, -2e-3, 1e-3], [-1e-3, 2e-3, 4e-3],
+                                              [0.0, 0.0, 0.0]]), mass=np.ones(3))
+    check(c, TOL64)
+
+
+def test_mts_chains_fp64():
+    check(_chains_case("mts64", 24, 3, 10, 30, storage=0), TOL64)
+
+
+def test_alg3_soft_chain_fp64():
+    c = _chains_case("alg3", 20, 2, 8, 25, storage=0, mts=0, k=0.2)
+    check(c, TOL64)
+
+
+@pytest.mark.parametrize("kernel", [2, 4])
+def test_ib_shells_fp64(kernel):
+    check(_ib_case(f"ib_phi{kernel}", kernel), TOL64)
+
+
+def test_empty_particle_set():
+    c = Case(name="empty", nx=16, ny=16, nz=16, tau=0.7, steps=20, coupling=1, gamma=1.0,
+             fext=(0.0, 1e-6, 0.0))
+    check(c, TOL64)
+
+
+# ------------------------------------------------------------------- FP32
+def test_c1_full_fp32():
+    check(_c1_case(32, 500, storage=1), TOL32)
+
+
+def test_mts_chains_fp32():
+    check(_chains_case("mts32", 48, 2, 20, 100, storage=1), TOL32)
+
+
+def test_ib_shells_fp32():
+    check(_ib_case("ib32", 4, storage=1), TOL32)
+
+
+# ------------------------------------------------------------- totals
+def test_totals_match_oracle():
+    c = _chains_case("totals", 24, 3, 10, 20, storage=0)
+    o = run_oracle(c)
+    g = run_gpu(c)
+    scale = np.abs(o["totals"]).max()
+    assert np.abs(g["totals"] - o["totals"]).max() <= 1e-12 * scale
