@@ -78,7 +78,8 @@ Layout carve(const lb_grid& g, const lb_params& p, const lb_limits& lim, void* b
 bool check_params(const lb_grid* g, const lb_params* p, const lb_limits* lim, std::string& err) {
   if (!g || !p || !lim) return err = "null argument", false;
   if (g->nx < 1 || g->ny < 1 || g->nz < 1) return err = "grid dimensions must be >= 1", false;
-  if ((long long)g->nx * g->ny * g->nz > (1ll << 36)) return err = "grid too large", false;
+  if ((long long)g->nx * g->ny * g->nz >= (1ll << 32))
+    return err = "grid too large (at most 2^32 - 1 sites)", false;
   if (g->wall_y != 0 && g->wall_y != 1) return err = "wall_y must be 0 or 1", false;
   if (g->wall_y && g->ny < 2) return err = "a walled channel needs ny >= 2", false;
   if (!(p->tau > 0.5) || !std::isfinite(p->tau))
@@ -247,7 +248,7 @@ static lb_status build_groups(lb_ctx* c) {
   int maxc = 1;
   for (auto& cl : clusters) maxc = std::max(maxc, cl.second);
   if (maxc > 1024) return fail(c, LB_EINVAL, "a bonded cluster has more than 1024 particles");
-  const int gcap = std::max(256, ((maxc + 63) / 64) * 64);
+  const int gcap = std::max(128, ((maxc + 63) / 64) * 64);
   std::vector<int32_t> perm, loc(n), goff{0};
   int fillg = 0;
   for (auto& cl : clusters) {

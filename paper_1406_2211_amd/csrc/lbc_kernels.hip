@@ -20,17 +20,43 @@ namespace lbc {
 // store.  One work-item per site; a 64-wide wavefront covers 64 consecutive
 // x sites of one row, i.e. exactly one 64-bit word of the force mask.
 // ======================================================================
-template <int S, int COL>
+//
+// Addressing: a block covers (part of) one x row, so the y and z of the nine
+// source rows are block-uniform and live in scalar registers together with
+// the per-population base pointers; each work-item adds a 32-bit site offset.
+// All 19 loads are issued before any arithmetic.  With y walls the
+// bounce-back choice is also block-uniform (it depends on y only).
+template <int S, int COL, bool WALL>
 __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
   using V4 = typename St::V4;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y, z = blockIdx.z;
-  if (x >= a.g.nx) return;
+  const uint32_t nx = (uint32_t)a.g.nx, ny = (uint32_t)a.g.ny, nz = (uint32_t)a.g.nz;
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t y = blockIdx.y, z = blockIdx.z;
+  if (x >= nx) return;
+  const uint32_t ys[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
+  const uint32_t zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
+  const uint32_t xs[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
+  const uint32_t own = (z * ny + y) * nx + x;
+  const size_t N = (size_t)a.g.N;
+  const T* __restrict__ fin = (const T*)a.fin;
+  const uint64_t* mp = a.mask + ((size_t)z * ny + y) * a.g.wpr + (x >> 6);
+  const uint64_t word = *mp;
   R f[Q];
-  pull<S, R>((const T*)a.fin, a.g, x, y, z, (R)a.inv, f);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    // source of population i: x - c_i
+    const uint32_t row = (zs[1 - CZ[i]] * ny + ys[1 - CY[i]]) * nx;
+    const T* base = fin + (size_t)i * N;
+    uint32_t off = row + xs[1 - CX[i]];
+    if (WALL && ((CY[i] == 1 && y == 0) || (CY[i] == -1 && y == ny - 1))) {
+      base = fin + (size_t)OPP[i] * N;  // halfway bounce-back: opposite population, same site
+      off = own;
+    }
+    f[i] = St::ld(base + off, (R)a.inv);
+  }
   R drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -42,9 +68,6 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
   const R rho = R(a.rho0) + drho;
   const R ir = R(1) / rho;
   R Fx = R(a.Fx), Fy = R(a.Fy), Fz = R(a.Fz);
-  const long long own = site_index(a.g, x, y, z);
-  uint64_t* mp = a.mask + ((long long)z * a.g.ny + y) * a.g.wpr + (x >> 6);
-  const uint64_t word = *mp;
   if (word) {
     if ((word >> (x & 63)) & 1ull) {
       V4* FA = (V4*)a.FA;
@@ -58,7 +81,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
       FA[own] = zero;
       FB[own] = zero;
     }
-    if ((x & 63) == 0) *mp = 0;
+    if ((x & 63) == 0) *(uint64_t*)mp = 0;
   }
   const R ux = jx * ir, uy = jy * ir, uz = jz * ir;         // post-stream velocity
   const R hx = ux + R(0.5) * Fx * ir, hy = uy + R(0.5) * Fy * ir,
@@ -71,7 +94,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
     for (int i = 0; i < Q; ++i) {
       const R eb = feq_dev<R>(i, drho, rho, ux, uy, uz, usq);
       const R ep = feq_dev<R>(i, drho, rho, hx, hy, hz, hsq);
-      St::st(fo + (long long)i * a.g.N + own, ep + omp * (f[i] - eb), sc);
+      St::st(fo + (size_t)i * N + own, ep + omp * (f[i] - eb), sc);
     }
   } else {
     {
@@ -88,8 +111,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
       const R Eh = w * (drho + rho * (R(4.5) * ch * ch - R(1.5) * hsq)), Oh = w * rho * R(3) * ch;
       const R ni = f[i] - (Eb + Ob), nj = f[i + 1] - (Eb - Ob);
       const R sym = R(0.5) * (ni + nj), anti = R(0.5) * (ni - nj);
-      St::st(fo + (long long)i * a.g.N + own, Eh + Oh + omp * sym + omm * anti, sc);
-      St::st(fo + (long long)(i + 1) * a.g.N + own, Eh - Oh + omp * sym - omm * anti, sc);
+      St::st(fo + (size_t)i * N + own, Eh + Oh + omp * sym + omm * anti, sc);
+      St::st(fo + (size_t)(i + 1) * N + own, Eh - Oh + omp * sym - omm * anti, sc);
     }
   }
 }
@@ -252,67 +275,92 @@ __global__ __launch_bounds__(256) void k_totals_final(const double* partial, int
 // Particle side: interpolation I (Eq. IBM-interpolation), spreading I*
 // (Eq. IBM-spreading), coupling forces (Eq. modified-force, Eq.
 // modified-ebf), velocity kicks and position drifts (Alg. 2 and 3).
+//
+// Work mapping: an aligned group of L lanes (L = 8, 32, 64 for the 2-, 3- and
+// 4-point kernels, L >= K^3) handles one particle, one lane per stencil site,
+// so the site gathers and the spreading atomics of a particle are issued in
+// parallel.  Weighted sums are reduced inside the group with butterfly
+// shuffles (fixed order), after which every lane holds the interpolated
+// values and evaluates the (cheap, FP64) coupling update redundantly.
 // ======================================================================
-template <int S>
-__device__ void interp(const PartArgs& a, const double X[3], bool phys, double& rp,
-                       double up[3]) {
-  double wx[4], wy[4], wz[4];
-  const int jx = stencil(a.K, X[0], wx), jy = stencil(a.K, X[1], wy), jz = stencil(a.K, X[2], wz);
-  rp = 0;
-  up[0] = up[1] = up[2] = 0;
-  for (int kz = 0; kz < a.K; ++kz) {
-    const int zz = wrap_idx(jz + kz, a.s.g.nz);
-    for (int ky = 0; ky < a.K; ++ky) {
-      int yy = jy + ky;
-      if (a.s.g.wall) {
-        if (yy < 0 || yy >= a.s.g.ny) continue;
-      } else {
-        yy = wrap_idx(yy, a.s.g.ny);
-      }
-      for (int kx = 0; kx < a.K; ++kx) {
-        const double W = wx[kx] * wy[ky] * wz[kz];
-        if (W == 0.0) continue;
-        const int xx = wrap_idx(jx + kx, a.s.g.nx);
-        double fl[Q], drho, j[3];
-        site_phys<S>(a.s, xx, yy, zz, fl, drho, j, phys);
-        const double r = a.s.rho0 + drho;
-        rp += W * r;
-        up[0] += W * j[0] / r;
-        up[1] += W * j[1] / r;
-        up[2] += W * j[2] / r;
-      }
-    }
+template <int K>
+struct Lanes {
+  static constexpr int L = K == 2 ? 8 : (K == 3 ? 32 : 64);
+};
+
+struct SiteSlot {
+  bool valid;
+  double W;
+  int x, y, z;
+};
+
+template <int K>
+__device__ __forceinline__ SiteSlot slot_of(const Geo& g, const double X[3], int lane) {
+  SiteSlot s{false, 0.0, 0, 0, 0};
+  if (lane >= K * K * K) return s;
+  const int kx = lane % K, ky = (lane / K) % K, kz = lane / (K * K);
+  double w[4];
+  const int jx = stencil(K, X[0], w);
+  const double wx = w[kx];
+  const int jy = stencil(K, X[1], w);
+  const double wy = w[ky];
+  const int jz = stencil(K, X[2], w);
+  const double wz = w[kz];
+  int yy = jy + ky;
+  if (g.wall) {
+    if (yy < 0 || yy >= g.ny) return s;  // beyond a wall: no weight
+  } else {
+    yy = wrap_idx(yy, g.ny);
   }
+  s.W = wx * wy * wz;
+  s.valid = s.W != 0.0;
+  s.x = wrap_idx(jx + kx, g.nx);
+  s.y = yy;
+  s.z = wrap_idx(jz + kz, g.nz);
+  return s;
 }
 
-template <typename E>
-__device__ void spread(const PartArgs& a, const double X[3], const double F[3], void* field) {
-  double wx[4], wy[4], wz[4];
-  const int jx = stencil(a.K, X[0], wx), jy = stencil(a.K, X[1], wy), jz = stencil(a.K, X[2], wz);
-  E* Fd = (E*)field;
-  for (int kz = 0; kz < a.K; ++kz) {
-    const int zz = wrap_idx(jz + kz, a.s.g.nz);
-    for (int ky = 0; ky < a.K; ++ky) {
-      int yy = jy + ky;
-      if (a.s.g.wall) {
-        if (yy < 0 || yy >= a.s.g.ny) continue;
-      } else {
-        yy = wrap_idx(yy, a.s.g.ny);
-      }
-      for (int kx = 0; kx < a.K; ++kx) {
-        const double W = wx[kx] * wy[ky] * wz[kz];
-        if (W == 0.0) continue;
-        const int xx = wrap_idx(jx + kx, a.s.g.nx);
-        const long long s = site_index(a.s.g, xx, yy, zz);
-        unsafeAtomicAdd(Fd + 4 * s + 0, (E)(W * F[0]));
-        unsafeAtomicAdd(Fd + 4 * s + 1, (E)(W * F[1]));
-        unsafeAtomicAdd(Fd + 4 * s + 2, (E)(W * F[2]));
-        atomicOr((unsigned long long*)(a.mask + ((long long)zz * a.s.g.ny + yy) * a.s.g.wpr +
-                                       (xx >> 6)),
-                 1ull << (xx & 63));
-      }
-    }
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int S, int K>
+__device__ __forceinline__ void group_interp(const PartArgs& a, const double X[3], bool phys,
+                                             int lane, double& rp, double up[3]) {
+  constexpr int L = Lanes<K>::L;
+  const SiteSlot sl = slot_of<K>(a.s.g, X, lane);
+  double r = 0, ux = 0, uy = 0, uz = 0;
+  if (sl.valid) {
+    double fl[Q], drho, j[3];
+    site_phys<S>(a.s, sl.x, sl.y, sl.z, fl, drho, j, phys);
+    const double rr = a.s.rho0 + drho;
+    r = sl.W * rr;
+    ux = sl.W * j[0] / rr;
+    uy = sl.W * j[1] / rr;
+    uz = sl.W * j[2] / rr;
   }
+  rp = group_sum<L>(r);
+  up[0] = group_sum<L>(ux);
+  up[1] = group_sum<L>(uy);
+  up[2] = group_sum<L>(uz);
+}
+
+template <typename E, int K>
+__device__ __forceinline__ void group_spread(const PartArgs& a, const double X[3],
+                                             const double F[3], void* field, int lane) {
+  const SiteSlot sl = slot_of<K>(a.s.g, X, lane);
+  if (!sl.valid) return;
+  E* Fd = (E*)field;
+  const long long s = site_index(a.s.g, sl.x, sl.y, sl.z);
+  unsafeAtomicAdd(Fd + 4 * s + 0, (E)(sl.W * F[0]));
+  unsafeAtomicAdd(Fd + 4 * s + 1, (E)(sl.W * F[1]));
+  unsafeAtomicAdd(Fd + 4 * s + 2, (E)(sl.W * F[2]));
+  atomicOr((unsigned long long*)(a.mask + ((long long)sl.z * a.s.g.ny + sl.y) * a.s.g.wpr +
+                                 (sl.x >> 6)),
+           1ull << (sl.x & 63));
 }
 
 __device__ __forceinline__ void wrap3(const Geo& g, double r[3]) {
@@ -341,11 +389,14 @@ __global__ void k_wrap(Geo g, long long n, double* pos) {
 
 // One coupling half step for FC / modified EBF: interpolate rho_p, u_p at r,
 // compute F^h (h' = h/2), kick v, optionally drift, and spread -F^h.
-template <int S>
-__global__ void k_couple_half(PartArgs a) {
+template <int S, int K>
+__global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
   using E = typename Store<S>::R;
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.n) return;
+  constexpr int L = Lanes<K>::L;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long p = gid / L;
+  const int lane = (int)(gid % L);
+  if (p >= a.n) return;  // whole groups leave together
   double r[3], v[3], Fi[3] = {0, 0, 0};
   for (int k = 0; k < 3; ++k) {
     r[k] = a.pos[3 * p + k];
@@ -354,7 +405,7 @@ __global__ void k_couple_half(PartArgs a) {
   }
   const double m = a.mass[p];
   double rp, up[3];
-  interp<S>(a, r, a.phys != 0, rp, up);
+  group_interp<S, K>(a, r, a.phys != 0, lane, rp, up);
   const double hh = 0.5, al = a.gamma * hh / m, be = a.gamma * hh / rp;
   double Fh[3];
   if (a.coupling == LB_COUPLE_FC) {
@@ -372,56 +423,71 @@ __global__ void k_couple_half(PartArgs a) {
     }
   }
   const double Ff[3] = {-Fh[0], -Fh[1], -Fh[2]};
-  spread<E>(a, r, Ff, a.target ? a.FB : a.FA);
-  if (a.drift_after) {
-    for (int k = 0; k < 3; ++k) r[k] += hh * v[k];
-    wrap3(a.s.g, r);
-    for (int k = 0; k < 3; ++k) a.pos[3 * p + k] = r[k];
+  group_spread<E, K>(a, r, Ff, a.target ? a.FB : a.FA, lane);
+  if (lane == 0) {
+    if (a.drift_after) {
+      for (int k = 0; k < 3; ++k) r[k] += hh * v[k];
+      wrap3(a.s.g, r);
+      for (int k = 0; k < 3; ++k) a.pos[3 * p + k] = r[k];
+    }
+    for (int k = 0; k < 3; ++k) a.vel[3 * p + k] = v[k];
   }
-  for (int k = 0; k < 3; ++k) a.vel[3 * p + k] = v[k];
 }
 
 // IB (Alg. 2): predictor X~ = X + (h/2) I[X] u(t)
-template <int S>
-__global__ void k_ib_predict(PartArgs a) {
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+template <int S, int K>
+__global__ __launch_bounds__(256) void k_ib_predict(PartArgs a) {
+  constexpr int L = Lanes<K>::L;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long p = gid / L;
+  const int lane = (int)(gid % L);
   if (p >= a.n) return;
   double X[3] = {a.pos[3 * p], a.pos[3 * p + 1], a.pos[3 * p + 2]}, rp, up[3];
-  interp<S>(a, X, true, rp, up);
-  for (int k = 0; k < 3; ++k) X[k] += 0.5 * up[k];
-  wrap3(a.s.g, X);
-  for (int k = 0; k < 3; ++k) a.aux[3 * p + k] = X[k];
+  group_interp<S, K>(a, X, true, lane, rp, up);
+  if (lane == 0) {
+    for (int k = 0; k < 3; ++k) X[k] += 0.5 * up[k];
+    wrap3(a.s.g, X);
+    for (int k = 0; k < 3; ++k) a.aux[3 * p + k] = X[k];
+  }
 }
 
-// IB: X <- X + (h/2) I[X~] u with the current physical u; with spread != 0
+// IB: X <- X + (h/2) I[X~] u with the current physical u; with spread_fint
 // also spreads +F_int at X~ into the A field (first half force).
-template <int S>
-__global__ void k_ib_advect(PartArgs a, int spread_fint) {
+template <int S, int K>
+__global__ __launch_bounds__(256) void k_ib_advect(PartArgs a, int spread_fint) {
   using E = typename Store<S>::R;
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int L = Lanes<K>::L;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long p = gid / L;
+  const int lane = (int)(gid % L);
   if (p >= a.n) return;
   const double Xt[3] = {a.aux[3 * p], a.aux[3 * p + 1], a.aux[3 * p + 2]};
   double rp, up[3];
-  interp<S>(a, Xt, true, rp, up);
-  double X[3];
-  for (int k = 0; k < 3; ++k) X[k] = a.pos[3 * p + k] + 0.5 * up[k];
-  wrap3(a.s.g, X);
-  for (int k = 0; k < 3; ++k) a.pos[3 * p + k] = X[k];
+  group_interp<S, K>(a, Xt, true, lane, rp, up);
+  if (lane == 0) {
+    double X[3];
+    for (int k = 0; k < 3; ++k) X[k] = a.pos[3 * p + k] + 0.5 * up[k];
+    wrap3(a.s.g, X);
+    for (int k = 0; k < 3; ++k) a.pos[3 * p + k] = X[k];
+  }
   if (spread_fint) {
     const double F[3] = {a.fint[3 * p], a.fint[3 * p + 1], a.fint[3 * p + 2]};
-    spread<E>(a, Xt, F, a.FA);
+    group_spread<E, K>(a, Xt, F, a.FA, lane);
   }
 }
 
 // IB: spread +F_int at X~ into the B field (second half force).
-template <int S>
-__global__ void k_ib_spread_b(PartArgs a) {
+template <int S, int K>
+__global__ __launch_bounds__(256) void k_ib_spread_b(PartArgs a) {
   using E = typename Store<S>::R;
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int L = Lanes<K>::L;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long p = gid / L;
+  const int lane = (int)(gid % L);
   if (p >= a.n) return;
   const double Xt[3] = {a.aux[3 * p], a.aux[3 * p + 1], a.aux[3 * p + 2]};
   const double F[3] = {a.fint[3 * p], a.fint[3 * p + 1], a.fint[3 * p + 2]};
-  spread<E>(a, Xt, F, a.FB);
+  group_spread<E, K>(a, Xt, F, a.FB, lane);
 }
 
 // ======================================================================
@@ -640,12 +706,19 @@ static dim3 lattice_grid(const Geo& g, dim3 b) {
     default: { constexpr int SS = LB_BF16; CALL; } break;           \
   }
 
+template <int COL, bool WALL>
+static void launch_sc(int storage, const LatArgs& a, dim3 gr, dim3 b, hipStream_t st) {
+  LBC_STORAGE_SWITCH(storage, (k_stream_collide<SS, COL, WALL><<<gr, b, 0, st>>>(a)));
+}
+
 hipError_t launch_stream_collide(int storage, int collision, const LatArgs& a, hipStream_t st) {
   const dim3 b = lattice_block(a.g), gr = lattice_grid(a.g, b);
   if (collision == LB_BGK) {
-    LBC_STORAGE_SWITCH(storage, (k_stream_collide<SS, LB_BGK><<<gr, b, 0, st>>>(a)));
+    if (a.g.wall) launch_sc<LB_BGK, true>(storage, a, gr, b, st);
+    else launch_sc<LB_BGK, false>(storage, a, gr, b, st);
   } else {
-    LBC_STORAGE_SWITCH(storage, (k_stream_collide<SS, LB_TRT><<<gr, b, 0, st>>>(a)));
+    if (a.g.wall) launch_sc<LB_TRT, true>(storage, a, gr, b, st);
+    else launch_sc<LB_TRT, false>(storage, a, gr, b, st);
   }
   return hipGetLastError();
 }
@@ -689,24 +762,43 @@ hipError_t launch_wrap(const Geo& g, long long n, double* pos, hipStream_t st) {
   return hipGetLastError();
 }
 
+#define LBC_KERNEL_SWITCH(K, CALL)                        \
+  switch (K) {                                            \
+    case 2: { constexpr int KK = 2; CALL; } break;        \
+    case 3: { constexpr int KK = 3; CALL; } break;        \
+    default: { constexpr int KK = 4; CALL; } break;       \
+  }
+
+static unsigned gblocks(long long n, int K) {
+  const long long L = K == 2 ? 8 : (K == 3 ? 32 : 64);
+  return (unsigned)((n * L + 255) / 256);
+}
+
 hipError_t launch_couple_half(int storage, const PartArgs& a, hipStream_t st) {
-  if (a.n > 0) LBC_STORAGE_SWITCH(storage, (k_couple_half<SS><<<pblocks(a.n), 128, 0, st>>>(a)));
+  if (a.n > 0)
+    LBC_KERNEL_SWITCH(a.K, LBC_STORAGE_SWITCH(storage, (k_couple_half<SS, KK>
+                                                        <<<gblocks(a.n, KK), 256, 0, st>>>(a))));
   return hipGetLastError();
 }
 
 hipError_t launch_ib_predict(int storage, const PartArgs& a, hipStream_t st) {
-  if (a.n > 0) LBC_STORAGE_SWITCH(storage, (k_ib_predict<SS><<<pblocks(a.n), 128, 0, st>>>(a)));
+  if (a.n > 0)
+    LBC_KERNEL_SWITCH(a.K, LBC_STORAGE_SWITCH(storage, (k_ib_predict<SS, KK>
+                                                        <<<gblocks(a.n, KK), 256, 0, st>>>(a))));
   return hipGetLastError();
 }
 
 hipError_t launch_ib_advect(int storage, const PartArgs& a, int spread_fint, hipStream_t st) {
   if (a.n > 0)
-    LBC_STORAGE_SWITCH(storage, (k_ib_advect<SS><<<pblocks(a.n), 128, 0, st>>>(a, spread_fint)));
+    LBC_KERNEL_SWITCH(a.K, LBC_STORAGE_SWITCH(storage, (k_ib_advect<SS, KK>
+                                                        <<<gblocks(a.n, KK), 256, 0, st>>>(a, spread_fint))));
   return hipGetLastError();
 }
 
 hipError_t launch_ib_spread_b(int storage, const PartArgs& a, hipStream_t st) {
-  if (a.n > 0) LBC_STORAGE_SWITCH(storage, (k_ib_spread_b<SS><<<pblocks(a.n), 128, 0, st>>>(a)));
+  if (a.n > 0)
+    LBC_KERNEL_SWITCH(a.K, LBC_STORAGE_SWITCH(storage, (k_ib_spread_b<SS, KK>
+                                                        <<<gblocks(a.n, KK), 256, 0, st>>>(a))));
   return hipGetLastError();
 }
 
