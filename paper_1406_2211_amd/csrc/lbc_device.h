@@ -38,7 +38,8 @@ struct Store<LB_F64> {
   using R = double;
   using V4 = double4;
   static __device__ __forceinline__ R ld(const T* p, R) { return *p; }
-  static __device__ __forceinline__ void st(T* p, R v, R) { *p = v; }
+  // populations are written once per pass and not re-read by it: non-temporal
+  static __device__ __forceinline__ void st(T* p, R v, R) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Store<LB_F32> {
@@ -46,7 +47,7 @@ struct Store<LB_F32> {
   using R = float;
   using V4 = float4;
   static __device__ __forceinline__ R ld(const T* p, R) { return *p; }
-  static __device__ __forceinline__ void st(T* p, R v, R) { *p = v; }
+  static __device__ __forceinline__ void st(T* p, R v, R) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Store<LB_F16> {
@@ -55,7 +56,9 @@ struct Store<LB_F16> {
   using V4 = float4;
   // stored value is scale * (f - w rho0); inv is 1/scale (a power of two)
   static __device__ __forceinline__ R ld(const T* p, R inv) { return __half2float(*p) * inv; }
-  static __device__ __forceinline__ void st(T* p, R v, R scale) { *p = __float2half_rn(v * scale); }
+  static __device__ __forceinline__ void st(T* p, R v, R scale) {
+    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v * scale)), (unsigned short*)p);
+  }
 };
 template <>
 struct Store<LB_BF16> {
@@ -63,7 +66,10 @@ struct Store<LB_BF16> {
   using R = float;
   using V4 = float4;
   static __device__ __forceinline__ R ld(const T* p, R inv) { return __bfloat162float(*p) * inv; }
-  static __device__ __forceinline__ void st(T* p, R v, R scale) { *p = __float2bfloat16(v * scale); }
+  static __device__ __forceinline__ void st(T* p, R v, R scale) {
+    const __hip_bfloat16 b = __float2bfloat16(v * scale);
+    __builtin_nontemporal_store(*(const unsigned short*)&b, (unsigned short*)p);
+  }
 };
 
 __device__ __forceinline__ long long site_index(const Geo& g, int x, int y, int z) {
@@ -132,7 +138,14 @@ __device__ __forceinline__ int wrap_idx(int j, int n) {
   return r < 0 ? r + n : r;
 }
 
-__device__ __forceinline__ double wrap_pos(double x, double L) { return x - L * floor(x / L); }
+// x - L floor(x/L); for x in [-L, 2L) (every drift of less than a box length)
+// the compare-and-add below performs the same single rounding operation.
+__device__ __forceinline__ double wrap_pos(double x, double L) {
+  if (x >= 0.0 && x < L) return x;
+  if (x >= -L && x < 0.0) return x + L;
+  if (x >= L && x < 2.0 * L) return x - L;
+  return x - L * floor(x / L);
+}
 
 // ------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {

@@ -499,24 +499,49 @@ __global__ __launch_bounds__(256) void k_ib_spread_b(PartArgs a) {
 // LDS.  mode 0: F_int at the current positions (stored, or added with acc).
 // mode 1: nsub velocity-Verlet sub-steps of length dt with F_int only
 // (the [P F_int P]^n factor of the multiple time-step split, Sec. 6).
-__device__ __forceinline__ void bond_force(const BondArgs& b, long long p, const double r[3],
+// Bond partners of one particle, held in registers across the sub-steps
+// (up to kMaxBondsReg; a particle with more partners reads the CSR list).
+constexpr int kMaxBondsReg = 6;
+
+struct Partners {
+  int n;
+  long long p;
+  int loc[kMaxBondsReg];
+};
+
+__device__ __forceinline__ void load_partners(const BondArgs& b, long long p, Partners& P) {
+  const int e0 = b.start[p], e1 = b.start[p + 1];
+  P.p = p;
+  P.n = e1 - e0;
+#pragma unroll
+  for (int k = 0; k < kMaxBondsReg; ++k) P.loc[k] = (k < P.n) ? b.loc[b.nbr[e0 + k]] : 0;
+}
+
+__device__ __forceinline__ void bond_pair(const BondArgs& b, const double r[3], const double* q,
+                                          double F[3]) {
+  double d[3];
+  for (int k = 0; k < 3; ++k) d[k] = q[k] - r[k];
+  d[0] -= b.g.nx * floor(d[0] / b.g.nx + 0.5);
+  if (!b.g.wall) d[1] -= b.g.ny * floor(d[1] / b.g.ny + 0.5);
+  d[2] -= b.g.nz * floor(d[2] / b.g.nz + 0.5);
+  const double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  double s;
+  if (b.type == LB_FENE)
+    s = b.k / (1.0 - L * L / (b.r0 * b.r0));
+  else
+    s = L > 0.0 ? b.k * (L - b.r0) / L : 0.0;
+  for (int k = 0; k < 3; ++k) F[k] += s * d[k];
+}
+
+__device__ __forceinline__ void bond_force(const BondArgs& b, const Partners& P, const double r[3],
                                            const double* lds, double F[3]) {
   F[0] = F[1] = F[2] = 0;
-  for (int e = b.start[p]; e < b.start[p + 1]; ++e) {
-    const int q = b.nbr[e];
-    const int lq = b.loc[q];
-    double d[3];
-    for (int k = 0; k < 3; ++k) d[k] = lds[3 * lq + k] - r[k];
-    d[0] -= b.g.nx * floor(d[0] / b.g.nx + 0.5);
-    if (!b.g.wall) d[1] -= b.g.ny * floor(d[1] / b.g.ny + 0.5);
-    d[2] -= b.g.nz * floor(d[2] / b.g.nz + 0.5);
-    const double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    double s;
-    if (b.type == LB_FENE)
-      s = b.k / (1.0 - L * L / (b.r0 * b.r0));
-    else
-      s = L > 0.0 ? b.k * (L - b.r0) / L : 0.0;
-    for (int k = 0; k < 3; ++k) F[k] += s * d[k];
+  if (P.n <= kMaxBondsReg) {
+#pragma unroll
+    for (int k = 0; k < kMaxBondsReg; ++k)
+      if (k < P.n) bond_pair(b, r, lds + 3 * P.loc[k], F);
+  } else {
+    for (int e = b.start[P.p]; e < b.start[P.p + 1]; ++e) bond_pair(b, r, lds + 3 * b.loc[b.nbr[e]], F);
   }
 }
 
@@ -527,12 +552,16 @@ __global__ void k_bond_groups(BondArgs b, int mode, int acc, int nsub, double dt
   const bool on = t < cnt;
   const long long p = on ? b.perm[g0 + t] : 0;
   double r[3] = {0, 0, 0}, v[3] = {0, 0, 0}, m = 1.0;
+  Partners P;
+  P.n = 0;
+  P.p = p;
   if (on) {
     for (int k = 0; k < 3; ++k) {
       r[k] = b.pos[3 * p + k];
       v[k] = b.vel ? b.vel[3 * p + k] : 0.0;
     }
     if (b.mass) m = b.mass[p];
+    load_partners(b, p, P);
   }
   if (mode == 0) {
     if (on)
@@ -540,11 +569,12 @@ __global__ void k_bond_groups(BondArgs b, int mode, int acc, int nsub, double dt
     __syncthreads();
     if (on) {
       double F[3];
-      bond_force(b, p, r, lds, F);
+      bond_force(b, P, r, lds, F);
       for (int k = 0; k < 3; ++k) b.fint[3 * p + k] = acc ? b.fint[3 * p + k] + F[k] : F[k];
     }
     return;
   }
+  const double dtm = dt / m;
   for (int s = 0; s < nsub; ++s) {
     if (on) {
       for (int k = 0; k < 3; ++k) r[k] += 0.5 * dt * v[k];
@@ -556,9 +586,9 @@ __global__ void k_bond_groups(BondArgs b, int mode, int acc, int nsub, double dt
     __syncthreads();
     if (on) {
       double F[3];
-      bond_force(b, p, r, lds, F);
+      bond_force(b, P, r, lds, F);
       for (int k = 0; k < 3; ++k) {
-        v[k] += dt / m * F[k];
+        v[k] += dtm * F[k];
         r[k] += 0.5 * dt * v[k];
       }
       wrap3(b.g, r);
