@@ -46,6 +46,21 @@ def workload(name):
                         mts_substeps=5),
             pos=pos, vel=vel, mass=np.ones(len(pos)), bonds=bonds, bond_k=30.0, bond_r0=1.0,
             bytes_per_site=152, dtype="f32")
+    if name in ("c3", "c3phi2"):
+        box = (128, 128, 256)
+        T = I.icosphere(3, 6.0)
+        cen = I.shell_centres(64, 6.0, box, True, 4.0, 3.0, seed=3)
+        X = np.vstack([c + T for c in cen])
+        k = 4 if name == "c3" else 2
+        return dict(
+            desc=f"D3Q19 BGK channel 128x128x256 with halfway bounce-back walls in y, tau=0.8, "
+                 f"body force 1e-6 along z, FP32; 64 rigid icosphere shells (R=6, 642 markers each, "
+                 f"tether k=0.05), immersed boundary coupling, {k}-point kernel",
+            grid=box + (1,),
+            params=dict(tau=0.8, body_force=(0.0, 0.0, 1e-6), collision=0, coupling=3, kernel=k,
+                        storage=1),
+            pos=X, vel=None, mass=None, nshell=64, template=T, tether_k=0.05,
+            bytes_per_site=152, dtype="f32")
     if name == "plain256":
         n = 256
         return dict(desc="D3Q19 two-rate MRT 256^3 periodic, FP32, no particles", grid=(n, n, n, 0),
@@ -91,10 +106,12 @@ def cpu_baseline(wl, steps):
                  coupling=p.get("coupling", 0), gamma=p.get("gamma", 0.0),
                  kernel=p.get("kernel", 2), mts_n=p.get("mts_substeps", 0),
                  fext=p.get("body_force", (0, 0, 0)), bonds=wl.get("bonds"),
-                 bond_k=wl.get("bond_k", 0.0), bond_r0=wl.get("bond_r0", 1.0))
+                 bond_k=wl.get("bond_k", 0.0), bond_r0=wl.get("bond_r0", 1.0),
+                 nshell=wl.get("nshell", 0), shell_template=wl.get("template"),
+                 tether_k=wl.get("tether_k", 0.0))
     df = o.init_fluid()
     pos = None if wl.get("pos") is None else wl["pos"].copy()
-    vel = None if pos is None else wl["vel"].copy()
+    vel = None if pos is None or wl.get("vel") is None else wl["vel"].copy()
     t0 = time.perf_counter()
     o.run(df, steps, pos, vel, wl.get("mass"))
     dt = time.perf_counter() - t0
@@ -102,6 +119,17 @@ def cpu_baseline(wl, steps):
             "cores": O.threads(), "kind": "oracle",
             "sample": f"{steps} full steps of the same workload ({nx}x{ny}x{nz}, all particles), "
                       f"{dt:.1f} s"}
+
+
+def copy_calibration(nbytes=1 << 30, reps=3):
+    import torch
+    a = torch.ones(nbytes // 4, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_copy": nbytes, "copies": reps}), flush=True)
 
 
 def main():
@@ -112,10 +140,16 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (for scaling the "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
     from paper_1406_2211_amd import lbc as L
@@ -126,14 +160,20 @@ def main():
     pos = wl.get("pos")
     npart = 0 if pos is None else len(pos)
     bonds = wl.get("bonds")
+    nshell = wl.get("nshell", 0)
+    tmpl = wl.get("template")
     lat = L.Lattice(nx, ny, nz, wall_y=wall, max_particles=npart,
-                    max_bonds=0 if bonds is None else len(bonds), **wl["params"])
+                    max_bonds=0 if bonds is None else len(bonds), max_shells=nshell,
+                    max_shell_size=0 if tmpl is None else len(tmpl), **wl["params"])
     lat.lb_init_fluid()
     if npart:
-        lat.lb_set_particles(torch.from_numpy(pos), torch.from_numpy(wl["vel"]),
-                             torch.from_numpy(wl["mass"]))
+        vel = None if wl.get("vel") is None else torch.from_numpy(wl["vel"])
+        mass = None if wl.get("mass") is None else torch.from_numpy(wl["mass"])
+        lat.lb_set_particles(torch.from_numpy(pos), vel, mass)
     if bonds is not None:
         lat.lb_set_bonds(bonds, wl["bond_k"], wl["bond_r0"])
+    if nshell:
+        lat.lb_set_shells(nshell, tmpl, wl["tether_k"])
     lat.lb_step(args.warmup)
     torch.cuda.synchronize()
     lat.lb_timing(args.steps)

@@ -173,6 +173,63 @@ lb_status lb_destroy(lb_ctx* ctx);
 const char* lb_last_error(const lb_ctx* ctx);
 const char* lb_status_string(lb_status s);
 
+/* ------------------------------------------------------------------------
+ * Ensembles: many independent periodic boxes (the same time step as above,
+ * Alg. 3 ordering, force coupling / modified EBF / no coupling, free
+ * particles) resident in one caller-owned pool and advanced together.  Each
+ * step is one batched lattice launch over every live box plus one batched
+ * launch per coupling half, replayed from captured HIP graphs.  Boxes have
+ * their own grid, tau, body force, particles and step budget; a box stops
+ * when its budget is spent while the others continue.
+ * ------------------------------------------------------------------------ */
+typedef struct lb_ensemble lb_ensemble;
+
+/* Device bytes one box occupies in the pool (its admission footprint). */
+lb_status lb_ensemble_footprint(const lb_grid* g, const lb_params* p, const lb_limits* lim,
+                                size_t* bytes);
+
+/* Creates an ensemble over the borrowed device pool d_pool (256-byte aligned,
+ * kept alive by the caller until lb_ensemble_destroy) for at most max_slots
+ * boxes, all with the given storage precision and delta kernel.  The ensemble
+ * creates its own (default-priority, blocking) stream; lb_ensemble_stream
+ * returns it, and every operation on the ensemble and on its slots is ordered
+ * on it. */
+lb_status lb_ensemble_create(void* d_pool, size_t bytes, int32_t max_slots, int32_t storage,
+                             int32_t kernel, lb_ensemble** out);
+lb_status lb_ensemble_stream(lb_ensemble* e, void** stream);
+
+/* Admits a box with a budget of nsteps time steps.  Returns its slot and a
+ * context handle for the slot (lb_init_fluid, lb_set_particles, lb_moments,
+ * lb_populations, lb_get_particles, lb_totals work on it; particles must be
+ * set before the slot's first ensemble step; lb_step is not valid on it).
+ * The box starts at rest.  Errors: LB_EBUSY when no slot is free or its
+ * footprint does not fit in the free pool memory (the caller may retry after a
+ * retirement); LB_EINVAL for walls, IB, sub-stepping, bonds, shells, or a
+ * storage / kernel different from the ensemble's. */
+lb_status lb_ensemble_admit(lb_ensemble* e, const lb_grid* g, const lb_params* p,
+                            const lb_limits* lim, int64_t nsteps, int32_t* slot, lb_ctx** ctx);
+
+/* Advances every live box by nsteps steps (boxes whose budget is spent do
+ * not move).  Asynchronous on the ensemble stream. */
+lb_status lb_ensemble_step(lb_ensemble* e, int64_t nsteps);
+
+/* Waits for the ensemble stream and reports the steps a slot has taken and
+ * whether its budget is spent; also brings the slot's context up to date for
+ * lb_moments and the other queries.  Synchronous. */
+lb_status lb_ensemble_query(lb_ensemble* e, int32_t slot, int64_t* steps_done, int32_t* done);
+
+/* Frees a slot and its pool memory (its context handle becomes invalid). */
+lb_status lb_ensemble_retire(lb_ensemble* e, int32_t slot);
+
+/* Times steps_per_candidate real steps of the live mix under each candidate
+ * persistent-grid shape of the batched launches, keeps the fastest and
+ * returns it.  The tuning steps count against the boxes' budgets. */
+lb_status lb_ensemble_autotune(lb_ensemble* e, int32_t steps_per_candidate, int32_t* lat_grid,
+                               int32_t* part_grid);
+
+lb_status lb_ensemble_destroy(lb_ensemble* e);
+const char* lb_ensemble_last_error(const lb_ensemble* e);
+
 #ifdef __cplusplus
 }
 #endif

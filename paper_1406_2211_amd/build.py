@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbc.so")
-SOURCES = ["lbc_kernels.hip", "lbc_api.hip"]
+SOURCES = ["lbc_kernels.hip", "lbc_tiles.hip", "lbc_api.hip"]
 ARCH = os.environ.get("LBC_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for all device code.

@@ -42,8 +42,11 @@ struct Layout {
   double *pos, *vel, *mass, *fint, *aux;
   int32_t *perm, *loc, *goff, *bstart, *bnbr;
   double *tmpl, *rot, *partial, *tot;
+  int *tcount, *tstart, *tcursor, *tocc, *tnocc, *ptile, *psorted;
   size_t bytes;
 };
+
+int tiles_along(int n) { return (n + 7) / 8; }
 
 Layout carve(const lb_grid& g, const lb_params& p, const lb_limits& lim, void* base) {
   Carver c{(char*)base};
@@ -71,6 +74,14 @@ Layout carve(const lb_grid& g, const lb_params& p, const lb_limits& lim, void* b
   L.rot = c.take<double>((size_t)std::max(lim.max_shells, 1) * 72);
   L.partial = c.take<double>((size_t)kTotalsBlocks * 4 * 8);
   L.tot = c.take<double>(8 * 8);
+  const size_t nt = (size_t)tiles_along(g.nx) * tiles_along(g.ny) * tiles_along(g.nz);
+  L.tcount = c.take<int>(nt * 4);
+  L.tstart = c.take<int>((nt + 1) * 4);
+  L.tcursor = c.take<int>(nt * 4);
+  L.tocc = c.take<int>(nt * 4);
+  L.tnocc = c.take<int>(64);
+  L.ptile = c.take<int>(np * 4);
+  L.psorted = c.take<int>(np * 4);
   L.bytes = c.off;
   return L;
 }
@@ -127,6 +138,8 @@ struct lb_ctx {
   int bond_type = LB_HARMONIC;
   bool groups_dirty = true;
   int ngroups = 0, gcap = 64;
+  bool tiled = false;   // binned LDS-staged particle path (dense IB markers)
+  bool member = false;  // slot of an ensemble: stepped only by lb_ensemble_step
   int nshell = 0, shell_size = 0;
   double k_tether = 0;
   double omp = 0, omm = 0;
@@ -186,6 +199,24 @@ static PartArgs part_args(const lb_ctx* c) {
   a.target = 0;
   a.drift_after = 0;
   return a;
+}
+
+static TileArgs tile_args(const lb_ctx* c) {
+  TileArgs t;
+  t.g = c->geo;
+  t.tx = tiles_along(c->geo.nx);
+  t.ty = tiles_along(c->geo.ny);
+  t.tz = tiles_along(c->geo.nz);
+  t.ntiles = t.tx * t.ty * t.tz;
+  t.count = c->L.tcount;
+  t.start = c->L.tstart;
+  t.cursor = c->L.tcursor;
+  t.occ = c->L.tocc;
+  t.nocc = c->L.tnocc;
+  t.ptile = c->L.ptile;
+  t.sorted = c->L.psorted;
+  t.mask = c->L.mask;
+  return t;
 }
 
 static BondArgs bond_args(const lb_ctx* c, double* pos) {
@@ -327,6 +358,24 @@ static lb_status step_once(lb_ctx* c) {
   const bool parts = c->p.coupling != LB_COUPLE_NONE && c->np > 0;
   lb_status s;
   if (!parts) return lattice_pass(c);
+  if (c->p.coupling == LB_COUPLE_IB && c->tiled) {
+    // binned, LDS-staged interpolation and spreading (dense markers)
+    const TileArgs t = tile_args(c);
+    const int S = c->p.storage, K = c->p.kernel;
+    HIPCHK(c, launch_bin(t, c->L.pos, c->np, c->st));
+    // X~ = X + h/2 I[X]u(t), then X <- X + h/2 I[X~]u(t): one staged pass
+    HIPCHK(c, launch_tile_interp(S, K, t, site_args(c), c->L.pos, c->L.pos, c->L.aux, 2, c->np,
+                                 c->st));
+    bool any;
+    if ((s = enqueue_fint(c, c->L.aux, any)) != LB_OK) return s;
+    if (!any) HIPCHK(c, hipMemsetAsync(c->L.fint, 0, (size_t)c->np * 24, c->st));
+    HIPCHK(c, launch_tile_spread(S, K, t, c->L.aux, c->L.fint, c->L.FA, c->np, c->st));
+    if ((s = lattice_pass(c)) != LB_OK) return s;
+    HIPCHK(c, launch_tile_spread(S, K, t, c->L.aux, c->L.fint, c->L.FB, c->np, c->st));
+    HIPCHK(c, launch_tile_interp(S, K, t, site_args(c), c->L.aux, c->L.pos, c->L.aux, 1, c->np,
+                                 c->st));
+    return LB_OK;
+  }
   if (c->p.coupling == LB_COUPLE_IB) {
     PartArgs a = part_args(c);
     HIPCHK(c, launch_ib_predict(c->p.storage, a, c->st));
@@ -393,8 +442,20 @@ lb_status lb_workspace_size(const lb_grid* g, const lb_params* p, const lb_limit
   return LB_OK;
 }
 
+static lb_status create_ctx(const lb_grid* g, const lb_params* p, const lb_limits* lim,
+                            void* d_workspace, size_t bytes, void* hip_stream, bool linear_mask,
+                            lb_ctx** out);
+
 lb_status lb_create(const lb_grid* g, const lb_params* p, const lb_limits* lim, void* d_workspace,
                     size_t bytes, void* hip_stream, lb_ctx** out) {
+  return create_ctx(g, p, lim, d_workspace, bytes, hip_stream, false, out);
+}
+
+}  // extern "C"
+
+static lb_status create_ctx(const lb_grid* g, const lb_params* p, const lb_limits* lim,
+                            void* d_workspace, size_t bytes, void* hip_stream, bool linear_mask,
+                            lb_ctx** out) {
   std::string err;
   if (!out) return fail(nullptr, LB_EINVAL, "null output");
   *out = nullptr;
@@ -414,9 +475,11 @@ lb_status lb_create(const lb_grid* g, const lb_params* p, const lb_limits* lim, 
   c->geo.ny = g->ny;
   c->geo.nz = g->nz;
   c->geo.wall = g->wall_y;
-  c->geo.wpr = (g->nx + 63) / 64;
+  c->geo.wpr = linear_mask ? 0 : (g->nx + 63) / 64;
+  c->member = linear_mask;
   c->geo.N = (long long)g->nx * g->ny * g->nz;
   c->L = carve(*g, *p, *lim, d_workspace);
+  c->tiled = p->coupling == LB_COUPLE_IB && p->kernel >= 3;
   const double lp = 1.0 / c->p.tau;
   const double lm = c->p.collision == LB_TRT ? 1.0 / (0.5 + c->p.trt_magic / (c->p.tau - 0.5)) : lp;
   c->omp = 1.0 - lp;
@@ -434,6 +497,8 @@ lb_status lb_create(const lb_grid* g, const lb_params* p, const lb_limits* lim, 
   *out = c;
   return LB_OK;
 }
+
+extern "C" {
 
 lb_status lb_init_fluid(lb_ctx* c, const double* d_rho, const double* d_u) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
@@ -516,6 +581,7 @@ lb_status lb_set_shells(lb_ctx* c, int32_t nshell, int32_t shell_size, const dou
 
 lb_status lb_step(lb_ctx* c, int64_t nsteps) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (c->member) return fail(c, LB_ESTATE, "an ensemble slot is stepped by lb_ensemble_step");
   if (nsteps < 0) return fail(c, LB_EINVAL, "negative step count");
   if ((int64_t)c->nshell * c->shell_size > c->np)
     return fail(c, LB_ESTATE, "shells need nshell*shell_size particles");
@@ -630,6 +696,399 @@ const char* lb_status_string(lb_status s) {
     case LB_ESTATE: return "invalid state";
   }
   return "unknown status";
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Ensembles: many boxes resident in one caller-owned pool, stepped together.
+// ===========================================================================
+namespace {
+
+struct EnsHost {
+  bool live = false;
+  bool fresh = false;  // admitted, host fields authoritative until the next refresh
+  lb_ctx* ctx = nullptr;
+  size_t off = 0, bytes = 0;
+  int64_t target = 0;
+};
+
+constexpr int kGraphSteps = 8;
+
+}  // namespace
+
+struct lb_ensemble {
+  char* pool = nullptr;
+  size_t bytes = 0, head = 0;
+  hipStream_t st = nullptr;
+  int max_slots = 0, storage = LB_F32, kernel = 2;
+  EnsSlot* d_slots = nullptr;
+  int2* d_litems = nullptr;
+  int2* d_pitems = nullptr;
+  int* d_counts = nullptr;  // [0] lattice items, [1] particle items
+  size_t max_items = 0;
+  std::vector<EnsHost> slots;
+  std::vector<std::pair<size_t, size_t>> used;  // (offset, bytes), sorted
+  bool dirty = true;
+  int lat_grid = 1024, part_grid = 512;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};  // kGraphSteps steps, one step
+  bool graphs_ok = false;
+  std::string err;
+};
+
+#define EHIPCHK(e, call)                                                              \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      (e)->err = std::string(#call) + ": " + hipGetErrorString(e_);                   \
+      return LB_EDEVICE;                                                              \
+    }                                                                                 \
+  } while (0)
+
+static lb_status efail(lb_ensemble* e, lb_status s, const std::string& m) {
+  if (e)
+    e->err = m;
+  else
+    g_last_error = m;
+  return s;
+}
+
+static EnsArgs ens_args(const lb_ensemble* e) {
+  EnsArgs a;
+  a.slots = e->d_slots;
+  a.nslots = e->max_slots;
+  a.litems = e->d_litems;
+  a.nlitems = e->d_counts;
+  a.pitems = e->d_pitems;
+  a.npitems = e->d_counts + 1;
+  return a;
+}
+
+static EnsSlot slot_from_ctx(const lb_ctx* c) {
+  EnsSlot s{};
+  s.g = c->geo;
+  s.f[0] = c->L.f[0];
+  s.f[1] = c->L.f[1];
+  s.FA = c->L.FA;
+  s.FB = c->L.FB;
+  s.mask = c->L.mask;
+  s.pos = c->L.pos;
+  s.vel = c->L.vel;
+  s.mass = c->L.mass;
+  s.np = c->np;
+  s.rho0 = c->p.rho0;
+  s.fx = c->p.body_force[0];
+  s.fy = c->p.body_force[1];
+  s.fz = c->p.body_force[2];
+  s.omp = c->omp;
+  s.omm = c->omm;
+  s.gamma = c->p.gamma;
+  s.scale = c->scale;
+  s.inv = c->inv;
+  s.collision = c->p.collision;
+  s.coupling = c->p.coupling;
+  s.cur = c->cur;
+  s.pend = c->pend;
+  s.steps_done = 0;
+  s.live = 1;
+  return s;
+}
+
+// Download the device slot table, take the device-advanced fields of running
+// slots, write host fields of freshly admitted ones, upload, rebuild the work
+// lists.
+static lb_status ens_refresh(lb_ensemble* e) {
+  std::vector<EnsSlot> hs(e->max_slots);
+  EHIPCHK(e, hipStreamSynchronize(e->st));
+  EHIPCHK(e, hipMemcpy(hs.data(), e->d_slots, hs.size() * sizeof(EnsSlot), hipMemcpyDeviceToHost));
+  std::vector<int2> li, pi;
+  const int L = e->kernel == 2 ? 8 : (e->kernel == 3 ? 32 : 64);
+  const int ppb = 256 / L;
+  for (int i = 0; i < e->max_slots; ++i) {
+    EnsHost& h = e->slots[i];
+    if (!h.live) {
+      hs[i].live = 0;
+      continue;
+    }
+    if (h.fresh) {
+      hs[i] = slot_from_ctx(h.ctx);
+      hs[i].steps_target = h.target;
+      h.fresh = false;
+    } else {
+      hs[i].np = h.ctx->np;  // particles may have been replaced
+    }
+    const long long nch = (h.ctx->geo.N + 255) / 256;
+    for (long long k = 0; k < nch; ++k) li.push_back(make_int2(i, (int)k));
+    for (long long p = 0; p < h.ctx->np; p += ppb) pi.push_back(make_int2(i, (int)p));
+  }
+  if (li.size() > e->max_items || pi.size() > e->max_items)
+    return efail(e, LB_ENOMEM, "ensemble work list exceeds its capacity");
+  const int counts[2] = {(int)li.size(), (int)pi.size()};
+  EHIPCHK(e, hipMemcpy(e->d_slots, hs.data(), hs.size() * sizeof(EnsSlot), hipMemcpyHostToDevice));
+  if (!li.empty())
+    EHIPCHK(e, hipMemcpy(e->d_litems, li.data(), li.size() * sizeof(int2), hipMemcpyHostToDevice));
+  if (!pi.empty())
+    EHIPCHK(e, hipMemcpy(e->d_pitems, pi.data(), pi.size() * sizeof(int2), hipMemcpyHostToDevice));
+  EHIPCHK(e, hipMemcpy(e->d_counts, counts, sizeof(counts), hipMemcpyHostToDevice));
+  e->dirty = false;
+  return LB_OK;
+}
+
+static void ens_drop_graphs(lb_ensemble* e) {
+  for (auto& x : e->exec)
+    if (x) {
+      (void)hipGraphExecDestroy(x);
+      x = nullptr;
+    }
+  e->graphs_ok = false;
+}
+
+// Capture kGraphSteps steps and one step into graphs (kernels only).
+static lb_status ens_build_graphs(lb_ensemble* e) {
+  ens_drop_graphs(e);
+  const EnsArgs a = ens_args(e);
+  for (int g = 0; g < 2; ++g) {
+    const int n = g == 0 ? kGraphSteps : 1;
+    hipGraph_t graph;
+    EHIPCHK(e, hipStreamBeginCapture(e->st, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < n; ++k) {
+      hipError_t r = launch_ens_step(e->storage, e->kernel, a, e->lat_grid, e->part_grid, e->st);
+      if (r != hipSuccess) {
+        (void)hipStreamEndCapture(e->st, &graph);
+        e->err = std::string("capture: ") + hipGetErrorString(r);
+        return LB_EDEVICE;
+      }
+    }
+    EHIPCHK(e, hipStreamEndCapture(e->st, &graph));
+    EHIPCHK(e, hipGraphInstantiate(&e->exec[g], graph, nullptr, nullptr, 0));
+    EHIPCHK(e, hipGraphDestroy(graph));
+  }
+  e->graphs_ok = true;
+  return LB_OK;
+}
+
+static bool ens_place(lb_ensemble* e, size_t need, size_t& off) {
+  size_t cur = e->head;
+  for (const auto& u : e->used) {
+    if (u.first >= cur + need) break;
+    cur = std::max(cur, align256(u.first + u.second));
+  }
+  if (cur + need > e->bytes) return false;
+  off = cur;
+  e->used.push_back({off, need});
+  std::sort(e->used.begin(), e->used.end());
+  return true;
+}
+
+extern "C" {
+
+lb_status lb_ensemble_footprint(const lb_grid* g, const lb_params* p, const lb_limits* lim,
+                                size_t* bytes) {
+  return lb_workspace_size(g, p, lim, bytes);
+}
+
+lb_status lb_ensemble_create(void* d_pool, size_t bytes, int32_t max_slots, int32_t storage,
+                             int32_t kernel, lb_ensemble** out) {
+  if (!out) return efail(nullptr, LB_EINVAL, "null output");
+  *out = nullptr;
+  if (!d_pool || ((uintptr_t)d_pool & 255)) return efail(nullptr, LB_EINVAL, "pool must be 256-byte aligned");
+  if (max_slots < 1 || max_slots > 65536) return efail(nullptr, LB_EINVAL, "max_slots out of range");
+  if (storage != LB_F32 && storage != LB_F16 && storage != LB_BF16 && storage != LB_F64)
+    return efail(nullptr, LB_EINVAL, "unknown storage");
+  if (kernel < 2 || kernel > 4) return efail(nullptr, LB_EINVAL, "kernel must be 2, 3 or 4");
+  lb_ensemble* e = new lb_ensemble();
+  e->pool = (char*)d_pool;
+  e->bytes = bytes;
+  e->max_slots = max_slots;
+  e->storage = storage;
+  e->kernel = kernel;
+  e->max_items = std::max<size_t>(bytes / 16384, 4096);
+  Carver c{e->pool};
+  e->d_slots = c.take<EnsSlot>(sizeof(EnsSlot) * max_slots);
+  e->d_litems = c.take<int2>(sizeof(int2) * e->max_items);
+  e->d_pitems = c.take<int2>(sizeof(int2) * e->max_items);
+  e->d_counts = c.take<int>(64);
+  e->head = c.off;
+  if (e->head >= bytes) {
+    delete e;
+    return efail(nullptr, LB_ENOMEM, "pool too small for the ensemble tables");
+  }
+  e->slots.resize(max_slots);
+  hipError_t r = hipStreamCreate(&e->st);
+  if (r != hipSuccess) {
+    delete e;
+    return efail(nullptr, LB_EDEVICE, hipGetErrorString(r));
+  }
+  std::vector<EnsSlot> zero(max_slots);
+  for (auto& z : zero) z.live = 0;
+  const int counts[2] = {0, 0};
+  if (hipMemcpy(e->d_slots, zero.data(), zero.size() * sizeof(EnsSlot), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(e->d_counts, counts, sizeof(counts), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipStreamDestroy(e->st);
+    delete e;
+    return efail(nullptr, LB_EDEVICE, "cannot initialise the ensemble tables");
+  }
+  *out = e;
+  return LB_OK;
+}
+
+lb_status lb_ensemble_stream(lb_ensemble* e, void** stream) {
+  if (!e || !stream) return efail(e, LB_EINVAL, "null argument");
+  *stream = (void*)e->st;
+  return LB_OK;
+}
+
+lb_status lb_ensemble_admit(lb_ensemble* e, const lb_grid* g, const lb_params* p,
+                            const lb_limits* lim, int64_t nsteps, int32_t* slot, lb_ctx** ctx) {
+  if (!e || !g || !p || !lim || !slot) return efail(e, LB_EINVAL, "null argument");
+  std::string err;
+  if (!check_params(g, p, lim, err)) return efail(e, LB_EINVAL, err);
+  if (g->wall_y) return efail(e, LB_EINVAL, "ensemble members are periodic boxes");
+  if (p->coupling == LB_COUPLE_IB || p->mts_substeps != 0)
+    return efail(e, LB_EINVAL, "ensemble members use FC, EBF or no coupling without sub-steps");
+  if (lim->max_bonds != 0 || lim->max_shells != 0)
+    return efail(e, LB_EINVAL, "ensemble members carry free particles only");
+  if (p->storage != e->storage || p->kernel != e->kernel)
+    return efail(e, LB_EINVAL, "storage and kernel must match the ensemble");
+  if (nsteps < 0) return efail(e, LB_EINVAL, "negative step budget");
+  int idx = -1;
+  for (int i = 0; i < e->max_slots; ++i)
+    if (!e->slots[i].live) {
+      idx = i;
+      break;
+    }
+  if (idx < 0) return efail(e, LB_EBUSY, "no free slot");
+  size_t need = carve(*g, *p, *lim, nullptr).bytes, off;
+  if (!ens_place(e, need, off)) return efail(e, LB_EBUSY, "not enough free memory in the pool");
+  lb_ctx* c = nullptr;
+  lb_status s = create_ctx(g, p, lim, e->pool + off, need, (void*)e->st, true, &c);
+  if (s != LB_OK) {
+    e->used.erase(std::find(e->used.begin(), e->used.end(), std::make_pair(off, need)));
+    return efail(e, s, g_last_error);
+  }
+  EnsHost& h = e->slots[idx];
+  h.live = true;
+  h.fresh = true;
+  h.ctx = c;
+  h.off = off;
+  h.bytes = need;
+  h.target = nsteps;
+  e->dirty = true;
+  *slot = idx;
+  if (ctx) *ctx = c;
+  return LB_OK;
+}
+
+lb_status lb_ensemble_step(lb_ensemble* e, int64_t nsteps) {
+  if (!e) return efail(nullptr, LB_EINVAL, "null ensemble");
+  if (nsteps < 0) return efail(e, LB_EINVAL, "negative step count");
+  lb_status s;
+  if (e->dirty && (s = ens_refresh(e)) != LB_OK) return s;
+  if (!e->graphs_ok && (s = ens_build_graphs(e)) != LB_OK) return s;
+  int64_t k = 0;
+  for (; k + kGraphSteps <= nsteps; k += kGraphSteps) EHIPCHK(e, hipGraphLaunch(e->exec[0], e->st));
+  for (; k < nsteps; ++k) EHIPCHK(e, hipGraphLaunch(e->exec[1], e->st));
+  return LB_OK;
+}
+
+lb_status lb_ensemble_query(lb_ensemble* e, int32_t slot, int64_t* steps_done, int32_t* done) {
+  if (!e) return efail(nullptr, LB_EINVAL, "null ensemble");
+  if (slot < 0 || slot >= e->max_slots || !e->slots[slot].live)
+    return efail(e, LB_EINVAL, "not a live slot");
+  EnsHost& h = e->slots[slot];
+  int64_t sd = 0;
+  if (!h.fresh) {
+    EnsSlot d;
+    EHIPCHK(e, hipStreamSynchronize(e->st));
+    EHIPCHK(e, hipMemcpy(&d, e->d_slots + slot, sizeof(EnsSlot), hipMemcpyDeviceToHost));
+    h.ctx->cur = d.cur;
+    h.ctx->pend = d.pend;
+    h.ctx->steps = d.steps_done;
+    sd = d.steps_done;
+  }
+  if (steps_done) *steps_done = sd;
+  if (done) *done = sd >= h.target ? 1 : 0;
+  return LB_OK;
+}
+
+lb_status lb_ensemble_retire(lb_ensemble* e, int32_t slot) {
+  if (!e) return efail(nullptr, LB_EINVAL, "null ensemble");
+  if (slot < 0 || slot >= e->max_slots || !e->slots[slot].live)
+    return efail(e, LB_EINVAL, "not a live slot");
+  EHIPCHK(e, hipStreamSynchronize(e->st));
+  EnsHost& h = e->slots[slot];
+  e->used.erase(std::find(e->used.begin(), e->used.end(), std::make_pair(h.off, h.bytes)));
+  lb_destroy(h.ctx);
+  h = EnsHost();
+  e->dirty = true;
+  return LB_OK;
+}
+
+// Project autotuner: time real steps of the current mix under each candidate
+// persistent-grid shape and keep the fastest (every shape computes the same
+// update, so tuning steps are ordinary steps of the live slots).
+lb_status lb_ensemble_autotune(lb_ensemble* e, int32_t steps_per_candidate, int32_t* lat_grid,
+                               int32_t* part_grid) {
+  if (!e) return efail(nullptr, LB_EINVAL, "null ensemble");
+  if (steps_per_candidate < 1) return efail(e, LB_EINVAL, "need at least one step per candidate");
+  lb_status s;
+  if (e->dirty && (s = ens_refresh(e)) != LB_OK) return s;
+  int cus = 256;
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      cus = prop.multiProcessorCount;
+  }
+  const int lat_c[] = {cus * 2, cus * 4, cus * 8, cus * 16};
+  const int part_c[] = {cus, cus * 4};
+  hipEvent_t t0, t1;
+  EHIPCHK(e, hipEventCreate(&t0));
+  EHIPCHK(e, hipEventCreate(&t1));
+  float best = 1e30f;
+  int bl = e->lat_grid, bp = e->part_grid;
+  const EnsArgs a = ens_args(e);
+  for (int lg : lat_c)
+    for (int pg : part_c) {
+      EHIPCHK(e, hipEventRecord(t0, e->st));
+      for (int k = 0; k < steps_per_candidate; ++k)
+        EHIPCHK(e, launch_ens_step(e->storage, e->kernel, a, lg, pg, e->st));
+      EHIPCHK(e, hipEventRecord(t1, e->st));
+      EHIPCHK(e, hipEventSynchronize(t1));
+      float ms;
+      EHIPCHK(e, hipEventElapsedTime(&ms, t0, t1));
+      if (ms < best) {
+        best = ms;
+        bl = lg;
+        bp = pg;
+      }
+    }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (bl != e->lat_grid || bp != e->part_grid) {
+    e->lat_grid = bl;
+    e->part_grid = bp;
+    ens_drop_graphs(e);
+  }
+  if (lat_grid) *lat_grid = bl;
+  if (part_grid) *part_grid = bp;
+  return LB_OK;
+}
+
+lb_status lb_ensemble_destroy(lb_ensemble* e) {
+  if (!e) return LB_OK;
+  (void)hipStreamSynchronize(e->st);
+  for (auto& h : e->slots)
+    if (h.live) lb_destroy(h.ctx);
+  ens_drop_graphs(e);
+  (void)hipStreamDestroy(e->st);
+  delete e;
+  return LB_OK;
+}
+
+const char* lb_ensemble_last_error(const lb_ensemble* e) {
+  return e ? e->err.c_str() : g_last_error.c_str();
 }
 
 }  // extern "C"

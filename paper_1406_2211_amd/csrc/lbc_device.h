@@ -76,6 +76,21 @@ __device__ __forceinline__ long long site_index(const Geo& g, int x, int y, int 
   return ((long long)z * g.ny + y) * g.nx + x;
 }
 
+// Force-mask word and bit of a site.  Single contexts keep one word per 64
+// x-sites of a row (wpr words per row, so a row-aligned wavefront owns its
+// word); ensemble slots (wpr == 0) use one word per 64 consecutive linear
+// site indices.
+__device__ __forceinline__ uint64_t* mask_word(uint64_t* m, const Geo& g, int x, int y, int z,
+                                               uint64_t& bit) {
+  if (g.wpr == 0) {
+    const long long s = site_index(g, x, y, z);
+    bit = 1ull << (s & 63);
+    return m + (s >> 6);
+  }
+  bit = 1ull << (x & 63);
+  return m + ((long long)z * g.ny + y) * g.wpr + (x >> 6);
+}
+
 // Pull gather: fbar_i(x) = f*_i(x - c_i), periodic, or the reflected opposite
 // population of the same site when x - c_i lies beyond a y wall (halfway
 // bounce-back).  Values are converted to the compute type R.
@@ -102,12 +117,88 @@ __device__ __forceinline__ void pull(const typename Store<S>::T* __restrict__ f,
   }
 }
 
+// Physical moments at one site: rho and rho u = sum f c + (h/2)(FB + pend F_ext)
+// (the redefined velocity of Sec. 4).
+template <int S>
+__device__ __forceinline__ void site_phys(const SiteArgs& a, int x, int y, int z, double fl[Q],
+                                          double& drho, double j[3], bool phys) {
+  using St = Store<S>;
+  pull<S, double>((const typename St::T*)a.f, a.g, x, y, z, (double)a.inv, fl);
+  drho = 0;
+  j[0] = j[1] = j[2] = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += fl[i];
+    j[0] += CX[i] * fl[i];
+    j[1] += CY[i] * fl[i];
+    j[2] += CZ[i] * fl[i];
+  }
+  if (phys) {
+    const long long s = site_index(a.g, x, y, z);
+    using V4 = typename St::V4;
+    const V4 fb = ((const V4*)a.FB)[s];
+    j[0] += 0.5 * ((double)fb.x + a.pfx);
+    j[1] += 0.5 * ((double)fb.y + a.pfy);
+    j[2] += 0.5 * ((double)fb.z + a.pfz);
+  }
+}
+
 // deviation equilibrium f^eq_i(rho,u) - w_i rho0 = w_i [drho + rho P_i(u)],
 // P_i(u) = 3 c.u + 9/2 (c.u)^2 - 3/2 u.u
 template <typename R>
 __device__ __forceinline__ R feq_dev(int i, R drho, R rho, R ux, R uy, R uz, R usq) {
   const R cu = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
   return wgt<R>(i) * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq));
+}
+
+// Both pending half forces as one equilibrium shift and the collision, then
+// the store (the fused-pass arithmetic shared by the single-box and the
+// batched passes).  f: post-stream populations; (drho, j): their moments;
+// F: total pending force (both halves).  BGK: f* = f^eq(u') + (1 - l)(f -
+// f^eq(u)); two-rate: (1 - l+) on the even and (1 - l-) on the odd part of
+// f - f^eq(u) over the opposite pairs (1,2), (3,4), ...
+template <int S>
+__device__ __forceinline__ void relax_store(const typename Store<S>::R f[Q],
+                                            typename Store<S>::R drho, typename Store<S>::R rho,
+                                            typename Store<S>::R ir, typename Store<S>::R jx,
+                                            typename Store<S>::R jy, typename Store<S>::R jz,
+                                            typename Store<S>::R Fx, typename Store<S>::R Fy,
+                                            typename Store<S>::R Fz, int collision,
+                                            typename Store<S>::R omp, typename Store<S>::R omm,
+                                            typename Store<S>::R sc, typename Store<S>::T* fo,
+                                            size_t N, size_t own) {
+  using St = Store<S>;
+  using R = typename St::R;
+  const R ux = jx * ir, uy = jy * ir, uz = jz * ir;  // post-stream velocity
+  const R hx = ux + R(0.5) * Fx * ir, hy = uy + R(0.5) * Fy * ir,
+          hz = uz + R(0.5) * Fz * ir;  // after both half forces
+  const R usq = ux * ux + uy * uy + uz * uz, hsq = hx * hx + hy * hy + hz * hz;
+  if (collision == LB_BGK) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R eb = feq_dev<R>(i, drho, rho, ux, uy, uz, usq);
+      const R ep = feq_dev<R>(i, drho, rho, hx, hy, hz, hsq);
+      St::st(fo + (size_t)i * N + own, ep + omp * (f[i] - eb), sc);
+    }
+  } else {
+    {
+      const R w0 = wgt<R>(0);
+      const R eb = w0 * (drho - R(1.5) * rho * usq), ep = w0 * (drho - R(1.5) * rho * hsq);
+      St::st(fo + own, ep + omp * (f[0] - eb), sc);
+    }
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+      const R w = wgt<R>(i);
+      const R cb = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
+      const R ch = R(CX[i]) * hx + R(CY[i]) * hy + R(CZ[i]) * hz;
+      const R Eb = w * (drho + rho * (R(4.5) * cb * cb - R(1.5) * usq)), Ob = w * rho * R(3) * cb;
+      const R Eh = w * (drho + rho * (R(4.5) * ch * ch - R(1.5) * hsq)), Oh = w * rho * R(3) * ch;
+      const R ni = f[i] - (Eb + Ob), nj = f[i + 1] - (Eb - Ob);
+      const R sym = R(0.5) * (ni + nj), anti = R(0.5) * (ni - nj);
+      St::st(fo + (size_t)i * N + own, Eh + Oh + omp * sym + omm * anti, sc);
+      St::st(fo + (size_t)(i + 1) * N + own, Eh - Oh + omp * sym - omm * anti, sc);
+    }
+  }
 }
 
 // ---------------------------------------------------------- delta functions

@@ -95,6 +95,61 @@ struct ShellArgs {
   double k;
 };
 
+// Binning of markers into 8^3 tiles (counting sort) for LDS-staged
+// interpolation and spreading.
+struct TileArgs {
+  Geo g;
+  int tx, ty, tz, ntiles;
+  int* count;   // [ntiles]
+  int* start;   // [ntiles + 1]
+  int* cursor;  // [ntiles]
+  int* occ;     // occupied tiles in increasing order
+  int* nocc;    // [1]
+  int* ptile;   // tile of every marker
+  int* sorted;  // markers grouped by tile
+  uint64_t* mask;
+};
+
+hipError_t launch_bin(const TileArgs& t, const double* pos, long long n, hipStream_t st);
+hipError_t launch_tile_interp(int storage, int K, const TileArgs& t, const SiteArgs& s,
+                              const double* at, double* pos, double* aux, int mode, long long n,
+                              hipStream_t st);
+hipError_t launch_tile_spread(int storage, int K, const TileArgs& t, const double* at,
+                              const double* F, void* field, long long n, hipStream_t st);
+
+// One ensemble member as the batched kernels see it (device memory).  The
+// fields cur, pend and steps_done are advanced on the device only.
+struct EnsSlot {
+  Geo g;  // wpr == 0: linear force mask
+  void* f[2];
+  void* FA;
+  void* FB;
+  uint64_t* mask;
+  double* pos;
+  double* vel;
+  const double* mass;
+  long long np;
+  double rho0, fx, fy, fz;
+  double omp, omm, gamma;
+  float scale, inv;
+  int collision, coupling;
+  int cur, pend;
+  long long steps_done, steps_target;
+  int live;
+};
+
+struct EnsArgs {
+  EnsSlot* slots;
+  int nslots;
+  const int2* litems;  // (slot, 256-site chunk)
+  const int* nlitems;
+  const int2* pitems;  // (slot, first particle of a 256-lane group block)
+  const int* npitems;
+};
+
+hipError_t launch_ens_step(int storage, int K, const EnsArgs& e, int lat_grid, int part_grid,
+                           hipStream_t st);
+
 hipError_t launch_stream_collide(int storage, int collision, const LatArgs& a, hipStream_t st);
 hipError_t launch_init(int storage, const InitArgs& a, hipStream_t st);
 hipError_t launch_moments(int storage, const SiteArgs& a, double* rho, double* u, hipStream_t st);

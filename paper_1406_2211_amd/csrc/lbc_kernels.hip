@@ -83,38 +83,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
     }
     if ((x & 63) == 0) *(uint64_t*)mp = 0;
   }
-  const R ux = jx * ir, uy = jy * ir, uz = jz * ir;         // post-stream velocity
-  const R hx = ux + R(0.5) * Fx * ir, hy = uy + R(0.5) * Fy * ir,
-          hz = uz + R(0.5) * Fz * ir;                      // after both half forces
-  const R usq = ux * ux + uy * uy + uz * uz, hsq = hx * hx + hy * hy + hz * hz;
-  T* fo = (T*)a.fout;
-  const R omp = R(a.omp), omm = R(a.omm), sc = R(a.scale);
-  if (COL == LB_BGK) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const R eb = feq_dev<R>(i, drho, rho, ux, uy, uz, usq);
-      const R ep = feq_dev<R>(i, drho, rho, hx, hy, hz, hsq);
-      St::st(fo + (size_t)i * N + own, ep + omp * (f[i] - eb), sc);
-    }
-  } else {
-    {
-      const R w0 = wgt<R>(0);
-      const R eb = w0 * (drho - R(1.5) * rho * usq), ep = w0 * (drho - R(1.5) * rho * hsq);
-      St::st(fo + own, ep + omp * (f[0] - eb), sc);
-    }
-#pragma unroll
-    for (int i = 1; i < Q; i += 2) {
-      const R w = wgt<R>(i);
-      const R cb = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
-      const R ch = R(CX[i]) * hx + R(CY[i]) * hy + R(CZ[i]) * hz;
-      const R Eb = w * (drho + rho * (R(4.5) * cb * cb - R(1.5) * usq)), Ob = w * rho * R(3) * cb;
-      const R Eh = w * (drho + rho * (R(4.5) * ch * ch - R(1.5) * hsq)), Oh = w * rho * R(3) * ch;
-      const R ni = f[i] - (Eb + Ob), nj = f[i + 1] - (Eb - Ob);
-      const R sym = R(0.5) * (ni + nj), anti = R(0.5) * (ni - nj);
-      St::st(fo + (size_t)i * N + own, Eh + Oh + omp * sym + omm * anti, sc);
-      St::st(fo + (size_t)(i + 1) * N + own, Eh - Oh + omp * sym - omm * anti, sc);
-    }
-  }
+  relax_store<S>(f, drho, rho, ir, jx, jy, jz, Fx, Fy, Fz, COL, R(a.omp), R(a.omm), R(a.scale),
+                 (T*)a.fout, N, own);
 }
 
 // ======================================================================
@@ -150,32 +120,6 @@ __global__ void k_init(InitArgs a) {
                        wrap_idx(z - CZ[i], a.g.nz));
     }
     St::st(f + dst, (R)v, (R)a.scale);
-  }
-}
-
-// Physical moments at one site: rho and rho u = sum f c + (h/2)(FB + pend F_ext)
-// (the redefined velocity of Sec. 4).
-template <int S>
-__device__ __forceinline__ void site_phys(const SiteArgs& a, int x, int y, int z, double fl[Q],
-                                          double& drho, double j[3], bool phys) {
-  using St = Store<S>;
-  pull<S, double>((const typename St::T*)a.f, a.g, x, y, z, (double)a.inv, fl);
-  drho = 0;
-  j[0] = j[1] = j[2] = 0;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    drho += fl[i];
-    j[0] += CX[i] * fl[i];
-    j[1] += CY[i] * fl[i];
-    j[2] += CZ[i] * fl[i];
-  }
-  if (phys) {
-    const long long s = site_index(a.g, x, y, z);
-    using V4 = typename St::V4;
-    const V4 fb = ((const V4*)a.FB)[s];
-    j[0] += 0.5 * ((double)fb.x + a.pfx);
-    j[1] += 0.5 * ((double)fb.y + a.pfy);
-    j[2] += 0.5 * ((double)fb.z + a.pfz);
   }
 }
 
@@ -358,9 +302,9 @@ __device__ __forceinline__ void group_spread(const PartArgs& a, const double X[3
   unsafeAtomicAdd(Fd + 4 * s + 0, (E)(sl.W * F[0]));
   unsafeAtomicAdd(Fd + 4 * s + 1, (E)(sl.W * F[1]));
   unsafeAtomicAdd(Fd + 4 * s + 2, (E)(sl.W * F[2]));
-  atomicOr((unsigned long long*)(a.mask + ((long long)sl.z * a.s.g.ny + sl.y) * a.s.g.wpr +
-                                 (sl.x >> 6)),
-           1ull << (sl.x & 63));
+  uint64_t bit;
+  uint64_t* mw = mask_word(a.mask, a.s.g, sl.x, sl.y, sl.z, bit);
+  atomicOr((unsigned long long*)mw, bit);
 }
 
 __device__ __forceinline__ void wrap3(const Geo& g, double r[3]) {
@@ -841,6 +785,170 @@ hipError_t launch_bond_groups(const BondArgs& b, int ngroups, int gcap, int mode
 
 hipError_t launch_shell_forces(const ShellArgs& s, int nshell, hipStream_t st) {
   if (nshell > 0) k_shell_forces<<<nshell, 256, 0, st>>>(s);
+  return hipGetLastError();
+}
+
+// ======================================================================
+// Batched ensemble step: many periodic boxes of different sizes advance
+// together.  Every kernel is a persistent grid that strides over a flat work
+// list: (slot, 256-site chunk) for the lattice, (slot, particle group) for
+// the coupling halves.  A slot takes part while steps_done < steps_target;
+// the per-slot state (ping-pong buffer, pending body-force half, step count)
+// lives on the device, so a captured graph of steps stays valid while slots
+// are admitted and retired.
+// ======================================================================
+__device__ __forceinline__ bool ens_active(const EnsSlot& s) {
+  return s.live && s.steps_done < s.steps_target;
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_ens_lattice(EnsArgs e) {
+  using St = Store<S>;
+  using T = typename St::T;
+  using R = typename St::R;
+  using V4 = typename St::V4;
+  const int n = *e.nlitems;
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int2 w = e.litems[it];
+    const EnsSlot& sl = e.slots[w.x];
+    if (!ens_active(sl)) continue;
+    const long long s = (long long)w.y * 256 + threadIdx.x;
+    const size_t N = (size_t)sl.g.N;
+    if (s >= (long long)N) continue;
+    const int nx = sl.g.nx, ny = sl.g.ny, nz = sl.g.nz;
+    const int x = (int)(s % nx);
+    const long long r = s / nx;
+    const int y = (int)(r % ny), z = (int)(r / ny);
+    const int xs[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
+    const int ys[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
+    const int zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
+    const T* fin = (const T*)sl.f[sl.cur];
+    uint64_t* mp = sl.mask + (s >> 6);
+    const uint64_t word = *mp;
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const size_t src = ((size_t)zs[1 - CZ[i]] * ny + ys[1 - CY[i]]) * nx + xs[1 - CX[i]];
+      f[i] = St::ld(fin + (size_t)i * N + src, (R)sl.inv);
+    }
+    R drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      drho += f[i];
+      jx += R(CX[i]) * f[i];
+      jy += R(CY[i]) * f[i];
+      jz += R(CZ[i]) * f[i];
+    }
+    const R rho = R(sl.rho0) + drho, ir = R(1) / rho;
+    const R fac = R(1 + sl.pend);
+    R Fx = fac * R(sl.fx), Fy = fac * R(sl.fy), Fz = fac * R(sl.fz);
+    if (word) {  // a 64-aligned group of 64 lanes owns this mask word
+      if ((word >> (s & 63)) & 1ull) {
+        V4* FA = (V4*)sl.FA;
+        V4* FB = (V4*)sl.FB;
+        const V4 fa = FA[s], fb = FB[s];
+        Fx += fa.x + fb.x;
+        Fy += fa.y + fb.y;
+        Fz += fa.z + fb.z;
+        V4 zero;
+        zero.x = zero.y = zero.z = zero.w = 0;
+        FA[s] = zero;
+        FB[s] = zero;
+      }
+      if ((s & 63) == 0) *mp = 0;
+    }
+    relax_store<S>(f, drho, rho, ir, jx, jy, jz, Fx, Fy, Fz, sl.collision, R(sl.omp), R(sl.omm),
+                   R(sl.scale), (T*)sl.f[1 - sl.cur], N, (size_t)s);
+  }
+}
+
+// half 0: P^1/2 then the first coupling half (physical u, spread into FA);
+// half 1: the second coupling half (post-stream u, spread into FB), then P^1/2.
+template <int S, int K>
+__global__ __launch_bounds__(256) void k_ens_couple(EnsArgs e, int half) {
+  using E = typename Store<S>::R;
+  constexpr int L = Lanes<K>::L;
+  const int n = *e.npitems;
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int2 w = e.pitems[it];
+    const EnsSlot& sl = e.slots[w.x];
+    if (!ens_active(sl) || sl.coupling == LB_COUPLE_NONE) continue;
+    const long long p = (long long)w.y + threadIdx.x / L;
+    const int lane = threadIdx.x % L;
+    if (p >= sl.np) continue;  // whole lane groups leave together
+    PartArgs a;
+    a.s.g = sl.g;
+    a.s.f = half == 0 ? sl.f[sl.cur] : sl.f[1 - sl.cur];
+    a.s.FB = sl.FB;
+    a.s.rho0 = sl.rho0;
+    a.s.pfx = sl.pend * sl.fx;
+    a.s.pfy = sl.pend * sl.fy;
+    a.s.pfz = sl.pend * sl.fz;
+    a.s.inv = sl.inv;
+    a.FA = sl.FA;
+    a.FB = sl.FB;
+    a.mask = sl.mask;
+    a.K = K;
+    const double hh = 0.5;
+    double r[3], v[3];
+    for (int k = 0; k < 3; ++k) {
+      r[k] = sl.pos[3 * p + k];
+      v[k] = sl.vel[3 * p + k];
+    }
+    if (half == 0) {
+      for (int k = 0; k < 3; ++k) r[k] += hh * v[k];
+      wrap3(sl.g, r);
+    }
+    const double m = sl.mass[p];
+    double rp, up[3];
+    group_interp<S, K>(a, r, half == 0, lane, rp, up);
+    const double al = sl.gamma * hh / m, be = sl.gamma * hh / rp;
+    double Fh[3];
+    if (sl.coupling == LB_COUPLE_FC) {
+      const double den = 1.0 + 0.5 * al + 0.5 * be;
+      for (int k = 0; k < 3; ++k) {
+        Fh[k] = -(sl.gamma * (v[k] - up[k])) / den;
+        v[k] += hh / m * Fh[k];
+      }
+    } else {
+      const double sm = al + be;
+      for (int k = 0; k < 3; ++k) {
+        const double d = v[k] - up[k];
+        Fh[k] = -sl.gamma / sm * d;
+        v[k] = v[k] - al / sm * d;
+      }
+    }
+    const double Ff[3] = {-Fh[0], -Fh[1], -Fh[2]};
+    group_spread<E, K>(a, r, Ff, half == 0 ? sl.FA : sl.FB, lane);
+    if (lane == 0) {
+      if (half == 1) {
+        for (int k = 0; k < 3; ++k) r[k] += hh * v[k];
+        wrap3(sl.g, r);
+      }
+      for (int k = 0; k < 3; ++k) {
+        sl.pos[3 * p + k] = r[k];
+        sl.vel[3 * p + k] = v[k];
+      }
+    }
+  }
+}
+
+__global__ void k_ens_advance(EnsArgs e) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= e.nslots) return;
+  EnsSlot& sl = e.slots[i];
+  if (!ens_active(sl)) return;
+  sl.cur = 1 - sl.cur;
+  sl.pend = 1;
+  sl.steps_done += 1;
+}
+
+hipError_t launch_ens_step(int storage, int K, const EnsArgs& e, int lat_grid, int part_grid,
+                           hipStream_t st) {
+  LBC_KERNEL_SWITCH(K, LBC_STORAGE_SWITCH(storage, (k_ens_couple<SS, KK><<<part_grid, 256, 0, st>>>(e, 0))));
+  LBC_STORAGE_SWITCH(storage, (k_ens_lattice<SS><<<lat_grid, 256, 0, st>>>(e)));
+  LBC_KERNEL_SWITCH(K, LBC_STORAGE_SWITCH(storage, (k_ens_couple<SS, KK><<<part_grid, 256, 0, st>>>(e, 1))));
+  k_ens_advance<<<(e.nslots + 63) / 64, 64, 0, st>>>(e);
   return hipGetLastError();
 }
 

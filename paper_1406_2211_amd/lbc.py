@@ -26,7 +26,10 @@ EXPORTS = ["lb_lattice_velocities", "lb_workspace_size", "lb_create", "lb_init_f
            "lb_set_particles", "lb_set_bonds", "lb_set_shells", "lb_step", "lb_moments",
            "lb_populations", "lb_get_particles", "lb_totals", "lb_timing", "lb_timing_read",
            "lb_info", "lb_destroy",
-           "lb_last_error", "lb_status_string"]
+           "lb_last_error", "lb_status_string", "lb_ensemble_footprint", "lb_ensemble_create",
+           "lb_ensemble_stream", "lb_ensemble_admit", "lb_ensemble_step", "lb_ensemble_query",
+           "lb_ensemble_retire", "lb_ensemble_autotune", "lb_ensemble_destroy",
+           "lb_ensemble_last_error"]
 
 
 class lb_grid(C.Structure):
@@ -63,6 +66,11 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1406_2211_amd/build.py "
                            "(or __graft_entry__.build())")
+    # PyTorch's HIP runtime must be the process's runtime: it carries the same
+    # soname as the one liblbc.so was linked against, so loading torch first
+    # makes the dynamic loader bind liblbc.so to it (one runtime, one device
+    # view).  Loading liblbc.so first would bring in a second runtime.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
     G, P, M = C.POINTER(lb_grid), C.POINTER(lb_params), C.POINTER(lb_limits)
@@ -85,6 +93,16 @@ def load():
         "lb_destroy": (i32, [vp]),
         "lb_last_error": (C.c_char_p, [vp]),
         "lb_status_string": (C.c_char_p, [i32]),
+        "lb_ensemble_footprint": (i32, [G, P, M, C.POINTER(C.c_size_t)]),
+        "lb_ensemble_create": (i32, [vp, C.c_size_t, i32, i32, i32, C.POINTER(vp)]),
+        "lb_ensemble_stream": (i32, [vp, C.POINTER(vp)]),
+        "lb_ensemble_admit": (i32, [vp, G, P, M, i64, C.POINTER(i32), C.POINTER(vp)]),
+        "lb_ensemble_step": (i32, [vp, i64]),
+        "lb_ensemble_query": (i32, [vp, i32, C.POINTER(i64), C.POINTER(i32)]),
+        "lb_ensemble_retire": (i32, [vp, i32]),
+        "lb_ensemble_autotune": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32)]),
+        "lb_ensemble_destroy": (i32, [vp]),
+        "lb_ensemble_last_error": (C.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -136,9 +154,22 @@ class Lattice:
     torch.cuda.Stream; default: the current stream at construction)."""
 
     def __init__(self, nx, ny, nz, wall_y=0, max_particles=0, max_bonds=0, max_shells=0,
-                 max_shell_size=0, stream=None, device="cuda", **params):
+                 max_shell_size=0, stream=None, device="cuda", _ctx=None, **params):
         import torch
         self.torch = torch
+        if _ctx is not None:  # a slot of an ensemble: the ensemble owns memory and stream
+            self.grid = lb_grid(int(nx), int(ny), int(nz), int(wall_y))
+            self.params = make_params(**params)
+            self.device = torch.device(device)
+            self.stream = stream
+            self.workspace = None
+            self.ctx = _ctx
+            self.shape = (int(nz), int(ny), int(nx))
+            self.N = int(nx) * int(ny) * int(nz)
+            self.np = 0
+            self._owned = False
+            return
+        self._owned = True
         self.grid = lb_grid(int(nx), int(ny), int(nz), int(wall_y))
         self.params = make_params(**params)
         self.limits = lb_limits(int(max_particles), int(max_bonds), int(max_shells),
@@ -170,15 +201,16 @@ class Lattice:
     def lb_init_fluid(self, rho=None, u=None):
         r = None if rho is None else self._f64(rho, self.shape)
         v = None if u is None else self._f64(u, (3,) + self.shape)
-        with self.torch.cuda.stream(self.stream):
-            self._call("lb_init_fluid", _ptr(r), _ptr(v))
-            self._keep = (r, v)
+        self.torch.cuda.synchronize(self.device)
+        self._call("lb_init_fluid", _ptr(r), _ptr(v))
+        self._keep = (r, v)
 
     def lb_set_particles(self, pos, vel=None, mass=None):
         p = self._f64(pos, (-1, 3))
         n = p.shape[0]
         v = None if vel is None else self._f64(vel, (n, 3))
         m = None if mass is None else self._f64(mass, (n,))
+        self.torch.cuda.synchronize(self.device)
         self._call("lb_set_particles", n, _ptr(p), _ptr(v), _ptr(m))
         self._keep_p = (p, v, m)
         self.np = n
@@ -233,12 +265,103 @@ class Lattice:
         return n.value, s.value
 
     def lb_destroy(self):
-        if self.ctx:
+        if self.ctx and getattr(self, "_owned", True):
             load().lb_destroy(self.ctx)
-            self.ctx = C.c_void_p()
+        self.ctx = C.c_void_p()
 
     def __del__(self):
         try:
             self.lb_destroy()
+        except Exception:
+            pass
+
+
+def _echeck(status, ens=None):
+    if status != LB_OK:
+        raise LbcError(status, load().lb_ensemble_last_error(ens).decode())
+
+
+def ensemble_footprint(nx, ny, nz, max_particles=0, **params):
+    n = C.c_size_t()
+    g = lb_grid(int(nx), int(ny), int(nz), 0)
+    p = make_params(**params)
+    m = lb_limits(int(max_particles), 0, 0, 0)
+    _check(load().lb_ensemble_footprint(C.byref(g), C.byref(p), C.byref(m), C.byref(n)))
+    return n.value
+
+
+class Ensemble:
+    """Many periodic boxes resident in one device pool (a torch uint8 tensor)
+    and stepped together by batched launches replayed from HIP graphs."""
+
+    def __init__(self, pool_bytes, max_slots, storage=LB_F32, kernel=LB_PHI2, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.pool = torch.empty(int(pool_bytes) + 256, dtype=torch.uint8, device=self.device)
+        base = self.pool.data_ptr()
+        ptr = base + ((-base) % 256)
+        self.storage, self.kernel = int(storage), int(kernel)
+        self.ens = C.c_void_p()
+        torch.cuda.synchronize(self.device)
+        _echeck(load().lb_ensemble_create(C.c_void_p(ptr), int(pool_bytes), int(max_slots),
+                                          self.storage, self.kernel, C.byref(self.ens)))
+        st = C.c_void_p()
+        _echeck(load().lb_ensemble_stream(self.ens, C.byref(st)), self.ens)
+        self.stream_ptr = st.value
+        self.slots = {}
+
+    def admit(self, nx, ny, nz, nsteps, max_particles=0, **params):
+        """Returns (slot, Lattice view of the slot) or None when the pool or the
+        slot table is full (LB_EBUSY)."""
+        g = lb_grid(int(nx), int(ny), int(nz), 0)
+        params.setdefault("storage", self.storage)
+        params.setdefault("kernel", self.kernel)
+        p = make_params(**params)
+        m = lb_limits(int(max_particles), 0, 0, 0)
+        slot, ctx = C.c_int32(), C.c_void_p()
+        st = load().lb_ensemble_admit(self.ens, C.byref(g), C.byref(p), C.byref(m), int(nsteps),
+                                      C.byref(slot), C.byref(ctx))
+        if st == LB_EBUSY:
+            return None
+        _echeck(st, self.ens)
+        lat = Lattice(nx, ny, nz, stream=None, device=self.device, _ctx=ctx, **params)
+        self.slots[slot.value] = lat
+        return slot.value, lat
+
+    def step(self, nsteps):
+        _echeck(load().lb_ensemble_step(self.ens, int(nsteps)), self.ens)
+
+    def query(self, slot):
+        sd, done = C.c_int64(), C.c_int32()
+        _echeck(load().lb_ensemble_query(self.ens, int(slot), C.byref(sd), C.byref(done)), self.ens)
+        return sd.value, bool(done.value)
+
+    def retire(self, slot):
+        _echeck(load().lb_ensemble_retire(self.ens, int(slot)), self.ens)
+        lat = self.slots.pop(slot, None)
+        if lat is not None:
+            lat.ctx = C.c_void_p()
+
+    def autotune(self, steps_per_candidate=2):
+        lg, pg = C.c_int32(), C.c_int32()
+        _echeck(load().lb_ensemble_autotune(self.ens, int(steps_per_candidate), C.byref(lg),
+                                            C.byref(pg)), self.ens)
+        return lg.value, pg.value
+
+    def synchronize(self):
+        self.torch.cuda.synchronize(self.device)
+
+    def destroy(self):
+        if self.ens:
+            for lat in self.slots.values():
+                lat.ctx = C.c_void_p()
+            self.slots = {}
+            load().lb_ensemble_destroy(self.ens)
+            self.ens = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
         except Exception:
             pass

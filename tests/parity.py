@@ -48,6 +48,8 @@ class Case:
 def initial_fields(c: Case):
     shape = (c.nz, c.ny, c.nx)
     u = I.noise_velocity(shape, c.u_noise, c.seed) if c.u_noise > 0 else np.zeros((3,) + shape)
+    if "u0" in c.extra:
+        u = u + np.asarray(c.extra["u0"], np.float64)[:, None, None, None]
     rho = None
     return rho, u
 

@@ -1,0 +1,42 @@
+"""16-bit population storage (FP16 with a power-of-two scale, BF16) against the
+FP64 oracle.  The bound is reported, not the FP32 1e-5: a 16-bit store rounds
+each population to 2^-11 (FP16) or 2^-8 (BF16) of its value every step.  The
+asserted limits are generous (they catch a broken storage path, not a rounding
+level); the measured errors are printed and recorded in the design notes."""
+import numpy as np
+import pytest
+
+from paper_1406_2211_amd import inputs as I
+from parity import Case, errors, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(storage, scale_log2, steps=100):
+    pos, vel, bonds = I.chains(4, 25, (48, 48, 48), 1.0, 1e-3, 2)
+    return Case(name=f"prec_s{storage}", nx=48, ny=48, nz=48, tau=0.6, steps=steps, collision=1,
+                coupling=1, gamma=2.0, kernel=2, storage=storage, mts=5, u_noise=1e-4, pos=pos,
+                vel=vel, mass=np.ones(len(pos)), bonds=bonds, bond_k=30.0, bond_r0=1.0,
+                f16_scale_log2=scale_log2)
+
+
+@pytest.mark.parametrize("storage,scale,limit", [(2, 20, 5e-3), (3, 0, 5e-2)])
+def test_16bit_storage_error_reported(storage, scale, limit):
+    c = _case(storage, scale)
+    o = run_oracle(c)
+    g = run_gpu(c)
+    e = errors(c, g, o)
+    print(f"[precision] storage={storage} scale=2^{scale}: " +
+          ", ".join(f"{k}={v:.3e}" for k, v in e.items()), flush=True)
+    assert np.all(np.isfinite(g["df"]))
+    assert e["u"] < limit and e["df"] < limit
+
+
+def test_fp16_scale_changes_nothing_but_resolution():
+    """The FP16 scale is a power of two: storing 2^p (f - w rho0) and dividing
+    by 2^p on load is exact apart from the FP16 rounding itself, so two scales
+    that both keep the values in the normal range agree to FP16 resolution."""
+    a = run_gpu(_case(2, 18, steps=20))
+    b = run_gpu(_case(2, 22, steps=20))
+    scale = np.abs(a["u"]).max()
+    assert np.abs(a["u"] - b["u"]).max() < 2e-3 * scale
