@@ -80,6 +80,10 @@ typedef struct lb_params {
   int32_t mts_substeps;  /* 0: Alg. 3 ordering; n > 0: Sec. 6 split with the coupling
                             outside and n velocity-Verlet sub-steps on each side */
   int32_t deterministic; /* reserved, must be 0 */
+  int32_t comoving;      /* 0: store f - w rho0; 1: store f - f^eq(rho0, U_ref) with U_ref
+                            advancing by F_ext/rho0 per step (the mean velocity a uniform body
+                            force gives the fluid); an exact change of variables that keeps
+                            stored values small in 16-bit storage */
 } lb_params;
 
 typedef struct lb_limits {

@@ -113,6 +113,9 @@ bool check_params(const lb_grid* g, const lb_params* p, const lb_limits* lim, st
   if (p->mts_substeps > 0 && p->coupling == LB_COUPLE_IB)
     return err = "multiple time stepping applies to force coupling only", false;
   if (p->deterministic != 0) return err = "deterministic mode is not available", false;
+  if (p->comoving != 0 && p->comoving != 1) return err = "comoving must be 0 or 1", false;
+  if (p->comoving && g->wall_y)
+    return err = "the comoving storage frame needs a periodic box (walls break uniform flow)", false;
   if (lim->max_particles < 0 || lim->max_particles > (1ll << 30) || lim->max_bonds < 0 ||
       lim->max_bonds > (1ll << 29) || lim->max_shells < 0 || lim->max_shell_size < 0)
     return err = "invalid limits", false;
@@ -144,6 +147,7 @@ struct lb_ctx {
   double k_tether = 0;
   double omp = 0, omm = 0;
   float scale = 1.f, inv = 1.f;
+  double uref[3] = {0, 0, 0};  // storage reference velocity of f[cur] (comoving frame)
   std::vector<hipEvent_t> ev;  // timing event pairs
   int32_t ev_used = 0;
   std::string err;
@@ -176,6 +180,7 @@ static SiteArgs site_args(const lb_ctx* c) {
   s.pfy = c->pend * c->p.body_force[1];
   s.pfz = c->pend * c->p.body_force[2];
   s.inv = c->inv;
+  for (int k = 0; k < 3; ++k) s.uref[k] = c->uref[k];
   return s;
 }
 
@@ -345,12 +350,17 @@ static lb_status lattice_pass(lb_ctx* c) {
   a.omm = c->omm;
   a.scale = c->scale;
   a.inv = c->inv;
+  for (int k = 0; k < 3; ++k) {
+    a.uin[k] = c->uref[k];
+    a.uout[k] = c->uref[k] + (c->p.comoving ? c->p.body_force[k] / c->p.rho0 : 0.0);
+  }
   const bool timed = 2 * (size_t)c->ev_used + 1 < c->ev.size();
   if (timed) HIPCHK(c, hipEventRecord(c->ev[2 * c->ev_used], c->st));
   HIPCHK(c, launch_stream_collide(c->p.storage, c->p.collision, a, c->st));
   if (timed) HIPCHK(c, hipEventRecord(c->ev[2 * c->ev_used++ + 1], c->st));
   c->cur = 1 - c->cur;
   c->pend = 1;
+  for (int k = 0; k < 3; ++k) c->uref[k] = a.uout[k];
   return LB_OK;
 }
 
@@ -510,6 +520,7 @@ lb_status lb_init_fluid(lb_ctx* c, const double* d_rho, const double* d_u) {
   HIPCHK(c, hipMemsetAsync(c->L.FB, 0, vb, c->st));
   HIPCHK(c, hipMemsetAsync(c->L.mask, 0, (size_t)c->geo.nz * c->geo.ny * c->geo.wpr * 8, c->st));
   c->pend = 0;
+  c->uref[0] = c->uref[1] = c->uref[2] = 0.0;
   return LB_OK;
 }
 
@@ -791,6 +802,8 @@ static EnsSlot slot_from_ctx(const lb_ctx* c) {
   s.pend = c->pend;
   s.steps_done = 0;
   s.live = 1;
+  s.comoving = c->p.comoving;
+  for (int k = 0; k < 3; ++k) s.uref[k] = c->uref[k];
   return s;
 }
 
@@ -1005,6 +1018,7 @@ lb_status lb_ensemble_query(lb_ensemble* e, int32_t slot, int64_t* steps_done, i
     h.ctx->cur = d.cur;
     h.ctx->pend = d.pend;
     h.ctx->steps = d.steps_done;
+    for (int k = 0; k < 3; ++k) h.ctx->uref[k] = d.uref[k];
     sd = d.steps_done;
   }
   if (steps_done) *steps_done = sd;

@@ -29,6 +29,14 @@ __device__ __forceinline__ R wgt(int i) {
   return WCLASS[i] == 0 ? R(1) / R(3) : (WCLASS[i] == 1 ? R(1) / R(18) : R(1) / R(36));
 }
 
+// Storage reference in the comoving frame: e_i(U) = f^eq_i(rho0, U) - w_i rho0
+// (zero density deviation); stored value = f - w rho0 - e_i(U_ref).
+template <typename R>
+__device__ __forceinline__ R eref(int i, R rho0, R ux, R uy, R uz) {
+  const R cu = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
+  return wgt<R>(i) * rho0 * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * (ux * ux + uy * uy + uz * uz));
+}
+
 // ------------------------------------------------------------------ storage
 template <int S>
 struct Store;
@@ -124,6 +132,10 @@ __device__ __forceinline__ void site_phys(const SiteArgs& a, int x, int y, int z
                                           double& drho, double j[3], bool phys) {
   using St = Store<S>;
   pull<S, double>((const typename St::T*)a.f, a.g, x, y, z, (double)a.inv, fl);
+  if (a.uref[0] != 0.0 || a.uref[1] != 0.0 || a.uref[2] != 0.0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fl[i] += eref<double>(i, a.rho0, a.uref[0], a.uref[1], a.uref[2]);
+  }
   drho = 0;
   j[0] = j[1] = j[2] = 0;
 #pragma unroll
@@ -166,9 +178,13 @@ __device__ __forceinline__ void relax_store(const typename Store<S>::R f[Q],
                                             typename Store<S>::R Fz, int collision,
                                             typename Store<S>::R omp, typename Store<S>::R omm,
                                             typename Store<S>::R sc, typename Store<S>::T* fo,
-                                            size_t N, size_t own) {
+                                            size_t N, size_t own, typename Store<S>::R rho0 = 0,
+                                            typename Store<S>::R ox = 0,
+                                            typename Store<S>::R oy = 0,
+                                            typename Store<S>::R oz = 0) {
   using St = Store<S>;
   using R = typename St::R;
+  // (ox, oy, oz): storage reference velocity of the output (comoving frame)
   const R ux = jx * ir, uy = jy * ir, uz = jz * ir;  // post-stream velocity
   const R hx = ux + R(0.5) * Fx * ir, hy = uy + R(0.5) * Fy * ir,
           hz = uz + R(0.5) * Fz * ir;  // after both half forces
@@ -178,13 +194,13 @@ __device__ __forceinline__ void relax_store(const typename Store<S>::R f[Q],
     for (int i = 0; i < Q; ++i) {
       const R eb = feq_dev<R>(i, drho, rho, ux, uy, uz, usq);
       const R ep = feq_dev<R>(i, drho, rho, hx, hy, hz, hsq);
-      St::st(fo + (size_t)i * N + own, ep + omp * (f[i] - eb), sc);
+      St::st(fo + (size_t)i * N + own, ep + omp * (f[i] - eb) - eref<R>(i, rho0, ox, oy, oz), sc);
     }
   } else {
     {
       const R w0 = wgt<R>(0);
       const R eb = w0 * (drho - R(1.5) * rho * usq), ep = w0 * (drho - R(1.5) * rho * hsq);
-      St::st(fo + own, ep + omp * (f[0] - eb), sc);
+      St::st(fo + own, ep + omp * (f[0] - eb) - eref<R>(0, rho0, ox, oy, oz), sc);
     }
 #pragma unroll
     for (int i = 1; i < Q; i += 2) {
@@ -195,8 +211,10 @@ __device__ __forceinline__ void relax_store(const typename Store<S>::R f[Q],
       const R Eh = w * (drho + rho * (R(4.5) * ch * ch - R(1.5) * hsq)), Oh = w * rho * R(3) * ch;
       const R ni = f[i] - (Eb + Ob), nj = f[i + 1] - (Eb - Ob);
       const R sym = R(0.5) * (ni + nj), anti = R(0.5) * (ni - nj);
-      St::st(fo + (size_t)i * N + own, Eh + Oh + omp * sym + omm * anti, sc);
-      St::st(fo + (size_t)(i + 1) * N + own, Eh - Oh + omp * sym - omm * anti, sc);
+      St::st(fo + (size_t)i * N + own,
+             Eh + Oh + omp * sym + omm * anti - eref<R>(i, rho0, ox, oy, oz), sc);
+      St::st(fo + (size_t)(i + 1) * N + own,
+             Eh - Oh + omp * sym - omm * anti - eref<R>(i + 1, rho0, ox, oy, oz), sc);
     }
   }
 }

@@ -29,6 +29,8 @@ struct LatArgs {
   double Fx, Fy, Fz;  // body force times the number of pending halves (1 or 2)
   double omp, omm;    // 1 - lambda for even / odd non-conserved moments
   float scale, inv;   // 16-bit storage scale 2^p and its inverse (1 otherwise)
+  double uin[3];      // storage reference velocity of fin (comoving frame; 0 otherwise)
+  double uout[3];     // storage reference velocity of fout
 };
 
 struct InitArgs {
@@ -48,6 +50,7 @@ struct SiteArgs {
   double rho0;
   double pfx, pfy, pfz;  // pending body force (0 before the first step, F_ext after)
   float inv;
+  double uref[3];  // storage reference velocity of f (comoving frame; 0 otherwise)
 };
 
 struct PartArgs {
@@ -136,6 +139,8 @@ struct EnsSlot {
   int cur, pend;
   long long steps_done, steps_target;
   int live;
+  int comoving;
+  double uref[3];  // storage reference velocity of f[cur]
 };
 
 struct EnsArgs {

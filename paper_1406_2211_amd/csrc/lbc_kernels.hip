@@ -57,6 +57,11 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
     }
     f[i] = St::ld(base + off, (R)a.inv);
   }
+  const R rho0 = R(a.rho0);
+  if (a.uin[0] != 0.0 || a.uin[1] != 0.0 || a.uin[2] != 0.0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] += eref<R>(i, rho0, R(a.uin[0]), R(a.uin[1]), R(a.uin[2]));
+  }
   R drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -84,7 +89,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
     if ((x & 63) == 0) *(uint64_t*)mp = 0;
   }
   relax_store<S>(f, drho, rho, ir, jx, jy, jz, Fx, Fy, Fz, COL, R(a.omp), R(a.omm), R(a.scale),
-                 (T*)a.fout, N, own);
+                 (T*)a.fout, N, own, rho0, R(a.uout[0]), R(a.uout[1]), R(a.uout[2]));
 }
 
 // ======================================================================
@@ -831,6 +836,11 @@ __global__ __launch_bounds__(256) void k_ens_lattice(EnsArgs e) {
       const size_t src = ((size_t)zs[1 - CZ[i]] * ny + ys[1 - CY[i]]) * nx + xs[1 - CX[i]];
       f[i] = St::ld(fin + (size_t)i * N + src, (R)sl.inv);
     }
+    const R ux0 = R(sl.uref[0]), uy0 = R(sl.uref[1]), uz0 = R(sl.uref[2]);
+    if (sl.comoving) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] += eref<R>(i, R(sl.rho0), ux0, uy0, uz0);
+    }
     R drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -857,8 +867,10 @@ __global__ __launch_bounds__(256) void k_ens_lattice(EnsArgs e) {
       }
       if ((s & 63) == 0) *mp = 0;
     }
+    const R cm = R(sl.comoving) / R(sl.rho0);
     relax_store<S>(f, drho, rho, ir, jx, jy, jz, Fx, Fy, Fz, sl.collision, R(sl.omp), R(sl.omm),
-                   R(sl.scale), (T*)sl.f[1 - sl.cur], N, (size_t)s);
+                   R(sl.scale), (T*)sl.f[1 - sl.cur], N, (size_t)s, R(sl.rho0),
+                   ux0 + cm * R(sl.fx), uy0 + cm * R(sl.fy), uz0 + cm * R(sl.fz));
   }
 }
 
@@ -885,6 +897,10 @@ __global__ __launch_bounds__(256) void k_ens_couple(EnsArgs e, int half) {
     a.s.pfy = sl.pend * sl.fy;
     a.s.pfz = sl.pend * sl.fz;
     a.s.inv = sl.inv;
+    for (int k = 0; k < 3; ++k) {  // reference of the buffer read (the new one in half 1)
+      const double fk = k == 0 ? sl.fx : (k == 1 ? sl.fy : sl.fz);
+      a.s.uref[k] = sl.comoving ? sl.uref[k] + (half == 1 ? fk / sl.rho0 : 0.0) : 0.0;
+    }
     a.FA = sl.FA;
     a.FB = sl.FB;
     a.mask = sl.mask;
@@ -941,6 +957,11 @@ __global__ void k_ens_advance(EnsArgs e) {
   sl.cur = 1 - sl.cur;
   sl.pend = 1;
   sl.steps_done += 1;
+  if (sl.comoving) {
+    sl.uref[0] += sl.fx / sl.rho0;
+    sl.uref[1] += sl.fy / sl.rho0;
+    sl.uref[2] += sl.fz / sl.rho0;
+  }
 }
 
 hipError_t launch_ens_step(int storage, int K, const EnsArgs& e, int lat_grid, int part_grid,

@@ -80,7 +80,8 @@ def make_gpu(c: Case):
     lat = L.Lattice(c.nx, c.ny, c.nz, wall_y=c.wall_y, max_particles=n, max_bonds=nb,
                     max_shells=c.nshell, max_shell_size=ms, tau=c.tau, body_force=c.fext,
                     collision=c.collision, coupling=c.coupling, gamma=c.gamma, kernel=c.kernel,
-                    storage=c.storage, mts_substeps=c.mts, f16_scale_log2=c.f16_scale_log2)
+                    storage=c.storage, mts_substeps=c.mts, f16_scale_log2=c.f16_scale_log2,
+                    comoving=c.extra.get("comoving", 0))
     rho, u = initial_fields(c)
     lat.lb_init_fluid(None if rho is None else torch.from_numpy(rho),
                       None if u is None else torch.from_numpy(np.ascontiguousarray(u)))

@@ -4,6 +4,8 @@ configurations before anything touches a device."""
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from paper_1406_2211_amd import lbc as L
@@ -91,3 +93,16 @@ def test_status_strings():
     lib = L.load()
     for s in range(6):
         assert lib.lb_status_string(s)
+
+
+def test_serving_request_generator_ranges():
+    from paper_1406_2211_amd import inputs as I
+    reqs = I.serving_requests(256, 10.0, seed=5)
+    sides = np.array([r.side for r in reqs])
+    nps = np.array([r.nparticles for r in reqs])
+    assert sides.min() >= 32 and sides.max() <= 160
+    assert nps.min() >= 10 and nps.max() <= 5000
+    assert all(0.55 <= r.tau <= 1.0 and 0 <= r.fext <= 1e-5 and 200 <= r.steps <= 2000 for r in reqs)
+    arr = np.array([r.arrival for r in reqs])
+    assert np.all(np.diff(arr) > 0)
+    assert 15.0 < arr[-1] < 40.0  # 256 arrivals at 10/s

@@ -40,3 +40,35 @@ def test_fp16_scale_changes_nothing_but_resolution():
     b = run_gpu(_case(2, 22, steps=20))
     scale = np.abs(a["u"]).max()
     assert np.abs(a["u"] - b["u"]).max() < 2e-3 * scale
+
+
+def _forced_case(storage, scale_log2, steps=400, comoving=0):
+    c = Case(name=f"forced_s{storage}_c{comoving}", nx=24, ny=24, nz=24, tau=0.7, steps=steps,
+             fext=(1e-5, 0.0, 0.0), storage=storage, u_noise=1e-4, seed=4,
+             f16_scale_log2=scale_log2)
+    c.extra["comoving"] = comoving
+    return c
+
+
+def test_comoving_frame_is_exact_in_fp64():
+    """Storing f - f^eq(rho0, U_ref) with U_ref following the body force is a
+    change of variables: FP64 results match the oracle at 1e-12."""
+    from parity import compare
+    pos = I.uniform_positions(2, (24, 24, 24), 9)
+    c = _forced_case(0, 0, steps=150, comoving=1)
+    c.coupling, c.gamma, c.pos = 1, 1.1, pos
+    c.vel, c.mass = np.full((2, 3), 2e-3), np.ones(2)
+    compare(c, run_gpu(c), run_oracle(c), 1e-12)
+
+
+def test_comoving_frame_keeps_fp16_increments():
+    """A uniform body force drives the whole box; in the rest frame the stored
+    FP16 values grow with the flow until the per-step force increment is a few
+    ulps and rounds away.  In the comoving frame only the fluctuations are
+    stored and the error drops by more than an order of magnitude."""
+    o = run_oracle(_forced_case(0, 0))
+    e_rest = errors(_forced_case(2, 22), run_gpu(_forced_case(2, 22)), o)["u"]
+    e_com = errors(_forced_case(2, 26), run_gpu(_forced_case(2, 26, comoving=1)), o)["u"]
+    print(f"[precision] forced uniform flow, FP16: rest frame u err {e_rest:.3e}, "
+          f"comoving frame {e_com:.3e}", flush=True)
+    assert e_com < e_rest / 10
