@@ -356,7 +356,7 @@ static lb_status lattice_pass(lb_ctx* c) {
   }
   const bool timed = 2 * (size_t)c->ev_used + 1 < c->ev.size();
   if (timed) HIPCHK(c, hipEventRecord(c->ev[2 * c->ev_used], c->st));
-  HIPCHK(c, launch_stream_collide(c->p.storage, c->p.collision, a, c->st));
+  HIPCHK(c, launch_stream_collide(c->p.storage, c->p.comoving != 0, a, c->st));
   if (timed) HIPCHK(c, hipEventRecord(c->ev[2 * c->ev_used++ + 1], c->st));
   c->cur = 1 - c->cur;
   c->pend = 1;
@@ -741,7 +741,8 @@ struct lb_ensemble {
   std::vector<EnsHost> slots;
   std::vector<std::pair<size_t, size_t>> used;  // (offset, bytes), sorted
   bool dirty = true;
-  int lat_grid = 1024, part_grid = 512;
+  int cus = 256;
+  int lat_grid = 2048, part_grid = 512;
   hipGraphExec_t exec[2] = {nullptr, nullptr};  // kGraphSteps steps, one step
   bool graphs_ok = false;
   std::string err;
@@ -778,6 +779,8 @@ static EnsArgs ens_args(const lb_ensemble* e) {
 static EnsSlot slot_from_ctx(const lb_ctx* c) {
   EnsSlot s{};
   s.g = c->geo;
+  s.rnx = 1.0 / c->geo.nx;
+  s.rny = 1.0 / c->geo.ny;
   s.f[0] = c->L.f[0];
   s.f[1] = c->L.f[1];
   s.FA = c->L.FA;
@@ -927,6 +930,17 @@ lb_status lb_ensemble_create(void* d_pool, size_t bytes, int32_t max_slots, int3
     return efail(nullptr, LB_ENOMEM, "pool too small for the ensemble tables");
   }
   e->slots.resize(max_slots);
+  {
+    // default persistent grids: eight resident 256-lane blocks per CU (eight
+    // waves per SIMD) for the lattice, two per CU for the particles
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+      e->cus = prop.multiProcessorCount;
+      e->lat_grid = 8 * e->cus;
+      e->part_grid = 2 * e->cus;
+    }
+  }
   hipError_t r = hipStreamCreate(&e->st);
   if (r != hipSuccess) {
     delete e;
@@ -1048,15 +1062,9 @@ lb_status lb_ensemble_autotune(lb_ensemble* e, int32_t steps_per_candidate, int3
   if (steps_per_candidate < 1) return efail(e, LB_EINVAL, "need at least one step per candidate");
   lb_status s;
   if (e->dirty && (s = ens_refresh(e)) != LB_OK) return s;
-  int cus = 256;
-  {
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-      cus = prop.multiProcessorCount;
-  }
-  const int lat_c[] = {cus * 2, cus * 4, cus * 8, cus * 16};
-  const int part_c[] = {cus, cus * 4};
+  const int cus = e->cus;
+  const int lat_c[] = {cus * 4, cus * 8, cus * 16};
+  const int part_c[] = {cus, cus * 2, cus * 4};
   hipEvent_t t0, t1;
   EHIPCHK(e, hipEventCreate(&t0));
   EHIPCHK(e, hipEventCreate(&t1));

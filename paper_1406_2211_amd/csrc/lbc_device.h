@@ -46,8 +46,10 @@ struct Store<LB_F64> {
   using R = double;
   using V4 = double4;
   static __device__ __forceinline__ R ld(const T* p, R) { return *p; }
+  static __device__ __forceinline__ R raw(const T* p) { return *p; }
   // populations are written once per pass and not re-read by it: non-temporal
   static __device__ __forceinline__ void st(T* p, R v, R) { __builtin_nontemporal_store(v, p); }
+  static __device__ __forceinline__ void st_raw(T* p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Store<LB_F32> {
@@ -55,7 +57,9 @@ struct Store<LB_F32> {
   using R = float;
   using V4 = float4;
   static __device__ __forceinline__ R ld(const T* p, R) { return *p; }
+  static __device__ __forceinline__ R raw(const T* p) { return *p; }
   static __device__ __forceinline__ void st(T* p, R v, R) { __builtin_nontemporal_store(v, p); }
+  static __device__ __forceinline__ void st_raw(T* p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Store<LB_F16> {
@@ -64,8 +68,10 @@ struct Store<LB_F16> {
   using V4 = float4;
   // stored value is scale * (f - w rho0); inv is 1/scale (a power of two)
   static __device__ __forceinline__ R ld(const T* p, R inv) { return __half2float(*p) * inv; }
-  static __device__ __forceinline__ void st(T* p, R v, R scale) {
-    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v * scale)), (unsigned short*)p);
+  static __device__ __forceinline__ R raw(const T* p) { return __half2float(*p); }
+  static __device__ __forceinline__ void st(T* p, R v, R scale) { st_raw(p, v * scale); }
+  static __device__ __forceinline__ void st_raw(T* p, R v) {
+    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)), (unsigned short*)p);
   }
 };
 template <>
@@ -74,8 +80,10 @@ struct Store<LB_BF16> {
   using R = float;
   using V4 = float4;
   static __device__ __forceinline__ R ld(const T* p, R inv) { return __bfloat162float(*p) * inv; }
-  static __device__ __forceinline__ void st(T* p, R v, R scale) {
-    const __hip_bfloat16 b = __float2bfloat16(v * scale);
+  static __device__ __forceinline__ R raw(const T* p) { return __bfloat162float(*p); }
+  static __device__ __forceinline__ void st(T* p, R v, R scale) { st_raw(p, v * scale); }
+  static __device__ __forceinline__ void st_raw(T* p, R v) {
+    const __hip_bfloat16 b = __float2bfloat16(v);
     __builtin_nontemporal_store(*(const unsigned short*)&b, (unsigned short*)p);
   }
 };
@@ -97,6 +105,23 @@ __device__ __forceinline__ uint64_t* mask_word(uint64_t* m, const Geo& g, int x,
   }
   bit = 1ull << (x & 63);
   return m + ((long long)z * g.ny + y) * g.wpr + (x >> 6);
+}
+
+// Quotient and remainder of n / d for 32-bit n and d >= 1, with rd = 1/d
+// (double, rounded) from the host: n * rd is within 1e-6 of n / d, so its
+// truncation is the quotient or one off, and one correction step fixes it.
+__device__ __forceinline__ uint32_t div_rem(uint32_t n, uint32_t d, double rd, uint32_t& rem) {
+  uint32_t q = (uint32_t)((double)n * rd);
+  long long r = (long long)n - (long long)q * d;
+  if (r < 0) {
+    q -= 1;
+    r += d;
+  } else if (r >= (long long)d) {
+    q += 1;
+    r -= d;
+  }
+  rem = (uint32_t)r;
+  return q;
 }
 
 // Pull gather: fbar_i(x) = f*_i(x - c_i), periodic, or the reflected opposite
@@ -163,59 +188,95 @@ __device__ __forceinline__ R feq_dev(int i, R drho, R rho, R ux, R uy, R uz, R u
   return wgt<R>(i) * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq));
 }
 
-// Both pending half forces as one equilibrium shift and the collision, then
-// the store (the fused-pass arithmetic shared by the single-box and the
-// batched passes).  f: post-stream populations; (drho, j): their moments;
-// F: total pending force (both halves).  BGK: f* = f^eq(u') + (1 - l)(f -
-// f^eq(u)); two-rate: (1 - l+) on the even and (1 - l-) on the odd part of
-// f - f^eq(u) over the opposite pairs (1,2), (3,4), ...
-template <int S>
-__device__ __forceinline__ void relax_store(const typename Store<S>::R f[Q],
-                                            typename Store<S>::R drho, typename Store<S>::R rho,
-                                            typename Store<S>::R ir, typename Store<S>::R jx,
-                                            typename Store<S>::R jy, typename Store<S>::R jz,
-                                            typename Store<S>::R Fx, typename Store<S>::R Fy,
-                                            typename Store<S>::R Fz, int collision,
-                                            typename Store<S>::R omp, typename Store<S>::R omm,
-                                            typename Store<S>::R sc, typename Store<S>::T* fo,
-                                            size_t N, size_t own, typename Store<S>::R rho0 = 0,
-                                            typename Store<S>::R ox = 0,
-                                            typename Store<S>::R oy = 0,
-                                            typename Store<S>::R oz = 0) {
+// Constants of one fused lattice pass in the compute type.  Storage units:
+// the stored value of population i is S (f_i - w_i rho0 - e_i(U)), with S the
+// 16-bit scale (1 otherwise) and e_i(U) the comoving reference of the buffer
+// (zero unless the comoving frame is on).
+template <typename R>
+struct PassK {
+  R rho0, sc, inv;  // rho0, S, 1/S
+  R hp, hm;         // (1 - lambda+)/2 and (1 - lambda-)/2
+  R ui[3], uo[3];   // reference velocities of the input and output buffers
+};
+
+// One site of the fused pass: both pending half forces as one equilibrium
+// shift, then the collision, then the store.  f: the pulled (post-stream)
+// populations in storage units; F: the total pending force (both halves).
+//   f*_i = f^eq_i(rho, u + F/2rho) + (1 - lambda+) (f - f^eq(rho, u))^even_i
+//                                  + (1 - lambda-) (f - f^eq(rho, u))^odd_i
+// with even/odd parts taken over the opposite pairs (1,2), (3,4), ...; BGK is
+// the case lambda- = lambda+.  All equilibria are formed directly in storage
+// units, split into the parts even and odd in c: with A = w S drho,
+// B = w S rho, B0 = w S rho0,
+//   even: A + B (9/2 (c.u)^2 - 3/2 u.u) - B0 (9/2 (c.U)^2 - 3/2 U.U)
+//   odd:  3 B (c.u) - 3 B0 (c.U)
+// so neither the loads nor the stores need the scale.
+template <int S, bool CM>
+__device__ __forceinline__ void fused_site(const typename Store<S>::R f[Q], typename Store<S>::R Fx,
+                                           typename Store<S>::R Fy, typename Store<S>::R Fz,
+                                           const PassK<typename Store<S>::R>& k,
+                                           typename Store<S>::T* __restrict__ fo, size_t N,
+                                           size_t own) {
   using St = Store<S>;
   using R = typename St::R;
-  // (ox, oy, oz): storage reference velocity of the output (comoving frame)
-  const R ux = jx * ir, uy = jy * ir, uz = jz * ir;  // post-stream velocity
-  const R hx = ux + R(0.5) * Fx * ir, hy = uy + R(0.5) * Fy * ir,
-          hz = uz + R(0.5) * Fz * ir;  // after both half forces
+  R d = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    d += f[i];
+    if (CX[i]) jx += R(CX[i]) * f[i];
+    if (CY[i]) jy += R(CY[i]) * f[i];
+    if (CZ[i]) jz += R(CZ[i]) * f[i];
+  }
+  const R rho = k.rho0 + d * k.inv;  // the references carry no density
+  const R ir = R(1) / rho;
+  const R js = k.inv * ir;
+  R ux = jx * js, uy = jy * js, uz = jz * js;
+  if (CM) {  // sum_i c_i e_i(U) = rho0 U
+    const R r0 = k.rho0 * ir;
+    ux += r0 * k.ui[0];
+    uy += r0 * k.ui[1];
+    uz += r0 * k.ui[2];
+  }
+  const R hf = R(0.5) * ir;
+  const R hx = ux + hf * Fx, hy = uy + hf * Fy, hz = uz + hf * Fz;
   const R usq = ux * ux + uy * uy + uz * uz, hsq = hx * hx + hy * hy + hz * hz;
-  if (collision == LB_BGK) {
+  const R rs = rho * k.sc;
+  R isq = 0, osq = 0, r0s = 0;
+  if (CM) {
+    isq = k.ui[0] * k.ui[0] + k.ui[1] * k.ui[1] + k.ui[2] * k.ui[2];
+    osq = k.uo[0] * k.uo[0] + k.uo[1] * k.uo[1] + k.uo[2] * k.uo[2];
+    r0s = k.rho0 * k.sc;
+  }
+  {
+    const R w = wgt<R>(0);
+    R eb = w * (d - R(1.5) * rs * usq), eh = w * (d - R(1.5) * rs * hsq);
+    if (CM) {
+      eb += w * R(1.5) * r0s * isq;
+      eh += w * R(1.5) * r0s * osq;
+    }
+    St::st_raw(fo + own, eh + R(2) * k.hp * (f[0] - eb));
+  }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const R eb = feq_dev<R>(i, drho, rho, ux, uy, uz, usq);
-      const R ep = feq_dev<R>(i, drho, rho, hx, hy, hz, hsq);
-      St::st(fo + (size_t)i * N + own, ep + omp * (f[i] - eb) - eref<R>(i, rho0, ox, oy, oz), sc);
+  for (int i = 1; i < Q; i += 2) {
+    const R w = wgt<R>(i);
+    const R A = w * d, B = w * rs;
+    const R cb = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
+    const R ch = R(CX[i]) * hx + R(CY[i]) * hy + R(CZ[i]) * hz;
+    R Eb = A + B * (R(4.5) * cb * cb - R(1.5) * usq), Ob = R(3) * B * cb;
+    R Eh = A + B * (R(4.5) * ch * ch - R(1.5) * hsq), Oh = R(3) * B * ch;
+    if (CM) {
+      const R B0 = w * r0s;
+      const R ci = R(CX[i]) * k.ui[0] + R(CY[i]) * k.ui[1] + R(CZ[i]) * k.ui[2];
+      const R co = R(CX[i]) * k.uo[0] + R(CY[i]) * k.uo[1] + R(CZ[i]) * k.uo[2];
+      Eb -= B0 * (R(4.5) * ci * ci - R(1.5) * isq);
+      Ob -= R(3) * B0 * ci;
+      Eh -= B0 * (R(4.5) * co * co - R(1.5) * osq);
+      Oh -= R(3) * B0 * co;
     }
-  } else {
-    {
-      const R w0 = wgt<R>(0);
-      const R eb = w0 * (drho - R(1.5) * rho * usq), ep = w0 * (drho - R(1.5) * rho * hsq);
-      St::st(fo + own, ep + omp * (f[0] - eb) - eref<R>(0, rho0, ox, oy, oz), sc);
-    }
-#pragma unroll
-    for (int i = 1; i < Q; i += 2) {
-      const R w = wgt<R>(i);
-      const R cb = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
-      const R ch = R(CX[i]) * hx + R(CY[i]) * hy + R(CZ[i]) * hz;
-      const R Eb = w * (drho + rho * (R(4.5) * cb * cb - R(1.5) * usq)), Ob = w * rho * R(3) * cb;
-      const R Eh = w * (drho + rho * (R(4.5) * ch * ch - R(1.5) * hsq)), Oh = w * rho * R(3) * ch;
-      const R ni = f[i] - (Eb + Ob), nj = f[i + 1] - (Eb - Ob);
-      const R sym = R(0.5) * (ni + nj), anti = R(0.5) * (ni - nj);
-      St::st(fo + (size_t)i * N + own,
-             Eh + Oh + omp * sym + omm * anti - eref<R>(i, rho0, ox, oy, oz), sc);
-      St::st(fo + (size_t)(i + 1) * N + own,
-             Eh - Oh + omp * sym - omm * anti - eref<R>(i + 1, rho0, ox, oy, oz), sc);
-    }
+    const R ni = f[i] - Eb - Ob, nj = f[i + 1] - Eb + Ob;
+    const R sym = k.hp * (ni + nj), anti = k.hm * (ni - nj);
+    St::st_raw(fo + (size_t)i * N + own, Eh + Oh + sym + anti);
+    St::st_raw(fo + (size_t)(i + 1) * N + own, Eh - Oh + sym - anti);
   }
 }
 

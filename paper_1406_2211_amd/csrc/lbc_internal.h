@@ -124,6 +124,7 @@ hipError_t launch_tile_spread(int storage, int K, const TileArgs& t, const doubl
 // fields cur, pend and steps_done are advanced on the device only.
 struct EnsSlot {
   Geo g;  // wpr == 0: linear force mask
+  double rnx, rny;  // 1/nx, 1/ny for the site decomposition
   void* f[2];
   void* FA;
   void* FB;
@@ -155,7 +156,7 @@ struct EnsArgs {
 hipError_t launch_ens_step(int storage, int K, const EnsArgs& e, int lat_grid, int part_grid,
                            hipStream_t st);
 
-hipError_t launch_stream_collide(int storage, int collision, const LatArgs& a, hipStream_t st);
+hipError_t launch_stream_collide(int storage, bool comoving, const LatArgs& a, hipStream_t st);
 hipError_t launch_init(int storage, const InitArgs& a, hipStream_t st);
 hipError_t launch_moments(int storage, const SiteArgs& a, double* rho, double* u, hipStream_t st);
 hipError_t launch_populations(int storage, const SiteArgs& a, double* out, hipStream_t st);

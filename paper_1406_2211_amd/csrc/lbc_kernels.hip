@@ -26,7 +26,7 @@ namespace lbc {
 // the per-population base pointers; each work-item adds a 32-bit site offset.
 // All 19 loads are issued before any arithmetic.  With y walls the
 // bounce-back choice is also block-uniform (it depends on y only).
-template <int S, int COL, bool WALL>
+template <int S, bool CM, bool WALL>
 __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
   using St = Store<S>;
   using T = typename St::T;
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
   const uint32_t own = (z * ny + y) * nx + x;
   const size_t N = (size_t)a.g.N;
   const T* __restrict__ fin = (const T*)a.fin;
-  const uint64_t* mp = a.mask + ((size_t)z * ny + y) * a.g.wpr + (x >> 6);
+  uint64_t* mp = a.mask + ((size_t)z * ny + y) * a.g.wpr + (x >> 6);
   const uint64_t word = *mp;
   R f[Q];
 #pragma unroll
@@ -55,23 +55,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
       base = fin + (size_t)OPP[i] * N;  // halfway bounce-back: opposite population, same site
       off = own;
     }
-    f[i] = St::ld(base + off, (R)a.inv);
+    f[i] = St::raw(base + off);
   }
-  const R rho0 = R(a.rho0);
-  if (a.uin[0] != 0.0 || a.uin[1] != 0.0 || a.uin[2] != 0.0) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] += eref<R>(i, rho0, R(a.uin[0]), R(a.uin[1]), R(a.uin[2]));
-  }
-  R drho = 0, jx = 0, jy = 0, jz = 0;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    drho += f[i];
-    jx += R(CX[i]) * f[i];
-    jy += R(CY[i]) * f[i];
-    jz += R(CZ[i]) * f[i];
-  }
-  const R rho = R(a.rho0) + drho;
-  const R ir = R(1) / rho;
   R Fx = R(a.Fx), Fy = R(a.Fy), Fz = R(a.Fz);
   if (word) {
     if ((word >> (x & 63)) & 1ull) {
@@ -86,10 +71,19 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
       FA[own] = zero;
       FB[own] = zero;
     }
-    if ((x & 63) == 0) *(uint64_t*)mp = 0;
+    if ((x & 63) == 0) *mp = 0;
   }
-  relax_store<S>(f, drho, rho, ir, jx, jy, jz, Fx, Fy, Fz, COL, R(a.omp), R(a.omm), R(a.scale),
-                 (T*)a.fout, N, own, rho0, R(a.uout[0]), R(a.uout[1]), R(a.uout[2]));
+  PassK<R> k;
+  k.rho0 = R(a.rho0);
+  k.sc = R(a.scale);
+  k.inv = R(a.inv);
+  k.hp = R(0.5) * R(a.omp);
+  k.hm = R(0.5) * R(a.omm);
+  for (int c = 0; c < 3; ++c) {
+    k.ui[c] = R(a.uin[c]);
+    k.uo[c] = R(a.uout[c]);
+  }
+  fused_site<S, CM>(f, Fx, Fy, Fz, k, (T*)a.fout, N, own);
 }
 
 // ======================================================================
@@ -685,19 +679,22 @@ static dim3 lattice_grid(const Geo& g, dim3 b) {
     default: { constexpr int SS = LB_BF16; CALL; } break;           \
   }
 
-template <int COL, bool WALL>
+template <bool CM, bool WALL>
 static void launch_sc(int storage, const LatArgs& a, dim3 gr, dim3 b, hipStream_t st) {
-  LBC_STORAGE_SWITCH(storage, (k_stream_collide<SS, COL, WALL><<<gr, b, 0, st>>>(a)));
+  LBC_STORAGE_SWITCH(storage, (k_stream_collide<SS, CM, WALL><<<gr, b, 0, st>>>(a)));
 }
 
-hipError_t launch_stream_collide(int storage, int collision, const LatArgs& a, hipStream_t st) {
+// BGK and the two-rate collision share one kernel (BGK: equal rates); the
+// comoving storage frame is a compile-time switch so that the rest frame
+// carries none of its arithmetic.
+hipError_t launch_stream_collide(int storage, bool comoving, const LatArgs& a, hipStream_t st) {
   const dim3 b = lattice_block(a.g), gr = lattice_grid(a.g, b);
-  if (collision == LB_BGK) {
-    if (a.g.wall) launch_sc<LB_BGK, true>(storage, a, gr, b, st);
-    else launch_sc<LB_BGK, false>(storage, a, gr, b, st);
+  if (comoving) {
+    if (a.g.wall) launch_sc<true, true>(storage, a, gr, b, st);
+    else launch_sc<true, false>(storage, a, gr, b, st);
   } else {
-    if (a.g.wall) launch_sc<LB_TRT, true>(storage, a, gr, b, st);
-    else launch_sc<LB_TRT, false>(storage, a, gr, b, st);
+    if (a.g.wall) launch_sc<false, true>(storage, a, gr, b, st);
+    else launch_sc<false, false>(storage, a, gr, b, st);
   }
   return hipGetLastError();
 }
@@ -806,71 +803,81 @@ __device__ __forceinline__ bool ens_active(const EnsSlot& s) {
   return s.live && s.steps_done < s.steps_target;
 }
 
-template <int S>
-__global__ __launch_bounds__(256) void k_ens_lattice(EnsArgs e) {
+// The slot table is read-only during the lattice pass (only k_ens_advance
+// writes it); with restrict-qualified arguments its fields are loaded into
+// scalar registers once per work item.
+template <int S, bool CM>
+__device__ __forceinline__ void ens_lattice_item(const EnsSlot& sl, uint32_t chunk) {
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
   using V4 = typename St::V4;
-  const int n = *e.nlitems;
+  const uint32_t N = (uint32_t)sl.g.N;
+  const uint32_t s = chunk * 256u + threadIdx.x;
+  if (s >= N) return;
+  const uint32_t nx = (uint32_t)sl.g.nx, ny = (uint32_t)sl.g.ny, nz = (uint32_t)sl.g.nz;
+  uint32_t x, y;
+  const uint32_t r = div_rem(s, nx, sl.rnx, x);
+  const uint32_t z = div_rem(r, ny, sl.rny, y);
+  const uint32_t xs[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
+  const uint32_t ys[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
+  const uint32_t zr[3] = {(z == 0 ? nz - 1 : z - 1) * ny, z * ny, (z == nz - 1 ? 0 : z + 1) * ny};
+  const T* __restrict__ fin = (const T*)sl.f[sl.cur];
+  uint64_t* mp = sl.mask + (s >> 6);
+  const uint64_t word = *mp;
+  R f[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const uint32_t src = (zr[1 - CZ[i]] + ys[1 - CY[i]]) * nx + xs[1 - CX[i]];
+    f[i] = St::raw(fin + (size_t)i * N + src);
+  }
+  const R fac = R(1 + sl.pend);
+  R Fx = fac * R(sl.fx), Fy = fac * R(sl.fy), Fz = fac * R(sl.fz);
+  if (word) {  // a 64-aligned group of 64 lanes owns this mask word
+    if ((word >> (s & 63)) & 1ull) {
+      V4* FA = (V4*)sl.FA;
+      V4* FB = (V4*)sl.FB;
+      const V4 fa = FA[s], fb = FB[s];
+      Fx += fa.x + fb.x;
+      Fy += fa.y + fb.y;
+      Fz += fa.z + fb.z;
+      V4 zero;
+      zero.x = zero.y = zero.z = zero.w = 0;
+      FA[s] = zero;
+      FB[s] = zero;
+    }
+    if ((s & 63) == 0) *mp = 0;
+  }
+  PassK<R> k;
+  k.rho0 = R(sl.rho0);
+  k.sc = R(sl.scale);
+  k.inv = R(sl.inv);
+  k.hp = R(0.5) * R(sl.omp);
+  k.hm = R(0.5) * R(sl.omm);
+  if (CM) {
+    k.ui[0] = R(sl.uref[0]);
+    k.ui[1] = R(sl.uref[1]);
+    k.ui[2] = R(sl.uref[2]);
+    k.uo[0] = R(sl.uref[0] + sl.fx / sl.rho0);
+    k.uo[1] = R(sl.uref[1] + sl.fy / sl.rho0);
+    k.uo[2] = R(sl.uref[2] + sl.fz / sl.rho0);
+  }
+  fused_site<S, CM>(f, Fx, Fy, Fz, k, (T*)sl.f[1 - sl.cur], N, s);
+}
+
+template <int S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == LB_F64 ? 4 : 8))) void k_ens_lattice(const EnsSlot* __restrict__ slots,
+                                                     const int2* __restrict__ items,
+                                                     const int* __restrict__ nitems) {
+  const int n = *nitems;
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
-    const int2 w = e.litems[it];
-    const EnsSlot& sl = e.slots[w.x];
+    const int2 w = items[it];
+    const EnsSlot& sl = slots[w.x];
     if (!ens_active(sl)) continue;
-    const long long s = (long long)w.y * 256 + threadIdx.x;
-    const size_t N = (size_t)sl.g.N;
-    if (s >= (long long)N) continue;
-    const int nx = sl.g.nx, ny = sl.g.ny, nz = sl.g.nz;
-    const int x = (int)(s % nx);
-    const long long r = s / nx;
-    const int y = (int)(r % ny), z = (int)(r / ny);
-    const int xs[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
-    const int ys[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
-    const int zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
-    const T* fin = (const T*)sl.f[sl.cur];
-    uint64_t* mp = sl.mask + (s >> 6);
-    const uint64_t word = *mp;
-    R f[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const size_t src = ((size_t)zs[1 - CZ[i]] * ny + ys[1 - CY[i]]) * nx + xs[1 - CX[i]];
-      f[i] = St::ld(fin + (size_t)i * N + src, (R)sl.inv);
-    }
-    const R ux0 = R(sl.uref[0]), uy0 = R(sl.uref[1]), uz0 = R(sl.uref[2]);
-    if (sl.comoving) {
-#pragma unroll
-      for (int i = 0; i < Q; ++i) f[i] += eref<R>(i, R(sl.rho0), ux0, uy0, uz0);
-    }
-    R drho = 0, jx = 0, jy = 0, jz = 0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      drho += f[i];
-      jx += R(CX[i]) * f[i];
-      jy += R(CY[i]) * f[i];
-      jz += R(CZ[i]) * f[i];
-    }
-    const R rho = R(sl.rho0) + drho, ir = R(1) / rho;
-    const R fac = R(1 + sl.pend);
-    R Fx = fac * R(sl.fx), Fy = fac * R(sl.fy), Fz = fac * R(sl.fz);
-    if (word) {  // a 64-aligned group of 64 lanes owns this mask word
-      if ((word >> (s & 63)) & 1ull) {
-        V4* FA = (V4*)sl.FA;
-        V4* FB = (V4*)sl.FB;
-        const V4 fa = FA[s], fb = FB[s];
-        Fx += fa.x + fb.x;
-        Fy += fa.y + fb.y;
-        Fz += fa.z + fb.z;
-        V4 zero;
-        zero.x = zero.y = zero.z = zero.w = 0;
-        FA[s] = zero;
-        FB[s] = zero;
-      }
-      if ((s & 63) == 0) *mp = 0;
-    }
-    const R cm = R(sl.comoving) / R(sl.rho0);
-    relax_store<S>(f, drho, rho, ir, jx, jy, jz, Fx, Fy, Fz, sl.collision, R(sl.omp), R(sl.omm),
-                   R(sl.scale), (T*)sl.f[1 - sl.cur], N, (size_t)s, R(sl.rho0),
-                   ux0 + cm * R(sl.fx), uy0 + cm * R(sl.fy), uz0 + cm * R(sl.fz));
+    if (sl.comoving)
+      ens_lattice_item<S, true>(sl, (uint32_t)w.y);
+    else
+      ens_lattice_item<S, false>(sl, (uint32_t)w.y);
   }
 }
 
@@ -967,7 +974,7 @@ __global__ void k_ens_advance(EnsArgs e) {
 hipError_t launch_ens_step(int storage, int K, const EnsArgs& e, int lat_grid, int part_grid,
                            hipStream_t st) {
   LBC_KERNEL_SWITCH(K, LBC_STORAGE_SWITCH(storage, (k_ens_couple<SS, KK><<<part_grid, 256, 0, st>>>(e, 0))));
-  LBC_STORAGE_SWITCH(storage, (k_ens_lattice<SS><<<lat_grid, 256, 0, st>>>(e)));
+  LBC_STORAGE_SWITCH(storage, (k_ens_lattice<SS><<<lat_grid, 256, 0, st>>>(e.slots, e.litems, e.nlitems)));
   LBC_KERNEL_SWITCH(K, LBC_STORAGE_SWITCH(storage, (k_ens_couple<SS, KK><<<part_grid, 256, 0, st>>>(e, 1))));
   k_ens_advance<<<(e.nslots + 63) / 64, 64, 0, st>>>(e);
   return hipGetLastError();
