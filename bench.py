@@ -150,10 +150,17 @@ def bench_serving(args):
            for r in base]
     keep = {r.rid for r in base[:: max(1, nreq // 8)]}
     pool = int(args.pool_gb * (1 << 30))
+    def phase(name):
+        print(f"[c5] {name} ({time.strftime('%H:%M:%S')})", file=sys.stderr, flush=True)
+
+    phase("saturated, per-run FP32 FIFO")
     fifo_sat, f32_fields = S.serve_fifo(sat, keep=keep)
     fifo_sum = S.summarize(fifo_sat)
-    ens_sat, f16_fields = S.serve_batched(sat, pool, max_slots=args.slots, keep=keep)
+    phase("saturated, batched FP16")
+    host = {}
+    ens_sat, f16_fields = S.serve_batched(sat, pool, max_slots=args.slots, keep=keep, prof=host)
     ens_sum = S.summarize(ens_sat)
+    ens_sum["host"] = host
     errs = []
     for rid in keep:
         a, b = f16_fields[rid], f32_fields[rid]
@@ -162,7 +169,9 @@ def bench_serving(args):
     scale = base[-1].arrival
     poisson = [I.Request(r.rid, r.arrival / scale * (nreq / rate), r.side, r.nparticles, r.tau,
                          r.fext, r.steps, r.seed) for r in base]
+    phase("Poisson arrivals, per-run FP32 FIFO")
     fifo_p = S.summarize(S.serve_fifo(poisson)[0])
+    phase("Poisson arrivals, batched FP16")
     ens_p = S.summarize(S.serve_batched(poisson, pool, max_slots=args.slots)[0])
     out = {
         "metric": METRIC, "value": ens_sum["runs_per_s"], "unit": "runs/s", "n_gpus": 1,

@@ -139,12 +139,12 @@ __device__ __forceinline__ void pull(const typename Store<S>::T* __restrict__ f,
     long long src;
     const bool bb = g.wall && ((CY[i] == 1 && y == 0) || (CY[i] == -1 && y == g.ny - 1));
     if (bb) {
-      src = (long long)OPP[i] * g.N + own;
+      src = (long long)OPP[i] * g.ps + own;
     } else {
       const int xs = CX[i] == 1 ? xm : (CX[i] == -1 ? xp : x);
       const int ys = CY[i] == 1 ? ym : (CY[i] == -1 ? yp : y);
       const int zs = CZ[i] == 1 ? zm : (CZ[i] == -1 ? zp : z);
-      src = (long long)i * g.N + site_index(g, xs, ys, zs);
+      src = (long long)i * g.ps + site_index(g, xs, ys, zs);
     }
     out[i] = Store<S>::ld(f + src, inv);
   }
@@ -215,7 +215,7 @@ template <int S, bool CM>
 __device__ __forceinline__ void fused_site(const typename Store<S>::R f[Q], typename Store<S>::R Fx,
                                            typename Store<S>::R Fy, typename Store<S>::R Fz,
                                            const PassK<typename Store<S>::R>& k,
-                                           typename Store<S>::T* __restrict__ fo, size_t N,
+                                           typename Store<S>::T* __restrict__ fo, size_t P,
                                            size_t own) {
   using St = Store<S>;
   using R = typename St::R;
@@ -275,8 +275,8 @@ __device__ __forceinline__ void fused_site(const typename Store<S>::R f[Q], type
     }
     const R ni = f[i] - Eb - Ob, nj = f[i + 1] - Eb + Ob;
     const R sym = k.hp * (ni + nj), anti = k.hm * (ni - nj);
-    St::st_raw(fo + (size_t)i * N + own, Eh + Oh + sym + anti);
-    St::st_raw(fo + (size_t)(i + 1) * N + own, Eh - Oh + sym - anti);
+    St::st_raw(fo + (size_t)i * P + own, Eh + Oh + sym + anti);
+    St::st_raw(fo + (size_t)(i + 1) * P + own, Eh - Oh + sym - anti);
   }
 }
 
@@ -318,6 +318,21 @@ __device__ __forceinline__ double wrap_pos(double x, double L) {
 }
 
 // ------------------------------------------------------------- reductions
+// Lanes per particle for a K-point stencil: one lane per stencil node (K^3),
+// rounded up to a power of two that divides the wavefront.
+template <int K>
+struct Lanes {
+  static constexpr int L = K == 2 ? 8 : (K == 3 ? 32 : 64);
+};
+
+// Sum over an aligned group of L lanes (butterfly; every lane gets the sum).
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

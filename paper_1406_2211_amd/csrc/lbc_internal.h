@@ -15,6 +15,8 @@ struct Geo {
   int wall;  // halfway bounce-back walls in y
   int wpr;   // 64-bit force-mask words per row
   long long N;
+  long long ps;  // population stride: N rounded up to a multiple of 128 sites, so that
+                 // every population array starts on a 256-byte boundary
 };
 
 // Fused lattice pass (stream, both pending half forces, collide).

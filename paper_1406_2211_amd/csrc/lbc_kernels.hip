@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
   const uint32_t zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
   const uint32_t xs[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
   const uint32_t own = (z * ny + y) * nx + x;
-  const size_t N = (size_t)a.g.N;
+  const size_t N = (size_t)a.g.ps;  // population stride
   const T* __restrict__ fin = (const T*)a.fin;
   uint64_t* mp = a.mask + ((size_t)z * ny + y) * a.g.wpr + (x >> 6);
   const uint64_t word = *mp;
@@ -112,9 +112,9 @@ __global__ void k_init(InitArgs a) {
     const int ys = y - CY[i];
     long long dst;
     if (a.g.wall && (ys < 0 || ys >= a.g.ny)) {
-      dst = (long long)OPP[i] * a.g.N + s;
+      dst = (long long)OPP[i] * a.g.ps + s;
     } else {
-      dst = (long long)i * a.g.N +
+      dst = (long long)i * a.g.ps +
             site_index(a.g, wrap_idx(x - CX[i], a.g.nx), wrap_idx(ys, a.g.ny),
                        wrap_idx(z - CZ[i], a.g.nz));
     }
@@ -226,11 +226,6 @@ __global__ __launch_bounds__(256) void k_totals_final(const double* partial, int
 // shuffles (fixed order), after which every lane holds the interpolated
 // values and evaluates the (cheap, FP64) coupling update redundantly.
 // ======================================================================
-template <int K>
-struct Lanes {
-  static constexpr int L = K == 2 ? 8 : (K == 3 ? 32 : 64);
-};
-
 struct SiteSlot {
   bool valid;
   double W;
@@ -261,13 +256,6 @@ __device__ __forceinline__ SiteSlot slot_of(const Geo& g, const double X[3], int
   s.y = yy;
   s.z = wrap_idx(jz + kz, g.nz);
   return s;
-}
-
-template <int L>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
 }
 
 template <int S, int K>
@@ -813,6 +801,7 @@ __device__ __forceinline__ void ens_lattice_item(const EnsSlot& sl, uint32_t chu
   using R = typename St::R;
   using V4 = typename St::V4;
   const uint32_t N = (uint32_t)sl.g.N;
+  const size_t P = (size_t)sl.g.ps;  // population stride
   const uint32_t s = chunk * 256u + threadIdx.x;
   if (s >= N) return;
   const uint32_t nx = (uint32_t)sl.g.nx, ny = (uint32_t)sl.g.ny, nz = (uint32_t)sl.g.nz;
@@ -829,7 +818,7 @@ __device__ __forceinline__ void ens_lattice_item(const EnsSlot& sl, uint32_t chu
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const uint32_t src = (zr[1 - CZ[i]] + ys[1 - CY[i]]) * nx + xs[1 - CX[i]];
-    f[i] = St::raw(fin + (size_t)i * N + src);
+    f[i] = St::raw(fin + (size_t)i * P + src);
   }
   const R fac = R(1 + sl.pend);
   R Fx = fac * R(sl.fx), Fy = fac * R(sl.fy), Fz = fac * R(sl.fz);
@@ -862,7 +851,7 @@ __device__ __forceinline__ void ens_lattice_item(const EnsSlot& sl, uint32_t chu
     k.uo[1] = R(sl.uref[1] + sl.fy / sl.rho0);
     k.uo[2] = R(sl.uref[2] + sl.fz / sl.rho0);
   }
-  fused_site<S, CM>(f, Fx, Fy, Fz, k, (T*)sl.f[1 - sl.cur], N, s);
+  fused_site<S, CM>(f, Fx, Fy, Fz, k, (T*)sl.f[1 - sl.cur], P, s);
 }
 
 template <int S>

@@ -13,10 +13,14 @@
 //
 //   interpolation (Eq. IBM-interpolation): physical moments rho, u of every
 //   region site are computed once (pull gather + pending half force) into LDS
-//   in FP64; each marker then sums K^3 weighted LDS entries.
+//   in FP64; each marker then sums K^3 weighted LDS entries, one lane per
+//   stencil site and a butterfly reduction over the lane group.
 //   spreading (Eq. IBM-spreading): markers add W F into an LDS accumulator of
-//   the region (LDS atomics); the workgroup then adds every nonzero region site
-//   to the global force field once and sets its mask bit if not yet set.
+//   the region (LDS atomics, one lane per stencil site); the workgroup then
+//   adds every nonzero region site to the global force field once and sets
+//   its mask bit.
+// Workgroups have 1024 lanes so that staging and flushing a region take two
+// rounds of loads with sixteen wavefronts in flight.
 #include "lbc_device.h"
 #include "lbc_internal.h"
 
@@ -56,43 +60,51 @@ __global__ void k_bin_count(TileArgs t, const double* pos, long long n) {
 }
 
 // Single workgroup: exclusive scan of the tile counts (start, cursor) and the
-// list of occupied tiles in increasing tile order.
+// list of occupied tiles in increasing tile order.  Each lane owns a run of
+// consecutive tiles; the run totals are scanned across the wavefront with
+// shuffles and across wavefronts through LDS.
 __global__ __launch_bounds__(1024) void k_bin_scan(TileArgs t) {
-  __shared__ int sc[1024];
-  __shared__ int so[1024];
-  __shared__ int carry[2];
-  if (threadIdx.x == 0) carry[0] = carry[1] = 0;
-  __syncthreads();
-  for (int base = 0; base < t.ntiles; base += 1024) {
-    const int i = base + threadIdx.x;
-    const int c = i < t.ntiles ? t.count[i] : 0;
-    sc[threadIdx.x] = c;
-    so[threadIdx.x] = c > 0 ? 1 : 0;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scans
-      const int a = threadIdx.x >= off ? sc[threadIdx.x - off] : 0;
-      const int b = threadIdx.x >= off ? so[threadIdx.x - off] : 0;
-      __syncthreads();
-      sc[threadIdx.x] += a;
-      so[threadIdx.x] += b;
-      __syncthreads();
-    }
-    if (i < t.ntiles) {
-      const int start = carry[0] + sc[threadIdx.x] - c;
-      t.start[i] = start;
-      t.cursor[i] = start;
-      if (c > 0) t.occ[carry[1] + so[threadIdx.x] - 1] = i;
-    }
-    __syncthreads();
-    if (threadIdx.x == 1023) {
-      carry[0] += sc[1023];
-      carry[1] += so[1023];
-    }
-    __syncthreads();
+  __shared__ int wsum[16][2];
+  const int per = (t.ntiles + 1023) / 1024;
+  const int b = threadIdx.x * per;
+  const int e = min(b + per, t.ntiles);
+  int cs = 0, os = 0;
+  for (int i = b; i < e; ++i) {
+    const int c = t.count[i];
+    cs += c;
+    os += c > 0 ? 1 : 0;
   }
-  if (threadIdx.x == 0) {
-    t.start[t.ntiles] = carry[0];
-    t.nocc[0] = carry[1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int ic = cs, io = os;  // inclusive scans over the wavefront
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int pc = __shfl_up(ic, o, 64), po = __shfl_up(io, o, 64);
+    if (lane >= o) {
+      ic += pc;
+      io += po;
+    }
+  }
+  if (lane == 63) {
+    wsum[wv][0] = ic;
+    wsum[wv][1] = io;
+  }
+  __syncthreads();
+  int pc = 0, po = 0;
+  for (int w = 0; w < wv; ++w) {
+    pc += wsum[w][0];
+    po += wsum[w][1];
+  }
+  int start = pc + ic - cs, occ = po + io - os;
+  for (int i = b; i < e; ++i) {
+    const int c = t.count[i];
+    t.start[i] = start;
+    t.cursor[i] = start;
+    start += c;
+    if (c > 0) t.occ[occ++] = i;
+  }
+  if (threadIdx.x == 1023) {
+    t.start[t.ntiles] = pc + ic;
+    t.nocc[0] = po + io;
   }
 }
 
@@ -128,73 +140,51 @@ __device__ __forceinline__ bool slot_site(const Geo& g, const Region& r, int ix,
   return true;
 }
 
-// Stencil of a marker in region slots; false if any node falls outside.
+// One lane of a marker's lane group: stencil node (kx, ky, kz) = lane
+// (x fastest) of the K-point stencil whose first node is j0 (Appendix A
+// kernels), its weight, and the node's region slot.
 template <int K>
-__device__ __forceinline__ bool stencil_in_region(const Region& r, const double X[3], int j0[3],
-                                                  double w[3][4]) {
-  bool ok = true;
+struct Node {
+  bool on;       // lane carries a node of nonzero weight
+  bool inside;   // the whole stencil lies in the staged region (same for the group)
+  double W;
+  int j[3];      // unwrapped node coordinates
+  int slot;      // region slot (when inside)
+};
+
+template <int K>
+__device__ __forceinline__ int first_node(double X) {
+  return K == 3 ? (int)floor(X + 0.5) - 1 : (K == 2 ? (int)floor(X) : (int)floor(X) - 1);
+}
+
+template <int K>
+__device__ __forceinline__ Node<K> node_of(const Region& r, const double X[3], int lane) {
+  Node<K> n;
+  const int k[3] = {lane % K, (lane / K) % K, lane / (K * K)};
+  n.inside = true;
+  n.W = 1.0;
+  int rel[3];
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const int j = stencil(K, X[a], w[a]);
-    j0[a] = j - r.o[a];
-    ok = ok && j0[a] >= 0 && j0[a] + K <= kReg;
+    const int j0 = first_node<K>(X[a]);
+    n.inside = n.inside && j0 - r.o[a] >= 0 && j0 - r.o[a] + K <= kReg;
+    n.j[a] = j0 + k[a];
+    rel[a] = n.j[a] - r.o[a];
+    n.W *= phi_eval(K, (double)n.j[a] - X[a]);
   }
-  return ok;
+  n.on = lane < K * K * K && n.W != 0.0;
+  n.slot = (rel[2] * kReg + rel[1]) * kReg + rel[0];
+  return n;
 }
 
-// ------------------------------------------------------- direct fallbacks
-template <int S, int K>
-__device__ void direct_interp(const SiteArgs& s, const double X[3], bool phys, double& rp,
-                              double up[3]) {
-  double w[3][4];
-  int j0[3];
-  for (int a = 0; a < 3; ++a) j0[a] = stencil(K, X[a], w[a]);
-  rp = 0;
-  up[0] = up[1] = up[2] = 0;
-  for (int kz = 0; kz < K; ++kz)
-    for (int ky = 0; ky < K; ++ky) {
-      int yy = j0[1] + ky;
-      if (s.g.wall) {
-        if (yy < 0 || yy >= s.g.ny) continue;
-      } else {
-        yy = wrap_idx(yy, s.g.ny);
-      }
-      for (int kx = 0; kx < K; ++kx) {
-        const double W = w[0][kx] * w[1][ky] * w[2][kz];
-        if (W == 0.0) continue;
-        double fl[Q], drho, j[3];
-        site_phys<S>(s, wrap_idx(j0[0] + kx, s.g.nx), yy, wrap_idx(j0[2] + kz, s.g.nz), fl, drho,
-                     j, phys);
-        const double rr = s.rho0 + drho;
-        rp += W * rr;
-        for (int a = 0; a < 3; ++a) up[a] += W * j[a] / rr;
-      }
-    }
-}
-
-template <typename E, int K>
-__device__ void direct_spread(const TileArgs& t, const double X[3], const double F[3], E* Fd) {
-  double w[3][4];
-  int j0[3];
-  for (int a = 0; a < 3; ++a) j0[a] = stencil(K, X[a], w[a]);
-  for (int kz = 0; kz < K; ++kz)
-    for (int ky = 0; ky < K; ++ky) {
-      int yy = j0[1] + ky;
-      if (t.g.wall) {
-        if (yy < 0 || yy >= t.g.ny) continue;
-      } else {
-        yy = wrap_idx(yy, t.g.ny);
-      }
-      for (int kx = 0; kx < K; ++kx) {
-        const double W = w[0][kx] * w[1][ky] * w[2][kz];
-        if (W == 0.0) continue;
-        const int xx = wrap_idx(j0[0] + kx, t.g.nx), zz = wrap_idx(j0[2] + kz, t.g.nz);
-        const long long sidx = site_index(t.g, xx, yy, zz);
-        for (int a = 0; a < 3; ++a) unsafeAtomicAdd(Fd + 4 * sidx + a, (E)(W * F[a]));
-        uint64_t bit;
-        uint64_t* mw = mask_word(t.mask, t.g, xx, yy, zz, bit);
-        atomicOr((unsigned long long*)mw, bit);
-      }
-    }
+// Wrapped site of a node; false beyond a wall.
+__device__ __forceinline__ bool node_site(const Geo& g, const int j[3], int& x, int& y, int& z) {
+  x = wrap_idx(j[0], g.nx);
+  z = wrap_idx(j[2], g.nz);
+  y = j[1];
+  if (g.wall) return y >= 0 && y < g.ny;
+  y = wrap_idx(y, g.ny);
+  return true;
 }
 
 // ------------------------------------------------------------- interpolation
@@ -203,9 +193,12 @@ __device__ void direct_spread(const TileArgs& t, const double X[3], const double
 // mode 2: both, in that order, from one staged region (at = pos); the first
 //         advection only needs the state before the lattice pass, like the
 //         predictor, so both read the same LDS moments.
+// A marker whose stencil leaves the region gathers its nodes from global
+// memory instead (same arithmetic per node).
 template <int S, int K>
-__global__ __launch_bounds__(256) void k_tile_interp(TileArgs t, SiteArgs s, const double* at,
-                                                     double* pos, double* aux, int mode) {
+__global__ __launch_bounds__(1024) void k_tile_interp(TileArgs t, SiteArgs s, const double* at,
+                                                      double* pos, double* aux, int mode) {
+  constexpr int L = Lanes<K>::L;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double4* mom = (double4*)lds_raw;  // kRegSites
   if ((int)blockIdx.x >= t.nocc[0]) return;
@@ -224,28 +217,33 @@ __global__ __launch_bounds__(256) void k_tile_interp(TileArgs t, SiteArgs s, con
     mom[k] = m;
   }
   __syncthreads();
-  const int b0 = t.start[tl], b1 = t.start[tl + 1];
+  const int lane = threadIdx.x % L;
   auto interp_at = [&](const double X[3], double up[3]) {
-    double w[3][4];
-    int j0[3];
-    double rp = 0;
-    up[0] = up[1] = up[2] = 0;
-    if (stencil_in_region<K>(r, X, j0, w)) {
-      for (int kz = 0; kz < K; ++kz)
-        for (int ky = 0; ky < K; ++ky)
-          for (int kx = 0; kx < K; ++kx) {
-            const double W = w[0][kx] * w[1][ky] * w[2][kz];
-            if (W == 0.0) continue;
-            const double4 m = mom[((j0[2] + kz) * kReg + (j0[1] + ky)) * kReg + (j0[0] + kx)];
-            if (m.x == 0.0) continue;  // beyond a wall
-            rp += W * m.x;
-            up[0] += W * m.y;
-            up[1] += W * m.z;
-            up[2] += W * m.w;
-          }
-    } else {
-      direct_interp<S, K>(s, X, true, rp, up);
+    const Node<K> n = node_of<K>(r, X, lane);
+    double ux = 0, uy = 0, uz = 0;
+    if (n.on) {
+      if (n.inside) {
+        const double4 m = mom[n.slot];
+        if (m.x != 0.0) {  // zero beyond a wall
+          ux = n.W * m.y;
+          uy = n.W * m.z;
+          uz = n.W * m.w;
+        }
+      } else {
+        int x, y, z;
+        if (node_site(s.g, n.j, x, y, z)) {
+          double fl[Q], drho, j[3];
+          site_phys<S>(s, x, y, z, fl, drho, j, true);
+          const double rr = s.rho0 + drho;
+          ux = n.W * j[0] / rr;
+          uy = n.W * j[1] / rr;
+          uz = n.W * j[2] / rr;
+        }
+      }
     }
+    up[0] = group_sum<L>(ux);
+    up[1] = group_sum<L>(uy);
+    up[2] = group_sum<L>(uz);
   };
   auto half_drift = [&](const double from[3], const double u[3], double to[3]) {
     for (int a = 0; a < 3; ++a) to[a] = from[a] + 0.5 * u[a];
@@ -253,33 +251,40 @@ __global__ __launch_bounds__(256) void k_tile_interp(TileArgs t, SiteArgs s, con
     if (!s.g.wall) to[1] = wrap_pos(to[1], (double)s.g.ny);
     to[2] = wrap_pos(to[2], (double)s.g.nz);
   };
-  for (int q = b0 + threadIdx.x; q < b1; q += blockDim.x) {
+  const int b0 = t.start[tl], b1 = t.start[tl + 1];
+  for (int q = b0 + (int)threadIdx.x / L; q < b1; q += (int)blockDim.x / L) {  // groups leave together
     const long long p = t.sorted[q];
     const double X[3] = {at[3 * p], at[3 * p + 1], at[3 * p + 2]};
     double up[3], Y[3];
     interp_at(X, up);
     if (mode == 0) {  // predictor only
       half_drift(X, up, Y);
-      for (int a = 0; a < 3; ++a) aux[3 * p + a] = Y[a];
+      if (lane == 0)
+        for (int a = 0; a < 3; ++a) aux[3 * p + a] = Y[a];
     } else if (mode == 1) {  // advection with the velocity at X~ = at
       const double P[3] = {pos[3 * p], pos[3 * p + 1], pos[3 * p + 2]};
       half_drift(P, up, Y);
-      for (int a = 0; a < 3; ++a) pos[3 * p + a] = Y[a];
+      if (lane == 0)
+        for (int a = 0; a < 3; ++a) pos[3 * p + a] = Y[a];
     } else {  // mode 2: predictor, then the first advection from the same staged state
       double Xt[3], u2[3];
       half_drift(X, up, Xt);
-      for (int a = 0; a < 3; ++a) aux[3 * p + a] = Xt[a];
       interp_at(Xt, u2);
       half_drift(X, u2, Y);
-      for (int a = 0; a < 3; ++a) pos[3 * p + a] = Y[a];
+      if (lane == 0)
+        for (int a = 0; a < 3; ++a) {
+          aux[3 * p + a] = Xt[a];
+          pos[3 * p + a] = Y[a];
+        }
     }
   }
 }
 
 // ------------------------------------------------------------------ spreading
 template <typename E, int K>
-__global__ __launch_bounds__(256) void k_tile_spread(TileArgs t, const double* at, const double* F,
-                                                     void* field) {
+__global__ __launch_bounds__(1024) void k_tile_spread(TileArgs t, const double* at,
+                                                      const double* F, void* field) {
+  constexpr int L = Lanes<K>::L;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   E* acc = (E*)lds_raw;  // 3 * kRegSites
   if ((int)blockIdx.x >= t.nocc[0]) return;
@@ -288,29 +293,30 @@ __global__ __launch_bounds__(256) void k_tile_spread(TileArgs t, const double* a
   for (int k = threadIdx.x; k < 3 * kRegSites; k += blockDim.x) acc[k] = E(0);
   __syncthreads();
   E* Fd = (E*)field;
+  const int lane = threadIdx.x % L;
   const int b0 = t.start[tl], b1 = t.start[tl + 1];
-  for (int q = b0 + threadIdx.x; q < b1; q += blockDim.x) {
+  for (int q = b0 + (int)threadIdx.x / L; q < b1; q += (int)blockDim.x / L) {
     const long long p = t.sorted[q];
     const double X[3] = {at[3 * p], at[3 * p + 1], at[3 * p + 2]};
-    const double f[3] = {F[3 * p], F[3 * p + 1], F[3 * p + 2]};
-    double w[3][4];
-    int j0[3];
-    if (stencil_in_region<K>(r, X, j0, w)) {
-      for (int kz = 0; kz < K; ++kz)
-        for (int ky = 0; ky < K; ++ky) {
-          const int yabs = r.o[1] + j0[1] + ky;
-          if (t.g.wall && (yabs < 0 || yabs >= t.g.ny)) continue;
-          for (int kx = 0; kx < K; ++kx) {
-            const double W = w[0][kx] * w[1][ky] * w[2][kz];
-            if (W == 0.0) continue;
-            E* a = acc + 3 * (((j0[2] + kz) * kReg + (j0[1] + ky)) * kReg + (j0[0] + kx));
-            atomicAdd(a + 0, (E)(W * f[0]));
-            atomicAdd(a + 1, (E)(W * f[1]));
-            atomicAdd(a + 2, (E)(W * f[2]));
-          }
-        }
+    const Node<K> n = node_of<K>(r, X, lane);
+    if (!n.on) continue;
+    if (t.g.wall && (n.j[1] < 0 || n.j[1] >= t.g.ny)) continue;  // beyond a wall
+    const E f0 = (E)(n.W * F[3 * p]), f1 = (E)(n.W * F[3 * p + 1]), f2 = (E)(n.W * F[3 * p + 2]);
+    if (n.inside) {
+      E* a = acc + 3 * n.slot;
+      atomicAdd(a + 0, f0);
+      atomicAdd(a + 1, f1);
+      atomicAdd(a + 2, f2);
     } else {
-      direct_spread<E, K>(t, X, f, Fd);
+      int x, y, z;
+      node_site(t.g, n.j, x, y, z);
+      const long long sidx = site_index(t.g, x, y, z);
+      unsafeAtomicAdd(Fd + 4 * sidx + 0, f0);
+      unsafeAtomicAdd(Fd + 4 * sidx + 1, f1);
+      unsafeAtomicAdd(Fd + 4 * sidx + 2, f2);
+      uint64_t bit;
+      uint64_t* mw = mask_word(t.mask, t.g, x, y, z, bit);
+      atomicOr((unsigned long long*)mw, bit);
     }
   }
   __syncthreads();
@@ -326,7 +332,7 @@ __global__ __launch_bounds__(256) void k_tile_spread(TileArgs t, const double* a
     unsafeAtomicAdd(Fd + 4 * sidx + 2, a2);
     uint64_t bit;
     uint64_t* mw = mask_word(t.mask, t.g, x, y, z, bit);
-    if (!(__atomic_load_n(mw, __ATOMIC_RELAXED) & bit)) atomicOr((unsigned long long*)mw, bit);
+    atomicOr((unsigned long long*)mw, bit);
   }
 }
 
@@ -364,7 +370,7 @@ hipError_t launch_tile_interp(int storage, int K, const TileArgs& t, const SiteA
   if (n <= 0) return hipSuccess;
   const size_t lds = sizeof(double4) * kRegSites;
   LBC_TILE_K_SWITCH(K, LBC_TILE_S_SWITCH(storage, (k_tile_interp<SS, KK>
-      <<<tile_grid(t, n), 256, lds, st>>>(t, s, at, pos, aux, mode))));
+      <<<tile_grid(t, n), 1024, lds, st>>>(t, s, at, pos, aux, mode))));
   return hipGetLastError();
 }
 
@@ -373,10 +379,10 @@ hipError_t launch_tile_spread(int storage, int K, const TileArgs& t, const doubl
   if (n <= 0) return hipSuccess;
   if (storage == LB_F64) {
     const size_t lds = sizeof(double) * 3 * kRegSites;
-    LBC_TILE_K_SWITCH(K, (k_tile_spread<double, KK><<<tile_grid(t, n), 256, lds, st>>>(t, at, F, field)));
+    LBC_TILE_K_SWITCH(K, (k_tile_spread<double, KK><<<tile_grid(t, n), 1024, lds, st>>>(t, at, F, field)));
   } else {
     const size_t lds = sizeof(float) * 3 * kRegSites;
-    LBC_TILE_K_SWITCH(K, (k_tile_spread<float, KK><<<tile_grid(t, n), 256, lds, st>>>(t, at, F, field)));
+    LBC_TILE_K_SWITCH(K, (k_tile_spread<float, KK><<<tile_grid(t, n), 1024, lds, st>>>(t, at, F, field)));
   }
   return hipGetLastError();
 }

@@ -76,12 +76,16 @@ def _init_box(lat, req):
 
 
 def serve_batched(requests, pool_bytes, max_slots=64, storage=L.LB_F16, chunk=20, comoving=1,
-                  autotune=True, keep=None, log=None):
+                  autotune=True, keep=None, log=None, prof=None):
     """Continuous batching over one ensemble.  Arrival times are honoured
     against the wall clock (requests arriving at time 0 model a saturated
     queue).  keep: optional set of request ids whose final velocity fields are
-    returned (as host arrays) for accuracy checks."""
+    returned (as host arrays) for accuracy checks.  prof: optional dict that
+    receives the host wall time spent admitting and initialising requests,
+    enqueueing steps, and polling/retiring (which waits for the device)."""
     import torch
+    clock = time.perf_counter
+    acc = {"admit_s": 0.0, "enqueue_s": 0.0, "poll_s": 0.0, "chunks": 0}
     ens = L.Ensemble(pool_bytes, max_slots, storage=storage, kernel=L.LB_PHI2)
     pending = sorted(requests, key=lambda r: r.arrival)
     queue, active, results, fields = [], {}, [], {}
@@ -91,6 +95,7 @@ def serve_batched(requests, pool_bytes, max_slots=64, storage=L.LB_F16, chunk=20
         now = time.perf_counter() - t0
         while pending and pending[0].arrival <= now:
             queue.append(pending.pop(0))
+        ta = clock()
         while queue:  # continuous admission: FIFO order, as far as memory and slots allow
             req = queue[0]
             got = ens.admit(req.side, req.side, req.side, req.steps, max_particles=req.nparticles,
@@ -101,6 +106,7 @@ def serve_batched(requests, pool_bytes, max_slots=64, storage=L.LB_F16, chunk=20
             slot, lat = got
             _init_box(lat, req)
             active[slot] = (req, lat, time.perf_counter() - t0)
+        acc["admit_s"] += clock() - ta
         if not active:
             if pending:
                 time.sleep(max(0.0, min(0.002, pending[0].arrival - now)))
@@ -108,7 +114,11 @@ def serve_batched(requests, pool_bytes, max_slots=64, storage=L.LB_F16, chunk=20
         if not tuned and len(active) >= 4:
             ens.autotune(1)
             tuned = True
+        te = clock()
         ens.step(chunk)
+        acc["chunks"] += 1
+        tp = clock()
+        acc["enqueue_s"] += tp - te
         for slot in list(active):
             done_steps, done = ens.query(slot)
             if not done:
@@ -124,7 +134,10 @@ def serve_batched(requests, pool_bytes, max_slots=64, storage=L.LB_F16, chunk=20
             ens.retire(slot)
             if log:
                 log(f"done {req.rid} L={req.side} steps={req.steps} latency={t_done - req.arrival:.3f}s")
+        acc["poll_s"] += clock() - tp
     ens.destroy()
+    if prof is not None:
+        prof.update({k: round(v, 4) if isinstance(v, float) else v for k, v in acc.items()})
     torch.cuda.synchronize()
     return results, fields
 
