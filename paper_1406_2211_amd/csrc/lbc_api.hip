@@ -360,6 +360,8 @@ static lb_status lattice_pass(lb_ctx* c) {
   a.omm = c->omm;
   a.scale = c->scale;
   a.inv = c->inv;
+  a.rnx = 1.0 / c->geo.nx;
+  a.rny = 1.0 / c->geo.ny;
   for (int k = 0; k < 3; ++k) {
     a.uin[k] = c->uref[k];
     a.uout[k] = c->uref[k] + (c->p.comoving ? c->p.body_force[k] / c->p.rho0 : 0.0);
@@ -502,7 +504,10 @@ static lb_status create_ctx(const lb_grid* g, const lb_params* p, const lb_limit
   c->geo.ny = g->ny;
   c->geo.nz = g->nz;
   c->geo.wall = g->wall_y;
-  c->geo.wpr = linear_mask ? 0 : (g->nx + 63) / 64;
+  // Row-aligned mask words (and the row-per-workgroup lattice pass) when x is
+  // a multiple of 64; otherwise one word per 64 consecutive linear sites and
+  // the linear-site pass.
+  c->geo.wpr = (linear_mask || g->nx % 64 != 0) ? 0 : g->nx / 64;
   c->member = linear_mask;
   c->geo.N = (long long)g->nx * g->ny * g->nz;
   c->geo.ps = pop_stride(c->geo.N);

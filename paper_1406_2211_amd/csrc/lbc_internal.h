@@ -33,6 +33,7 @@ struct LatArgs {
   float scale, inv;   // 16-bit storage scale 2^p and its inverse (1 otherwise)
   double uin[3];      // storage reference velocity of fin (comoving frame; 0 otherwise)
   double uout[3];     // storage reference velocity of fout
+  double rnx, rny;    // 1/nx, 1/ny (linear-site pass)
 };
 
 struct InitArgs {

@@ -667,9 +667,17 @@ static dim3 lattice_grid(const Geo& g, dim3 b) {
     default: { constexpr int SS = LB_BF16; CALL; } break;           \
   }
 
+template <int S, bool CM, bool WALL>
+__global__ __launch_bounds__(256) void k_stream_collide_lin(LatArgs a);
+
 template <bool CM, bool WALL>
 static void launch_sc(int storage, const LatArgs& a, dim3 gr, dim3 b, hipStream_t st) {
-  LBC_STORAGE_SWITCH(storage, (k_stream_collide<SS, CM, WALL><<<gr, b, 0, st>>>(a)));
+  if (a.g.wpr == 0) {  // linear mask: x extent not a multiple of 64
+    const unsigned nb = (unsigned)((a.g.N + 255) / 256);
+    LBC_STORAGE_SWITCH(storage, (k_stream_collide_lin<SS, CM, WALL><<<nb, 256, 0, st>>>(a)));
+  } else {
+    LBC_STORAGE_SWITCH(storage, (k_stream_collide<SS, CM, WALL><<<gr, b, 0, st>>>(a)));
+  }
 }
 
 // BGK and the two-rate collision share one kernel (BGK: equal rates); the
@@ -791,41 +799,91 @@ __device__ __forceinline__ bool ens_active(const EnsSlot& s) {
   return s.live && s.steps_done < s.steps_target;
 }
 
-// The slot table is read-only during the lattice pass (only k_ens_advance
-// writes it); with restrict-qualified arguments its fields are loaded into
-// scalar registers once per work item.
-template <int S, bool CM>
-__device__ __forceinline__ void ens_lattice_item(const EnsSlot& sl, uint32_t chunk) {
+// Fused pass over linear site indices: a wavefront covers 64 consecutive
+// sites whatever the row length, and owns one word of a linear force mask
+// (wpr == 0).  Used by the batched ensemble pass and by single boxes whose x
+// extent is not a multiple of 64 (where row-aligned wavefronts would idle
+// lanes).  Site coordinates come from a 32-bit quotient by nx and ny.
+// V is a view of the pass parameters (kernel arguments or a slot record);
+// its accessors read them where they are used, so the compiler can reload
+// them from memory instead of holding every one in scalar registers.
+struct LatView {
+  const LatArgs& a;
+  __device__ const Geo& g() const { return a.g; }
+  __device__ double rnx() const { return a.rnx; }
+  __device__ double rny() const { return a.rny; }
+  __device__ const void* fin() const { return a.fin; }
+  __device__ void* fout() const { return a.fout; }
+  __device__ void* FA() const { return a.FA; }
+  __device__ void* FB() const { return a.FB; }
+  __device__ uint64_t* mask() const { return a.mask; }
+  __device__ double F(int c) const { return c == 0 ? a.Fx : (c == 1 ? a.Fy : a.Fz); }
+  __device__ double rho0() const { return a.rho0; }
+  __device__ float scale() const { return a.scale; }
+  __device__ float inv() const { return a.inv; }
+  __device__ double omp() const { return a.omp; }
+  __device__ double omm() const { return a.omm; }
+  __device__ double uin(int c) const { return a.uin[c]; }
+  __device__ double uout(int c) const { return a.uout[c]; }
+};
+
+struct SlotView {
+  const EnsSlot& s;
+  __device__ const Geo& g() const { return s.g; }
+  __device__ double rnx() const { return s.rnx; }
+  __device__ double rny() const { return s.rny; }
+  __device__ const void* fin() const { return s.f[s.cur]; }
+  __device__ void* fout() const { return s.f[1 - s.cur]; }
+  __device__ void* FA() const { return s.FA; }
+  __device__ void* FB() const { return s.FB; }
+  __device__ uint64_t* mask() const { return s.mask; }
+  __device__ double F(int c) const {
+    return (1 + s.pend) * (c == 0 ? s.fx : (c == 1 ? s.fy : s.fz));
+  }
+  __device__ double rho0() const { return s.rho0; }
+  __device__ float scale() const { return s.scale; }
+  __device__ float inv() const { return s.inv; }
+  __device__ double omp() const { return s.omp; }
+  __device__ double omm() const { return s.omm; }
+  __device__ double uin(int c) const { return s.uref[c]; }
+  __device__ double uout(int c) const {
+    return s.uref[c] + (c == 0 ? s.fx : (c == 1 ? s.fy : s.fz)) / s.rho0;
+  }
+};
+
+template <int S, bool CM, bool WALL, class V>
+__device__ __forceinline__ void linear_site(const V& v, uint32_t s) {
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
   using V4 = typename St::V4;
-  const uint32_t N = (uint32_t)sl.g.N;
-  const size_t P = (size_t)sl.g.ps;  // population stride
-  const uint32_t s = chunk * 256u + threadIdx.x;
-  if (s >= N) return;
-  const uint32_t nx = (uint32_t)sl.g.nx, ny = (uint32_t)sl.g.ny, nz = (uint32_t)sl.g.nz;
+  const Geo& g = v.g();
+  if (s >= (uint32_t)g.N) return;
+  const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny, nz = (uint32_t)g.nz;
+  const size_t P = (size_t)g.ps;  // population stride
   uint32_t x, y;
-  const uint32_t r = div_rem(s, nx, sl.rnx, x);
-  const uint32_t z = div_rem(r, ny, sl.rny, y);
+  const uint32_t r = div_rem(s, nx, v.rnx(), x);
+  const uint32_t z = div_rem(r, ny, v.rny(), y);
   const uint32_t xs[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
   const uint32_t ys[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
   const uint32_t zr[3] = {(z == 0 ? nz - 1 : z - 1) * ny, z * ny, (z == nz - 1 ? 0 : z + 1) * ny};
-  const T* __restrict__ fin = (const T*)sl.f[sl.cur];
-  uint64_t* mp = sl.mask + (s >> 6);
+  const T* __restrict__ fin = (const T*)v.fin();
+  uint64_t* mp = v.mask() + (s >> 6);
   const uint64_t word = *mp;
   R f[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const uint32_t src = (zr[1 - CZ[i]] + ys[1 - CY[i]]) * nx + xs[1 - CX[i]];
-    f[i] = St::raw(fin + (size_t)i * P + src);
+    const uint32_t off = (zr[1 - CZ[i]] + ys[1 - CY[i]]) * nx + xs[1 - CX[i]];
+    const T* src = fin + (size_t)i * P + off;
+    if (WALL && ((CY[i] == 1 && y == 0) || (CY[i] == -1 && y == ny - 1)))
+      src = fin + (size_t)OPP[i] * P + s;  // halfway bounce-back: opposite population, same site
+    f[i] = St::raw(src);
   }
-  const R fac = R(1 + sl.pend);
-  R Fx = fac * R(sl.fx), Fy = fac * R(sl.fy), Fz = fac * R(sl.fz);
+  R Fx = R(v.F(0)), Fy = R(v.F(1)), Fz = R(v.F(2));
   if (word) {  // a 64-aligned group of 64 lanes owns this mask word
     if ((word >> (s & 63)) & 1ull) {
-      V4* FA = (V4*)sl.FA;
-      V4* FB = (V4*)sl.FB;
+      V4* FA = (V4*)v.FA();
+      V4* FB = (V4*)v.FB();
       const V4 fa = FA[s], fb = FB[s];
       Fx += fa.x + fb.x;
       Fy += fa.y + fb.y;
@@ -838,20 +896,30 @@ __device__ __forceinline__ void ens_lattice_item(const EnsSlot& sl, uint32_t chu
     if ((s & 63) == 0) *mp = 0;
   }
   PassK<R> k;
-  k.rho0 = R(sl.rho0);
-  k.sc = R(sl.scale);
-  k.inv = R(sl.inv);
-  k.hp = R(0.5) * R(sl.omp);
-  k.hm = R(0.5) * R(sl.omm);
+  k.rho0 = R(v.rho0());
+  k.sc = R(v.scale());
+  k.inv = R(v.inv());
+  k.hp = R(0.5) * R(v.omp());
+  k.hm = R(0.5) * R(v.omm());
   if (CM) {
-    k.ui[0] = R(sl.uref[0]);
-    k.ui[1] = R(sl.uref[1]);
-    k.ui[2] = R(sl.uref[2]);
-    k.uo[0] = R(sl.uref[0] + sl.fx / sl.rho0);
-    k.uo[1] = R(sl.uref[1] + sl.fy / sl.rho0);
-    k.uo[2] = R(sl.uref[2] + sl.fz / sl.rho0);
+    for (int c = 0; c < 3; ++c) {
+      k.ui[c] = R(v.uin(c));
+      k.uo[c] = R(v.uout(c));
+    }
   }
-  fused_site<S, CM>(f, Fx, Fy, Fz, k, (T*)sl.f[1 - sl.cur], P, s);
+  fused_site<S, CM>(f, Fx, Fy, Fz, k, (T*)v.fout(), P, s);
+}
+
+template <int S, bool CM, bool WALL>
+__global__ __launch_bounds__(256) void k_stream_collide_lin(LatArgs a) {
+  linear_site<S, CM, WALL>(LatView{a}, blockIdx.x * 256u + threadIdx.x);
+}
+
+// The slot table is read-only during the lattice pass (only k_ens_advance
+// writes it); with restrict-qualified arguments its fields are scalar loads.
+template <int S, bool CM>
+__device__ __forceinline__ void ens_lattice_item(const EnsSlot& sl, uint32_t chunk) {
+  linear_site<S, CM, false>(SlotView{sl}, chunk * 256u + threadIdx.x);
 }
 
 template <int S>
