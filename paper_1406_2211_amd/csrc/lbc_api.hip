@@ -43,8 +43,15 @@ struct Layout {
   int32_t *perm, *loc, *goff, *bstart, *bnbr;
   double *tmpl, *rot, *partial, *tot;
   int *tcount, *tstart, *tcursor, *tocc, *tnocc, *ptile, *psorted;
+  double4* mcache;
+  int4* mbase;
   size_t bytes;
 };
+
+int kernel_lanes(int K) { return K == 2 ? 8 : (K == 3 ? 32 : 64); }
+
+// 64-bit force-mask words allocated for a box (enough for both layouts).
+size_t mask_words(const lb_grid& g) { return (size_t)g.nz * g.ny * ((g.nx + 63) / 64); }
 
 int tiles_along(int n) { return (n + 7) / 8; }
 
@@ -58,13 +65,12 @@ Layout carve(const lb_grid& g, const lb_params& p, const lb_limits& lim, void* b
   Carver c{(char*)base};
   Layout L{};
   const long long N = (long long)g.nx * g.ny * g.nz;
-  const long long wpr = (g.nx + 63) / 64;
   const size_t fb = (size_t)19 * pop_stride(N) * storage_bytes(p.storage);
   L.f[0] = c.take<void>(fb);
   L.f[1] = c.take<void>(fb);
   L.FA = c.take<void>((size_t)N * force_vec_bytes(p.storage));
   L.FB = c.take<void>((size_t)N * force_vec_bytes(p.storage));
-  L.mask = c.take<uint64_t>((size_t)g.nz * g.ny * wpr * 8);
+  L.mask = c.take<uint64_t>(mask_words(g) * 8);
   const size_t np = (size_t)std::max<int64_t>(lim.max_particles, 1);
   L.pos = c.take<double>(np * 24);
   L.vel = c.take<double>(np * 24);
@@ -88,6 +94,9 @@ Layout carve(const lb_grid& g, const lb_params& p, const lb_limits& lim, void* b
   L.tnocc = c.take<int>(64);
   L.ptile = c.take<int>(np * 4);
   L.psorted = c.take<int>(np * 4);
+  const bool cached = p.coupling == LB_COUPLE_FC || p.coupling == LB_COUPLE_EBF;
+  L.mcache = c.take<double4>(cached ? np * kernel_lanes(p.kernel) * 32 : 32);
+  L.mbase = c.take<int4>(cached ? np * 16 : 16);
   L.bytes = c.off;
   return L;
 }
@@ -153,6 +162,8 @@ struct lb_ctx {
   bool tiled = false;   // binned LDS-staged particle path (dense IB markers)
   int64_t binned_at = -1;  // step of the last marker binning (-1: markers changed since)
   bool member = false;  // slot of an ensemble: stepped only by lb_ensemble_step
+  bool running = false;  // ensemble slot whose device record has been uploaded
+  bool mvalid = false;   // coupling moment cache holds the state of f[cur]
   int nshell = 0, shell_size = 0;
   double k_tether = 0;
   double omp = 0, omm = 0;
@@ -213,6 +224,10 @@ static PartArgs part_args(const lb_ctx* c) {
   a.phys = 1;
   a.target = 0;
   a.drift_after = 0;
+  a.mcache = c->L.mcache;
+  a.mbase = c->L.mbase;
+  a.cache_use = 0;
+  a.cache_fill = 0;
   return a;
 }
 
@@ -379,7 +394,10 @@ static lb_status lattice_pass(lb_ctx* c) {
 static lb_status step_once(lb_ctx* c) {
   const bool parts = c->p.coupling != LB_COUPLE_NONE && c->np > 0;
   lb_status s;
-  if (!parts) return lattice_pass(c);
+  if (!parts) {
+    c->mvalid = false;
+    return lattice_pass(c);
+  }
   if (c->p.coupling == LB_COUPLE_IB && c->tiled) {
     // binned, LDS-staged interpolation and spreading (dense markers)
     const TileArgs t = tile_args(c);
@@ -423,6 +441,7 @@ static lb_status step_once(lb_ctx* c) {
     const double dt = 1.0 / (2.0 * n);
     PartArgs a = part_args(c);
     a.target = 0;
+    a.cache_use = c->mvalid ? 1 : 0;
     HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
     HIPCHK(c, launch_bond_groups(bond_args(c, c->L.pos), c->ngroups, c->gcap, 1, 0, n, dt, c->st));
     if ((s = lattice_pass(c)) != LB_OK) return s;
@@ -430,7 +449,9 @@ static lb_status step_once(lb_ctx* c) {
     a = part_args(c);
     a.phys = 0;
     a.target = 1;
+    a.cache_fill = 1;
     HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
+    c->mvalid = true;
     return LB_OK;
   }
   // Alg. 3: P^1/2, F_int, coupling half (+ spread A), LB, coupling half (+ spread B), P^1/2
@@ -440,6 +461,7 @@ static lb_status step_once(lb_ctx* c) {
   PartArgs a = part_args(c);
   a.use_fint = any ? 1 : 0;
   a.target = 0;
+  a.cache_use = c->mvalid ? 1 : 0;
   HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
   if ((s = lattice_pass(c)) != LB_OK) return s;
   a = part_args(c);
@@ -447,7 +469,9 @@ static lb_status step_once(lb_ctx* c) {
   a.phys = 0;
   a.target = 1;
   a.drift_after = 1;
+  a.cache_fill = 1;
   HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
+  c->mvalid = true;
   return LB_OK;
 }
 
@@ -535,14 +559,16 @@ extern "C" {
 
 lb_status lb_init_fluid(lb_ctx* c, const double* d_rho, const double* d_u) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (c->running) return fail(c, LB_ESTATE, "an ensemble slot is initialised before its first step");
   InitArgs a{c->geo, c->L.f[0], d_rho, d_u, c->p.rho0, c->scale};
   c->cur = 0;
   HIPCHK(c, launch_init(c->p.storage, a, c->st));
   const size_t vb = (size_t)c->geo.N * force_vec_bytes(c->p.storage);
   HIPCHK(c, hipMemsetAsync(c->L.FA, 0, vb, c->st));
   HIPCHK(c, hipMemsetAsync(c->L.FB, 0, vb, c->st));
-  HIPCHK(c, hipMemsetAsync(c->L.mask, 0, (size_t)c->geo.nz * c->geo.ny * c->geo.wpr * 8, c->st));
+  HIPCHK(c, hipMemsetAsync(c->L.mask, 0, mask_words(c->g) * 8, c->st));
   c->pend = 0;
+  c->mvalid = false;
   c->uref[0] = c->uref[1] = c->uref[2] = 0.0;
   return LB_OK;
 }
@@ -550,6 +576,7 @@ lb_status lb_init_fluid(lb_ctx* c, const double* d_rho, const double* d_u) {
 lb_status lb_set_particles(lb_ctx* c, int64_t n, const double* d_pos, const double* d_vel,
                            const double* d_mass) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (c->running) return fail(c, LB_ESTATE, "an ensemble slot is given particles before its first step");
   if (n < 0) return fail(c, LB_EINVAL, "negative particle count");
   if (n > c->lim.max_particles) return fail(c, LB_ENOMEM, "more particles than max_particles");
   const bool massive = c->p.coupling == LB_COUPLE_FC || c->p.coupling == LB_COUPLE_EBF;
@@ -574,6 +601,7 @@ lb_status lb_set_particles(lb_ctx* c, int64_t n, const double* d_pos, const doub
   c->np = n;
   c->groups_dirty = true;
   c->binned_at = -1;
+  c->mvalid = false;
   return LB_OK;
 }
 
@@ -831,6 +859,9 @@ static EnsSlot slot_from_ctx(const lb_ctx* c) {
   s.live = 1;
   s.comoving = c->p.comoving;
   for (int k = 0; k < 3; ++k) s.uref[k] = c->uref[k];
+  s.mcache = c->L.mcache;
+  s.mbase = c->L.mbase;
+  s.mvalid = 0;
   return s;
 }
 
@@ -854,8 +885,7 @@ static lb_status ens_refresh(lb_ensemble* e) {
       hs[i] = slot_from_ctx(h.ctx);
       hs[i].steps_target = h.target;
       h.fresh = false;
-    } else {
-      hs[i].np = h.ctx->np;  // particles may have been replaced
+      h.ctx->running = true;
     }
     const long long nch = (h.ctx->geo.N + 255) / 256;
     for (long long k = 0; k < nch; ++k) li.push_back(make_int2(i, (int)k));

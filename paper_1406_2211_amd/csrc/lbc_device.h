@@ -150,6 +150,17 @@ __device__ __forceinline__ void pull(const typename Store<S>::T* __restrict__ f,
   }
 }
 
+// The pending half force of site s added to its momentum: rho u = sum f c +
+// (h/2)(FB + pend F_ext) (the redefined velocity of Sec. 4).
+template <int S>
+__device__ __forceinline__ void add_pending(const SiteArgs& a, long long s, double j[3]) {
+  using V4 = typename Store<S>::V4;
+  const V4 fb = ((const V4*)a.FB)[s];
+  j[0] += 0.5 * ((double)fb.x + a.pfx);
+  j[1] += 0.5 * ((double)fb.y + a.pfy);
+  j[2] += 0.5 * ((double)fb.z + a.pfz);
+}
+
 // Physical moments at one site: rho and rho u = sum f c + (h/2)(FB + pend F_ext)
 // (the redefined velocity of Sec. 4).
 template <int S>
@@ -170,14 +181,7 @@ __device__ __forceinline__ void site_phys(const SiteArgs& a, int x, int y, int z
     j[1] += CY[i] * fl[i];
     j[2] += CZ[i] * fl[i];
   }
-  if (phys) {
-    const long long s = site_index(a.g, x, y, z);
-    using V4 = typename St::V4;
-    const V4 fb = ((const V4*)a.FB)[s];
-    j[0] += 0.5 * ((double)fb.x + a.pfx);
-    j[1] += 0.5 * ((double)fb.y + a.pfy);
-    j[2] += 0.5 * ((double)fb.z + a.pfz);
-  }
+  if (phys) add_pending<S>(a, site_index(a.g, x, y, z), j);
 }
 
 // deviation equilibrium f^eq_i(rho,u) - w_i rho0 = w_i [drho + rho P_i(u)],
@@ -294,6 +298,12 @@ __device__ __forceinline__ double phi_eval(int K, double r) {
   if (a <= 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * r * r)) / 8.0;
   if (a <= 2.0) return (5.0 - 2.0 * a - sqrt(fmax(0.0, -7.0 + 12.0 * a - 4.0 * r * r))) / 8.0;
   return 0.0;
+}
+
+// First node of the K-point stencil of X: nodes j0 .. j0+K-1.
+template <int K>
+__device__ __forceinline__ int first_node(double X) {
+  return K == 3 ? (int)floor(X + 0.5) - 1 : (K == 2 ? (int)floor(X) : (int)floor(X) - 1);
 }
 
 __device__ __forceinline__ int stencil(int K, double X, double w[4]) {

@@ -74,6 +74,14 @@ struct PartArgs {
   int phys;         // interpolate the physical velocity (with pending FB)
   int target;       // spread into FA (0) or FB (1)
   int drift_after;  // final P^1/2 of Alg. 3
+  // Moment cache: the second coupling half stores, per particle and stencil
+  // node, the moments it gathered; the next step's first half reads the same
+  // populations (no lattice pass in between) and reuses them when the
+  // particle's first stencil node is unchanged.
+  double4* mcache;  // [n][L] (drho, j) of each node, before the pending force
+  int4* mbase;      // [n] first stencil node (x, y, z) of the cached entries
+  int cache_use;    // first half: cached entries are current
+  int cache_fill;   // second half: store the gathered moments
 };
 
 struct BondArgs {
@@ -145,6 +153,9 @@ struct EnsSlot {
   int live;
   int comoving;
   double uref[3];  // storage reference velocity of f[cur]
+  double4* mcache;  // coupling moment cache (see PartArgs)
+  int4* mbase;
+  int mvalid;       // the cache holds the state of f[cur]
 };
 
 struct EnsArgs {

@@ -227,52 +227,76 @@ __global__ __launch_bounds__(256) void k_totals_final(const double* partial, int
 // values and evaluates the (cheap, FP64) coupling update redundantly.
 // ======================================================================
 struct SiteSlot {
-  bool valid;
+  bool site;   // the node lies in the box (not beyond a wall)
+  bool valid;  // ... and carries a nonzero weight
   double W;
-  int x, y, z;
+  int x, y, z;  // wrapped node
+  int j0[3];    // first stencil node, unwrapped
 };
 
 template <int K>
 __device__ __forceinline__ SiteSlot slot_of(const Geo& g, const double X[3], int lane) {
-  SiteSlot s{false, 0.0, 0, 0, 0};
+  SiteSlot s{false, false, 0.0, 0, 0, 0, {0, 0, 0}};
+  for (int a = 0; a < 3; ++a) s.j0[a] = first_node<K>(X[a]);
   if (lane >= K * K * K) return s;
   const int kx = lane % K, ky = (lane / K) % K, kz = lane / (K * K);
-  double w[4];
-  const int jx = stencil(K, X[0], w);
-  const double wx = w[kx];
-  const int jy = stencil(K, X[1], w);
-  const double wy = w[ky];
-  const int jz = stencil(K, X[2], w);
-  const double wz = w[kz];
-  int yy = jy + ky;
+  int yy = s.j0[1] + ky;
   if (g.wall) {
     if (yy < 0 || yy >= g.ny) return s;  // beyond a wall: no weight
   } else {
     yy = wrap_idx(yy, g.ny);
   }
-  s.W = wx * wy * wz;
+  s.W = phi_eval(K, (double)(s.j0[0] + kx) - X[0]) * phi_eval(K, (double)(s.j0[1] + ky) - X[1]) *
+        phi_eval(K, (double)(s.j0[2] + kz) - X[2]);
+  s.site = true;
   s.valid = s.W != 0.0;
-  s.x = wrap_idx(jx + kx, g.nx);
+  s.x = wrap_idx(s.j0[0] + kx, g.nx);
   s.y = yy;
-  s.z = wrap_idx(jz + kz, g.nz);
+  s.z = wrap_idx(s.j0[2] + kz, g.nz);
   return s;
 }
 
+// Interpolated rho_p and u_p of particle p at X.  With a.cache_fill (second
+// coupling half, post-stream moments without the pending force) every node in
+// the box stores its gathered moments, also at zero weight, so that a later
+// position with the same first node finds all of them; with a.cache_use and
+// an unchanged first node the cached moments replace the gather, and the
+// pending half force is added exactly as the gather would add it.
 template <int S, int K>
 __device__ __forceinline__ void group_interp(const PartArgs& a, const double X[3], bool phys,
-                                             int lane, double& rp, double up[3]) {
+                                             int lane, double& rp, double up[3], long long p) {
   constexpr int L = Lanes<K>::L;
   const SiteSlot sl = slot_of<K>(a.s.g, X, lane);
-  double r = 0, ux = 0, uy = 0, uz = 0;
-  if (sl.valid) {
-    double fl[Q], drho, j[3];
-    site_phys<S>(a.s, sl.x, sl.y, sl.z, fl, drho, j, phys);
-    const double rr = a.s.rho0 + drho;
-    r = sl.W * rr;
-    ux = sl.W * j[0] / rr;
-    uy = sl.W * j[1] / rr;
-    uz = sl.W * j[2] / rr;
+  const bool fill = a.cache_fill != 0 && !phys;
+  bool hit = false;
+  if (a.cache_use) {
+    const int4 b = a.mbase[p];
+    hit = b.x == sl.j0[0] && b.y == sl.j0[1] && b.z == sl.j0[2];
   }
+  double r = 0, ux = 0, uy = 0, uz = 0;
+  if (sl.site && (sl.valid || fill)) {
+    double drho, j[3];
+    if (hit) {
+      const double4 m = a.mcache[p * L + lane];
+      drho = m.x;
+      j[0] = m.y;
+      j[1] = m.z;
+      j[2] = m.w;
+      if (phys) add_pending<S>(a.s, site_index(a.s.g, sl.x, sl.y, sl.z), j);
+    } else {
+      double fl[Q];
+      site_phys<S>(a.s, sl.x, sl.y, sl.z, fl, drho, j, phys);
+      if (fill) a.mcache[p * L + lane] = make_double4(drho, j[0], j[1], j[2]);
+    }
+    if (sl.valid) {
+      const double rr = a.s.rho0 + drho;
+      r = sl.W * rr;
+      ux = sl.W * j[0] / rr;
+      uy = sl.W * j[1] / rr;
+      uz = sl.W * j[2] / rr;
+    }
+  }
+  if (fill && lane == 0) a.mbase[p] = make_int4(sl.j0[0], sl.j0[1], sl.j0[2], 0);
   rp = group_sum<L>(r);
   up[0] = group_sum<L>(ux);
   up[1] = group_sum<L>(uy);
@@ -336,7 +360,7 @@ __global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
   }
   const double m = a.mass[p];
   double rp, up[3];
-  group_interp<S, K>(a, r, a.phys != 0, lane, rp, up);
+  group_interp<S, K>(a, r, a.phys != 0, lane, rp, up, p);
   const double hh = 0.5, al = a.gamma * hh / m, be = a.gamma * hh / rp;
   double Fh[3];
   if (a.coupling == LB_COUPLE_FC) {
@@ -374,7 +398,7 @@ __global__ __launch_bounds__(256) void k_ib_predict(PartArgs a) {
   const int lane = (int)(gid % L);
   if (p >= a.n) return;
   double X[3] = {a.pos[3 * p], a.pos[3 * p + 1], a.pos[3 * p + 2]}, rp, up[3];
-  group_interp<S, K>(a, X, true, lane, rp, up);
+  group_interp<S, K>(a, X, true, lane, rp, up, p);
   if (lane == 0) {
     for (int k = 0; k < 3; ++k) X[k] += 0.5 * up[k];
     wrap3(a.s.g, X);
@@ -394,7 +418,7 @@ __global__ __launch_bounds__(256) void k_ib_advect(PartArgs a, int spread_fint) 
   if (p >= a.n) return;
   const double Xt[3] = {a.aux[3 * p], a.aux[3 * p + 1], a.aux[3 * p + 2]};
   double rp, up[3];
-  group_interp<S, K>(a, Xt, true, lane, rp, up);
+  group_interp<S, K>(a, Xt, true, lane, rp, up, p);
   if (lane == 0) {
     double X[3];
     for (int k = 0; k < 3; ++k) X[k] = a.pos[3 * p + k] + 0.5 * up[k];
@@ -969,6 +993,10 @@ __global__ __launch_bounds__(256) void k_ens_couple(EnsArgs e, int half) {
     a.FB = sl.FB;
     a.mask = sl.mask;
     a.K = K;
+    a.mcache = sl.mcache;
+    a.mbase = sl.mbase;
+    a.cache_use = half == 0 ? sl.mvalid : 0;
+    a.cache_fill = half == 1 ? 1 : 0;
     const double hh = 0.5;
     double r[3], v[3];
     for (int k = 0; k < 3; ++k) {
@@ -981,7 +1009,7 @@ __global__ __launch_bounds__(256) void k_ens_couple(EnsArgs e, int half) {
     }
     const double m = sl.mass[p];
     double rp, up[3];
-    group_interp<S, K>(a, r, half == 0, lane, rp, up);
+    group_interp<S, K>(a, r, half == 0, lane, rp, up, p);
     const double al = sl.gamma * hh / m, be = sl.gamma * hh / rp;
     double Fh[3];
     if (sl.coupling == LB_COUPLE_FC) {
@@ -1021,6 +1049,7 @@ __global__ void k_ens_advance(EnsArgs e) {
   sl.cur = 1 - sl.cur;
   sl.pend = 1;
   sl.steps_done += 1;
+  if (sl.coupling != LB_COUPLE_NONE && sl.np > 0) sl.mvalid = 1;  // filled by the second half
   if (sl.comoving) {
     sl.uref[0] += sl.fx / sl.rho0;
     sl.uref[1] += sl.fy / sl.rho0;

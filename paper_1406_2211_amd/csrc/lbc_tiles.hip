@@ -153,11 +153,6 @@ struct Node {
 };
 
 template <int K>
-__device__ __forceinline__ int first_node(double X) {
-  return K == 3 ? (int)floor(X + 0.5) - 1 : (K == 2 ? (int)floor(X) : (int)floor(X) - 1);
-}
-
-template <int K>
 __device__ __forceinline__ Node<K> node_of(const Region& r, const double X[3], int lane) {
   Node<K> n;
   const int k[3] = {lane % K, (lane / K) % K, lane / (K * K)};

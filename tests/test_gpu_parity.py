@@ -99,6 +99,23 @@ def test_particles_at_periodic_seam_phi4():
     check(c, TOL64)
 
 
+@pytest.mark.parametrize("kernel,coupling", [(2, 1), (3, 2), (4, 1)])
+def test_moment_cache_zero_weight_nodes_and_cell_crossings(kernel, coupling):
+    """The second coupling half caches the moments it gathers; the next first
+    half reuses them while a particle's first stencil node is unchanged.
+    Particle 0 sits exactly on a zero-weight node boundary along x at the
+    first midpoint (so one node of its cached stencil has zero weight, and a
+    nonzero weight one step later); particle 1 crosses cells every few steps
+    (cache misses); particle 2 is slow."""
+    xs = 10.0 if kernel != 3 else 10.5  # phi2/phi4: integer; phi3: half-integer
+    pos = np.array([[xs - 0.125, 6.3, 9.7], [3.2, 12.9, 4.4], [8.1, 2.2, 13.6]])
+    vel = np.array([[0.25, 0.0, 0.0], [0.35, -0.3, 0.2], [1e-3, -2e-3, 3e-3]])
+    c = Case(name=f"mcache_k{kernel}", nx=16, ny=16, nz=16, tau=0.75, steps=25,
+             coupling=coupling, gamma=0.7, kernel=kernel, pos=pos, vel=vel, mass=np.ones(3),
+             u_noise=1e-3, seed=8)
+    check(c, TOL64)
+
+
 def test_mts_stiff_chains_fp64():
     """The bead-spring parameters of the force-coupling workload (k = 30):
     ill-conditioned, so the bound follows the oracle's one-ulp sensitivity."""
