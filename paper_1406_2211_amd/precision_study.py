@@ -41,7 +41,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, nargs="+", default=[100, 1000, 5000])
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--f16-scale-log2", type=int, default=24)
+    # FP16 scale 2^p: the largest stored deviation of this workload is about
+    # 3e-3 (the chains' initial kick, step ~100), so p = 20 puts it near 2^12
+    ap.add_argument("--f16-scale-log2", type=int, default=20)
     a = ap.parse_args()
     ck = sorted(a.steps)
     t0 = time.time()
