@@ -377,6 +377,7 @@ static lb_status lattice_pass(lb_ctx* c) {
   a.inv = c->inv;
   a.rnx = 1.0 / c->geo.nx;
   a.rny = 1.0 / c->geo.ny;
+  a.clear_mask = c->steps % kMaskKeep == 0 ? 1 : 0;
   for (int k = 0; k < 3; ++k) {
     a.uin[k] = c->uref[k];
     a.uout[k] = c->uref[k] + (c->p.comoving ? c->p.body_force[k] / c->p.rho0 : 0.0);

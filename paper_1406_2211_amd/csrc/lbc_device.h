@@ -92,10 +92,18 @@ __device__ __forceinline__ long long site_index(const Geo& g, int x, int y, int 
   return ((long long)z * g.ny + y) * g.nx + x;
 }
 
-// Force-mask word and bit of a site.  Single contexts keep one word per 64
-// x-sites of a row (wpr words per row, so a row-aligned wavefront owns its
-// word); ensemble slots (wpr == 0) use one word per 64 consecutive linear
-// site indices.
+// Force-mask word and bit of a site.  Boxes whose x extent is a multiple of
+// 64 keep one word per 64 x-sites of a row (wpr words per row, so a
+// row-aligned wavefront owns its word); other boxes and ensemble slots
+// (wpr == 0) use one word per 64 consecutive linear site indices.
+//
+// A set bit means: the lattice pass reads (and zeroes) FA and FB at this
+// site.  Bits persist across steps and are cleared by the lattice pass only
+// every kMaskKeep steps, so a particle that keeps touching the same sites
+// finds its bits set and spreads without an atomic on the mask; a bit that
+// is no longer needed costs the pass one read of zeros until the next clear.
+constexpr int kMaskKeep = 32;
+
 __device__ __forceinline__ uint64_t* mask_word(uint64_t* m, const Geo& g, int x, int y, int z,
                                                uint64_t& bit) {
   if (g.wpr == 0) {
@@ -105,6 +113,12 @@ __device__ __forceinline__ uint64_t* mask_word(uint64_t* m, const Geo& g, int x,
   }
   bit = 1ull << (x & 63);
   return m + ((long long)z * g.ny + y) * g.wpr + (x >> 6);
+}
+
+// Flag a site for the next lattice pass (after its force was added): a plain
+// load first, since in steady state the bit is usually set already.
+__device__ __forceinline__ void flag_site(uint64_t* mw, uint64_t bit) {
+  if (!(__atomic_load_n(mw, __ATOMIC_RELAXED) & bit)) atomicOr((unsigned long long*)mw, bit);
 }
 
 // Quotient and remainder of n / d for 32-bit n and d >= 1, with rd = 1/d

@@ -34,6 +34,7 @@ struct LatArgs {
   double uin[3];      // storage reference velocity of fin (comoving frame; 0 otherwise)
   double uout[3];     // storage reference velocity of fout
   double rnx, rny;    // 1/nx, 1/ny (linear-site pass)
+  int clear_mask;     // clear the force mask after reading it (every kMaskKeep steps)
 };
 
 struct InitArgs {

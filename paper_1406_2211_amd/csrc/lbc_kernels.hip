@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
       FA[own] = zero;
       FB[own] = zero;
     }
-    if ((x & 63) == 0) *mp = 0;
+    if ((x & 63) == 0 && a.clear_mask) *mp = 0;
   }
   PassK<R> k;
   k.rho0 = R(a.rho0);
@@ -314,8 +314,7 @@ __device__ __forceinline__ void group_spread(const PartArgs& a, const double X[3
   unsafeAtomicAdd(Fd + 4 * s + 1, (E)(sl.W * F[1]));
   unsafeAtomicAdd(Fd + 4 * s + 2, (E)(sl.W * F[2]));
   uint64_t bit;
-  uint64_t* mw = mask_word(a.mask, a.s.g, sl.x, sl.y, sl.z, bit);
-  atomicOr((unsigned long long*)mw, bit);
+  flag_site(mask_word(a.mask, a.s.g, sl.x, sl.y, sl.z, bit), bit);
 }
 
 __device__ __forceinline__ void wrap3(const Geo& g, double r[3]) {
@@ -849,6 +848,7 @@ struct LatView {
   __device__ double omm() const { return a.omm; }
   __device__ double uin(int c) const { return a.uin[c]; }
   __device__ double uout(int c) const { return a.uout[c]; }
+  __device__ bool clear_mask() const { return a.clear_mask != 0; }
 };
 
 struct SlotView {
@@ -873,6 +873,7 @@ struct SlotView {
   __device__ double uout(int c) const {
     return s.uref[c] + (c == 0 ? s.fx : (c == 1 ? s.fy : s.fz)) / s.rho0;
   }
+  __device__ bool clear_mask() const { return s.steps_done % kMaskKeep == 0; }
 };
 
 template <int S, bool CM, bool WALL, class V>
@@ -917,7 +918,7 @@ __device__ __forceinline__ void linear_site(const V& v, uint32_t s) {
       FA[s] = zero;
       FB[s] = zero;
     }
-    if ((s & 63) == 0) *mp = 0;
+    if ((s & 63) == 0 && v.clear_mask()) *mp = 0;
   }
   PassK<R> k;
   k.rho0 = R(v.rho0());

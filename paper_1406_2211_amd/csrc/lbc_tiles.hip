@@ -17,8 +17,8 @@
 //   stencil site and a butterfly reduction over the lane group.
 //   spreading (Eq. IBM-spreading): markers add W F into an LDS accumulator of
 //   the region (LDS atomics, one lane per stencil site); the workgroup then
-//   adds every nonzero region site to the global force field once and sets
-//   its mask bit.
+//   adds every nonzero region site to the global force field once and flags
+//   it for the lattice pass.
 // Workgroups have 1024 lanes so that staging and flushing a region take two
 // rounds of loads with sixteen wavefronts in flight.
 #include "lbc_device.h"
@@ -310,8 +310,7 @@ __global__ __launch_bounds__(1024) void k_tile_spread(TileArgs t, const double* 
       unsafeAtomicAdd(Fd + 4 * sidx + 1, f1);
       unsafeAtomicAdd(Fd + 4 * sidx + 2, f2);
       uint64_t bit;
-      uint64_t* mw = mask_word(t.mask, t.g, x, y, z, bit);
-      atomicOr((unsigned long long*)mw, bit);
+      flag_site(mask_word(t.mask, t.g, x, y, z, bit), bit);
     }
   }
   __syncthreads();
@@ -326,8 +325,7 @@ __global__ __launch_bounds__(1024) void k_tile_spread(TileArgs t, const double* 
     unsafeAtomicAdd(Fd + 4 * sidx + 1, a1);
     unsafeAtomicAdd(Fd + 4 * sidx + 2, a2);
     uint64_t bit;
-    uint64_t* mw = mask_word(t.mask, t.g, x, y, z, bit);
-    atomicOr((unsigned long long*)mw, bit);
+    flag_site(mask_word(t.mask, t.g, x, y, z, bit), bit);
   }
 }
 
