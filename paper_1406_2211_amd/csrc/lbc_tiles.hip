@@ -3,24 +3,27 @@
 //
 // Markers are binned into 8x8x8 lattice tiles by the cell containing them
 // (counting sort: count, single-block scan that also lists the occupied tiles
-// in increasing order, scatter).  A workgroup then owns one occupied tile and
-// works on a staged region of 12^3 sites: the tile and two sites on each side.
-// That covers the 2-, 3- and 4-point stencils of every marker binned into the
-// tile, also after it has moved down by up to one lattice spacing or up within
-// its cell, so one binning serves the whole time step.  A marker whose stencil
-// leaves the region (it crossed the upper cell face or a periodic seam) takes
-// the direct path that gathers from global memory.
+// in increasing order, scatter).  Workgroups loop over the occupied tiles;
+// for each they work on a staged region of 12^3 sites: the tile and two sites
+// on each side.  That covers the 2-, 3- and 4-point stencils of every marker
+// binned into the tile, also after it has moved down by up to one lattice
+// spacing or up within its cell.  A marker whose stencil leaves the region
+// (it crossed the upper cell face or a periodic seam, or the binning is a few
+// steps old) takes the direct path that gathers from global memory.  The
+// markers of a tile are staged in LDS too, in chunks.
 //
 //   interpolation (Eq. IBM-interpolation): physical moments rho, u of every
 //   region site are computed once (pull gather + pending half force) into LDS
 //   in FP64; each marker then sums K^3 weighted LDS entries, one lane per
-//   stencil site and a butterfly reduction over the lane group.
-//   spreading (Eq. IBM-spreading): markers add W F into an LDS accumulator of
-//   the region (LDS atomics, one lane per stencil site); the workgroup then
-//   adds every nonzero region site to the global force field once and flags
-//   it for the lattice pass.
+//   x-row of stencil nodes and a butterfly reduction over the lane group.
+//   spreading (Eq. IBM-spreading): markers add W F into an FP64 LDS
+//   accumulator of the region (LDS atomics, one lane per stencil site); the
+//   workgroup then adds every nonzero region site to the global force field
+//   once and flags it for the lattice pass.
 // Workgroups have 1024 lanes so that staging and flushing a region take two
 // rounds of loads with sixteen wavefronts in flight.
+#include <algorithm>
+
 #include "lbc_device.h"
 #include "lbc_internal.h"
 
@@ -182,6 +185,81 @@ __device__ __forceinline__ bool node_site(const Geo& g, const int j[3], int& x, 
   return true;
 }
 
+// Interpolation lane groups: one lane per x-row of stencil nodes (ky, kz),
+// K^2 rows rounded up to a power of two (4 lanes for K = 2, 16 for K = 3, 4).
+template <int K>
+struct RowLanes {
+  static constexpr int L = K == 2 ? 4 : 16;
+};
+
+// Weighted sum over the lane's row of K nodes of the region moments (or of
+// gathered moments when the stencil leaves the region), reduced over the
+// marker's lane group: u_p = sum_nodes W u(node), W = phi(x) phi(y) phi(z).
+template <int S, int K>
+__device__ __forceinline__ void row_interp(const SiteArgs& s, const Region& r, const double4* mom,
+                                           const double X[3], int lane, double up[3]) {
+  constexpr int L = RowLanes<K>::L;
+  const int ky = lane % K, kz = lane / K;
+  int j0[3];
+  bool inside = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    j0[a] = first_node<K>(X[a]);
+    inside = inside && j0[a] - r.o[a] >= 0 && j0[a] - r.o[a] + K <= kReg;
+  }
+  double ux = 0, uy = 0, uz = 0;
+  if (lane < K * K) {
+    double wx[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) wx[k] = phi_eval(K, (double)(j0[0] + k) - X[0]);
+    const double wy = phi_eval(K, (double)(j0[1] + ky) - X[1]);
+    const double wz = phi_eval(K, (double)(j0[2] + kz) - X[2]);
+    if (inside) {
+      const double4* row =
+          mom + ((j0[2] + kz - r.o[2]) * kReg + (j0[1] + ky - r.o[1])) * kReg + (j0[0] - r.o[0]);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double W = wx[k] * wy * wz;
+        if (W == 0.0) continue;
+        const double4 m = row[k];
+        if (m.x == 0.0) continue;  // beyond a wall
+        ux += W * m.y;
+        uy += W * m.z;
+        uz += W * m.w;
+      }
+    } else {
+      const int jy = j0[1] + ky;
+      const bool in_y = !s.g.wall || (jy >= 0 && jy < s.g.ny);
+      for (int k = 0; k < K && in_y; ++k) {
+        const double W = wx[k] * wy * wz;
+        if (W == 0.0) continue;
+        const int x = wrap_idx(j0[0] + k, s.g.nx), z = wrap_idx(j0[2] + kz, s.g.nz);
+        const int y = s.g.wall ? jy : wrap_idx(jy, s.g.ny);
+        double fl[Q], drho, j[3];
+        site_phys<S>(s, x, y, z, fl, drho, j, true);
+        const double rr = s.rho0 + drho;
+        ux += W * (j[0] / rr);
+        uy += W * (j[1] / rr);
+        uz += W * (j[2] / rr);
+      }
+    }
+  }
+  up[0] = group_sum<L>(ux);
+  up[1] = group_sum<L>(uy);
+  up[2] = group_sum<L>(uz);
+}
+
+// Markers of the tile being processed, staged in LDS in chunks of kChunk
+// (index and the positions and forces the kernel reads), so that the marker
+// loops never wait on dependent global loads.
+constexpr int kChunk = 256;
+
+struct MarkerLds {
+  int p[kChunk];
+  double X[kChunk][3];  // position the stencil is built at
+  double Y[kChunk][3];  // second vector: pos (interpolation) or force (spreading)
+};
+
 // ------------------------------------------------------------- interpolation
 // mode 0: IB predictor       aux = wrap(pos + h/2 u(pos))
 // mode 1: IB advection       pos = wrap(pos + h/2 u(aux))
@@ -189,143 +267,153 @@ __device__ __forceinline__ bool node_site(const Geo& g, const int j[3], int& x, 
 //         advection only needs the state before the lattice pass, like the
 //         predictor, so both read the same LDS moments.
 // A marker whose stencil leaves the region gathers its nodes from global
-// memory instead (same arithmetic per node).
+// memory instead (same arithmetic per node).  Workgroups loop over the
+// occupied tiles (persistent grid).
 template <int S, int K>
 __global__ __launch_bounds__(1024) void k_tile_interp(TileArgs t, SiteArgs s, const double* at,
                                                       double* pos, double* aux, int mode) {
-  constexpr int L = Lanes<K>::L;
+  constexpr int L = RowLanes<K>::L;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double4* mom = (double4*)lds_raw;  // kRegSites
-  if ((int)blockIdx.x >= t.nocc[0]) return;
-  const int tl = t.occ[blockIdx.x];
-  const Region r = region_of(t, tl);
-  for (int k = threadIdx.x; k < kRegSites; k += blockDim.x) {
-    const int ix = k % kReg, iy = (k / kReg) % kReg, iz = k / (kReg * kReg);
-    int x, y, z;
-    double4 m = make_double4(0, 0, 0, 0);
-    if (slot_site(s.g, r, ix, iy, iz, x, y, z)) {
-      double fl[Q], drho, j[3];
-      site_phys<S>(s, x, y, z, fl, drho, j, true);
-      const double rr = s.rho0 + drho;
-      m = make_double4(rr, j[0] / rr, j[1] / rr, j[2] / rr);
-    }
-    mom[k] = m;
-  }
-  __syncthreads();
+  double4* mom = (double4*)lds_raw;                                    // kRegSites
+  MarkerLds* mk = (MarkerLds*)(lds_raw + sizeof(double4) * kRegSites);  // one chunk
   const int lane = threadIdx.x % L;
-  auto interp_at = [&](const double X[3], double up[3]) {
-    const Node<K> n = node_of<K>(r, X, lane);
-    double ux = 0, uy = 0, uz = 0;
-    if (n.on) {
-      if (n.inside) {
-        const double4 m = mom[n.slot];
-        if (m.x != 0.0) {  // zero beyond a wall
-          ux = n.W * m.y;
-          uy = n.W * m.z;
-          uz = n.W * m.w;
+  const int nocc = t.nocc[0];
+  for (int ot = blockIdx.x; ot < nocc; ot += gridDim.x) {
+    const int tl = t.occ[ot];
+    const Region r = region_of(t, tl);
+    for (int k = threadIdx.x; k < kRegSites; k += blockDim.x) {
+      const int ix = k % kReg, iy = (k / kReg) % kReg, iz = k / (kReg * kReg);
+      int x, y, z;
+      double4 m = make_double4(0, 0, 0, 0);
+      if (slot_site(s.g, r, ix, iy, iz, x, y, z)) {
+        double fl[Q], drho, j[3];
+        site_phys<S>(s, x, y, z, fl, drho, j, true);
+        const double rr = s.rho0 + drho;
+        m = make_double4(rr, j[0] / rr, j[1] / rr, j[2] / rr);
+      }
+      mom[k] = m;
+    }
+    auto interp_at = [&](const double X[3], double up[3]) {
+      row_interp<S, K>(s, r, mom, X, lane, up);
+    };
+    auto half_drift = [&](const double from[3], const double u[3], double to[3]) {
+      for (int a = 0; a < 3; ++a) to[a] = from[a] + 0.5 * u[a];
+      to[0] = wrap_pos(to[0], (double)s.g.nx);
+      if (!s.g.wall) to[1] = wrap_pos(to[1], (double)s.g.ny);
+      to[2] = wrap_pos(to[2], (double)s.g.nz);
+    };
+    const int b0 = t.start[tl], b1 = t.start[tl + 1];
+    for (int c0 = b0; c0 < b1; c0 += kChunk) {
+      const int nc = min(kChunk, b1 - c0);
+      __syncthreads();  // previous chunk (or region staging) done with mk
+      for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+        const int p = t.sorted[c0 + i];
+        mk->p[i] = p;
+        for (int a = 0; a < 3; ++a) {
+          mk->X[i][a] = at[3 * (long long)p + a];
+          mk->Y[i][a] = mode == 1 ? pos[3 * (long long)p + a] : 0.0;
         }
-      } else {
-        int x, y, z;
-        if (node_site(s.g, n.j, x, y, z)) {
-          double fl[Q], drho, j[3];
-          site_phys<S>(s, x, y, z, fl, drho, j, true);
-          const double rr = s.rho0 + drho;
-          ux = n.W * j[0] / rr;
-          uy = n.W * j[1] / rr;
-          uz = n.W * j[2] / rr;
+      }
+      __syncthreads();
+      for (int i = (int)threadIdx.x / L; i < nc; i += (int)blockDim.x / L) {  // groups leave together
+        const long long p = mk->p[i];
+        const double X[3] = {mk->X[i][0], mk->X[i][1], mk->X[i][2]};
+        double up[3], Y[3];
+        interp_at(X, up);
+        if (mode == 0) {  // predictor only
+          half_drift(X, up, Y);
+          if (lane == 0)
+            for (int a = 0; a < 3; ++a) aux[3 * p + a] = Y[a];
+        } else if (mode == 1) {  // advection with the velocity at X~ = at
+          const double P[3] = {mk->Y[i][0], mk->Y[i][1], mk->Y[i][2]};
+          half_drift(P, up, Y);
+          if (lane == 0)
+            for (int a = 0; a < 3; ++a) pos[3 * p + a] = Y[a];
+        } else {  // mode 2: predictor, then the first advection from the same staged state
+          double Xt[3], u2[3];
+          half_drift(X, up, Xt);
+          interp_at(Xt, u2);
+          half_drift(X, u2, Y);
+          if (lane == 0)
+            for (int a = 0; a < 3; ++a) {
+              aux[3 * p + a] = Xt[a];
+              pos[3 * p + a] = Y[a];
+            }
         }
       }
     }
-    up[0] = group_sum<L>(ux);
-    up[1] = group_sum<L>(uy);
-    up[2] = group_sum<L>(uz);
-  };
-  auto half_drift = [&](const double from[3], const double u[3], double to[3]) {
-    for (int a = 0; a < 3; ++a) to[a] = from[a] + 0.5 * u[a];
-    to[0] = wrap_pos(to[0], (double)s.g.nx);
-    if (!s.g.wall) to[1] = wrap_pos(to[1], (double)s.g.ny);
-    to[2] = wrap_pos(to[2], (double)s.g.nz);
-  };
-  const int b0 = t.start[tl], b1 = t.start[tl + 1];
-  for (int q = b0 + (int)threadIdx.x / L; q < b1; q += (int)blockDim.x / L) {  // groups leave together
-    const long long p = t.sorted[q];
-    const double X[3] = {at[3 * p], at[3 * p + 1], at[3 * p + 2]};
-    double up[3], Y[3];
-    interp_at(X, up);
-    if (mode == 0) {  // predictor only
-      half_drift(X, up, Y);
-      if (lane == 0)
-        for (int a = 0; a < 3; ++a) aux[3 * p + a] = Y[a];
-    } else if (mode == 1) {  // advection with the velocity at X~ = at
-      const double P[3] = {pos[3 * p], pos[3 * p + 1], pos[3 * p + 2]};
-      half_drift(P, up, Y);
-      if (lane == 0)
-        for (int a = 0; a < 3; ++a) pos[3 * p + a] = Y[a];
-    } else {  // mode 2: predictor, then the first advection from the same staged state
-      double Xt[3], u2[3];
-      half_drift(X, up, Xt);
-      interp_at(Xt, u2);
-      half_drift(X, u2, Y);
-      if (lane == 0)
-        for (int a = 0; a < 3; ++a) {
-          aux[3 * p + a] = Xt[a];
-          pos[3 * p + a] = Y[a];
-        }
-    }
+    __syncthreads();  // region moments are overwritten by the next tile
   }
 }
 
 // ------------------------------------------------------------------ spreading
+// The region accumulator is FP64 whatever the field precision: LDS atomic
+// adds run several times faster in FP64 than in FP32 on this device.
 template <typename E, int K>
 __global__ __launch_bounds__(1024) void k_tile_spread(TileArgs t, const double* at,
                                                       const double* F, void* field) {
   constexpr int L = Lanes<K>::L;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  E* acc = (E*)lds_raw;  // 3 * kRegSites
-  if ((int)blockIdx.x >= t.nocc[0]) return;
-  const int tl = t.occ[blockIdx.x];
-  const Region r = region_of(t, tl);
-  for (int k = threadIdx.x; k < 3 * kRegSites; k += blockDim.x) acc[k] = E(0);
-  __syncthreads();
+  MarkerLds* mk = (MarkerLds*)lds_raw;                     // one chunk
+  double* acc = (double*)(lds_raw + sizeof(MarkerLds));    // 3 * kRegSites
   E* Fd = (E*)field;
   const int lane = threadIdx.x % L;
-  const int b0 = t.start[tl], b1 = t.start[tl + 1];
-  for (int q = b0 + (int)threadIdx.x / L; q < b1; q += (int)blockDim.x / L) {
-    const long long p = t.sorted[q];
-    const double X[3] = {at[3 * p], at[3 * p + 1], at[3 * p + 2]};
-    const Node<K> n = node_of<K>(r, X, lane);
-    if (!n.on) continue;
-    if (t.g.wall && (n.j[1] < 0 || n.j[1] >= t.g.ny)) continue;  // beyond a wall
-    const E f0 = (E)(n.W * F[3 * p]), f1 = (E)(n.W * F[3 * p + 1]), f2 = (E)(n.W * F[3 * p + 2]);
-    if (n.inside) {
-      E* a = acc + 3 * n.slot;
-      atomicAdd(a + 0, f0);
-      atomicAdd(a + 1, f1);
-      atomicAdd(a + 2, f2);
-    } else {
+  const int nocc = t.nocc[0];
+  for (int ot = blockIdx.x; ot < nocc; ot += gridDim.x) {
+    const int tl = t.occ[ot];
+    const Region r = region_of(t, tl);
+    for (int k = threadIdx.x; k < 3 * kRegSites; k += blockDim.x) acc[k] = 0.0;
+    const int b0 = t.start[tl], b1 = t.start[tl + 1];
+    for (int c0 = b0; c0 < b1; c0 += kChunk) {
+      const int nc = min(kChunk, b1 - c0);
+      __syncthreads();  // previous chunk done with mk (and acc cleared)
+      for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+        const int p = t.sorted[c0 + i];
+        mk->p[i] = p;
+        for (int a = 0; a < 3; ++a) {
+          mk->X[i][a] = at[3 * (long long)p + a];
+          mk->Y[i][a] = F[3 * (long long)p + a];
+        }
+      }
+      __syncthreads();
+      for (int i = (int)threadIdx.x / L; i < nc; i += (int)blockDim.x / L) {
+        const double X[3] = {mk->X[i][0], mk->X[i][1], mk->X[i][2]};
+        const Node<K> n = node_of<K>(r, X, lane);
+        if (!n.on) continue;
+        if (t.g.wall && (n.j[1] < 0 || n.j[1] >= t.g.ny)) continue;  // beyond a wall
+        const double f0 = n.W * mk->Y[i][0], f1 = n.W * mk->Y[i][1], f2 = n.W * mk->Y[i][2];
+        if (n.inside) {
+          double* a = acc + 3 * n.slot;
+          atomicAdd(a + 0, f0);
+          atomicAdd(a + 1, f1);
+          atomicAdd(a + 2, f2);
+        } else {
+          int x, y, z;
+          node_site(t.g, n.j, x, y, z);
+          const long long sidx = site_index(t.g, x, y, z);
+          unsafeAtomicAdd(Fd + 4 * sidx + 0, (E)f0);
+          unsafeAtomicAdd(Fd + 4 * sidx + 1, (E)f1);
+          unsafeAtomicAdd(Fd + 4 * sidx + 2, (E)f2);
+          uint64_t bit;
+          flag_site(mask_word(t.mask, t.g, x, y, z, bit), bit);
+        }
+      }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kRegSites; k += blockDim.x) {
+      const E a0 = (E)acc[3 * k], a1 = (E)acc[3 * k + 1], a2 = (E)acc[3 * k + 2];
+      if (a0 == E(0) && a1 == E(0) && a2 == E(0)) continue;
+      const int ix = k % kReg, iy = (k / kReg) % kReg, iz = k / (kReg * kReg);
       int x, y, z;
-      node_site(t.g, n.j, x, y, z);
+      if (!slot_site(t.g, r, ix, iy, iz, x, y, z)) continue;
       const long long sidx = site_index(t.g, x, y, z);
-      unsafeAtomicAdd(Fd + 4 * sidx + 0, f0);
-      unsafeAtomicAdd(Fd + 4 * sidx + 1, f1);
-      unsafeAtomicAdd(Fd + 4 * sidx + 2, f2);
+      unsafeAtomicAdd(Fd + 4 * sidx + 0, a0);
+      unsafeAtomicAdd(Fd + 4 * sidx + 1, a1);
+      unsafeAtomicAdd(Fd + 4 * sidx + 2, a2);
       uint64_t bit;
       flag_site(mask_word(t.mask, t.g, x, y, z, bit), bit);
     }
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < kRegSites; k += blockDim.x) {
-    const E a0 = acc[3 * k], a1 = acc[3 * k + 1], a2 = acc[3 * k + 2];
-    if (a0 == E(0) && a1 == E(0) && a2 == E(0)) continue;
-    const int ix = k % kReg, iy = (k / kReg) % kReg, iz = k / (kReg * kReg);
-    int x, y, z;
-    if (!slot_site(t.g, r, ix, iy, iz, x, y, z)) continue;
-    const long long sidx = site_index(t.g, x, y, z);
-    unsafeAtomicAdd(Fd + 4 * sidx + 0, a0);
-    unsafeAtomicAdd(Fd + 4 * sidx + 1, a1);
-    unsafeAtomicAdd(Fd + 4 * sidx + 2, a2);
-    uint64_t bit;
-    flag_site(mask_word(t.mask, t.g, x, y, z, bit), bit);
+    __syncthreads();  // acc is cleared for the next tile
   }
 }
 
@@ -339,8 +427,18 @@ hipError_t launch_bin(const TileArgs& t, const double* pos, long long n, hipStre
   return hipGetLastError();
 }
 
-static unsigned tile_grid(const TileArgs& t, long long n) {
-  return (unsigned)(n < t.ntiles ? n : t.ntiles);
+// Persistent grid over the occupied tiles (their number is only known on the
+// device): two 1024-lane workgroups per CU, at most one per tile.
+static unsigned tile_grid(const TileArgs& t) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+              ? prop.multiProcessorCount
+              : 256;
+  }
+  return (unsigned)std::min(t.ntiles, 2 * cus);
 }
 
 #define LBC_TILE_K_SWITCH(K, CALL)                        \
@@ -361,21 +459,20 @@ hipError_t launch_tile_interp(int storage, int K, const TileArgs& t, const SiteA
                               const double* at, double* pos, double* aux, int mode, long long n,
                               hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const size_t lds = sizeof(double4) * kRegSites;
+  const size_t lds = sizeof(double4) * kRegSites + sizeof(MarkerLds);
   LBC_TILE_K_SWITCH(K, LBC_TILE_S_SWITCH(storage, (k_tile_interp<SS, KK>
-      <<<tile_grid(t, n), 1024, lds, st>>>(t, s, at, pos, aux, mode))));
+      <<<tile_grid(t), 1024, lds, st>>>(t, s, at, pos, aux, mode))));
   return hipGetLastError();
 }
 
 hipError_t launch_tile_spread(int storage, int K, const TileArgs& t, const double* at,
                               const double* F, void* field, long long n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  const size_t lds = sizeof(MarkerLds) + sizeof(double) * 3 * kRegSites;
   if (storage == LB_F64) {
-    const size_t lds = sizeof(double) * 3 * kRegSites;
-    LBC_TILE_K_SWITCH(K, (k_tile_spread<double, KK><<<tile_grid(t, n), 1024, lds, st>>>(t, at, F, field)));
+    LBC_TILE_K_SWITCH(K, (k_tile_spread<double, KK><<<tile_grid(t), 1024, lds, st>>>(t, at, F, field)));
   } else {
-    const size_t lds = sizeof(float) * 3 * kRegSites;
-    LBC_TILE_K_SWITCH(K, (k_tile_spread<float, KK><<<tile_grid(t, n), 1024, lds, st>>>(t, at, F, field)));
+    LBC_TILE_K_SWITCH(K, (k_tile_spread<float, KK><<<tile_grid(t), 1024, lds, st>>>(t, at, F, field)));
   }
   return hipGetLastError();
 }
