@@ -163,6 +163,11 @@ struct lb_ctx {
   int64_t binned_at = -1;  // step of the last marker binning (-1: markers changed since)
   bool member = false;  // slot of an ensemble: stepped only by lb_ensemble_step
   bool running = false;  // ensemble slot whose device record has been uploaded
+  // Auxiliary stream for particle work that runs beside the lattice pass
+  // (default priority, joined back to st by an event before anything that
+  // depends on it, so callers see all work ordered on st).
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   bool mvalid = false;   // coupling moment cache holds the state of f[cur]
   int nshell = 0, shell_size = 0;
   double k_tether = 0;
@@ -223,6 +228,7 @@ static PartArgs part_args(const lb_ctx* c) {
   a.use_fint = 0;
   a.phys = 1;
   a.target = 0;
+  a.drift_before = 0;
   a.drift_after = 0;
   a.mcache = c->L.mcache;
   a.mbase = c->L.mbase;
@@ -392,6 +398,14 @@ static lb_status lattice_pass(lb_ctx* c) {
   return LB_OK;
 }
 
+static lb_status ensure_aux(lb_ctx* c) {
+  if (c->aux) return LB_OK;
+  HIPCHK(c, hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+  HIPCHK(c, hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+  HIPCHK(c, hipEventCreateWithFlags(&c->join, hipEventDisableTiming));
+  return LB_OK;
+}
+
 static lb_status step_once(lb_ctx* c) {
   const bool parts = c->p.coupling != LB_COUPLE_NONE && c->np > 0;
   lb_status s;
@@ -444,9 +458,17 @@ static lb_status step_once(lb_ctx* c) {
     a.target = 0;
     a.cache_use = c->mvalid ? 1 : 0;
     HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
-    HIPCHK(c, launch_bond_groups(bond_args(c, c->L.pos), c->ngroups, c->gcap, 1, 0, n, dt, c->st));
+    // The 2n intrinsic-force sub-steps between the two coupling halves touch
+    // only particle state, and the lattice pass only fluid state: the
+    // sub-steps run as one launch on the auxiliary stream beside the pass.
+    if ((s = ensure_aux(c)) != LB_OK) return s;
+    HIPCHK(c, hipEventRecord(c->fork, c->st));
+    HIPCHK(c, hipStreamWaitEvent(c->aux, c->fork, 0));
+    HIPCHK(c, launch_bond_groups(bond_args(c, c->L.pos), c->ngroups, c->gcap, 1, 0, 2 * n, dt,
+                                 c->aux));
+    HIPCHK(c, hipEventRecord(c->join, c->aux));
     if ((s = lattice_pass(c)) != LB_OK) return s;
-    HIPCHK(c, launch_bond_groups(bond_args(c, c->L.pos), c->ngroups, c->gcap, 1, 0, n, dt, c->st));
+    HIPCHK(c, hipStreamWaitEvent(c->st, c->join, 0));
     a = part_args(c);
     a.phys = 0;
     a.target = 1;
@@ -455,12 +477,17 @@ static lb_status step_once(lb_ctx* c) {
     c->mvalid = true;
     return LB_OK;
   }
-  // Alg. 3: P^1/2, F_int, coupling half (+ spread A), LB, coupling half (+ spread B), P^1/2
-  HIPCHK(c, launch_drift(c->geo, c->np, c->L.pos, c->L.vel, 0.5, c->st));
-  bool any;
-  if ((s = enqueue_fint(c, c->L.pos, any)) != LB_OK) return s;
+  // Alg. 3: P^1/2, F_int, coupling half (+ spread A), LB, coupling half (+ spread B), P^1/2.
+  // Without intrinsic forces the first P^1/2 is done by the coupling kernel.
+  const bool fint = c->nshell > 0 || c->nbond > 0;
+  bool any = false;
+  if (fint) {
+    HIPCHK(c, launch_drift(c->geo, c->np, c->L.pos, c->L.vel, 0.5, c->st));
+    if ((s = enqueue_fint(c, c->L.pos, any)) != LB_OK) return s;
+  }
   PartArgs a = part_args(c);
   a.use_fint = any ? 1 : 0;
+  a.drift_before = fint ? 0 : 1;
   a.target = 0;
   a.cache_use = c->mvalid ? 1 : 0;
   HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
@@ -744,6 +771,12 @@ lb_status lb_info(const lb_ctx* c, int64_t* nparticles, int64_t* steps) {
 lb_status lb_destroy(lb_ctx* c) {
   if (!c) return LB_OK;
   free_events(c);
+  if (c->aux) {
+    (void)hipStreamSynchronize(c->aux);
+    (void)hipEventDestroy(c->fork);
+    (void)hipEventDestroy(c->join);
+    (void)hipStreamDestroy(c->aux);
+  }
   delete c;
   return LB_OK;
 }

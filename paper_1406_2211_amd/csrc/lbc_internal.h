@@ -74,7 +74,8 @@ struct PartArgs {
   int use_fint;     // F_int enters the coupling force and the kick (Alg. 3)
   int phys;         // interpolate the physical velocity (with pending FB)
   int target;       // spread into FA (0) or FB (1)
-  int drift_after;  // final P^1/2 of Alg. 3
+  int drift_before;  // first P^1/2 of Alg. 3 (when no intrinsic forces sit between)
+  int drift_after;   // final P^1/2 of Alg. 3
   // Moment cache: the second coupling half stores, per particle and stencil
   // node, the moments it gathered; the next step's first half reads the same
   // populations (no lattice pass in between) and reuses them when the

@@ -357,6 +357,10 @@ __global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
     v[k] = a.vel[3 * p + k];
     if (a.use_fint) Fi[k] = a.fint[3 * p + k];
   }
+  if (a.drift_before) {  // P^1/2: r <- wrap(r + (h/2) v), as k_drift does
+    for (int k = 0; k < 3; ++k) r[k] += 0.5 * v[k];
+    wrap3(a.s.g, r);
+  }
   const double m = a.mass[p];
   double rp, up[3];
   group_interp<S, K>(a, r, a.phys != 0, lane, rp, up, p);
@@ -382,8 +386,9 @@ __global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
     if (a.drift_after) {
       for (int k = 0; k < 3; ++k) r[k] += hh * v[k];
       wrap3(a.s.g, r);
-      for (int k = 0; k < 3; ++k) a.pos[3 * p + k] = r[k];
     }
+    if (a.drift_after || a.drift_before)
+      for (int k = 0; k < 3; ++k) a.pos[3 * p + k] = r[k];
     for (int k = 0; k < 3; ++k) a.vel[3 * p + k] = v[k];
   }
 }
