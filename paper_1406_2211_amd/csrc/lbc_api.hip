@@ -161,6 +161,7 @@ struct lb_ctx {
   int ngroups = 0, gcap = 64;
   bool tiled = false;   // binned LDS-staged particle path (dense IB markers)
   int64_t binned_at = -1;  // step of the last marker binning (-1: markers changed since)
+  bool adv_pending = false;  // tiled IB: the final half advection of the last step is due
   bool member = false;  // slot of an ensemble: stepped only by lb_ensemble_step
   bool running = false;  // ensemble slot whose device record has been uploaded
   // Auxiliary stream for particle work that runs beside the lattice pass
@@ -384,6 +385,7 @@ static lb_status lattice_pass(lb_ctx* c) {
   a.rnx = 1.0 / c->geo.nx;
   a.rny = 1.0 / c->geo.ny;
   a.clear_mask = c->steps % kMaskKeep == 0 ? 1 : 0;
+  a.ib_copy = (c->p.coupling == LB_COUPLE_IB && c->np > 0) ? 1 : 0;
   for (int k = 0; k < 3; ++k) {
     a.uin[k] = c->uref[k];
     a.uout[k] = c->uref[k] + (c->p.comoving ? c->p.body_force[k] / c->p.rho0 : 0.0);
@@ -395,6 +397,17 @@ static lb_status lattice_pass(lb_ctx* c) {
   c->cur = 1 - c->cur;
   c->pend = 1;
   for (int k = 0; k < 3; ++k) c->uref[k] = a.uout[k];
+  return LB_OK;
+}
+
+// Complete a deferred final half advection of the tiled IB path, so that
+// lb_step returns at a step boundary.
+static lb_status finish_step(lb_ctx* c) {
+  if (!c->adv_pending) return LB_OK;
+  const TileArgs t = tile_args(c);
+  HIPCHK(c, launch_tile_interp(c->p.storage, c->p.kernel, t, site_args(c), c->L.aux, c->L.pos,
+                               c->L.aux, 1, c->np, c->st));
+  c->adv_pending = false;
   return LB_OK;
 }
 
@@ -425,17 +438,23 @@ static lb_status step_once(lb_ctx* c) {
       HIPCHK(c, launch_bin(t, c->L.pos, c->np, c->st));
       c->binned_at = c->steps;
     }
-    // X~ = X + h/2 I[X]u(t), then X <- X + h/2 I[X~]u(t): one staged pass
-    HIPCHK(c, launch_tile_interp(S, K, t, site_args(c), c->L.pos, c->L.pos, c->L.aux, 2, c->np,
-                                 c->st));
+    // X~ = X + h/2 I[X]u(t), then X <- X + h/2 I[X~]u(t): one staged pass.
+    // The final advection of the previous step, X <- X + h/2 I[X~]u(t), reads
+    // the same state and is done first in the same pass (mode 3).
+    if (c->adv_pending)
+      HIPCHK(c, launch_tile_interp(S, K, t, site_args(c), c->L.aux, c->L.pos, c->L.aux, 3, c->np,
+                                   c->st));
+    else
+      HIPCHK(c, launch_tile_interp(S, K, t, site_args(c), c->L.pos, c->L.pos, c->L.aux, 2, c->np,
+                                   c->st));
     bool any;
     if ((s = enqueue_fint(c, c->L.aux, any)) != LB_OK) return s;
     if (!any) HIPCHK(c, hipMemsetAsync(c->L.fint, 0, (size_t)c->np * 24, c->st));
     HIPCHK(c, launch_tile_spread(S, K, t, c->L.aux, c->L.fint, c->L.FA, c->np, c->st));
+    // The second half force is the same spread of the same F_int at X~: the
+    // lattice pass keeps the first-half field as the pending one (ib_copy).
     if ((s = lattice_pass(c)) != LB_OK) return s;
-    HIPCHK(c, launch_tile_spread(S, K, t, c->L.aux, c->L.fint, c->L.FB, c->np, c->st));
-    HIPCHK(c, launch_tile_interp(S, K, t, site_args(c), c->L.aux, c->L.pos, c->L.aux, 1, c->np,
-                                 c->st));
+    c->adv_pending = true;  // X <- X + h/2 I[X~]u(t+h): with the next step, or finish_step
     return LB_OK;
   }
   if (c->p.coupling == LB_COUPLE_IB) {
@@ -445,9 +464,8 @@ static lb_status step_once(lb_ctx* c) {
     if ((s = enqueue_fint(c, c->L.aux, any)) != LB_OK) return s;
     if (!any) HIPCHK(c, hipMemsetAsync(c->L.fint, 0, (size_t)c->np * 24, c->st));
     HIPCHK(c, launch_ib_advect(c->p.storage, a, 1, c->st));
-    if ((s = lattice_pass(c)) != LB_OK) return s;
+    if ((s = lattice_pass(c)) != LB_OK) return s;  // FB <- FA (ib_copy)
     a = part_args(c);
-    HIPCHK(c, launch_ib_spread_b(c->p.storage, a, c->st));
     HIPCHK(c, launch_ib_advect(c->p.storage, a, 0, c->st));
     return LB_OK;
   }
@@ -687,7 +705,7 @@ lb_status lb_step(lb_ctx* c, int64_t nsteps) {
     if (s != LB_OK) return s;
     c->steps++;
   }
-  return LB_OK;
+  return finish_step(c);
 }
 
 lb_status lb_moments(lb_ctx* c, double* d_rho, double* d_u) {

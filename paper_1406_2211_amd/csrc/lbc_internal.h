@@ -35,6 +35,7 @@ struct LatArgs {
   double uout[3];     // storage reference velocity of fout
   double rnx, rny;    // 1/nx, 1/ny (linear-site pass)
   int clear_mask;     // clear the force mask after reading it (every kMaskKeep steps)
+  int ib_copy;        // immersed boundary: FA becomes the pending FB (same spread)
 };
 
 struct InitArgs {
@@ -185,7 +186,6 @@ hipError_t launch_wrap(const Geo& g, long long n, double* pos, hipStream_t st);
 hipError_t launch_couple_half(int storage, const PartArgs& a, hipStream_t st);
 hipError_t launch_ib_predict(int storage, const PartArgs& a, hipStream_t st);
 hipError_t launch_ib_advect(int storage, const PartArgs& a, int spread_fint, hipStream_t st);
-hipError_t launch_ib_spread_b(int storage, const PartArgs& a, hipStream_t st);
 hipError_t launch_bond_groups(const BondArgs& b, int ngroups, int gcap, int mode, int acc,
                               int nsub, double dt, hipStream_t st);
 hipError_t launch_shell_forces(const ShellArgs& s, int nshell, hipStream_t st);

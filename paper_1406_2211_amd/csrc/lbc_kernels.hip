@@ -26,6 +26,43 @@ namespace lbc {
 // the per-population base pointers; each work-item adds a 32-bit site offset.
 // All 19 loads are issued before any arithmetic.  With y walls the
 // bounce-back choice is also block-uniform (it depends on y only).
+// Coupling forces of one site for the fused pass, from the two force fields
+// where the mask word flags the site.  Normally both fields are zeroed after
+// the read.  With ib_copy (immersed boundary: the second half force of a
+// step is the same spread of the same F_int as the first, Sec. 5.1) the
+// first-half field becomes the pending second half: FB <- FA, FA <- 0, and
+// the owning lane rewrites the word to flag exactly the sites with a
+// nonzero pending force.  Called by all lanes of a wavefront that owns the
+// (nonzero) word; lane = site index within the word.
+template <int S>
+__device__ __forceinline__ void take_forces(uint64_t word, uint64_t* mp, size_t site, uint32_t lane,
+                                            void* FAp, void* FBp, bool ib_copy, bool clear,
+                                            typename Store<S>::R& Fx, typename Store<S>::R& Fy,
+                                            typename Store<S>::R& Fz) {
+  using V4 = typename Store<S>::V4;
+  V4 zero;
+  zero.x = zero.y = zero.z = zero.w = 0;
+  V4 fa = zero;
+  const bool mine = (word >> lane) & 1ull;
+  if (mine) {
+    V4* FA = (V4*)FAp;
+    V4* FB = (V4*)FBp;
+    fa = FA[site];
+    const V4 fb = FB[site];
+    Fx += fa.x + fb.x;
+    Fy += fa.y + fb.y;
+    Fz += fa.z + fb.z;
+    FA[site] = zero;
+    FB[site] = ib_copy ? fa : zero;
+  }
+  if (ib_copy) {
+    const uint64_t keep = __ballot(mine && (fa.x != 0 || fa.y != 0 || fa.z != 0));
+    if (lane == 0) *mp = keep;
+  } else if (lane == 0 && clear) {
+    *mp = 0;
+  }
+}
+
 template <int S, bool CM, bool WALL>
 __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
   using St = Store<S>;
@@ -58,21 +95,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
     f[i] = St::raw(base + off);
   }
   R Fx = R(a.Fx), Fy = R(a.Fy), Fz = R(a.Fz);
-  if (word) {
-    if ((word >> (x & 63)) & 1ull) {
-      V4* FA = (V4*)a.FA;
-      V4* FB = (V4*)a.FB;
-      const V4 fa = FA[own], fb = FB[own];
-      Fx += fa.x + fb.x;
-      Fy += fa.y + fb.y;
-      Fz += fa.z + fb.z;
-      V4 zero;
-      zero.x = zero.y = zero.z = zero.w = 0;
-      FA[own] = zero;
-      FB[own] = zero;
-    }
-    if ((x & 63) == 0 && a.clear_mask) *mp = 0;
-  }
+  if (word) take_forces<S>(word, mp, own, x & 63, a.FA, a.FB, a.ib_copy != 0, a.clear_mask != 0,
+                           Fx, Fy, Fz);
   PassK<R> k;
   k.rho0 = R(a.rho0);
   k.sc = R(a.scale);
@@ -435,20 +459,6 @@ __global__ __launch_bounds__(256) void k_ib_advect(PartArgs a, int spread_fint) 
   }
 }
 
-// IB: spread +F_int at X~ into the B field (second half force).
-template <int S, int K>
-__global__ __launch_bounds__(256) void k_ib_spread_b(PartArgs a) {
-  using E = typename Store<S>::R;
-  constexpr int L = Lanes<K>::L;
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long p = gid / L;
-  const int lane = (int)(gid % L);
-  if (p >= a.n) return;
-  const double Xt[3] = {a.aux[3 * p], a.aux[3 * p + 1], a.aux[3 * p + 2]};
-  const double F[3] = {a.fint[3 * p], a.fint[3 * p + 1], a.fint[3 * p + 2]};
-  group_spread<E, K>(a, Xt, F, a.FB, lane);
-}
-
 // ======================================================================
 // Intrinsic forces.
 // ======================================================================
@@ -795,13 +805,6 @@ hipError_t launch_ib_advect(int storage, const PartArgs& a, int spread_fint, hip
   return hipGetLastError();
 }
 
-hipError_t launch_ib_spread_b(int storage, const PartArgs& a, hipStream_t st) {
-  if (a.n > 0)
-    LBC_KERNEL_SWITCH(a.K, LBC_STORAGE_SWITCH(storage, (k_ib_spread_b<SS, KK>
-                                                        <<<gblocks(a.n, KK), 256, 0, st>>>(a))));
-  return hipGetLastError();
-}
-
 hipError_t launch_bond_groups(const BondArgs& b, int ngroups, int gcap, int mode, int acc,
                               int nsub, double dt, hipStream_t st) {
   if (ngroups > 0)
@@ -854,6 +857,7 @@ struct LatView {
   __device__ double uin(int c) const { return a.uin[c]; }
   __device__ double uout(int c) const { return a.uout[c]; }
   __device__ bool clear_mask() const { return a.clear_mask != 0; }
+  __device__ bool ib_copy() const { return a.ib_copy != 0; }
 };
 
 struct SlotView {
@@ -879,6 +883,7 @@ struct SlotView {
     return s.uref[c] + (c == 0 ? s.fx : (c == 1 ? s.fy : s.fz)) / s.rho0;
   }
   __device__ bool clear_mask() const { return s.steps_done % kMaskKeep == 0; }
+  __device__ bool ib_copy() const { return false; }
 };
 
 template <int S, bool CM, bool WALL, class V>
@@ -910,21 +915,8 @@ __device__ __forceinline__ void linear_site(const V& v, uint32_t s) {
     f[i] = St::raw(src);
   }
   R Fx = R(v.F(0)), Fy = R(v.F(1)), Fz = R(v.F(2));
-  if (word) {  // a 64-aligned group of 64 lanes owns this mask word
-    if ((word >> (s & 63)) & 1ull) {
-      V4* FA = (V4*)v.FA();
-      V4* FB = (V4*)v.FB();
-      const V4 fa = FA[s], fb = FB[s];
-      Fx += fa.x + fb.x;
-      Fy += fa.y + fb.y;
-      Fz += fa.z + fb.z;
-      V4 zero;
-      zero.x = zero.y = zero.z = zero.w = 0;
-      FA[s] = zero;
-      FB[s] = zero;
-    }
-    if ((s & 63) == 0 && v.clear_mask()) *mp = 0;
-  }
+  if (word)  // a 64-aligned group of 64 lanes owns this mask word
+    take_forces<S>(word, mp, s, s & 63, v.FA(), v.FB(), v.ib_copy(), v.clear_mask(), Fx, Fy, Fz);
   PassK<R> k;
   k.rho0 = R(v.rho0());
   k.sc = R(v.scale());

@@ -266,6 +266,9 @@ struct MarkerLds {
 // mode 2: both, in that order, from one staged region (at = pos); the first
 //         advection only needs the state before the lattice pass, like the
 //         predictor, so both read the same LDS moments.
+// mode 3: mode 1 of one step followed by mode 2 of the next (at = aux): the
+//         final advection of a step and the predictor and first advection of
+//         the next read the same fluid state, so one staging serves all three.
 // A marker whose stencil leaves the region gathers its nodes from global
 // memory instead (same arithmetic per node).  Workgroups loop over the
 // occupied tiles (persistent grid).
@@ -311,7 +314,7 @@ __global__ __launch_bounds__(1024) void k_tile_interp(TileArgs t, SiteArgs s, co
         mk->p[i] = p;
         for (int a = 0; a < 3; ++a) {
           mk->X[i][a] = at[3 * (long long)p + a];
-          mk->Y[i][a] = mode == 1 ? pos[3 * (long long)p + a] : 0.0;
+          mk->Y[i][a] = (mode == 1 || mode == 3) ? pos[3 * (long long)p + a] : 0.0;
         }
       }
       __syncthreads();
@@ -329,11 +332,23 @@ __global__ __launch_bounds__(1024) void k_tile_interp(TileArgs t, SiteArgs s, co
           half_drift(P, up, Y);
           if (lane == 0)
             for (int a = 0; a < 3; ++a) pos[3 * p + a] = Y[a];
-        } else {  // mode 2: predictor, then the first advection from the same staged state
-          double Xt[3], u2[3];
-          half_drift(X, up, Xt);
+        } else {
+          // mode 2: predictor, then the first advection from the same staged
+          // state; mode 3: first the final advection of the previous step
+          double Xs[3], Xt[3], u0[3], u2[3];
+          if (mode == 3) {
+            const double P[3] = {mk->Y[i][0], mk->Y[i][1], mk->Y[i][2]};
+            half_drift(P, up, Xs);
+            interp_at(Xs, u0);
+          } else {
+            for (int a = 0; a < 3; ++a) {
+              Xs[a] = X[a];
+              u0[a] = up[a];
+            }
+          }
+          half_drift(Xs, u0, Xt);
           interp_at(Xt, u2);
-          half_drift(X, u2, Y);
+          half_drift(Xs, u2, Y);
           if (lane == 0)
             for (int a = 0; a < 3; ++a) {
               aux[3 * p + a] = Xt[a];
