@@ -105,7 +105,13 @@ def run_gpu(c: Case, lat=None):
           f"coupling={c.coupling} kernel={c.kernel} np={0 if c.pos is None else len(c.pos)}",
           flush=True)
     sys.stdout.flush()
-    lat.lb_step(c.steps)
+    chunks = c.extra.get("chunks", [c.steps])  # several lb_step calls, reading state between
+    assert sum(chunks) == c.steps
+    for k, n in enumerate(chunks):
+        lat.lb_step(n)
+        if k + 1 < len(chunks):
+            lat.lb_moments()
+            lat.lb_get_particles()
     rho, u = lat.lb_moments()
     df = lat.lb_populations()
     pos, vel = lat.lb_get_particles()

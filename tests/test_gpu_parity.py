@@ -116,6 +116,28 @@ def test_moment_cache_zero_weight_nodes_and_cell_crossings(kernel, coupling):
     check(c, TOL64)
 
 
+@pytest.mark.parametrize("which", ["ib_tiled", "mts", "alg3"])
+def test_step_calls_split_into_chunks(which):
+    """lb_step(n) ends at a step boundary: a run split into several calls (with
+    reads in between) matches the oracle run of the total step count.  Covers
+    the deferred final advection of the tiled IB path, the bond sub-steps on
+    the auxiliary stream, and the coupling moment cache across calls."""
+    if which == "ib_tiled":
+        c = _ib_case("chunks_ib", 4, steps=20)
+    elif which == "mts":
+        pos, vel, bonds = I.chains(2, 8, (20, 20, 20), 1.0, 2e-2, 6)
+        c = Case(name="chunks_mts", nx=20, ny=20, nz=20, tau=0.7, steps=20, collision=1,
+                 coupling=1, gamma=1.0, kernel=2, storage=0, mts=3, u_noise=1e-3, pos=pos,
+                 vel=vel, mass=np.full(len(pos), 2.0), bonds=bonds, bond_k=0.02, bond_r0=1.0)
+    else:
+        pos = np.array([[3.2, 12.9, 4.4], [8.1, 2.2, 13.6]])
+        c = Case(name="chunks_alg3", nx=16, ny=16, nz=16, tau=0.75, steps=20, coupling=1,
+                 gamma=0.7, kernel=2, pos=pos, vel=np.array([[0.2, -0.1, 0.05], [1e-3, 0, 0]]),
+                 mass=np.ones(2), u_noise=1e-3, seed=8)
+    c.extra["chunks"] = [1, 3, 5, 2, 9]
+    check(c, TOL64)
+
+
 def test_mts_stiff_chains_fp64():
     """The bead-spring parameters of the force-coupling workload (k = 30):
     ill-conditioned, so the bound follows the oracle's one-ulp sensitivity."""
