@@ -301,18 +301,21 @@ __device__ __forceinline__ void fused_site(const typename Store<S>::R f[Q], type
 // ---------------------------------------------------------- delta functions
 // One-dimensional weights of a delta-function stencil (Appendix A kernels).
 // Returns the first node j0; weights for nodes j0 .. j0+K-1.
-__device__ __forceinline__ double phi_eval(int K, double r) {
-  const double a = fabs(r);
-  if (K == 2) return a < 1.0 ? 1.0 - a : 0.0;
+template <typename T>
+__device__ __forceinline__ T phi_eval_t(int K, T r) {
+  const T a = fabs(r);
+  if (K == 2) return a < T(1) ? T(1) - a : T(0);
   if (K == 3) {
-    if (a <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * r * r)) / 3.0;
-    if (a <= 1.5) return (5.0 - 3.0 * a - sqrt(fmax(0.0, 6.0 * a - 2.0 - 3.0 * r * r))) / 6.0;
-    return 0.0;
+    if (a <= T(0.5)) return (T(1) + sqrt(T(1) - T(3) * r * r)) / T(3);
+    if (a <= T(1.5)) return (T(5) - T(3) * a - sqrt(fmax(T(0), T(6) * a - T(2) - T(3) * r * r))) / T(6);
+    return T(0);
   }
-  if (a <= 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * r * r)) / 8.0;
-  if (a <= 2.0) return (5.0 - 2.0 * a - sqrt(fmax(0.0, -7.0 + 12.0 * a - 4.0 * r * r))) / 8.0;
-  return 0.0;
+  if (a <= T(1)) return (T(3) - T(2) * a + sqrt(T(1) + T(4) * a - T(4) * r * r)) / T(8);
+  if (a <= T(2)) return (T(5) - T(2) * a - sqrt(fmax(T(0), T(-7) + T(12) * a - T(4) * r * r))) / T(8);
+  return T(0);
 }
+
+__device__ __forceinline__ double phi_eval(int K, double r) { return phi_eval_t<double>(K, r); }
 
 // First node of the K-point stencil of X: nodes j0 .. j0+K-1.
 template <int K>
@@ -350,6 +353,13 @@ struct Lanes {
 };
 
 // Sum over an aligned group of L lanes (butterfly; every lane gets the sum).
+template <int L, typename T>
+__device__ __forceinline__ T group_sum_t(T v) {
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 template <int L>
 __device__ __forceinline__ double group_sum(double v) {
 #pragma unroll

@@ -145,7 +145,7 @@ __device__ __forceinline__ bool slot_site(const Geo& g, const Region& r, int ix,
 
 // One lane of a marker's lane group: stencil node (kx, ky, kz) = lane
 // (x fastest) of the K-point stencil whose first node is j0 (Appendix A
-// kernels), its weight, and the node's region slot.
+// kernels), its weight (evaluated in T), and the node's region slot.
 template <int K>
 struct Node {
   bool on;       // lane carries a node of nonzero weight
@@ -155,12 +155,12 @@ struct Node {
   int slot;      // region slot (when inside)
 };
 
-template <int K>
+template <int K, typename T>
 __device__ __forceinline__ Node<K> node_of(const Region& r, const double X[3], int lane) {
   Node<K> n;
   const int k[3] = {lane % K, (lane / K) % K, lane / (K * K)};
   n.inside = true;
-  n.W = 1.0;
+  T w = T(1);
   int rel[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -168,8 +168,9 @@ __device__ __forceinline__ Node<K> node_of(const Region& r, const double X[3], i
     n.inside = n.inside && j0 - r.o[a] >= 0 && j0 - r.o[a] + K <= kReg;
     n.j[a] = j0 + k[a];
     rel[a] = n.j[a] - r.o[a];
-    n.W *= phi_eval(K, (double)n.j[a] - X[a]);
+    w *= phi_eval_t<T>(K, (T)((double)n.j[a] - X[a]));
   }
+  n.W = (double)w;
   n.on = lane < K * K * K && n.W != 0.0;
   n.slot = (rel[2] * kReg + rel[1]) * kReg + rel[0];
   return n;
@@ -185,6 +186,30 @@ __device__ __forceinline__ bool node_site(const Geo& g, const int j[3], int& x, 
   return true;
 }
 
+// Arithmetic type of interpolation and spreading weights and of the staged
+// moments: FP64 with FP64 storage, FP32 otherwise (node offsets j - X are
+// formed in FP64 from the FP64 positions and then rounded).
+template <int S>
+struct TileT {
+  using W = double;
+  using M4 = double4;
+};
+template <>
+struct TileT<LB_F32> {
+  using W = float;
+  using M4 = float4;
+};
+template <>
+struct TileT<LB_F16> {
+  using W = float;
+  using M4 = float4;
+};
+template <>
+struct TileT<LB_BF16> {
+  using W = float;
+  using M4 = float4;
+};
+
 // Interpolation lane groups: one lane per x-row of stencil nodes (ky, kz),
 // K^2 rows rounded up to a power of two (4 lanes for K = 2, 16 for K = 3, 4).
 template <int K>
@@ -196,8 +221,10 @@ struct RowLanes {
 // gathered moments when the stencil leaves the region), reduced over the
 // marker's lane group: u_p = sum_nodes W u(node), W = phi(x) phi(y) phi(z).
 template <int S, int K>
-__device__ __forceinline__ void row_interp(const SiteArgs& s, const Region& r, const double4* mom,
-                                           const double X[3], int lane, double up[3]) {
+__device__ __forceinline__ void row_interp(const SiteArgs& s, const Region& r,
+                                           const typename TileT<S>::M4* mom, const double X[3],
+                                           int lane, double up[3]) {
+  using W = typename TileT<S>::W;
   constexpr int L = RowLanes<K>::L;
   const int ky = lane % K, kz = lane / K;
   int j0[3];
@@ -207,46 +234,46 @@ __device__ __forceinline__ void row_interp(const SiteArgs& s, const Region& r, c
     j0[a] = first_node<K>(X[a]);
     inside = inside && j0[a] - r.o[a] >= 0 && j0[a] - r.o[a] + K <= kReg;
   }
-  double ux = 0, uy = 0, uz = 0;
+  W ux = 0, uy = 0, uz = 0;
   if (lane < K * K) {
-    double wx[K];
+    W wx[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) wx[k] = phi_eval(K, (double)(j0[0] + k) - X[0]);
-    const double wy = phi_eval(K, (double)(j0[1] + ky) - X[1]);
-    const double wz = phi_eval(K, (double)(j0[2] + kz) - X[2]);
+    for (int k = 0; k < K; ++k) wx[k] = phi_eval_t<W>(K, (W)((double)(j0[0] + k) - X[0]));
+    const W wy = phi_eval_t<W>(K, (W)((double)(j0[1] + ky) - X[1]));
+    const W wz = phi_eval_t<W>(K, (W)((double)(j0[2] + kz) - X[2]));
     if (inside) {
-      const double4* row =
+      const typename TileT<S>::M4* row =
           mom + ((j0[2] + kz - r.o[2]) * kReg + (j0[1] + ky - r.o[1])) * kReg + (j0[0] - r.o[0]);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const double W = wx[k] * wy * wz;
-        if (W == 0.0) continue;
-        const double4 m = row[k];
-        if (m.x == 0.0) continue;  // beyond a wall
-        ux += W * m.y;
-        uy += W * m.z;
-        uz += W * m.w;
+        const W Wt = wx[k] * wy * wz;
+        if (Wt == W(0)) continue;
+        const typename TileT<S>::M4 m = row[k];
+        if (m.x == W(0)) continue;  // beyond a wall
+        ux += Wt * m.y;
+        uy += Wt * m.z;
+        uz += Wt * m.w;
       }
     } else {
       const int jy = j0[1] + ky;
       const bool in_y = !s.g.wall || (jy >= 0 && jy < s.g.ny);
       for (int k = 0; k < K && in_y; ++k) {
-        const double W = wx[k] * wy * wz;
-        if (W == 0.0) continue;
+        const W Wt = wx[k] * wy * wz;
+        if (Wt == W(0)) continue;
         const int x = wrap_idx(j0[0] + k, s.g.nx), z = wrap_idx(j0[2] + kz, s.g.nz);
         const int y = s.g.wall ? jy : wrap_idx(jy, s.g.ny);
         double fl[Q], drho, j[3];
         site_phys<S>(s, x, y, z, fl, drho, j, true);
         const double rr = s.rho0 + drho;
-        ux += W * (j[0] / rr);
-        uy += W * (j[1] / rr);
-        uz += W * (j[2] / rr);
+        ux += Wt * (W)(j[0] / rr);
+        uy += Wt * (W)(j[1] / rr);
+        uz += Wt * (W)(j[2] / rr);
       }
     }
   }
-  up[0] = group_sum<L>(ux);
-  up[1] = group_sum<L>(uy);
-  up[2] = group_sum<L>(uz);
+  up[0] = (double)group_sum_t<L, W>(ux);
+  up[1] = (double)group_sum_t<L, W>(uy);
+  up[2] = (double)group_sum_t<L, W>(uz);
 }
 
 // Markers of the tile being processed, staged in LDS in chunks of kChunk
@@ -276,9 +303,11 @@ template <int S, int K>
 __global__ __launch_bounds__(1024) void k_tile_interp(TileArgs t, SiteArgs s, const double* at,
                                                       double* pos, double* aux, int mode) {
   constexpr int L = RowLanes<K>::L;
+  using W = typename TileT<S>::W;
+  using M4 = typename TileT<S>::M4;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double4* mom = (double4*)lds_raw;                                    // kRegSites
-  MarkerLds* mk = (MarkerLds*)(lds_raw + sizeof(double4) * kRegSites);  // one chunk
+  M4* mom = (M4*)lds_raw;                                          // kRegSites
+  MarkerLds* mk = (MarkerLds*)(lds_raw + sizeof(M4) * kRegSites);  // one chunk
   const int lane = threadIdx.x % L;
   const int nocc = t.nocc[0];
   for (int ot = blockIdx.x; ot < nocc; ot += gridDim.x) {
@@ -287,12 +316,16 @@ __global__ __launch_bounds__(1024) void k_tile_interp(TileArgs t, SiteArgs s, co
     for (int k = threadIdx.x; k < kRegSites; k += blockDim.x) {
       const int ix = k % kReg, iy = (k / kReg) % kReg, iz = k / (kReg * kReg);
       int x, y, z;
-      double4 m = make_double4(0, 0, 0, 0);
+      M4 m;
+      m.x = m.y = m.z = m.w = W(0);
       if (slot_site(s.g, r, ix, iy, iz, x, y, z)) {
         double fl[Q], drho, j[3];
         site_phys<S>(s, x, y, z, fl, drho, j, true);
         const double rr = s.rho0 + drho;
-        m = make_double4(rr, j[0] / rr, j[1] / rr, j[2] / rr);
+        m.x = (W)rr;
+        m.y = (W)(j[0] / rr);
+        m.z = (W)(j[1] / rr);
+        m.w = (W)(j[2] / rr);
       }
       mom[k] = m;
     }
@@ -393,7 +426,7 @@ __global__ __launch_bounds__(1024) void k_tile_spread(TileArgs t, const double* 
       __syncthreads();
       for (int i = (int)threadIdx.x / L; i < nc; i += (int)blockDim.x / L) {
         const double X[3] = {mk->X[i][0], mk->X[i][1], mk->X[i][2]};
-        const Node<K> n = node_of<K>(r, X, lane);
+        const Node<K> n = node_of<K, E>(r, X, lane);  // weights in the field precision
         if (!n.on) continue;
         if (t.g.wall && (n.j[1] < 0 || n.j[1] >= t.g.ny)) continue;  // beyond a wall
         const double f0 = n.W * mk->Y[i][0], f1 = n.W * mk->Y[i][1], f2 = n.W * mk->Y[i][2];
@@ -474,9 +507,9 @@ hipError_t launch_tile_interp(int storage, int K, const TileArgs& t, const SiteA
                               const double* at, double* pos, double* aux, int mode, long long n,
                               hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const size_t lds = sizeof(double4) * kRegSites + sizeof(MarkerLds);
   LBC_TILE_K_SWITCH(K, LBC_TILE_S_SWITCH(storage, (k_tile_interp<SS, KK>
-      <<<tile_grid(t), 1024, lds, st>>>(t, s, at, pos, aux, mode))));
+      <<<tile_grid(t), 1024, sizeof(typename TileT<SS>::M4) * kRegSites + sizeof(MarkerLds), st>>>(
+          t, s, at, pos, aux, mode))));
   return hipGetLastError();
 }
 
