@@ -102,6 +102,8 @@ __device__ __forceinline__ long long site_index(const Geo& g, int x, int y, int 
 // every kMaskKeep steps, so a particle that keeps touching the same sites
 // finds its bits set and spreads without an atomic on the mask; a bit that
 // is no longer needed costs the pass one read of zeros until the next clear.
+// (The immersed-boundary pass instead rewrites each word to the sites of its
+// pending field, see take_forces.)
 constexpr int kMaskKeep = 32;
 
 __device__ __forceinline__ uint64_t* mask_word(uint64_t* m, const Geo& g, int x, int y, int z,

@@ -27,40 +27,57 @@ namespace lbc {
 // All 19 loads are issued before any arithmetic.  With y walls the
 // bounce-back choice is also block-uniform (it depends on y only).
 // Coupling forces of one site for the fused pass, from the two force fields
-// where the mask word flags the site.  Normally both fields are zeroed after
-// the read.  With ib_copy (immersed boundary: the second half force of a
-// step is the same spread of the same F_int as the first, Sec. 5.1) the
-// first-half field becomes the pending second half: FB <- FA, FA <- 0, and
-// the owning lane rewrites the word to flag exactly the sites with a
-// nonzero pending force.  Called by all lanes of a wavefront that owns the
-// (nonzero) word; lane = site index within the word.
+// where the mask word flags the site; both fields are zeroed after the read,
+// and the owning lane clears the word when the pass clears the mask.
 template <int S>
 __device__ __forceinline__ void take_forces(uint64_t word, uint64_t* mp, size_t site, uint32_t lane,
-                                            void* FAp, void* FBp, bool ib_copy, bool clear,
+                                            void* FAp, void* FBp, bool clear,
                                             typename Store<S>::R& Fx, typename Store<S>::R& Fy,
                                             typename Store<S>::R& Fz) {
   using V4 = typename Store<S>::V4;
-  V4 zero;
-  zero.x = zero.y = zero.z = zero.w = 0;
-  V4 fa = zero;
-  const bool mine = (word >> lane) & 1ull;
-  if (mine) {
+  if ((word >> lane) & 1ull) {
     V4* FA = (V4*)FAp;
     V4* FB = (V4*)FBp;
-    fa = FA[site];
-    const V4 fb = FB[site];
+    const V4 fa = FA[site], fb = FB[site];
     Fx += fa.x + fb.x;
     Fy += fa.y + fb.y;
     Fz += fa.z + fb.z;
+    V4 zero;
+    zero.x = zero.y = zero.z = zero.w = 0;
     FA[site] = zero;
-    FB[site] = ib_copy ? fa : zero;
+    FB[site] = zero;
   }
-  if (ib_copy) {
-    const uint64_t keep = __ballot(mine && (fa.x != 0 || fa.y != 0 || fa.z != 0));
-    if (lane == 0) *mp = keep;
-  } else if (lane == 0 && clear) {
-    *mp = 0;
+  if (lane == 0 && clear) *mp = 0;
+}
+
+// Immersed boundary: the second half force of a step is the same spread of
+// the same F_int as the first (Sec. 5.1), so the first-half field becomes the
+// pending second half: FB <- FA, FA <- 0, and the owning lane rewrites the
+// word to flag exactly the sites of the pending field (which the next pass
+// must read).  Called by all lanes of a wavefront that owns the (nonzero)
+// word.
+template <int S>
+__device__ __forceinline__ void take_forces_ib(uint64_t word, uint64_t* mp, size_t site,
+                                               uint32_t lane, void* FAp, void* FBp,
+                                               typename Store<S>::R& Fx, typename Store<S>::R& Fy,
+                                               typename Store<S>::R& Fz) {
+  using V4 = typename Store<S>::V4;
+  bool live = false;
+  if ((word >> lane) & 1ull) {
+    V4* FA = (V4*)FAp;
+    V4* FB = (V4*)FBp;
+    const V4 fa = FA[site], fb = FB[site];
+    Fx += fa.x + fb.x;
+    Fy += fa.y + fb.y;
+    Fz += fa.z + fb.z;
+    V4 zero;
+    zero.x = zero.y = zero.z = zero.w = 0;
+    FA[site] = zero;
+    FB[site] = fa;
+    live = fa.x != 0 || fa.y != 0 || fa.z != 0;
   }
+  const uint64_t keep = __ballot(live);
+  if (lane == 0 && keep != word) *mp = keep;
 }
 
 template <int S, bool CM, bool WALL>
@@ -95,8 +112,12 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
     f[i] = St::raw(base + off);
   }
   R Fx = R(a.Fx), Fy = R(a.Fy), Fz = R(a.Fz);
-  if (word) take_forces<S>(word, mp, own, x & 63, a.FA, a.FB, a.ib_copy != 0, a.clear_mask != 0,
-                           Fx, Fy, Fz);
+  if (word) {
+    if (a.ib_copy)
+      take_forces_ib<S>(word, mp, own, x & 63, a.FA, a.FB, Fx, Fy, Fz);
+    else
+      take_forces<S>(word, mp, own, x & 63, a.FA, a.FB, a.clear_mask != 0, Fx, Fy, Fz);
+  }
   PassK<R> k;
   k.rho0 = R(a.rho0);
   k.sc = R(a.scale);
@@ -856,8 +877,8 @@ struct LatView {
   __device__ double omm() const { return a.omm; }
   __device__ double uin(int c) const { return a.uin[c]; }
   __device__ double uout(int c) const { return a.uout[c]; }
-  __device__ bool clear_mask() const { return a.clear_mask != 0; }
   __device__ bool ib_copy() const { return a.ib_copy != 0; }
+  __device__ bool clear_mask() const { return a.clear_mask != 0; }
 };
 
 struct SlotView {
@@ -882,8 +903,8 @@ struct SlotView {
   __device__ double uout(int c) const {
     return s.uref[c] + (c == 0 ? s.fx : (c == 1 ? s.fy : s.fz)) / s.rho0;
   }
-  __device__ bool clear_mask() const { return s.steps_done % kMaskKeep == 0; }
   __device__ bool ib_copy() const { return false; }
+  __device__ bool clear_mask() const { return s.steps_done % kMaskKeep == 0; }
 };
 
 template <int S, bool CM, bool WALL, class V>
@@ -915,8 +936,12 @@ __device__ __forceinline__ void linear_site(const V& v, uint32_t s) {
     f[i] = St::raw(src);
   }
   R Fx = R(v.F(0)), Fy = R(v.F(1)), Fz = R(v.F(2));
-  if (word)  // a 64-aligned group of 64 lanes owns this mask word
-    take_forces<S>(word, mp, s, s & 63, v.FA(), v.FB(), v.ib_copy(), v.clear_mask(), Fx, Fy, Fz);
+  if (word) {  // a 64-aligned group of 64 lanes owns this mask word
+    if (v.ib_copy())
+      take_forces_ib<S>(word, mp, s, s & 63, v.FA(), v.FB(), Fx, Fy, Fz);
+    else
+      take_forces<S>(word, mp, s, s & 63, v.FA(), v.FB(), v.clear_mask(), Fx, Fy, Fz);
+  }
   PassK<R> k;
   k.rho0 = R(v.rho0());
   k.sc = R(v.scale());
