@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 METRIC = ("MLUPS & HBM GB/s fraction (D3Q19+coupling); ensemble runs/s + p50/p99 latency")
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1406_2211_amd/csrc/lbc_kernels.hip",
-                  "paper_1406_2211_amd/csrc/lbc_device.h"]
+                  "paper_1406_2211_amd/csrc/lbc_device.h",
+                  "paper_1406_2211_amd/csrc/lbc_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_c2.json")
 
 
