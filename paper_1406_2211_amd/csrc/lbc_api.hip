@@ -385,6 +385,7 @@ static lb_status lattice_pass(lb_ctx* c) {
     a.uin[k] = c->uref[k];
     a.uout[k] = c->uref[k] + (c->p.comoving ? c->p.body_force[k] / c->p.rho0 : 0.0);
   }
+  comoving_terms(c->scale, c->p.rho0, a.uin, a.uout, a.cm, a.cmf);
   const bool timed = 2 * (size_t)c->ev_used + 1 < c->ev.size();
   if (timed) HIPCHK(c, hipEventRecord(c->ev[2 * c->ev_used], c->st));
   HIPCHK(c, launch_stream_collide(c->p.storage, c->p.comoving != 0, a, c->st));
@@ -892,6 +893,10 @@ static EnsSlot slot_from_ctx(const lb_ctx* c) {
   s.mcache = c->L.mcache;
   s.mbase = c->L.mbase;
   s.mvalid = 0;
+  double uo[3];
+  for (int k = 0; k < 3; ++k)
+    uo[k] = c->uref[k] + (c->p.comoving ? c->p.body_force[k] / c->p.rho0 : 0.0);
+  comoving_terms(c->scale, c->p.rho0, c->uref, uo, s.cm, s.cmf);
   return s;
 }
 

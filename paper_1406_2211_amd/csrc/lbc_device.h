@@ -216,8 +216,51 @@ template <typename R>
 struct PassK {
   R rho0, sc, inv;  // rho0, S, 1/S
   R hp, hm;         // (1 - lambda+)/2 and (1 - lambda-)/2
-  R ui[3], uo[3];   // reference velocities of the input and output buffers
+  R ui[3];          // reference velocity of the input buffer (comoving frame)
+  const R* cm;      // comoving reference terms per pair, see comoving_terms
 };
+
+// Comoving frame: the reference parts of the storage-unit equilibria, the same
+// for every site of a box in one pass.  Pair p = 1..9 is (2p-1, 2p), p = 0 the
+// rest population; with B0 = w S rho0, U_in/U_out the references of the input
+// and output buffers:
+//   cm[0*10+p] = B0 (9/2 (c.U_in)^2 - 3/2 U_in.U_in)    (even, input)
+//   cm[1*10+p] = 3 B0 (c.U_in)                         (odd, input)
+//   cm[2*10+p], cm[3*10+p]: the same with U_out          (output)
+// They are subtracted from the equilibria formed in fused_site.
+__host__ __device__ inline void comoving_terms(double S, double rho0, const double ui[3],
+                                               const double uo[3], double cm[40], float cmf[40]) {
+  const double isq = ui[0] * ui[0] + ui[1] * ui[1] + ui[2] * ui[2];
+  const double osq = uo[0] * uo[0] + uo[1] * uo[1] + uo[2] * uo[2];
+  const double w0 = 1.0 / 3.0;
+  cm[0] = w0 * S * rho0 * (-1.5 * isq);
+  cm[10] = 0.0;
+  cm[20] = w0 * S * rho0 * (-1.5 * osq);
+  cm[30] = 0.0;
+  for (int p = 1; p <= 9; ++p) {
+    const int i = 2 * p - 1;
+    const double w = WCLASS[i] == 1 ? 1.0 / 18.0 : 1.0 / 36.0;
+    const double B0 = w * S * rho0;
+    const double ci = CX[i] * ui[0] + CY[i] * ui[1] + CZ[i] * ui[2];
+    const double co = CX[i] * uo[0] + CY[i] * uo[1] + CZ[i] * uo[2];
+    cm[p] = B0 * (4.5 * ci * ci - 1.5 * isq);
+    cm[10 + p] = 3.0 * B0 * ci;
+    cm[20 + p] = B0 * (4.5 * co * co - 1.5 * osq);
+    cm[30 + p] = 3.0 * B0 * co;
+  }
+  for (int q = 0; q < 40; ++q) cmf[q] = (float)cm[q];
+}
+
+template <typename R>
+__host__ __device__ inline const R* pick_terms(const double* cm, const float* cmf);
+template <>
+__host__ __device__ inline const double* pick_terms<double>(const double* cm, const float*) {
+  return cm;
+}
+template <>
+__host__ __device__ inline const float* pick_terms<float>(const double*, const float* cmf) {
+  return cmf;
+}
 
 // One site of the fused pass: both pending half forces as one equilibrium
 // shift, then the collision, then the store.  f: the pulled (post-stream)
@@ -230,7 +273,8 @@ struct PassK {
 // B = w S rho, B0 = w S rho0,
 //   even: A + B (9/2 (c.u)^2 - 3/2 u.u) - B0 (9/2 (c.U)^2 - 3/2 U.U)
 //   odd:  3 B (c.u) - 3 B0 (c.U)
-// so neither the loads nor the stores need the scale.
+// so neither the loads nor the stores need the scale; the U terms are
+// per-pass constants (comoving_terms).
 template <int S, bool CM>
 __device__ __forceinline__ void fused_site(const typename Store<S>::R f[Q], typename Store<S>::R Fx,
                                            typename Store<S>::R Fy, typename Store<S>::R Fz,
@@ -261,18 +305,12 @@ __device__ __forceinline__ void fused_site(const typename Store<S>::R f[Q], type
   const R hx = ux + hf * Fx, hy = uy + hf * Fy, hz = uz + hf * Fz;
   const R usq = ux * ux + uy * uy + uz * uz, hsq = hx * hx + hy * hy + hz * hz;
   const R rs = rho * k.sc;
-  R isq = 0, osq = 0, r0s = 0;
-  if (CM) {
-    isq = k.ui[0] * k.ui[0] + k.ui[1] * k.ui[1] + k.ui[2] * k.ui[2];
-    osq = k.uo[0] * k.uo[0] + k.uo[1] * k.uo[1] + k.uo[2] * k.uo[2];
-    r0s = k.rho0 * k.sc;
-  }
   {
     const R w = wgt<R>(0);
     R eb = w * (d - R(1.5) * rs * usq), eh = w * (d - R(1.5) * rs * hsq);
     if (CM) {
-      eb += w * R(1.5) * r0s * isq;
-      eh += w * R(1.5) * r0s * osq;
+      eb -= k.cm[0];
+      eh -= k.cm[20];
     }
     St::st_raw(fo + own, eh + R(2) * k.hp * (f[0] - eb));
   }
@@ -285,13 +323,11 @@ __device__ __forceinline__ void fused_site(const typename Store<S>::R f[Q], type
     R Eb = A + B * (R(4.5) * cb * cb - R(1.5) * usq), Ob = R(3) * B * cb;
     R Eh = A + B * (R(4.5) * ch * ch - R(1.5) * hsq), Oh = R(3) * B * ch;
     if (CM) {
-      const R B0 = w * r0s;
-      const R ci = R(CX[i]) * k.ui[0] + R(CY[i]) * k.ui[1] + R(CZ[i]) * k.ui[2];
-      const R co = R(CX[i]) * k.uo[0] + R(CY[i]) * k.uo[1] + R(CZ[i]) * k.uo[2];
-      Eb -= B0 * (R(4.5) * ci * ci - R(1.5) * isq);
-      Ob -= R(3) * B0 * ci;
-      Eh -= B0 * (R(4.5) * co * co - R(1.5) * osq);
-      Oh -= R(3) * B0 * co;
+      const int q = (i + 1) / 2;
+      Eb -= k.cm[q];
+      Ob -= k.cm[10 + q];
+      Eh -= k.cm[20 + q];
+      Oh -= k.cm[30 + q];
     }
     const R ni = f[i] - Eb - Ob, nj = f[i + 1] - Eb + Ob;
     const R sym = k.hp * (ni + nj), anti = k.hm * (ni - nj);

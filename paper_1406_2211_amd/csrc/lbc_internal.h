@@ -33,6 +33,8 @@ struct LatArgs {
   float scale, inv;   // 16-bit storage scale 2^p and its inverse (1 otherwise)
   double uin[3];      // storage reference velocity of fin (comoving frame; 0 otherwise)
   double uout[3];     // storage reference velocity of fout
+  double cm[40];      // comoving reference terms of the pass (comoving_terms)
+  float cmf[40];      // the same in FP32
   double rnx, rny;    // 1/nx, 1/ny (linear-site pass)
   int clear_mask;     // clear the force mask after reading it (every kMaskKeep steps)
   int ib_copy;        // immersed boundary: FA becomes the pending FB (same spread)
@@ -159,6 +161,8 @@ struct EnsSlot {
   double4* mcache;  // coupling moment cache (see PartArgs)
   int4* mbase;
   int mvalid;       // the cache holds the state of f[cur]
+  double cm[40];    // comoving reference terms of the next pass (comoving_terms)
+  float cmf[40];    // the same in FP32
 };
 
 struct EnsArgs {

@@ -124,10 +124,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
   k.inv = R(a.inv);
   k.hp = R(0.5) * R(a.omp);
   k.hm = R(0.5) * R(a.omm);
-  for (int c = 0; c < 3; ++c) {
-    k.ui[c] = R(a.uin[c]);
-    k.uo[c] = R(a.uout[c]);
-  }
+  for (int c = 0; c < 3; ++c) k.ui[c] = R(a.uin[c]);
+  k.cm = pick_terms<R>(a.cm, a.cmf);
   fused_site<S, CM>(f, Fx, Fy, Fz, k, (T*)a.fout, N, own);
 }
 
@@ -876,7 +874,8 @@ struct LatView {
   __device__ double omp() const { return a.omp; }
   __device__ double omm() const { return a.omm; }
   __device__ double uin(int c) const { return a.uin[c]; }
-  __device__ double uout(int c) const { return a.uout[c]; }
+  __device__ const double* cm() const { return a.cm; }
+  __device__ const float* cmf() const { return a.cmf; }
   __device__ bool ib_copy() const { return a.ib_copy != 0; }
   __device__ bool clear_mask() const { return a.clear_mask != 0; }
 };
@@ -900,9 +899,8 @@ struct SlotView {
   __device__ double omp() const { return s.omp; }
   __device__ double omm() const { return s.omm; }
   __device__ double uin(int c) const { return s.uref[c]; }
-  __device__ double uout(int c) const {
-    return s.uref[c] + (c == 0 ? s.fx : (c == 1 ? s.fy : s.fz)) / s.rho0;
-  }
+  __device__ const double* cm() const { return s.cm; }
+  __device__ const float* cmf() const { return s.cmf; }
   __device__ bool ib_copy() const { return false; }
   __device__ bool clear_mask() const { return s.steps_done % kMaskKeep == 0; }
 };
@@ -949,11 +947,9 @@ __device__ __forceinline__ void linear_site(const V& v, uint32_t s) {
   k.hp = R(0.5) * R(v.omp());
   k.hm = R(0.5) * R(v.omm());
   if (CM) {
-    for (int c = 0; c < 3; ++c) {
-      k.ui[c] = R(v.uin(c));
-      k.uo[c] = R(v.uout(c));
-    }
+    for (int c = 0; c < 3; ++c) k.ui[c] = R(v.uin(c));
   }
+  k.cm = pick_terms<R>(v.cm(), v.cmf());
   fused_site<S, CM>(f, Fx, Fy, Fz, k, (T*)v.fout(), P, s);
 }
 
@@ -1077,6 +1073,9 @@ __global__ void k_ens_advance(EnsArgs e) {
     sl.uref[0] += sl.fx / sl.rho0;
     sl.uref[1] += sl.fy / sl.rho0;
     sl.uref[2] += sl.fz / sl.rho0;
+    const double uo[3] = {sl.uref[0] + sl.fx / sl.rho0, sl.uref[1] + sl.fy / sl.rho0,
+                          sl.uref[2] + sl.fz / sl.rho0};
+    comoving_terms(sl.scale, sl.rho0, sl.uref, uo, sl.cm, sl.cmf);
   }
 }
 
