@@ -40,6 +40,7 @@ class _Cfg(C.Structure):
         ("bond_r0", C.c_double), ("bond_type", C.c_int),
         ("nshell", C.c_int), ("shell_size", C.c_int), ("shell_template", C.c_void_p),
         ("tether_k", C.c_double),
+        ("csc", C.c_int),
     ]
 
 
@@ -65,6 +66,8 @@ def lib():
         "lbo_moments": (None, [P, _dp, _dp, _dp]),
         "lbo_force_half": (None, [P, _dp, vp]),
         "lbo_collide": (None, [P, _dp]),
+        "lbo_collide_half": (None, [P, _dp]),
+        "lbo_stress": (None, [P, _dp, _dp]),
         "lbo_stream": (None, [P, _dp, _dp]),
         "lbo_phi": (C.c_double, [C.c_int, C.c_double]),
         "lbo_interp": (None, [P, C.c_int, _dp, _dp, _dp, _dp, _dp]),
@@ -148,7 +151,7 @@ class Oracle:
     nx, ny, nz, wall_y [0], tau, rho0 [1], fext [(0,0,0)], collision [BGK],
     magic [3/16], coupling [NONE], gamma [0], kernel [2], mts_n [0],
     bonds [None: int32 [nb,2]], bond_k, bond_r0, bond_type [HARMONIC],
-    nshell [0], shell_template [None: [M,3]], tether_k."""
+    nshell [0], shell_template [None: [M,3]], tether_k, csc [0: the C S form; 1: C^1/2 S C^1/2]."""
 
     def __init__(self, **cfg):
         self.nx, self.ny, self.nz = int(cfg["nx"]), int(cfg["ny"]), int(cfg["nz"])
@@ -182,6 +185,7 @@ class Oracle:
             c.shell_size = self._tmpl.shape[0]
             c.shell_template = self._tmpl.ctypes.data
         c.tether_k = float(cfg.get("tether_k", 0.0))
+        c.csc = int(cfg.get("csc", 0))
         self.cfg = c
         self.N = self.nx * self.ny * self.nz
         self.shape = (self.nz, self.ny, self.nx)
@@ -210,6 +214,17 @@ class Oracle:
         df = _f64(df).copy()
         lib().lbo_collide(C.byref(self.cfg), df)
         return df
+
+    def collide_half(self, df):
+        df = _f64(df).copy()
+        lib().lbo_collide_half(C.byref(self.cfg), df)
+        return df
+
+    def stress(self, df):
+        """Pi_ab = sum_i (f_i - f^eq_i) c_ia c_ib, [6] + shape: xx yy zz xy xz yz."""
+        pi = np.zeros((6,) + self.shape)
+        lib().lbo_stress(C.byref(self.cfg), _f64(df), pi)
+        return pi
 
     def collide_site(self, f):
         f = _f64(f).copy()

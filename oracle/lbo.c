@@ -206,7 +206,7 @@ static void collide_site_with(const lbo_cfg *cfg, double df[LBO_Q], const double
   site_rho_u(cfg, df, &drho, &rho, u);
   lbo_feq_dev(drho, rho, u, feq);
   if (cfg->collision == LBO_BGK) {
-    const double om = 1.0 - 1.0 / cfg->tau;
+    const double om = 1.0 - lam[4]; /* every non-conserved row relaxes at the same rate */
     for (int i = 0; i < LBO_Q; ++i) df[i] = feq[i] + om * (df[i] - feq[i]);
     return;
   }
@@ -303,6 +303,47 @@ void lbo_collide(const lbo_cfg *cfg, double *df) {
     for (int i = 0; i < LBO_Q; ++i) f[i] = df[i * N + s];
     collide_site_with(cfg, f, E, b, lam);
     for (int i = 0; i < LBO_Q; ++i) df[i * N + s] = f[i];
+  }
+}
+
+/* Half-step collision C^1/2 of the collide-stream-collide form (Sec. 4):
+ * the same relaxation with 1 - lambda_1/2 = sqrt(1 - lambda) for every
+ * eigenvalue (Sec. 3.2, the exact half step), so that C^1/2 C^1/2 = C.  Real
+ * only for lambda <= 1. */
+void lbo_collide_half(const lbo_cfg *cfg, double *df) {
+  lattice_init();
+  double E[LBO_Q * LBO_Q], b[LBO_Q], lam[LBO_Q];
+  lbo_mrt_basis(E, b);
+  lbo_rates(cfg, lam);
+  for (int k = 0; k < LBO_Q; ++k) lam[k] = 1.0 - sqrt(1.0 - lam[k]);
+  const long N = nsites(cfg);
+#pragma omp parallel for schedule(static)
+  for (long s = 0; s < N; ++s) {
+    double f[LBO_Q];
+    for (int i = 0; i < LBO_Q; ++i) f[i] = df[i * N + s];
+    collide_site_with(cfg, f, E, b, lam);
+    for (int i = 0; i < LBO_Q; ++i) df[i * N + s] = f[i];
+  }
+}
+
+/* Non-equilibrium second moment Pi_ab = sum_i (f_i - f^eq_i(rho, u)) c_ia c_ib
+ * of the given populations, u their own velocity (the stress of Eq. viscstress
+ * before its prefactor). */
+void lbo_stress(const lbo_cfg *cfg, const double *df, double *pi) {
+  lattice_init();
+  const long N = nsites(cfg);
+  static const int A[6] = {0, 1, 2, 0, 0, 1}, B[6] = {0, 1, 2, 1, 2, 2};
+#pragma omp parallel for schedule(static)
+  for (long s = 0; s < N; ++s) {
+    double f[LBO_Q], d, r, uu[3], feq[LBO_Q];
+    for (int i = 0; i < LBO_Q; ++i) f[i] = df[i * N + s];
+    site_rho_u(cfg, f, &d, &r, uu);
+    lbo_feq_dev(d, r, uu, feq);
+    for (int q = 0; q < 6; ++q) {
+      double acc = 0.0;
+      for (int i = 0; i < LBO_Q; ++i) acc += (f[i] - feq[i]) * C[i][A[q]] * C[i][B[q]];
+      pi[q * N + s] = acc;
+    }
   }
 }
 
@@ -628,8 +669,16 @@ static void drift(const lbo_cfg *cfg, int np, double *pos, const double *vel, do
   wrap_positions(cfg, np, pos);
 }
 
-/* stream the collided populations and swap the buffers */
+/* The LB update between the two half forces: C S (Eq. LB-splitting-combined),
+ * or C^1/2 S C^1/2 in the collide-stream-collide form (Eq. csc); streams into
+ * the other buffer and returns it. */
 static double *collide_stream(const lbo_cfg *cfg, double *df, work *w) {
+  if (cfg->csc) {
+    lbo_collide_half(cfg, df);
+    lbo_stream(cfg, df, w->df2);
+    lbo_collide_half(cfg, w->df2);
+    return w->df2;
+  }
   lbo_collide(cfg, df);
   lbo_stream(cfg, df, w->df2);
   return w->df2;
@@ -744,6 +793,12 @@ static double *step_ib(const lbo_cfg *cfg, double *df, int np, double *X, work *
 static int check_cfg(const lbo_cfg *cfg, int np, const double *mass) {
   if (cfg->nx <= 0 || cfg->ny <= 0 || cfg->nz <= 0) return -1;
   if (!(cfg->tau > 0.5)) return -1;
+  if (cfg->csc) { /* the exact half step needs every rate <= 1 */
+    double lam[LBO_Q];
+    lbo_rates(cfg, lam);
+    for (int k = 0; k < LBO_Q; ++k)
+      if (lam[k] > 1.0) return -1;
+  }
   if (cfg->kernel < 2 || cfg->kernel > 4) return -1;
   if (cfg->coupling == LBO_IB && cfg->mts_n > 0) return -1;
   if ((cfg->coupling == LBO_FC || cfg->coupling == LBO_EBF) && np > 0 && !mass) return -1;

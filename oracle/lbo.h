@@ -48,6 +48,8 @@ typedef struct lbo_cfg {
   int nshell, shell_size;      /* markers i*shell_size .. (i+1)*shell_size-1 form shell i */
   const double *shell_template;/* [shell_size][3], centred on the origin */
   double tether_k;
+  int csc;                     /* 1: collide-stream-collide form C^1/2 S C^1/2 with
+                                  1 - lambda_1/2 = sqrt(1 - lambda) (needs all rates <= 1) */
 } lbo_cfg;
 
 /* lattice and local operators */
@@ -64,6 +66,8 @@ void lbo_init_fluid(const lbo_cfg *cfg, double *df, const double *rho /*nullable
 void lbo_moments(const lbo_cfg *cfg, const double *df, double *rho, double *u);
 void lbo_force_half(const lbo_cfg *cfg, double *df, const double *Fc /*nullable [3][N]*/);
 void lbo_collide(const lbo_cfg *cfg, double *df);
+void lbo_collide_half(const lbo_cfg *cfg, double *df);
+void lbo_stress(const lbo_cfg *cfg, const double *df, double *pi /*[6][N]: xx yy zz xy xz yz*/);
 void lbo_stream(const lbo_cfg *cfg, const double *src, double *dst);
 
 /* delta functions, interpolation and spreading */
