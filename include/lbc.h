@@ -84,6 +84,13 @@ typedef struct lb_params {
                             advancing by F_ext/rho0 per step (the mean velocity a uniform body
                             force gives the fluid); an exact change of variables that keeps
                             stored values small in 16-bit storage */
+  int32_t csc;           /* 0: the standard state; 1: the collide-stream-collide form of
+                            Sec. 4 (Eq. csc): the state at a step boundary is the half
+                            collision C^1/2 of the standard one (Eq. LB-splitting-combined),
+                            with 1 - lambda_1/2 = sqrt(1 - lambda) per rate (Sec. 3.2), so
+                            every rate must be <= 1 (tau >= 1; for LB_TRT also
+                            trt_magic >= (tau - 1/2)/2), else LB_EINVAL.  Dynamics, moments,
+                            particles and stress are those of the standard form. */
 } lb_params;
 
 typedef struct lb_limits {
@@ -151,8 +158,22 @@ lb_status lb_step(lb_ctx* ctx, int64_t nsteps);
  * (may be NULL) and d_u [3][nz][ny][nx]. */
 lb_status lb_moments(lb_ctx* ctx, double* d_rho, double* d_u);
 
-/* Physical populations as deviations f_i - w_i rho0, FP64 [19][nz][ny][nx]. */
+/* Physical populations as deviations f_i - w_i rho0, FP64 [19][nz][ny][nx].
+ * With csc = 1 these are the collide-stream-collide populations (Eq. csc):
+ * f^eq(rho, u) + sqrt(1 - lambda) (f - f^eq(rho, u)) per relaxation mode of
+ * the standard physical populations f, which have the same rho and u. */
 lb_status lb_populations(lb_ctx* ctx, double* d_df);
+
+/* Local viscous stress (Eq. viscstress) at every site, FP64 device output
+ * d_sigma [6][nz][ny][nx] in the order xx, yy, zz, xy, xz, yz:
+ * sigma = (1 - lambda_+/2) sum_i (f_i - f^eq_i(rho, u)) c_i c_i of the
+ * standard physical populations, lambda_+ = 1/tau the rate of the stress
+ * modes.  This equals (1/2)((1 - lambda_1/2)^-1 + (1 - lambda_1/2)) times the
+ * same sum over the collide-stream-collide populations, and -rho nu
+ * (grad u + grad u^T) with nu = (tau - 1/2)/3 up to second-order terms.  The
+ * same physical quantity in both forms; the half forces are equilibrium
+ * shifts and do not enter it.  Asynchronous. */
+lb_status lb_stress(lb_ctx* ctx, double* d_sigma);
 
 /* Current particle positions and velocities, FP64 device [n][3] (either may be NULL). */
 lb_status lb_get_particles(lb_ctx* ctx, double* d_pos, double* d_vel);

@@ -131,6 +131,13 @@ bool check_params(const lb_grid* g, const lb_params* p, const lb_limits* lim, st
   if (p->comoving != 0 && p->comoving != 1) return err = "comoving must be 0 or 1", false;
   if (p->comoving && g->wall_y)
     return err = "the comoving storage frame needs a periodic box (walls break uniform flow)", false;
+  if (p->csc != 0 && p->csc != 1) return err = "csc must be 0 or 1", false;
+  if (p->csc) {  // the exact half collision sqrt(1 - lambda) needs every rate <= 1
+    const double magic = p->trt_magic > 0 ? p->trt_magic : 3.0 / 16.0;
+    if (p->tau < 1.0) return err = "the collide-stream-collide form needs tau >= 1", false;
+    if (p->collision == LB_TRT && 0.5 + magic / (p->tau - 0.5) < 1.0)
+      return err = "the collide-stream-collide form needs trt_magic >= (tau - 1/2)/2", false;
+  }
   if (lim->max_particles < 0 || lim->max_particles > (1ll << 30) || lim->max_bonds < 0 ||
       lim->max_bonds > (1ll << 29) || lim->max_shells < 0 || lim->max_shell_size < 0)
     return err = "invalid limits", false;
@@ -703,7 +710,16 @@ lb_status lb_moments(lb_ctx* c, double* d_rho, double* d_u) {
 lb_status lb_populations(lb_ctx* c, double* d_df) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
   if (!d_df) return fail(c, LB_EINVAL, "null output");
-  HIPCHK(c, launch_populations(c->p.storage, site_args(c), d_df, c->st));
+  const double gp = c->p.csc ? std::sqrt(c->omp) : 1.0, gm = c->p.csc ? std::sqrt(c->omm) : 1.0;
+  HIPCHK(c, launch_populations(c->p.storage, site_args(c), d_df, gp, gm, c->st));
+  return LB_OK;
+}
+
+lb_status lb_stress(lb_ctx* c, double* d_sigma) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (!d_sigma) return fail(c, LB_EINVAL, "null output");
+  // 1 - lambda+/2 with 1 - lambda+ = omp
+  HIPCHK(c, launch_stress(c->p.storage, site_args(c), d_sigma, 0.5 * (1.0 + c->omp), c->st));
   return LB_OK;
 }
 

@@ -180,7 +180,11 @@ hipError_t launch_ens_step(int storage, int K, const EnsArgs& e, int lat_grid, i
 hipError_t launch_stream_collide(int storage, bool comoving, const LatArgs& a, hipStream_t st);
 hipError_t launch_init(int storage, const InitArgs& a, hipStream_t st);
 hipError_t launch_moments(int storage, const SiteArgs& a, double* rho, double* u, hipStream_t st);
-hipError_t launch_populations(int storage, const SiteArgs& a, double* out, hipStream_t st);
+// gp, gm: factors of the even and odd non-equilibrium parts (1, 1: the
+// physical populations; sqrt(1 - lambda+-): the collide-stream-collide state).
+hipError_t launch_populations(int storage, const SiteArgs& a, double* out, double gp, double gm,
+                              hipStream_t st);
+hipError_t launch_stress(int storage, const SiteArgs& a, double* out, double pref, hipStream_t st);
 hipError_t launch_totals(int storage, const SiteArgs& a, double* partial, int nblk,
                          const double* vel, const double* mass, long long np, double* out,
                          hipStream_t st);

@@ -85,7 +85,6 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
-  using V4 = typename St::V4;
   const uint32_t nx = (uint32_t)a.g.nx, ny = (uint32_t)a.g.ny, nz = (uint32_t)a.g.nz;
   const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t y = blockIdx.y, z = blockIdx.z;
@@ -180,8 +179,13 @@ __global__ void k_moments(SiteArgs a, double* rho, double* u) {
   u[2 * a.g.N + s] = j[2] / r;
 }
 
+// Physical populations: the stored ones moved by the pending half force, an
+// equilibrium shift f -> f + f^eq(rho, u_phys) - f^eq(rho, u).  With csc the
+// non-equilibrium part f - f^eq(rho, u) is split into even and odd parts
+// over opposite directions and scaled by gp, gm: the exact half collision of
+// the two-rate operator (Sec. 3.2), which leaves rho and u unchanged.
 template <int S>
-__global__ void k_populations(SiteArgs a, double* out) {
+__global__ void k_populations(SiteArgs a, double* out, double gp, double gm, int csc) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y, z = blockIdx.z;
   if (x >= a.g.nx) return;
@@ -193,10 +197,51 @@ __global__ void k_populations(SiteArgs a, double* out) {
   const double ub[3] = {jb[0] / r, jb[1] / r, jb[2] / r}, up[3] = {j[0] / r, j[1] / r, j[2] / r};
   const double sb = ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2];
   const double sp = up[0] * up[0] + up[1] * up[1] + up[2] * up[2];
+  if (!csc) {
 #pragma unroll
-  for (int i = 0; i < Q; ++i)
-    out[(long long)i * a.g.N + s] = fl[i] + feq_dev<double>(i, drho, r, up[0], up[1], up[2], sp) -
-                                    feq_dev<double>(i, drho, r, ub[0], ub[1], ub[2], sb);
+    for (int i = 0; i < Q; ++i)
+      out[(long long)i * a.g.N + s] = fl[i] + feq_dev<double>(i, drho, r, up[0], up[1], up[2], sp) -
+                                      feq_dev<double>(i, drho, r, ub[0], ub[1], ub[2], sb);
+    return;
+  }
+  double ne[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) ne[i] = fl[i] - feq_dev<double>(i, drho, r, ub[0], ub[1], ub[2], sb);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double e = 0.5 * (ne[i] + ne[OPP[i]]), o = 0.5 * (ne[i] - ne[OPP[i]]);
+    out[(long long)i * a.g.N + s] =
+        feq_dev<double>(i, drho, r, up[0], up[1], up[2], sp) + gp * e + gm * o;
+  }
+}
+
+// Local viscous stress pref * sum_i (f_i - f^eq_i(rho, u)) c_i c_i (order xx,
+// yy, zz, xy, xz, yz).  The pending half force is an equilibrium shift and
+// drops out, so the stored populations and their own velocity give it.
+template <int S>
+__global__ void k_stress(SiteArgs a, double* out, double pref) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y, z = blockIdx.z;
+  if (x >= a.g.nx) return;
+  double fl[Q], drho, j[3];
+  site_phys<S>(a, x, y, z, fl, drho, j, false);
+  const double r = a.rho0 + drho;
+  const double u[3] = {j[0] / r, j[1] / r, j[2] / r};
+  const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  double p[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double ne = fl[i] - feq_dev<double>(i, drho, r, u[0], u[1], u[2], usq);
+    p[0] += ne * (CX[i] * CX[i]);
+    p[1] += ne * (CY[i] * CY[i]);
+    p[2] += ne * (CZ[i] * CZ[i]);
+    p[3] += ne * (CX[i] * CY[i]);
+    p[4] += ne * (CX[i] * CZ[i]);
+    p[5] += ne * (CY[i] * CZ[i]);
+  }
+  const long long s = site_index(a.g, x, y, z);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) out[(long long)q * a.g.N + s] = pref * p[q];
 }
 
 // Block reduction of 4 doubles in a fixed order (deterministic).
@@ -764,9 +809,17 @@ hipError_t launch_moments(int storage, const SiteArgs& a, double* rho, double* u
   return hipGetLastError();
 }
 
-hipError_t launch_populations(int storage, const SiteArgs& a, double* out, hipStream_t st) {
+hipError_t launch_populations(int storage, const SiteArgs& a, double* out, double gp, double gm,
+                              hipStream_t st) {
   const dim3 b = lattice_block(a.g), gr = lattice_grid(a.g, b);
-  LBC_STORAGE_SWITCH(storage, (k_populations<SS><<<gr, b, 0, st>>>(a, out)));
+  const int csc = gp != 1.0 || gm != 1.0;
+  LBC_STORAGE_SWITCH(storage, (k_populations<SS><<<gr, b, 0, st>>>(a, out, gp, gm, csc)));
+  return hipGetLastError();
+}
+
+hipError_t launch_stress(int storage, const SiteArgs& a, double* out, double pref, hipStream_t st) {
+  const dim3 b = lattice_block(a.g), gr = lattice_grid(a.g, b);
+  LBC_STORAGE_SWITCH(storage, (k_stress<SS><<<gr, b, 0, st>>>(a, out, pref)));
   return hipGetLastError();
 }
 
@@ -910,7 +963,6 @@ __device__ __forceinline__ void linear_site(const V& v, uint32_t s) {
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
-  using V4 = typename St::V4;
   const Geo& g = v.g();
   if (s >= (uint32_t)g.N) return;
   const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny, nz = (uint32_t)g.nz;

@@ -24,8 +24,8 @@ LB_HARMONIC, LB_FENE = 0, 1
 
 EXPORTS = ["lb_lattice_velocities", "lb_workspace_size", "lb_create", "lb_init_fluid",
            "lb_set_particles", "lb_set_bonds", "lb_set_shells", "lb_step", "lb_moments",
-           "lb_populations", "lb_get_particles", "lb_totals", "lb_timing", "lb_timing_read",
-           "lb_info", "lb_destroy",
+           "lb_populations", "lb_stress", "lb_get_particles", "lb_totals", "lb_timing",
+           "lb_timing_read", "lb_info", "lb_destroy",
            "lb_last_error", "lb_status_string", "lb_ensemble_footprint", "lb_ensemble_create",
            "lb_ensemble_stream", "lb_ensemble_admit", "lb_ensemble_step", "lb_ensemble_query",
            "lb_ensemble_retire", "lb_ensemble_autotune", "lb_ensemble_destroy",
@@ -42,7 +42,7 @@ class lb_params(C.Structure):
                 ("coupling", C.c_int32), ("gamma", C.c_double), ("kernel", C.c_int32),
                 ("storage", C.c_int32), ("f16_scale_log2", C.c_int32),
                 ("mts_substeps", C.c_int32), ("deterministic", C.c_int32),
-                ("comoving", C.c_int32)]
+                ("comoving", C.c_int32), ("csc", C.c_int32)]
 
 
 class lb_limits(C.Structure):
@@ -86,6 +86,7 @@ def load():
         "lb_step": (i32, [vp, i64]),
         "lb_moments": (i32, [vp, vp, vp]),
         "lb_populations": (i32, [vp, vp]),
+        "lb_stress": (i32, [vp, vp]),
         "lb_get_particles": (i32, [vp, vp, vp]),
         "lb_totals": (i32, [vp, C.POINTER(dbl)]),
         "lb_timing": (i32, [vp, i32]),
@@ -127,7 +128,7 @@ def lattice_velocities():
 
 def make_params(tau, rho0=1.0, body_force=(0.0, 0.0, 0.0), collision=LB_BGK, trt_magic=3.0 / 16.0,
                 coupling=LB_COUPLE_NONE, gamma=0.0, kernel=LB_PHI2, storage=LB_F64,
-                f16_scale_log2=0, mts_substeps=0, comoving=0):
+                f16_scale_log2=0, mts_substeps=0, comoving=0, csc=0):
     p = lb_params()
     p.tau, p.rho0 = float(tau), float(rho0)
     for a in range(3):
@@ -136,7 +137,7 @@ def make_params(tau, rho0=1.0, body_force=(0.0, 0.0, 0.0), collision=LB_BGK, trt
     p.coupling, p.gamma, p.kernel = int(coupling), float(gamma), int(kernel)
     p.storage, p.f16_scale_log2 = int(storage), int(f16_scale_log2)
     p.mts_substeps, p.deterministic = int(mts_substeps), 0
-    p.comoving = int(comoving)
+    p.comoving, p.csc = int(comoving), int(csc)
     return p
 
 
@@ -240,6 +241,11 @@ class Lattice:
         df = self.torch.empty((19,) + self.shape, dtype=self.torch.float64, device=self.device)
         self._call("lb_populations", _ptr(df))
         return df
+
+    def lb_stress(self):
+        sigma = self.torch.empty((6,) + self.shape, dtype=self.torch.float64, device=self.device)
+        self._call("lb_stress", _ptr(sigma))
+        return sigma
 
     def lb_get_particles(self):
         pos = self.torch.empty((self.np, 3), dtype=self.torch.float64, device=self.device)

@@ -50,6 +50,10 @@ def initial_fields(c: Case):
     u = I.noise_velocity(shape, c.u_noise, c.seed) if c.u_noise > 0 else np.zeros((3,) + shape)
     if "u0" in c.extra:
         u = u + np.asarray(c.extra["u0"], np.float64)[:, None, None, None]
+    if "shear" in c.extra:  # u_x += U sin(2 pi y / ny): a decaying shear wave
+        y = np.arange(c.ny)
+        u = u.copy()
+        u[0] += c.extra["shear"] * np.sin(2 * np.pi * y / c.ny)[None, :, None]
     rho = None
     return rho, u
 
@@ -59,7 +63,8 @@ def run_oracle(c: Case):
                  collision=c.collision, coupling=COUPLING_TO_ORACLE[c.coupling], gamma=c.gamma,
                  kernel=c.kernel, mts_n=c.mts, bonds=c.bonds, bond_k=c.bond_k, bond_r0=c.bond_r0,
                  bond_type=c.bond_type, nshell=c.nshell, shell_template=c.template,
-                 tether_k=c.tether_k)
+                 tether_k=c.tether_k, magic=c.extra.get("magic", 3.0 / 16.0),
+                 csc=c.extra.get("csc", 0))
     rho, u = initial_fields(c)
     df = o.init_fluid(rho, u)
     pos = None if c.pos is None else np.array(c.pos, dtype=np.float64, copy=True)
@@ -68,7 +73,22 @@ def run_oracle(c: Case):
         vel = np.zeros_like(pos) if c.vel is None else np.array(c.vel, dtype=np.float64, copy=True)
     o.run(df, c.steps, pos, vel, c.mass)
     rho_o, u_o = o.moments(df)
-    return dict(df=df, rho=rho_o, u=u_o, pos=pos, vel=vel, totals=o.totals(df, vel, c.mass))
+    out = dict(df=df, rho=rho_o, u=u_o, pos=pos, vel=vel, totals=o.totals(df, vel, c.mass))
+    if c.extra.get("stress"):
+        out["sigma"] = stress_prefactor(c) * o.stress(df)
+    return out
+
+
+def stress_prefactor(c: Case):
+    """Eq. viscstress: sigma = p Pi^neq of the state the run returns, with
+    p = 1 - lambda/2 for the standard state and (1/2)(g^-1 + g), g =
+    sqrt(1 - lambda), for the collide-stream-collide state (lambda = 1/tau,
+    the rate of the stress modes)."""
+    lam = 1.0 / c.tau
+    if c.extra.get("csc", 0):
+        g = np.sqrt(1.0 - lam)
+        return 0.5 * (1.0 / g + g)
+    return 1.0 - 0.5 * lam
 
 
 def make_gpu(c: Case):
@@ -81,7 +101,8 @@ def make_gpu(c: Case):
                     max_shells=c.nshell, max_shell_size=ms, tau=c.tau, body_force=c.fext,
                     collision=c.collision, coupling=c.coupling, gamma=c.gamma, kernel=c.kernel,
                     storage=c.storage, mts_substeps=c.mts, f16_scale_log2=c.f16_scale_log2,
-                    comoving=c.extra.get("comoving", 0))
+                    comoving=c.extra.get("comoving", 0), csc=c.extra.get("csc", 0),
+                    trt_magic=c.extra.get("magic", 3.0 / 16.0))
     rho, u = initial_fields(c)
     lat.lb_init_fluid(None if rho is None else torch.from_numpy(rho),
                       None if u is None else torch.from_numpy(np.ascontiguousarray(u)))
@@ -114,12 +135,15 @@ def run_gpu(c: Case, lat=None):
             lat.lb_get_particles()
     rho, u = lat.lb_moments()
     df = lat.lb_populations()
+    sigma = lat.lb_stress() if c.extra.get("stress") else None
     pos, vel = lat.lb_get_particles()
     torch.cuda.synchronize()
     tot = lat.lb_totals()
     out = dict(df=df.cpu().numpy(), rho=rho.cpu().numpy(), u=u.cpu().numpy(),
                pos=pos.cpu().numpy() if c.pos is not None else None,
                vel=vel.cpu().numpy() if c.pos is not None else None, totals=tot)
+    if sigma is not None:
+        out["sigma"] = sigma.cpu().numpy()
     lat.lb_destroy()
     return out
 

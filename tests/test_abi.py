@@ -60,6 +60,8 @@ def test_workspace_size_scales_with_storage():
     dict(tau=0.8, storage=9), dict(tau=0.8, coupling=L.LB_COUPLE_FC, gamma=0.0),
     dict(tau=0.8, coupling=L.LB_COUPLE_IB, mts_substeps=3), dict(tau=0.8, mts_substeps=-1),
     dict(tau=0.8, body_force=(float("inf"), 0, 0)),
+    dict(tau=0.8, csc=1), dict(tau=1.2, collision=1, trt_magic=3.0 / 16.0, csc=1),
+    dict(tau=1.2, csc=2),
 ])
 def test_invalid_parameters_rejected(bad):
     with pytest.raises(L.LbcError) as e:
@@ -106,3 +108,11 @@ def test_serving_request_generator_ranges():
     arr = np.array([r.arrival for r in reqs])
     assert np.all(np.diff(arr) > 0)
     assert 15.0 < arr[-1] < 40.0  # 256 arrivals at 10/s
+
+
+@pytest.mark.parametrize("ok", [dict(tau=1.0, csc=1), dict(tau=1.0, collision=1, trt_magic=0.25, csc=1),
+                                dict(tau=1.2, collision=1, trt_magic=0.5, csc=1)])
+def test_collide_stream_collide_accepts_rates_up_to_one(ok):
+    """The exact half collision sqrt(1 - lambda) is real for every rate <= 1
+    (lambda = 1 included: the half collision then returns the equilibrium)."""
+    assert L.workspace_size(_g(), L.make_params(**ok), _lim()) > 0

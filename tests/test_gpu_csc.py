@@ -1,0 +1,203 @@
+"""GPU parity of the collide-stream-collide form (Sec. 4, Eq. csc) and of the
+local viscous stress (Eq. viscstress) against the FP64 oracle, which runs the
+two half collisions around streaming as separate sweeps.  Tolerances as in
+the other parity tests: FP64 storage 1e-12, FP32 storage 1e-5 of the
+oracle's largest population.  The stress is a linear combination of the 19
+populations at a site with coefficients of magnitude at most one, so its
+bound is 19 times the population bound in absolute terms."""
+import numpy as np
+import pytest
+
+from paper_1406_2211_amd import inputs as I
+from parity import Case, compare, initial_fields, run_gpu, run_oracle, ulp_sensitivity
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def _parts(n, box, seed):
+    pos = I.uniform_positions(n, box, seed)
+    vel = np.random.default_rng(seed).normal(0.0, 1e-3, (n, 3))
+    return pos, vel, np.ones(n)
+
+
+def _csc_case(which, storage=0, steps=40):
+    if which == "fc_body_force":
+        pos, vel, m = _parts(4, (20, 23, 19), 5)
+        c = Case(name="csc_fc", nx=20, ny=23, nz=19, tau=1.3, steps=steps,
+                 fext=(2e-6, -1e-6, 0.0), coupling=1, gamma=1.1, kernel=2, storage=storage,
+                 pos=pos, vel=vel, mass=m)
+    elif which == "trt_walls_ragged":
+        c = Case(name="csc_trt_walls", nx=24, ny=17, nz=9, tau=1.2, steps=steps, wall_y=1,
+                 fext=(0.0, 0.0, 1e-6), collision=1, storage=storage)
+        c.extra["magic"] = 0.5
+    elif which == "ebf_phi3_tau1":
+        # lambda = 1: the half collision has g = 0 and returns the equilibrium
+        pos, vel, m = _parts(3, (18, 18, 18), 6)
+        c = Case(name="csc_ebf_tau1", nx=18, ny=18, nz=18, tau=1.0, steps=steps, coupling=2,
+                 gamma=0.9, kernel=3, storage=storage, pos=pos, vel=vel, mass=m)
+    elif which == "row_layout_trt_odd_rate_1":
+        # nx = 64 takes the row-mapped lattice kernel; magic 0.25 at tau 1 puts
+        # the odd rate at exactly 1
+        c = Case(name="csc_row64", nx=64, ny=8, nz=6, tau=1.0, steps=steps, collision=1,
+                 fext=(1e-6, 0.0, 0.0), storage=storage)
+        c.extra["magic"] = 0.25
+    elif which == "ib_shells_phi4":
+        T = I.icosphere(1, 4.0)
+        cen = I.shell_centres(2, 4.0, (24, 24, 32), True, 2.0, 3.0, seed=3)
+        X = np.vstack([q + T for q in cen])
+        X = X + 0.15 * np.random.default_rng(5).standard_normal(X.shape)
+        c = Case(name="csc_ib", nx=24, ny=24, nz=32, tau=1.1, steps=min(steps, 30), wall_y=1,
+                 fext=(0.0, 0.0, 1e-6), coupling=3, kernel=4, storage=storage, u_noise=0.0,
+                 pos=X, nshell=2, template=T, tether_k=0.05)
+    elif which == "mts_chains":
+        pos, vel, bonds = I.chains(2, 12, (24, 24, 24), 1.0, 1e-3, 2)
+        c = Case(name="csc_mts", nx=24, ny=24, nz=24, tau=1.2, steps=steps, collision=1,
+                 coupling=1, gamma=2.0, kernel=2, storage=storage, mts=3, u_noise=0.0,
+                 pos=pos, vel=vel, mass=np.ones(len(pos)), bonds=bonds, bond_k=2.0,
+                 bond_r0=1.0)
+        c.extra["magic"] = 0.5
+    elif which == "comoving":
+        pos, vel, m = _parts(2, (16, 16, 16), 9)
+        c = Case(name="csc_comoving", nx=16, ny=16, nz=16, tau=1.1, steps=steps,
+                 fext=(1e-5, 0.0, 0.0), coupling=1, gamma=1.1, storage=storage, pos=pos,
+                 vel=vel, mass=m)
+        c.extra["comoving"] = 1
+    elif which == "one_site":
+        pos, vel, m = _parts(1, (1, 1, 1), 4)
+        c = Case(name="csc_one_site", nx=1, ny=1, nz=1, tau=1.25, steps=steps,
+                 fext=(1e-6, 2e-6, 0.0), coupling=1, gamma=1.0, storage=storage, pos=pos,
+                 vel=vel, mass=m)
+    else:
+        raise ValueError(which)
+    c.extra["csc"] = 1
+    return c
+
+
+CASES = ["fc_body_force", "trt_walls_ragged", "ebf_phi3_tau1", "row_layout_trt_odd_rate_1",
+         "ib_shells_phi4", "mts_chains", "comoving", "one_site"]
+
+
+@pytest.mark.parametrize("which", CASES)
+def test_csc_state_fp64(which):
+    """Bonded chains make the trajectory ill-conditioned: there the bound is
+    raised to 20 times the oracle's own response to a one-ulp change of the
+    positions, as for the other chain cases."""
+    c = _csc_case(which)
+    o = run_oracle(c)
+    sens = ulp_sensitivity(c, o) if c.bonds is not None else 0.0
+    compare(c, run_gpu(c), o, TOL64, sens=sens)
+
+
+def test_csc_state_fp32():
+    c = _csc_case("fc_body_force", storage=1, steps=100)
+    compare(c, run_gpu(c), run_oracle(c), TOL32)
+
+
+def test_csc_differs_from_standard_state():
+    """The populations returned in the two forms differ by the half collision
+    (a check that the flag reaches the output), while rho and u agree."""
+    c = _csc_case("fc_body_force", steps=10)
+    a = run_gpu(c)
+    c.extra["csc"] = 0
+    b = run_gpu(c)
+    assert np.abs(a["df"] - b["df"]).max() > 1e-3 * np.abs(b["df"]).max()
+    assert np.abs(a["u"] - b["u"]).max() <= 1e-14 * np.abs(b["u"]).max()
+
+
+def _stress_case(collision, tau, csc, storage=0, wall_y=0, steps=40):
+    c = Case(name=f"stress_c{collision}_t{tau}_csc{csc}_s{storage}", nx=12, ny=16, nz=10,
+             tau=tau, steps=steps, wall_y=wall_y, fext=(1e-6, 0.0, 0.0) if not wall_y else
+             (0.0, 0.0, 1e-6), collision=collision, storage=storage, u_noise=1e-3, seed=3)
+    c.extra.update(shear=2e-2, stress=1, csc=csc)
+    if collision:
+        c.extra["magic"] = 0.5
+    return c
+
+
+def _check_stress(c, tol):
+    g, o = run_gpu(c), run_oracle(c)
+    bound = 19 * tol * np.abs(o["df"]).max()
+    err = np.abs(g["sigma"] - o["sigma"]).max()
+    rel = err / np.abs(o["sigma"]).max()
+    print(f"[stress] {c.name}: max|sigma| {np.abs(o['sigma']).max():.3e}, abs err {err:.3e} "
+          f"(bound {bound:.1e}), relative {rel:.3e}", flush=True)
+    assert np.abs(o["sigma"]).max() > 1e-4
+    assert err <= bound
+
+
+@pytest.mark.parametrize("collision,tau,csc,wall_y", [
+    (0, 1.5, 0, 0), (0, 1.5, 1, 0), (0, 0.7, 0, 0), (1, 1.25, 0, 1), (1, 1.25, 1, 1)])
+def test_stress_fp64(collision, tau, csc, wall_y):
+    _check_stress(_stress_case(collision, tau, csc, wall_y=wall_y), TOL64)
+
+
+def test_stress_fp32():
+    _check_stress(_stress_case(1, 0.8, 0, storage=1, steps=60), TOL32)
+
+
+def test_stress_of_a_shear_wave_is_newtonian():
+    """Independent of the oracle: on a decaying shear wave u_x = U(t) sin(k y)
+    the stress equals -rho nu du_x/dy, nu = (tau - 1/2)/3, up to O(k^2)."""
+    c = _stress_case(0, 1.5, 1, steps=100)
+    c.nx, c.ny, c.nz, c.u_noise = 4, 32, 4, 0.0
+    g = run_gpu(c)
+    n, k = c.ny, 2 * np.pi / c.ny
+    y = np.arange(n)
+    Ut = np.sum(g["u"][0, 0, :, 0] * np.sin(k * y)) * 2.0 / n
+    expected = -(c.tau - 0.5) / 3.0 * g["rho"][0, :, 0] * Ut * k * np.cos(k * y)
+    err = np.abs(g["sigma"][3, 0, :, 0] - expected).max() / np.abs(expected).max()
+    print(f"[stress] shear wave ny=32: relative error {err:.3e}", flush=True)
+    assert err < 2e-2, err
+    # no z dependence and no z velocity: the xz and yz components vanish
+    assert np.abs(g["sigma"][[4, 5]]).max() < 1e-12 * np.abs(expected).max()
+
+
+def _admit(ens, c):
+    import torch
+    got = ens.admit(c.nx, c.ny, c.nz, c.steps, max_particles=0 if c.pos is None else len(c.pos),
+                    tau=c.tau, body_force=c.fext, collision=c.collision, coupling=c.coupling,
+                    gamma=c.gamma, kernel=c.kernel, storage=c.storage,
+                    csc=c.extra.get("csc", 0), trt_magic=c.extra.get("magic", 3.0 / 16.0))
+    assert got is not None
+    slot, lat = got
+    _, u = initial_fields(c)
+    lat.lb_init_fluid(None, torch.from_numpy(np.ascontiguousarray(u)))
+    if c.pos is not None:
+        lat.lb_set_particles(torch.from_numpy(c.pos), torch.from_numpy(c.vel),
+                             torch.from_numpy(c.mass))
+    return slot, lat
+
+
+def test_csc_and_stress_in_an_ensemble():
+    """Slots of one batched ensemble, one in each form, against the oracle."""
+    from paper_1406_2211_amd import lbc as L
+    from parity import to_oracle_order
+    a = _csc_case("fc_body_force", steps=25)
+    b = _csc_case("fc_body_force", steps=25)
+    b.extra["csc"] = 0
+    b.nx = b.ny = b.nz = 16
+    b.pos = I.uniform_positions(4, (16, 16, 16), 7)
+    a.nx = a.ny = a.nz = 20
+    a.pos = I.uniform_positions(4, (20, 20, 20), 5)
+    for c in (a, b):
+        c.extra["stress"] = 1
+    pool = 0
+    for c in (a, b):
+        pool += L.ensemble_footprint(c.nx, c.ny, c.nz, len(c.pos), tau=c.tau, storage=0,
+                                     kernel=2, coupling=1, gamma=c.gamma) + 4096
+    ens = L.Ensemble(int(pool * 1.2) + (8 << 20), max_slots=4, storage=L.LB_F64, kernel=2)
+    handles = [_admit(ens, c) for c in (a, b)]
+    print("[gpu] ensemble with a collide-stream-collide slot", flush=True)
+    ens.step(30)
+    for c, (slot, lat) in zip((a, b), handles):
+        done, fin = ens.query(slot)
+        assert done == c.steps and fin
+        o = run_oracle(c)
+        df = to_oracle_order(lat.lb_populations().cpu().numpy())
+        sig = lat.lb_stress().cpu().numpy()
+        assert np.abs(df - o["df"]).max() <= TOL64 * np.abs(o["df"]).max()
+        assert np.abs(sig - o["sigma"]).max() <= 19 * TOL64 * np.abs(o["df"]).max()
+    ens.destroy()

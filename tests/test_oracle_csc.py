@@ -126,3 +126,24 @@ def test_viscous_stress_of_a_shear_wave(tau, csc):
         errs.append(np.abs(sigma[0, :, 0] - expected).max() / np.abs(expected).max())
     assert errs[-1] < 5e-3
     assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
+
+
+@pytest.mark.parametrize("collision,tau,magic", [(O.BGK, 1.3, 0.5), (O.TRT, 1.6, 0.75)])
+def test_stress_is_the_same_in_both_forms(collision, tau, magic):
+    """Eq. viscstress evaluated on the collide-stream-collide state, with its
+    prefactor (1/2)(g^-1 + g), g = sqrt(1 - lambda), equals (1 - lambda/2)
+    Pi^neq of the standard state: the half collision scales the even
+    non-equilibrium part by g and leaves rho and u alone."""
+    kw = dict(tau=tau, collision=collision, magic=magic, fext=(1e-6, 0.0, -2e-6))
+    std, csc = _oracle(**kw), _oracle(csc=1, **kw)
+    u0 = I.noise_velocity(std.shape, 2e-3, 9)
+    a, b = std.init_fluid(None, u0), csc.init_fluid(None, u0)
+    std.run(a, 5)
+    csc.run(b, 5)
+    lam = 1.0 / tau
+    g = np.sqrt(1.0 - lam)
+    s_std = (1.0 - 0.5 * lam) * std.stress(a)
+    s_csc = 0.5 * (1.0 / g + g) * csc.stress(b)
+    scale = np.abs(s_std).max()
+    assert scale > 1e-7
+    assert np.abs(s_std - s_csc).max() < 1e-11 * scale
