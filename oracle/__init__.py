@@ -41,6 +41,7 @@ class _Cfg(C.Structure):
         ("nshell", C.c_int), ("shell_size", C.c_int), ("shell_template", C.c_void_p),
         ("tether_k", C.c_double),
         ("csc", C.c_int),
+        ("mts_inside", C.c_int),
     ]
 
 
@@ -151,7 +152,8 @@ class Oracle:
     nx, ny, nz, wall_y [0], tau, rho0 [1], fext [(0,0,0)], collision [BGK],
     magic [3/16], coupling [NONE], gamma [0], kernel [2], mts_n [0],
     bonds [None: int32 [nb,2]], bond_k, bond_r0, bond_type [HARMONIC],
-    nshell [0], shell_template [None: [M,3]], tether_k, csc [0: the C S form; 1: C^1/2 S C^1/2]."""
+    nshell [0], shell_template [None: [M,3]], tether_k, csc [0: the C S form; 1: C^1/2 S C^1/2],
+    mts_inside [0: coupling outside the sub-steps; 1: inside every sub-step]."""
 
     def __init__(self, **cfg):
         self.nx, self.ny, self.nz = int(cfg["nx"]), int(cfg["ny"]), int(cfg["nz"])
@@ -186,6 +188,7 @@ class Oracle:
             c.shell_template = self._tmpl.ctypes.data
         c.tether_k = float(cfg.get("tether_k", 0.0))
         c.csc = int(cfg.get("csc", 0))
+        c.mts_inside = int(cfg.get("mts_inside", 0))
         self.cfg = c
         self.N = self.nx * self.ny * self.nz
         self.shape = (self.nz, self.ny, self.nx)

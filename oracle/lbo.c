@@ -273,9 +273,10 @@ void lbo_moments(const lbo_cfg *cfg, const double *df, double *rho, double *u) {
   }
 }
 
-/* Half-step force operator F^1/2 (Eq. force-midpoint with h -> h/2; R4):
- * f <- f + (h/2) G(F, u_mid), u_mid = u + (h/4) F/rho, F = F_ext + Fc(x). */
-void lbo_force_half(const lbo_cfg *cfg, double *df, const double *Fc) {
+/* Force operator over a time dt (Eq. force-midpoint with h -> dt; R4):
+ * f <- f + dt G(F, u_mid), u_mid = u + (dt/2) F/rho, F = F_ext + Fc(x).  The
+ * half step F^1/2 is dt = h/2; the sub-steps of Eq. multistep take dt = h/2n. */
+void lbo_force_dt(const lbo_cfg *cfg, double *df, const double *Fc, double dt) {
   lattice_init();
   const long N = nsites(cfg);
 #pragma omp parallel for schedule(static)
@@ -285,10 +286,14 @@ void lbo_force_half(const lbo_cfg *cfg, double *df, const double *Fc) {
     for (int a = 0; a < 3; ++a) F[a] = cfg->fext[a] + (Fc ? Fc[a * N + s] : 0.0);
     site_rho_u(cfg, f, &d, &r, uu);
     double um[3];
-    for (int a = 0; a < 3; ++a) um[a] = uu[a] + 0.25 * F[a] / r;
+    for (int a = 0; a < 3; ++a) um[a] = uu[a] + 0.5 * dt * F[a] / r;
     lbo_force_term(um, F, G);
-    for (int i = 0; i < LBO_Q; ++i) df[i * N + s] = f[i] + 0.5 * G[i];
+    for (int i = 0; i < LBO_Q; ++i) df[i * N + s] = f[i] + dt * G[i];
   }
+}
+
+void lbo_force_half(const lbo_cfg *cfg, double *df, const double *Fc) {
+  lbo_force_dt(cfg, df, Fc, 0.5);
 }
 
 void lbo_collide(const lbo_cfg *cfg, double *df) {
@@ -684,14 +689,14 @@ static double *collide_stream(const lbo_cfg *cfg, double *df, work *w) {
   return w->df2;
 }
 
-/* One coupling half step (Alg. 3 CalculateCoupling, velocity half kick and
- * SpreadForce): computes F^h at every particle from the current fluid fields
- * (w->rho, w->u), kicks v by (h/2m)(F^h + F_int) (R7), and writes the lattice
- * force -I*[r] F^h into w->Fc. */
-static void coupling_half(const lbo_cfg *cfg, int np, const double *pos, double *vel,
-                          const double *mass, const double *Fint, work *w) {
+/* One coupling step of length hh (Alg. 3 CalculateCoupling, velocity kick
+ * and SpreadForce; hh = h/2 for the half steps): computes F^h at every
+ * particle from the current fluid fields (w->rho, w->u), kicks v by
+ * (hh/m)(F^h + F_int) (R7), and writes the lattice force -I*[r] F^h into
+ * w->Fc. */
+static void coupling_step(const lbo_cfg *cfg, int np, const double *pos, double *vel,
+                          const double *mass, const double *Fint, double hh, work *w) {
   const long N = nsites(cfg);
-  const double hh = 0.5;
   lbo_interp(cfg, np, pos, w->rho, w->u, w->rho_p, w->u_p);
   for (int p = 0; p < np; ++p) {
     double *Fh = w->Fh + 3 * p, *v = vel + 3 * p;
@@ -719,13 +724,13 @@ static double *step_fc(const lbo_cfg *cfg, double *df, int np, double *pos, doub
     drift(cfg, np, pos, vel, 0.5);
     lbo_intrinsic(cfg, np, pos, w->Fint);
     lbo_moments(cfg, df, w->rho, w->u);
-    coupling_half(cfg, np, pos, vel, mass, w->Fint, w);
+    coupling_step(cfg, np, pos, vel, mass, w->Fint, 0.5, w);
   }
   lbo_force_half(cfg, df, part ? w->Fc : NULL);
   df = collide_stream(cfg, df, w);
   if (part) {
     lbo_moments(cfg, df, w->rho, w->u); /* post-stream, before the half force (R6) */
-    coupling_half(cfg, np, pos, vel, mass, w->Fint, w);
+    coupling_step(cfg, np, pos, vel, mass, w->Fint, 0.5, w);
   }
   lbo_force_half(cfg, df, part ? w->Fc : NULL);
   if (part) drift(cfg, np, pos, vel, 0.5);
@@ -753,14 +758,42 @@ static double *step_mts(const lbo_cfg *cfg, double *df, int np, double *pos, dou
                         const double *mass, work *w) {
   memset(w->X1, 0, sizeof(double) * 3 * (np > 0 ? np : 1));
   lbo_moments(cfg, df, w->rho, w->u);
-  coupling_half(cfg, np, pos, vel, mass, w->X1, w);
+  coupling_step(cfg, np, pos, vel, mass, w->X1, 0.5, w);
   lbo_force_half(cfg, df, w->Fc);
   substeps(cfg, np, pos, vel, mass, w);
   df = collide_stream(cfg, df, w);
   substeps(cfg, np, pos, vel, mass, w);
   lbo_moments(cfg, df, w->rho, w->u);
-  coupling_half(cfg, np, pos, vel, mass, w->X1, w);
+  coupling_step(cfg, np, pos, vel, mass, w->X1, 0.5, w);
   lbo_force_half(cfg, df, w->Fc);
+  return df;
+}
+
+/* One sub-step P^(1/4n) F^(1/2n) P^(1/4n) of Eq. multistep, dt = h/2n: drift
+ * dt/2, the intrinsic force at the midpoint, the coupling over dt (particles
+ * and lattice, with the body force), drift dt/2.  The fluid velocity is that
+ * of the populations as they stand, so each sub-step sees the forces of the
+ * earlier ones; after the LB update the first sees the post-stream velocity
+ * (R6). */
+static void coupled_substep(const lbo_cfg *cfg, double *df, int np, double *pos, double *vel,
+                            const double *mass, double dt, work *w) {
+  drift(cfg, np, pos, vel, 0.5 * dt);
+  lbo_intrinsic(cfg, np, pos, w->Fint);
+  lbo_moments(cfg, df, w->rho, w->u);
+  coupling_step(cfg, np, pos, vel, mass, w->Fint, dt, w);
+  lbo_force_dt(cfg, df, w->Fc, dt);
+  drift(cfg, np, pos, vel, 0.5 * dt);
+}
+
+/* Multiple time-step splitting with the coupling inside (Eq. multistep):
+ * [P^(1/4n) F^(1/2n) P^(1/4n)]^n (C S) [P^(1/4n) F^(1/2n) P^(1/4n)]^n, where
+ * F holds every force (intrinsic, coupling, body force). */
+static double *step_mts_inside(const lbo_cfg *cfg, double *df, int np, double *pos,
+                               double *vel, const double *mass, work *w) {
+  const double dt = 1.0 / (2.0 * cfg->mts_n);
+  for (int k = 0; k < cfg->mts_n; ++k) coupled_substep(cfg, df, np, pos, vel, mass, dt, w);
+  df = collide_stream(cfg, df, w);
+  for (int k = 0; k < cfg->mts_n; ++k) coupled_substep(cfg, df, np, pos, vel, mass, dt, w);
   return df;
 }
 
@@ -801,6 +834,7 @@ static int check_cfg(const lbo_cfg *cfg, int np, const double *mass) {
   }
   if (cfg->kernel < 2 || cfg->kernel > 4) return -1;
   if (cfg->coupling == LBO_IB && cfg->mts_n > 0) return -1;
+  if (cfg->mts_inside != 0 && cfg->mts_inside != 1) return -1;
   if ((cfg->coupling == LBO_FC || cfg->coupling == LBO_EBF) && np > 0 && !mass) return -1;
   if (cfg->nshell > 0 && cfg->nshell * cfg->shell_size > np) return -1;
   return 0;
@@ -823,7 +857,8 @@ int lbo_run(const lbo_cfg *cfg, int nsteps, double *df, int np, double *pos, dou
     if (cfg->coupling == LBO_IB)
       out = step_ib(cfg, cur, np, pos, &w);
     else if (cfg->mts_n > 0 && cfg->coupling != LBO_NONE && np > 0)
-      out = step_mts(cfg, cur, np, pos, vel, mass, &w);
+      out = cfg->mts_inside ? step_mts_inside(cfg, cur, np, pos, vel, mass, &w)
+                            : step_mts(cfg, cur, np, pos, vel, mass, &w);
     else
       out = step_fc(cfg, cur, np, pos, vel, mass, &w);
     /* out is the buffer that was w.df2; the old one becomes scratch */

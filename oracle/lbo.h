@@ -39,7 +39,7 @@ typedef struct lbo_cfg {
   int coupling;          /* LBO_NONE, LBO_FC, LBO_EBF (modified EBF), LBO_IB */
   double gamma;          /* friction for FC / EBF */
   int kernel;            /* 2, 3 or 4 point delta function */
-  int mts_n;             /* 0: Alg. 3 ordering; n>0: coupling outside, n sub-steps per side */
+  int mts_n;             /* 0: Alg. 3 ordering; n>0: n sub-steps per side (see mts_inside) */
   /* intrinsic forces */
   int nbond;
   const int32_t *bond_pairs;   /* [nbond][2] */
@@ -50,6 +50,9 @@ typedef struct lbo_cfg {
   double tether_k;
   int csc;                     /* 1: collide-stream-collide form C^1/2 S C^1/2 with
                                   1 - lambda_1/2 = sqrt(1 - lambda) (needs all rates <= 1) */
+  int mts_inside;              /* with mts_n > 0: 0 the coupling outside the sub-steps
+                                  (Sec. 6, second decomposition); 1 the coupling inside every
+                                  sub-step (Eq. multistep), 2n coupling evaluations per step */
 } lbo_cfg;
 
 /* lattice and local operators */
@@ -65,6 +68,7 @@ void lbo_init_fluid(const lbo_cfg *cfg, double *df, const double *rho /*nullable
                     const double *u /*nullable [3][N]*/);
 void lbo_moments(const lbo_cfg *cfg, const double *df, double *rho, double *u);
 void lbo_force_half(const lbo_cfg *cfg, double *df, const double *Fc /*nullable [3][N]*/);
+void lbo_force_dt(const lbo_cfg *cfg, double *df, const double *Fc /*nullable*/, double dt);
 void lbo_collide(const lbo_cfg *cfg, double *df);
 void lbo_collide_half(const lbo_cfg *cfg, double *df);
 void lbo_stress(const lbo_cfg *cfg, const double *df, double *pi /*[6][N]: xx yy zz xy xz yz*/);

@@ -1,0 +1,180 @@
+"""Pins of the two multiple time-step schemes of Sec. 6 in the oracle: the
+coupling inside every sub-step (Eq. multistep: [P^(1/4n) F^(1/2n)
+P^(1/4n)]^n around the LB update, F holding every force) and the coupling
+outside (F_h^1/2 [P F_int P]^n LB [P F_int P]^n F_h^1/2).
+
+A one-site periodic lattice decouples the relative motion of a bonded pair
+from the fluid: both particles see the single cell's velocity, which cancels
+in the difference.  With a harmonic bond of zero rest length the relative
+coordinate d and velocity w then follow a linear map per sub-step, whose
+powers and whose limits for many sub-steps are closed forms."""
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+import oracle as O
+from paper_1406_2211_amd import inputs as I
+
+GAMMA, M, K = 0.9, 1.3, 2.5  # friction, particle mass, bond stiffness
+
+
+def _pair_run(n, inside, steps, d0=0.12, w0=0.01, coupling=O.FC, rho0=1.0):
+    o = O.Oracle(nx=1, ny=1, nz=1, tau=0.8, coupling=coupling, gamma=GAMMA, kernel=2,
+                 mts_n=n, mts_inside=inside, bonds=np.array([[0, 1]]), bond_k=K, bond_r0=0.0,
+                 rho0=rho0)
+    df = o.init_fluid(None, np.array([2e-3, 0.0, 0.0]).reshape(3, 1, 1, 1))
+    pos = np.array([[0.5 + d0 / 2, 0.4, 0.6], [0.5 - d0 / 2, 0.4, 0.6]])
+    vel = np.array([[w0 / 2 + 1e-3, 0.0, 0.0], [-w0 / 2 + 1e-3, 0.0, 0.0]])
+    mass = np.full(2, M)
+    p0 = o.totals(df, vel, mass)
+    o.run(df, steps, pos, vel, mass)
+    d = pos[0, 0] - pos[1, 0]
+    d -= np.round(d)  # minimum image in the unit box
+    p1 = o.totals(df, vel, mass)
+    return d, vel[0, 0] - vel[1, 0], p0, p1, df
+
+
+def _kick(w, F, dt, rho=1.0):
+    """Crank-Nicolson coupling over dt (Sec. 5.2, Eq. modified-force) for the
+    difference of the two particles: w += (dt/m)(F^h_rel + F_rel)."""
+    al, be = GAMMA * dt / M, GAMMA * dt / rho
+    Fh = -(GAMMA * w + 0.5 * al * F) / (1 + 0.5 * al + 0.5 * be)
+    return w + dt / M * (Fh + F)
+
+
+def _inside_map(n, steps, d, w):
+    dt = 1.0 / (2 * n)
+    for _ in range(2 * n * steps):
+        d = d + 0.5 * dt * w
+        w = _kick(w, -2 * K * d, dt)
+        d = d + 0.5 * dt * w
+    return d, w
+
+
+def _outside_map(n, steps, d, w):
+    dt = 1.0 / (2 * n)
+    for _ in range(steps):
+        w = _kick(w, 0.0, 0.5)
+        for _ in range(2 * n):
+            d = d + 0.5 * dt * w
+            w = w + dt / M * (-2 * K * d)
+            d = d + 0.5 * dt * w
+        w = _kick(w, 0.0, 0.5)
+    return d, w
+
+
+@pytest.mark.parametrize("inside", [1, 0])
+@pytest.mark.parametrize("n", [1, 3])
+def test_one_cell_pair_follows_the_sub_step_map(inside, n):
+    """The relative motion of a bonded pair in a one-site fluid equals the
+    closed-form sub-step map of the scheme, and fluid + particle momentum is
+    conserved (the bond forces cancel, the coupling forces are equal and
+    opposite)."""
+    steps = 9
+    d, w, p0, p1, _ = _pair_run(n, inside, steps)
+    ref = (_inside_map if inside else _outside_map)(n, steps, 0.12, 0.01)
+    assert abs(d - ref[0]) < 1e-13 and abs(w - ref[1]) < 1e-13, (d, w, ref)
+    assert abs(w - 0.01) > 1e-3  # the pair moved
+    assert np.abs((p1[1:4] + p1[4:7]) - (p0[1:4] + p0[4:7])).max() < 1e-16
+
+
+def _exact(A, T, d0=0.12, w0=0.01):
+    return expm(A * T) @ np.array([d0, w0])
+
+
+@pytest.mark.parametrize("rho0,order", [(1e6, 2), (1.0, 1)])
+def test_coupling_inside_converges_to_the_damped_oscillator(rho0, order):
+    """With the coupling inside, the sub-steps integrate m w' = -gamma w -
+    2 k d (the fluid velocity cancels) and converge to the exact damped
+    oscillator as dt = h/2n shrinks.  The lumped implicit coupling of Sec. 5.2
+    treats each particle as alone in its cell (beta/2 in the denominator), which
+    the relative motion of two particles sharing a cell does not see: the
+    friction is off by O(beta) and the error falls at first order.  With a heavy
+    cell (beta -> 0) the sub-step is the implicit midpoint rule and the error
+    falls four-fold per doubling of n."""
+    T = 6
+    ex = _exact(np.array([[0.0, 1.0], [-2 * K / M, -GAMMA / M]]), T)
+    errs = []
+    for n in (4, 8, 16):
+        d, w, *_ = _pair_run(n, 1, T, rho0=rho0)
+        errs.append(max(abs(d - ex[0]), abs(w - ex[1])))
+    lo, hi = (3.5, 4.5) if order == 2 else (1.7, 2.3)
+    assert lo < errs[0] / errs[1] < hi and lo < errs[1] / errs[2] < hi, errs
+
+
+def test_coupling_outside_converges_to_split_friction():
+    """With the coupling outside, more sub-steps integrate only the bond: the
+    scheme converges (second order) to the friction half steps around the
+    exact undamped motion over h, not to the damped oscillator; the splitting
+    error of the coupling stays (the inaccuracy noted at the end of Sec. 6)."""
+    T = 6
+    al, be = GAMMA * 0.5 / M, GAMMA * 0.5 / 1.0
+    c = 1.0 - 0.5 / M * GAMMA / (1 + 0.5 * al + 0.5 * be)
+    Fr = np.diag([1.0, c])
+    R = expm(np.array([[0.0, 1.0], [-2 * K / M, 0.0]]))
+    lim = np.linalg.matrix_power(Fr @ R @ Fr, T) @ np.array([0.12, 0.01])
+    damped = _exact(np.array([[0.0, 1.0], [-2 * K / M, -GAMMA / M]]), T)
+    errs, gaps = [], []
+    for n in (4, 8, 16):
+        d, w, *_ = _pair_run(n, 0, T)
+        errs.append(max(abs(d - lim[0]), abs(w - lim[1])))
+        gaps.append(max(abs(d - damped[0]), abs(w - damped[1])))
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs
+    assert gaps[2] > 0.5 * gaps[1] > 0  # no convergence to the damped oscillator
+    assert gaps[2] > 20 * errs[2]
+
+
+@pytest.mark.parametrize("n", [1, 4])
+def test_one_cell_free_particle_relaxes_per_sub_step(n):
+    """Without intrinsic forces each coupled sub-step is the Crank-Nicolson
+    update of Sec. 5.2 over dt = h/2n: v - u contracts by
+    (1 - (alpha+beta)/2)/(1 + (alpha+beta)/2), alpha = gamma dt/m,
+    beta = gamma dt/rho, 2n times per step."""
+    o = O.Oracle(nx=1, ny=1, nz=1, tau=0.9, coupling=O.FC, gamma=1.7, kernel=2, mts_n=n,
+                 mts_inside=1)
+    u0 = np.array([1e-3, -4e-4, 2e-4])
+    df = o.init_fluid(None, u0.reshape(3, 1, 1, 1))
+    v0 = np.array([[-2e-3, 1e-3, 5e-4]])
+    vel = v0.copy()
+    steps, m = 5, 0.6
+    o.run(df, steps, np.array([[0.3, 0.6, 0.2]]), vel, np.array([m]))
+    dt = 1.0 / (2 * n)
+    al, be = 1.7 * dt / m, 1.7 * dt
+    kappa = (1 - (al + be) / 2) / (1 + (al + be) / 2)
+    _, u = o.moments(df)
+    u = u.ravel()
+    assert np.abs((vel[0] - u) - kappa ** (2 * n * steps) * (v0[0] - u0)).max() < 1e-15
+    assert np.abs((m * vel[0] + u) - (m * v0[0] + u0)).max() < 1e-17
+
+
+@pytest.mark.parametrize("coupling", [O.FC, O.EBF])
+def test_coupling_inside_momentum_with_body_force(coupling):
+    """Chains in a 12^3 fluid under a body force: the body force is applied in
+    2n pieces of dt each, so fluid + particle momentum grows by exactly h F N
+    per step."""
+    F = np.array([1e-6, -2e-6, 5e-7])
+    pos, vel, bonds = I.chains(2, 8, (12, 12, 12), 1.0, 1e-3, 4)
+    o = O.Oracle(nx=12, ny=12, nz=12, tau=0.7, coupling=coupling, gamma=1.5, kernel=3,
+                 mts_n=3, mts_inside=1, bonds=bonds, bond_k=0.5, bond_r0=1.0, fext=F,
+                 collision=O.TRT)
+    m = np.full(len(pos), 0.8)
+    df = o.init_fluid(None, I.noise_velocity(o.shape, 1e-4, 3))
+    t0 = o.totals(df, vel, m)
+    o.run(df, 12, pos, vel, m)
+    t1 = o.totals(df, vel, m)
+    assert np.abs(vel).max() > 1e-6
+    gain = (t1[1:4] + t1[4:7]) - (t0[1:4] + t0[4:7])
+    assert np.abs(gain - 12 * o.N * F).max() < 1e-13
+    assert abs(t1[0] - t0[0]) < 1e-13
+
+
+def test_coupling_inside_stiff_chain_is_stable():
+    """The stiff chains of the force-coupling workload (k = 30, m = 1) are
+    stable with the coupling inside from the same sub-step counts as with the
+    coupling outside."""
+    pos, vel, bonds = I.chains(1, 20, (16, 16, 16), 1.0, 1e-3, 2)
+    o = O.Oracle(nx=16, ny=16, nz=16, tau=0.6, collision=O.TRT, coupling=O.FC, gamma=2.0,
+                 kernel=2, mts_n=3, mts_inside=1, bonds=bonds, bond_k=30.0, bond_r0=1.0)
+    df = o.init_fluid()
+    o.run(df, 30, pos, vel, np.ones(20))
+    assert np.abs(vel).max() < 1e-2
