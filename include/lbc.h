@@ -91,6 +91,12 @@ typedef struct lb_params {
                             every rate must be <= 1 (tau >= 1; for LB_TRT also
                             trt_magic >= (tau - 1/2)/2), else LB_EINVAL.  Dynamics, moments,
                             particles and stress are those of the standard form. */
+  int32_t mts_inside;    /* with mts_substeps = n > 0: 0 the coupling outside the sub-steps
+                            (Sec. 6, second decomposition: F_h^1/2 [P F_int P]^n (C S)
+                            [P F_int P]^n F_h^1/2); 1 the coupling inside every sub-step
+                            (Eq. multistep: [P^(1/4n) F^(1/2n) P^(1/4n)]^n (C S) [...]^n, F
+                            holding every force; 2n coupling evaluations per step).
+                            LB_EINVAL without sub-steps. */
 } lb_params;
 
 typedef struct lb_limits {

@@ -127,6 +127,9 @@ bool check_params(const lb_grid* g, const lb_params* p, const lb_limits* lim, st
   if (p->mts_substeps < 0 || p->mts_substeps > 256) return err = "mts_substeps out of range", false;
   if (p->mts_substeps > 0 && p->coupling == LB_COUPLE_IB)
     return err = "multiple time stepping applies to force coupling only", false;
+  if (p->mts_inside != 0 && p->mts_inside != 1) return err = "mts_inside must be 0 or 1", false;
+  if (p->mts_inside && p->mts_substeps < 1)
+    return err = "mts_inside needs mts_substeps >= 1", false;
   if (p->deterministic != 0) return err = "deterministic mode is not available", false;
   if (p->comoving != 0 && p->comoving != 1) return err = "comoving must be 0 or 1", false;
   if (p->comoving && g->wall_y)
@@ -237,6 +240,11 @@ static PartArgs part_args(const lb_ctx* c) {
   a.mbase = c->L.mbase;
   a.cache_use = 0;
   a.cache_fill = 0;
+  a.hh = 0.5;
+  a.hd = 0.5;
+  a.fa_rd = 0;
+  a.sw = 1.0;
+  a.defer = nullptr;
   return a;
 }
 
@@ -414,6 +422,61 @@ static lb_status finish_step(lb_ctx* c) {
   return LB_OK;
 }
 
+// Multiple time stepping with the coupling inside (Eq. multistep): n coupled
+// sub-steps of dt = h/2n on each side of the lattice pass.  A sub-step drifts
+// dt/2, takes the intrinsic force at the midpoint, couples over dt (F^h, kick,
+// lattice force) and drifts dt/2.  Its lattice force goes into FA (before the
+// pass) or FB (after), scaled by 2 dt, so each field holds the impulse of its
+// n sub-steps as a half-step force and the pass is unchanged.  The fluid
+// velocity a sub-step sees is that of the populations with every force
+// applied so far: the pending fields of the earlier sub-steps and k dt of the
+// body force; after the pass the first sub-step sees the post-stream velocity
+// (as the second half of Alg. 3).  A sub-step that reads the field it writes
+// stores its forces and spreads them in a second launch.
+static lb_status step_mts_inside(lb_ctx* c) {
+  const int n = c->p.mts_substeps;
+  const double dt = 1.0 / (2.0 * n);
+  const bool fint = c->nshell > 0 || c->nbond > 0;
+  lb_status s;
+  for (int side = 0; side < 2; ++side) {
+    if (side == 1 && (s = lattice_pass(c)) != LB_OK) return s;
+    for (int k = 0; k < n; ++k) {
+      bool any = false;
+      if (fint) {
+        HIPCHK(c, launch_drift(c->geo, c->np, c->L.pos, c->L.vel, 0.5 * dt, c->st));
+        if ((s = enqueue_fint(c, c->L.pos, any)) != LB_OK) return s;
+      }
+      PartArgs a = part_args(c);
+      a.hh = dt;
+      a.hd = 0.5 * dt;
+      a.sw = 2.0 * dt;
+      a.use_fint = any ? 1 : 0;
+      a.drift_before = fint ? 0 : 1;
+      a.drift_after = 1;
+      a.target = side;
+      const double ext = (side == 0 ? c->pend : 0) + 2.0 * k * dt;  // body force applied, x h/2
+      a.s.pfx = ext * c->p.body_force[0];
+      a.s.pfy = ext * c->p.body_force[1];
+      a.s.pfz = ext * c->p.body_force[2];
+      a.phys = (side == 0 || k > 0) ? 1 : 0;  // side 1, k > 0: FB holds the earlier sub-steps
+      a.fa_rd = (side == 0 && k > 0) ? 1 : 0;
+      a.cache_fill = (side == 1 && k == 0) ? 1 : 0;
+      a.cache_use = (side == 1 && k > 0) || (side == 0 && c->mvalid) ? 1 : 0;
+      if (k == 0) {
+        HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
+      } else {  // spread and closing drift in a second launch, from the midpoint positions
+        a.defer = c->L.aux;
+        PartArgs b = a;
+        b.drift_after = 0;
+        HIPCHK(c, launch_couple_half(c->p.storage, b, c->st));
+        HIPCHK(c, launch_spread_deferred(c->p.storage, a, c->st));
+      }
+    }
+  }
+  c->mvalid = true;
+  return LB_OK;
+}
+
 static lb_status step_once(lb_ctx* c) {
   const bool parts = c->p.coupling != LB_COUPLE_NONE && c->np > 0;
   lb_status s;
@@ -464,6 +527,7 @@ static lb_status step_once(lb_ctx* c) {
     HIPCHK(c, launch_ib_advect(c->p.storage, a, 0, c->st));
     return LB_OK;
   }
+  if (c->p.mts_substeps > 0 && c->p.mts_inside) return step_mts_inside(c);
   if (c->p.mts_substeps > 0) {
     const int n = c->p.mts_substeps;
     const double dt = 1.0 / (2.0 * n);

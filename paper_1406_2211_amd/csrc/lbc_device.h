@@ -177,6 +177,16 @@ __device__ __forceinline__ void add_pending(const SiteArgs& a, long long s, doub
   j[2] += 0.5 * ((double)fb.z + a.pfz);
 }
 
+// (h/2) of a pending force field added to the momentum at site s.
+template <int S>
+__device__ __forceinline__ void add_field(const void* field, long long s, double j[3]) {
+  using V4 = typename Store<S>::V4;
+  const V4 f = ((const V4*)field)[s];
+  j[0] += 0.5 * (double)f.x;
+  j[1] += 0.5 * (double)f.y;
+  j[2] += 0.5 * (double)f.z;
+}
+
 // Physical moments at one site: rho and rho u = sum f c + (h/2)(FB + pend F_ext)
 // (the redefined velocity of Sec. 4).
 template <int S>

@@ -79,6 +79,13 @@ struct PartArgs {
   int target;       // spread into FA (0) or FB (1)
   int drift_before;  // first P^1/2 of Alg. 3 (when no intrinsic forces sit between)
   int drift_after;   // final P^1/2 of Alg. 3
+  double hh;         // coupling step length: h/2 (half steps) or h/2n (coupled sub-steps)
+  double hd;         // length of drift_before / drift_after
+  int fa_rd;         // the interpolated momentum also takes (h/2) FA (earlier sub-steps)
+  double sw;         // scale of the lattice force written: 1, or 2 hh for sub-steps
+  double* defer;     // non-null: store the lattice force per particle [n][3] here; a
+                     // separate launch spreads it (the interpolation of a sub-step must
+                     // not see the spreads of the same sub-step)
   // Moment cache: the second coupling half stores, per particle and stencil
   // node, the moments it gathered; the next step's first half reads the same
   // populations (no lattice pass in between) and reuses them when the
@@ -192,6 +199,7 @@ hipError_t launch_drift(const Geo& g, long long n, double* pos, const double* ve
                         hipStream_t st);
 hipError_t launch_wrap(const Geo& g, long long n, double* pos, hipStream_t st);
 hipError_t launch_couple_half(int storage, const PartArgs& a, hipStream_t st);
+hipError_t launch_spread_deferred(int storage, const PartArgs& a, hipStream_t st);
 hipError_t launch_ib_predict(int storage, const PartArgs& a, hipStream_t st);
 hipError_t launch_ib_advect(int storage, const PartArgs& a, int spread_fint, hipStream_t st);
 hipError_t launch_bond_groups(const BondArgs& b, int ngroups, int gcap, int mode, int acc,

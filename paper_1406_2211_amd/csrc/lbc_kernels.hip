@@ -376,6 +376,7 @@ __device__ __forceinline__ void group_interp(const PartArgs& a, const double X[3
       site_phys<S>(a.s, sl.x, sl.y, sl.z, fl, drho, j, phys);
       if (fill) a.mcache[p * L + lane] = make_double4(drho, j[0], j[1], j[2]);
     }
+    if (phys && a.fa_rd) add_field<S>(a.FA, site_index(a.s.g, sl.x, sl.y, sl.z), j);
     if (sl.valid) {
       const double rr = a.s.rho0 + drho;
       r = sl.W * rr;
@@ -429,8 +430,10 @@ __global__ void k_wrap(Geo g, long long n, double* pos) {
   for (int k = 0; k < 3; ++k) pos[3 * p + k] = r[k];
 }
 
-// One coupling half step for FC / modified EBF: interpolate rho_p, u_p at r,
-// compute F^h (h' = h/2), kick v, optionally drift, and spread -F^h.
+// One coupling step for FC / modified EBF: interpolate rho_p, u_p at r,
+// compute F^h over h' = a.hh (h/2 for the half steps of Alg. 3, h/2n for the
+// sub-steps of Eq. multistep), kick v, optionally drift, and spread -F^h
+// (scaled by a.sw) or store it for k_spread_deferred.
 template <int S, int K>
 __global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
   using E = typename Store<S>::R;
@@ -446,13 +449,13 @@ __global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
     if (a.use_fint) Fi[k] = a.fint[3 * p + k];
   }
   if (a.drift_before) {  // P^1/2: r <- wrap(r + (h/2) v), as k_drift does
-    for (int k = 0; k < 3; ++k) r[k] += 0.5 * v[k];
+    for (int k = 0; k < 3; ++k) r[k] += a.hd * v[k];
     wrap3(a.s.g, r);
   }
   const double m = a.mass[p];
   double rp, up[3];
   group_interp<S, K>(a, r, a.phys != 0, lane, rp, up, p);
-  const double hh = 0.5, al = a.gamma * hh / m, be = a.gamma * hh / rp;
+  const double hh = a.hh, al = a.gamma * hh / m, be = a.gamma * hh / rp;
   double Fh[3];
   if (a.coupling == LB_COUPLE_FC) {
     const double den = 1.0 + 0.5 * al + 0.5 * be;
@@ -468,16 +471,46 @@ __global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
       v[k] = v[k] - al / sm * d + (hh / m) * (be / sm) * Fi[k];
     }
   }
-  const double Ff[3] = {-Fh[0], -Fh[1], -Fh[2]};
-  group_spread<E, K>(a, r, Ff, a.target ? a.FB : a.FA, lane);
+  const double Ff[3] = {-a.sw * Fh[0], -a.sw * Fh[1], -a.sw * Fh[2]};
+  if (a.defer) {
+    if (lane == 0)
+      for (int k = 0; k < 3; ++k) a.defer[3 * p + k] = Ff[k];
+  } else {
+    group_spread<E, K>(a, r, Ff, a.target ? a.FB : a.FA, lane);
+  }
   if (lane == 0) {
     if (a.drift_after) {
-      for (int k = 0; k < 3; ++k) r[k] += hh * v[k];
+      for (int k = 0; k < 3; ++k) r[k] += a.hd * v[k];
       wrap3(a.s.g, r);
     }
     if (a.drift_after || a.drift_before)
       for (int k = 0; k < 3; ++k) a.pos[3 * p + k] = r[k];
     for (int k = 0; k < 3; ++k) a.vel[3 * p + k] = v[k];
+  }
+}
+
+// Spread of the lattice forces a deferred coupling step stored, then the
+// closing drift of the sub-step (Eq. multistep: the interpolation of every
+// particle in a sub-step sees the spreads of the earlier sub-steps and none
+// of its own, so the spread runs as a launch of its own).
+template <int S, int K>
+__global__ __launch_bounds__(256) void k_spread_deferred(PartArgs a) {
+  using E = typename Store<S>::R;
+  constexpr int L = Lanes<K>::L;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long p = gid / L;
+  const int lane = (int)(gid % L);
+  if (p >= a.n) return;  // whole groups leave together
+  double r[3], F[3];
+  for (int k = 0; k < 3; ++k) {
+    r[k] = a.pos[3 * p + k];
+    F[k] = a.defer[3 * p + k];
+  }
+  group_spread<E, K>(a, r, F, a.target ? a.FB : a.FA, lane);
+  if (lane == 0 && a.drift_after) {
+    for (int k = 0; k < 3; ++k) r[k] += a.hd * a.vel[3 * p + k];
+    wrap3(a.s.g, r);
+    for (int k = 0; k < 3; ++k) a.pos[3 * p + k] = r[k];
   }
 }
 
@@ -863,6 +896,13 @@ hipError_t launch_couple_half(int storage, const PartArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_spread_deferred(int storage, const PartArgs& a, hipStream_t st) {
+  if (a.n > 0)
+    LBC_KERNEL_SWITCH(a.K, LBC_STORAGE_SWITCH(storage, (k_spread_deferred<SS, KK>
+                                                        <<<gblocks(a.n, KK), 256, 0, st>>>(a))));
+  return hipGetLastError();
+}
+
 hipError_t launch_ib_predict(int storage, const PartArgs& a, hipStream_t st) {
   if (a.n > 0)
     LBC_KERNEL_SWITCH(a.K, LBC_STORAGE_SWITCH(storage, (k_ib_predict<SS, KK>
@@ -1068,6 +1108,7 @@ __global__ __launch_bounds__(256) void k_ens_couple(EnsArgs e, int half) {
     a.mbase = sl.mbase;
     a.cache_use = half == 0 ? sl.mvalid : 0;
     a.cache_fill = half == 1 ? 1 : 0;
+    a.fa_rd = 0;
     const double hh = 0.5;
     double r[3], v[3];
     for (int k = 0; k < 3; ++k) {

@@ -64,7 +64,8 @@ def run_oracle(c: Case):
                  kernel=c.kernel, mts_n=c.mts, bonds=c.bonds, bond_k=c.bond_k, bond_r0=c.bond_r0,
                  bond_type=c.bond_type, nshell=c.nshell, shell_template=c.template,
                  tether_k=c.tether_k, magic=c.extra.get("magic", 3.0 / 16.0),
-                 csc=c.extra.get("csc", 0))
+                 csc=c.extra.get("csc", 0), mts_inside=c.extra.get("mts_inside", 0),
+                 rho0=c.extra.get("rho0", 1.0))
     rho, u = initial_fields(c)
     df = o.init_fluid(rho, u)
     pos = None if c.pos is None else np.array(c.pos, dtype=np.float64, copy=True)
@@ -102,7 +103,8 @@ def make_gpu(c: Case):
                     collision=c.collision, coupling=c.coupling, gamma=c.gamma, kernel=c.kernel,
                     storage=c.storage, mts_substeps=c.mts, f16_scale_log2=c.f16_scale_log2,
                     comoving=c.extra.get("comoving", 0), csc=c.extra.get("csc", 0),
-                    trt_magic=c.extra.get("magic", 3.0 / 16.0))
+                    trt_magic=c.extra.get("magic", 3.0 / 16.0),
+                    mts_inside=c.extra.get("mts_inside", 0), rho0=c.extra.get("rho0", 1.0))
     rho, u = initial_fields(c)
     lat.lb_init_fluid(None if rho is None else torch.from_numpy(rho),
                       None if u is None else torch.from_numpy(np.ascontiguousarray(u)))

@@ -61,7 +61,8 @@ def test_workspace_size_scales_with_storage():
     dict(tau=0.8, coupling=L.LB_COUPLE_IB, mts_substeps=3), dict(tau=0.8, mts_substeps=-1),
     dict(tau=0.8, body_force=(float("inf"), 0, 0)),
     dict(tau=0.8, csc=1), dict(tau=1.2, collision=1, trt_magic=3.0 / 16.0, csc=1),
-    dict(tau=1.2, csc=2),
+    dict(tau=1.2, csc=2), dict(tau=0.8, coupling=1, gamma=1.0, mts_inside=1),
+    dict(tau=0.8, coupling=1, gamma=1.0, mts_substeps=2, mts_inside=2),
 ])
 def test_invalid_parameters_rejected(bad):
     with pytest.raises(L.LbcError) as e:
