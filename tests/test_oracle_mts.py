@@ -168,13 +168,21 @@ def test_coupling_inside_momentum_with_body_force(coupling):
     assert abs(t1[0] - t0[0]) < 1e-13
 
 
-def test_coupling_inside_stiff_chain_is_stable():
-    """The stiff chains of the force-coupling workload (k = 30, m = 1) are
-    stable with the coupling inside from the same sub-step counts as with the
-    coupling outside."""
-    pos, vel, bonds = I.chains(1, 20, (16, 16, 16), 1.0, 1e-3, 2)
-    o = O.Oracle(nx=16, ny=16, nz=16, tau=0.6, collision=O.TRT, coupling=O.FC, gamma=2.0,
-                 kernel=2, mts_n=3, mts_inside=1, bonds=bonds, bond_k=30.0, bond_r0=1.0)
-    df = o.init_fluid()
-    o.run(df, 30, pos, vel, np.ones(20))
-    assert np.abs(vel).max() < 1e-2
+@pytest.mark.parametrize("inside", [1, 0])
+def test_stiff_chain_stability_boundary(inside):
+    """The stiff chains of the force-coupling workload (k = 30, m = 1, h = 1):
+    unstable with n = 2 sub-steps per side in either scheme, stable from
+    n = 3: the chain's fastest mode has omega^2 = 4k/m, so omega dt = 2.7 at
+    dt = h/4 and 1.8 at dt = h/6, against the Verlet limit 2."""
+    vmax = {}
+    for n in (2, 3):
+        pos, vel, bonds = I.chains(1, 20, (16, 16, 16), 1.0, 1e-3, 2)
+        o = O.Oracle(nx=16, ny=16, nz=16, tau=0.6, collision=O.TRT, coupling=O.FC, gamma=2.0,
+                     kernel=2, mts_n=n, mts_inside=inside, bonds=bonds, bond_k=30.0,
+                     bond_r0=1.0)
+        df = o.init_fluid()
+        with np.errstate(all="ignore"):
+            o.run(df, 30, pos, vel, np.ones(20))
+        vmax[n] = np.abs(vel).max()
+    assert not vmax[2] < 1.0
+    assert vmax[3] < 1e-3
