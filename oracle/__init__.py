@@ -27,6 +27,7 @@ Q = 19
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
 
 
 class _Cfg(C.Structure):
@@ -42,6 +43,7 @@ class _Cfg(C.Structure):
         ("tether_k", C.c_double),
         ("csc", C.c_int),
         ("mts_inside", C.c_int),
+        ("kT", C.c_double), ("seed", C.c_uint64), ("step0", C.c_int64),
     ]
 
 
@@ -81,6 +83,9 @@ def lib():
         "lbo_run": (C.c_int, [P, C.c_int, _dp, C.c_int, vp, vp, vp]),
         "lbo_totals": (None, [P, _dp, C.c_int, vp, vp, _dp]),
         "lbo_threads": (C.c_int, []),
+        "lbo_philox": (None, [_u32p, _u32p, _u32p]),
+        "lbo_normals4": (None, [_u32p, _u32p, _dp]),
+        "lbo_site_normals": (None, [P, C.c_int64, C.c_uint32, _dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -134,6 +139,20 @@ def phi(kernel, r):
     return lib().lbo_phi(int(kernel), float(r))
 
 
+def philox(ctr, key):
+    """Philox4x32-10 block of the 4-word counter ctr under the 2-word key."""
+    out = np.zeros(4, np.uint32)
+    lib().lbo_philox(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), out)
+    return out
+
+
+def normals4(ctr, key):
+    """Four standard normal deviates (Box-Muller) from one Philox block."""
+    g = np.zeros(4)
+    lib().lbo_normals4(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), g)
+    return g
+
+
 def fc_force(gamma, m, rho_p, hh, v, u_p, Fint):
     Fh = np.zeros(3)
     lib().lbo_fc_force(gamma, m, rho_p, hh, _f64(v), _f64(u_p), _f64(Fint), Fh)
@@ -153,7 +172,8 @@ class Oracle:
     magic [3/16], coupling [NONE], gamma [0], kernel [2], mts_n [0],
     bonds [None: int32 [nb,2]], bond_k, bond_r0, bond_type [HARMONIC],
     nshell [0], shell_template [None: [M,3]], tether_k, csc [0: the C S form; 1: C^1/2 S C^1/2],
-    mts_inside [0: coupling outside the sub-steps; 1: inside every sub-step]."""
+    mts_inside [0: coupling outside the sub-steps; 1: inside every sub-step], kT [0: no
+    fluctuations], seed [0], step0 [0: index of the first step in the random streams]."""
 
     def __init__(self, **cfg):
         self.nx, self.ny, self.nz = int(cfg["nx"]), int(cfg["ny"]), int(cfg["nz"])
@@ -189,6 +209,9 @@ class Oracle:
         c.tether_k = float(cfg.get("tether_k", 0.0))
         c.csc = int(cfg.get("csc", 0))
         c.mts_inside = int(cfg.get("mts_inside", 0))
+        c.kT = float(cfg.get("kT", 0.0))
+        c.seed = int(cfg.get("seed", 0))
+        c.step0 = int(cfg.get("step0", 0))
         self.cfg = c
         self.N = self.nx * self.ny * self.nz
         self.shape = (self.nz, self.ny, self.nx)
@@ -222,6 +245,12 @@ class Oracle:
         df = _f64(df).copy()
         lib().lbo_collide_half(C.byref(self.cfg), df)
         return df
+
+    def site_normals(self, step, site):
+        """The 19 normal deviates of one site in one step, g[i] for velocity c_i."""
+        g = np.zeros(Q)
+        lib().lbo_site_normals(C.byref(self.cfg), int(step), int(site), g)
+        return g
 
     def stress(self, df):
         """Pi_ab = sum_i (f_i - f^eq_i) c_ia c_ib, [6] + shape: xx yy zz xy xz yz."""

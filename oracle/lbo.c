@@ -48,6 +48,7 @@
 static int C[LBO_Q][3];
 static double W[LBO_Q];
 static int OPP[LBO_Q];
+static int RANK[LBO_Q]; /* order of c in increasing 9(cx+1) + 3(cy+1) + (cz+1) */
 static int lattice_ready = 0;
 
 static void lattice_init(void) {
@@ -74,6 +75,12 @@ static void lattice_init(void) {
     for (int j = 0; j < LBO_Q; ++j)
       if (C[j][0] == -C[i][0] && C[j][1] == -C[i][1] && C[j][2] == -C[i][2])
         OPP[i] = j;
+  for (int i = 0; i < LBO_Q; ++i) {
+    const int ki = 9 * (C[i][0] + 1) + 3 * (C[i][1] + 1) + (C[i][2] + 1);
+    RANK[i] = 0;
+    for (int j = 0; j < LBO_Q; ++j)
+      if (9 * (C[j][0] + 1) + 3 * (C[j][1] + 1) + (C[j][2] + 1) < ki) ++RANK[i];
+  }
   lattice_ready = 1;
 }
 
@@ -196,6 +203,105 @@ static void site_rho_u(const lbo_cfg *cfg, const double df[LBO_Q], double *drho,
   u[2] = jz / *rho;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Random numbers.  Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel */
+/* random numbers: as easy as 1, 2, 3", SC 2011): ten rounds, each taking   */
+/* the two 32x32 -> 64-bit products of words 0 and 2 with the published     */
+/* multipliers and mixing their halves with words 1 and 3 and the key; the  */
+/* key advances by the published Weyl increments between rounds.  Normal    */
+/* deviates by the Box-Muller transform (Box and Muller 1958) of uniforms   */
+/* u = (x / 2^8 + 1/2) / 2^24 in (0, 1) made from the top 24 bits.          */
+/* ------------------------------------------------------------------------ */
+void lbo_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n1 = (uint32_t)p1;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1, n3 = (uint32_t)p0;
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    c3 = n3;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+static double unit24(uint32_t x) { return ((double)(x >> 8) + 0.5) / 16777216.0; }
+
+void lbo_normals4(const uint32_t ctr[4], const uint32_t key[2], double g[4]) {
+  uint32_t x[4];
+  lbo_philox(ctr, key, x);
+  for (int p = 0; p < 2; ++p) {
+    const double r = sqrt(-2.0 * log(unit24(x[2 * p])));
+    const double th = 6.283185307179586 * unit24(x[2 * p + 1]);
+    g[2 * p] = r * cos(th);
+    g[2 * p + 1] = r * sin(th);
+  }
+}
+
+/* The 19 normal deviates of one site in one step: five Philox blocks with
+ * counter (site, step low word, block, step high word), stream 0; deviate
+ * RANK[i] belongs to velocity c_i. */
+void lbo_site_normals(const lbo_cfg *cfg, int64_t step, uint32_t site, double g[LBO_Q]) {
+  lattice_init();
+  const uint32_t key[2] = {(uint32_t)cfg->seed, (uint32_t)(cfg->seed >> 32)};
+  double all[20];
+  for (int k = 0; k < 5; ++k) {
+    const uint32_t ctr[4] = {site, (uint32_t)step, (uint32_t)k, (uint32_t)((uint64_t)step >> 32)};
+    lbo_normals4(ctr, key, all + 4 * k);
+  }
+  for (int i = 0; i < LBO_Q; ++i) g[i] = all[RANK[i]];
+}
+
+/* Three normal deviates of particle p for coupling step j of a step:
+ * counter (p, step low word, 2^16 + j, step high word). */
+static void particle_normals(const lbo_cfg *cfg, int64_t step, int p, int j, double g[3]) {
+  const uint32_t key[2] = {(uint32_t)cfg->seed, (uint32_t)(cfg->seed >> 32)};
+  const uint32_t ctr[4] = {(uint32_t)p, (uint32_t)step, 65536u + (uint32_t)j,
+                           (uint32_t)((uint64_t)step >> 32)};
+  double all[4];
+  lbo_normals4(ctr, key, all);
+  g[0] = all[0];
+  g[1] = all[1];
+  g[2] = all[2];
+}
+
+/* Noise of the fluctuating collision (Eq. mrt-fluct) in population form:
+ * sqrt(rho) phi_k r_k added to every non-conserved moment (rows 4..18),
+ * phi_k = sqrt(mu b_k lambda_k (2 - lambda_k)), mu = k_B T / c_s^2 (a = 1),
+ * then f_i = w_i sum_k E_ki m_k / b_k.  The amplitude keeps the variance of
+ * each non-conserved moment at its equilibrium value mu rho b_k under
+ * m <- (1 - lambda) m + phi r (the fluctuation-dissipation relation of the
+ * cited fluctuating LB).  The standard normal r_k are the normalised
+ * moments m_k(z)/sqrt(b_k) of z_i = sqrt(w_i) g_i, g_i iid standard normal
+ * (independent because the basis is w-orthogonal). */
+static void collision_noise(const lbo_cfg *cfg, double rho, const double *g, const double *E,
+                            const double *b, const double *lam, double out[LBO_Q]) {
+  const double mu = 3.0 * cfg->kT;
+  double z[LBO_Q], add[LBO_Q];
+  for (int i = 0; i < LBO_Q; ++i) z[i] = sqrt(W[i]) * g[i];
+  for (int k = 0; k < LBO_Q; ++k) {
+    add[k] = 0.0;
+    if (k < 4) continue; /* density and momentum are conserved */
+    double m = 0.0;
+    for (int i = 0; i < LBO_Q; ++i) m += E[k * LBO_Q + i] * z[i];
+    const double r = m / sqrt(b[k]);
+    add[k] = sqrt(rho) * sqrt(mu * b[k] * lam[k] * (2.0 - lam[k])) * r;
+  }
+  for (int i = 0; i < LBO_Q; ++i) {
+    double s2 = 0.0;
+    for (int k = 4; k < LBO_Q; ++k) s2 += E[k * LBO_Q + i] * add[k] / b[k];
+    out[i] = W[i] * s2;
+  }
+}
+
 /* Collision C (Eq. CN-coll / collision-operator, Eq. mrt-coll) on one site.
  * BGK: f <- f^eq + (1 - lambda)(f - f^eq).  Two-rate MRT: the same relaxation
  * applied row by row in moment space, m_k <- m_k^eq + (1 - lambda_k)(m_k - m_k^eq),
@@ -296,7 +402,10 @@ void lbo_force_half(const lbo_cfg *cfg, double *df, const double *Fc) {
   lbo_force_dt(cfg, df, Fc, 0.5);
 }
 
-void lbo_collide(const lbo_cfg *cfg, double *df) {
+/* Collision of every site; with kT > 0 the fluctuating collision of Eq.
+ * mrt-fluct, its random numbers drawn for the given step.  The noise uses the
+ * site density before the collision (which the collision conserves). */
+void lbo_collide_noisy(const lbo_cfg *cfg, double *df, int64_t step) {
   lattice_init();
   double E[LBO_Q * LBO_Q], b[LBO_Q], lam[LBO_Q];
   lbo_mrt_basis(E, b);
@@ -304,12 +413,21 @@ void lbo_collide(const lbo_cfg *cfg, double *df) {
   const long N = nsites(cfg);
 #pragma omp parallel for schedule(static)
   for (long s = 0; s < N; ++s) {
-    double f[LBO_Q];
+    double f[LBO_Q], d, r, u[3];
     for (int i = 0; i < LBO_Q; ++i) f[i] = df[i * N + s];
+    site_rho_u(cfg, f, &d, &r, u);
     collide_site_with(cfg, f, E, b, lam);
+    if (cfg->kT > 0.0) {
+      double g[LBO_Q], n[LBO_Q];
+      lbo_site_normals(cfg, step, (uint32_t)s, g);
+      collision_noise(cfg, r, g, E, b, lam, n);
+      for (int i = 0; i < LBO_Q; ++i) f[i] += n[i];
+    }
     for (int i = 0; i < LBO_Q; ++i) df[i * N + s] = f[i];
   }
 }
+
+void lbo_collide(const lbo_cfg *cfg, double *df) { lbo_collide_noisy(cfg, df, cfg->step0); }
 
 /* Half-step collision C^1/2 of the collide-stream-collide form (Sec. 4):
  * the same relaxation with 1 - lambda_1/2 = sqrt(1 - lambda) for every
@@ -638,6 +756,7 @@ void lbo_intrinsic(const lbo_cfg *cfg, int np, const double *pos, double *F) {
 /* ------------------------------------------------------------------------ */
 typedef struct work {
   double *df2, *rho, *u, *Fc, *Fint, *rho_p, *u_p, *Fh, *X1;
+  int64_t t; /* index of the current step in the random streams */
 } work;
 
 static int work_alloc(const lbo_cfg *cfg, int np, work *w) {
@@ -684,7 +803,7 @@ static double *collide_stream(const lbo_cfg *cfg, double *df, work *w) {
     lbo_collide_half(cfg, w->df2);
     return w->df2;
   }
-  lbo_collide(cfg, df);
+  lbo_collide_noisy(cfg, df, w->t);
   lbo_stream(cfg, df, w->df2);
   return w->df2;
 }
@@ -695,13 +814,23 @@ static double *collide_stream(const lbo_cfg *cfg, double *df, work *w) {
  * (hh/m)(F^h + F_int) (R7), and writes the lattice force -I*[r] F^h into
  * w->Fc. */
 static void coupling_step(const lbo_cfg *cfg, int np, const double *pos, double *vel,
-                          const double *mass, const double *Fint, double hh, work *w) {
+                          const double *mass, const double *Fint, double hh, int j, work *w) {
   const long N = nsites(cfg);
   lbo_interp(cfg, np, pos, w->rho, w->u, w->rho_p, w->u_p);
   for (int p = 0; p < np; ++p) {
     double *Fh = w->Fh + 3 * p, *v = vel + 3 * p;
     if (cfg->coupling == LBO_FC) {
       lbo_fc_force(cfg->gamma, mass[p], w->rho_p[p], hh, v, w->u_p + 3 * p, Fint + 3 * p, Fh);
+      if (cfg->kT > 0.0) {
+        /* random force zeta of Eq. viscous-coupling, variance 2 k_B T gamma / hh
+         * per component over a coupling step of length hh, entering the implicit
+         * solution like the drag: F^h gains zeta / (1 + alpha/2 + beta/2) */
+        double g[3];
+        particle_normals(cfg, w->t, p, j, g);
+        const double al = cfg->gamma * hh / mass[p], be = cfg->gamma * hh / w->rho_p[p];
+        const double sig = sqrt(2.0 * cfg->kT * cfg->gamma / hh);
+        for (int a = 0; a < 3; ++a) Fh[a] += sig * g[a] / (1.0 + 0.5 * al + 0.5 * be);
+      }
       for (int a = 0; a < 3; ++a) v[a] += hh / mass[p] * (Fh[a] + Fint[3 * p + a]);
     } else {
       double vn[3];
@@ -724,13 +853,13 @@ static double *step_fc(const lbo_cfg *cfg, double *df, int np, double *pos, doub
     drift(cfg, np, pos, vel, 0.5);
     lbo_intrinsic(cfg, np, pos, w->Fint);
     lbo_moments(cfg, df, w->rho, w->u);
-    coupling_step(cfg, np, pos, vel, mass, w->Fint, 0.5, w);
+    coupling_step(cfg, np, pos, vel, mass, w->Fint, 0.5, 0, w);
   }
   lbo_force_half(cfg, df, part ? w->Fc : NULL);
   df = collide_stream(cfg, df, w);
   if (part) {
     lbo_moments(cfg, df, w->rho, w->u); /* post-stream, before the half force (R6) */
-    coupling_step(cfg, np, pos, vel, mass, w->Fint, 0.5, w);
+    coupling_step(cfg, np, pos, vel, mass, w->Fint, 0.5, 1, w);
   }
   lbo_force_half(cfg, df, part ? w->Fc : NULL);
   if (part) drift(cfg, np, pos, vel, 0.5);
@@ -758,13 +887,13 @@ static double *step_mts(const lbo_cfg *cfg, double *df, int np, double *pos, dou
                         const double *mass, work *w) {
   memset(w->X1, 0, sizeof(double) * 3 * (np > 0 ? np : 1));
   lbo_moments(cfg, df, w->rho, w->u);
-  coupling_step(cfg, np, pos, vel, mass, w->X1, 0.5, w);
+  coupling_step(cfg, np, pos, vel, mass, w->X1, 0.5, 0, w);
   lbo_force_half(cfg, df, w->Fc);
   substeps(cfg, np, pos, vel, mass, w);
   df = collide_stream(cfg, df, w);
   substeps(cfg, np, pos, vel, mass, w);
   lbo_moments(cfg, df, w->rho, w->u);
-  coupling_step(cfg, np, pos, vel, mass, w->X1, 0.5, w);
+  coupling_step(cfg, np, pos, vel, mass, w->X1, 0.5, 1, w);
   lbo_force_half(cfg, df, w->Fc);
   return df;
 }
@@ -776,11 +905,11 @@ static double *step_mts(const lbo_cfg *cfg, double *df, int np, double *pos, dou
  * earlier ones; after the LB update the first sees the post-stream velocity
  * (R6). */
 static void coupled_substep(const lbo_cfg *cfg, double *df, int np, double *pos, double *vel,
-                            const double *mass, double dt, work *w) {
+                            const double *mass, double dt, int j, work *w) {
   drift(cfg, np, pos, vel, 0.5 * dt);
   lbo_intrinsic(cfg, np, pos, w->Fint);
   lbo_moments(cfg, df, w->rho, w->u);
-  coupling_step(cfg, np, pos, vel, mass, w->Fint, dt, w);
+  coupling_step(cfg, np, pos, vel, mass, w->Fint, dt, j, w);
   lbo_force_dt(cfg, df, w->Fc, dt);
   drift(cfg, np, pos, vel, 0.5 * dt);
 }
@@ -791,9 +920,10 @@ static void coupled_substep(const lbo_cfg *cfg, double *df, int np, double *pos,
 static double *step_mts_inside(const lbo_cfg *cfg, double *df, int np, double *pos,
                                double *vel, const double *mass, work *w) {
   const double dt = 1.0 / (2.0 * cfg->mts_n);
-  for (int k = 0; k < cfg->mts_n; ++k) coupled_substep(cfg, df, np, pos, vel, mass, dt, w);
+  const int n = cfg->mts_n;
+  for (int k = 0; k < n; ++k) coupled_substep(cfg, df, np, pos, vel, mass, dt, k, w);
   df = collide_stream(cfg, df, w);
-  for (int k = 0; k < cfg->mts_n; ++k) coupled_substep(cfg, df, np, pos, vel, mass, dt, w);
+  for (int k = 0; k < n; ++k) coupled_substep(cfg, df, np, pos, vel, mass, dt, n + k, w);
   return df;
 }
 
@@ -835,6 +965,9 @@ static int check_cfg(const lbo_cfg *cfg, int np, const double *mass) {
   if (cfg->kernel < 2 || cfg->kernel > 4) return -1;
   if (cfg->coupling == LBO_IB && cfg->mts_n > 0) return -1;
   if (cfg->mts_inside != 0 && cfg->mts_inside != 1) return -1;
+  if (!(cfg->kT >= 0.0)) return -1;
+  if (cfg->kT > 0.0 && cfg->csc) return -1; /* C^1/2 of a fluctuating state is not the
+                                               fluctuating half step (Sec. 3.2) */
   if ((cfg->coupling == LBO_FC || cfg->coupling == LBO_EBF) && np > 0 && !mass) return -1;
   if (cfg->nshell > 0 && cfg->nshell * cfg->shell_size > np) return -1;
   return 0;
@@ -854,6 +987,7 @@ int lbo_run(const lbo_cfg *cfg, int nsteps, double *df, int np, double *pos, dou
   double *cur = df;
   for (int t = 0; t < nsteps; ++t) {
     double *out;
+    w.t = cfg->step0 + t;
     if (cfg->coupling == LBO_IB)
       out = step_ib(cfg, cur, np, pos, &w);
     else if (cfg->mts_n > 0 && cfg->coupling != LBO_NONE && np > 0)

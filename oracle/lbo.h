@@ -53,6 +53,11 @@ typedef struct lbo_cfg {
   int mts_inside;              /* with mts_n > 0: 0 the coupling outside the sub-steps
                                   (Sec. 6, second decomposition); 1 the coupling inside every
                                   sub-step (Eq. multistep), 2n coupling evaluations per step */
+  double kT;                   /* thermal energy k_B T; 0: no fluctuations.  > 0: the
+                                  fluctuating collision (Eq. mrt-fluct) and, for FC, the random
+                                  force zeta of Eq. viscous-coupling */
+  uint64_t seed;               /* key of the counter-based generator */
+  int64_t step0;               /* index of the first step of a run in the random streams */
 } lbo_cfg;
 
 /* lattice and local operators */
@@ -80,6 +85,12 @@ void lbo_interp(const lbo_cfg *cfg, int np, const double *pos, const double *rho
                 const double *u, double *rho_p, double *u_p);
 void lbo_spread(const lbo_cfg *cfg, int np, const double *pos, const double *Fp,
                 double *Fgrid);
+
+/* counter-based random numbers: Philox4x32-10 and Box-Muller normal deviates */
+void lbo_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void lbo_normals4(const uint32_t ctr[4], const uint32_t key[2], double g[4]);
+void lbo_site_normals(const lbo_cfg *cfg, int64_t step, uint32_t site, double g[LBO_Q]);
+void lbo_collide_noisy(const lbo_cfg *cfg, double *df, int64_t step);
 
 /* coupling forces (one half step of length hh) */
 void lbo_fc_force(double gamma, double m, double rho_p, double hh, const double v[3],
