@@ -97,6 +97,16 @@ typedef struct lb_params {
                             (Eq. multistep: [P^(1/4n) F^(1/2n) P^(1/4n)]^n (C S) [...]^n, F
                             holding every force; 2n coupling evaluations per step).
                             LB_EINVAL without sub-steps. */
+  double kT;             /* thermal energy k_B T (lattice units); 0: deterministic.  > 0: the
+                            fluctuating collision of Eq. mrt-fluct (noise sqrt(rho) phi_k r_k
+                            on every non-conserved moment, phi_k = sqrt(mu b_k lambda_k
+                            (2 - lambda_k)), mu = k_B T / c_s^2) and, for LB_COUPLE_FC, the
+                            random force zeta of Eq. viscous-coupling (variance
+                            2 k_B T gamma / h' per component over a coupling step h').  Not
+                            with csc or comoving (LB_EINVAL) nor in ensembles. */
+  uint64_t seed;         /* key of the Philox4x32-10 streams; the random numbers of a step
+                            depend only on (seed, step index, site or particle), not on the
+                            launch configuration */
 } lb_params;
 
 typedef struct lb_limits {

@@ -128,6 +128,11 @@ bool check_params(const lb_grid* g, const lb_params* p, const lb_limits* lim, st
   if (p->mts_substeps > 0 && p->coupling == LB_COUPLE_IB)
     return err = "multiple time stepping applies to force coupling only", false;
   if (p->mts_inside != 0 && p->mts_inside != 1) return err = "mts_inside must be 0 or 1", false;
+  if (!(p->kT >= 0.0) || !std::isfinite(p->kT)) return err = "kT must be finite and >= 0", false;
+  if (p->kT > 0.0 && p->csc)
+    return err = "the collide-stream-collide output is not defined for a fluctuating fluid", false;
+  if (p->kT > 0.0 && p->comoving)
+    return err = "the comoving storage frame is not combined with thermal fluctuations", false;
   if (p->mts_inside && p->mts_substeps < 1)
     return err = "mts_inside needs mts_substeps >= 1", false;
   if (p->deterministic != 0) return err = "deterministic mode is not available", false;
@@ -240,6 +245,12 @@ static PartArgs part_args(const lb_ctx* c) {
   a.mbase = c->L.mbase;
   a.cache_use = 0;
   a.cache_fill = 0;
+  a.kT = c->p.coupling == LB_COUPLE_FC ? c->p.kT : 0.0;
+  a.key0 = (uint32_t)c->p.seed;
+  a.key1 = (uint32_t)(c->p.seed >> 32);
+  a.t0 = (uint32_t)c->steps;
+  a.t1 = (uint32_t)((uint64_t)c->steps >> 32);
+  a.jc = 0;
   a.hh = 0.5;
   a.hd = 0.5;
   a.fa_rd = 0;
@@ -396,6 +407,16 @@ static lb_status lattice_pass(lb_ctx* c) {
   a.rny = 1.0 / c->geo.ny;
   a.clear_mask = c->steps % kMaskKeep == 0 ? 1 : 0;
   a.ib_copy = (c->p.coupling == LB_COUPLE_IB && c->np > 0) ? 1 : 0;
+  a.noise = c->p.kT > 0.0 ? 1 : 0;
+  {  // S sqrt(mu lambda (2 - lambda)), mu = k_B T / c_s^2 = 3 k_B T
+    const double lp = 1.0 - c->omp, lm = 1.0 - c->omm, mu = 3.0 * c->p.kT;
+    a.ap = c->scale * std::sqrt(mu * lp * (2.0 - lp));
+    a.am = c->scale * std::sqrt(mu * lm * (2.0 - lm));
+  }
+  a.key0 = (uint32_t)c->p.seed;
+  a.key1 = (uint32_t)(c->p.seed >> 32);
+  a.t0 = (uint32_t)c->steps;
+  a.t1 = (uint32_t)((uint64_t)c->steps >> 32);
   for (int k = 0; k < 3; ++k) {
     a.uin[k] = c->uref[k];
     a.uout[k] = c->uref[k] + (c->p.comoving ? c->p.body_force[k] / c->p.rho0 : 0.0);
@@ -450,6 +471,7 @@ static lb_status step_mts_inside(lb_ctx* c) {
       a.hh = dt;
       a.hd = 0.5 * dt;
       a.sw = 2.0 * dt;
+      a.jc = side * n + k;
       a.use_fint = any ? 1 : 0;
       a.drift_before = fint ? 0 : 1;
       a.drift_after = 1;
@@ -547,6 +569,7 @@ static lb_status step_once(lb_ctx* c) {
     a.phys = 0;
     a.target = 1;
     a.cache_fill = 1;
+    a.jc = 1;
     HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
     c->mvalid = true;
     return LB_OK;
@@ -572,6 +595,7 @@ static lb_status step_once(lb_ctx* c) {
   a.target = 1;
   a.drift_after = 1;
   a.cache_fill = 1;
+  a.jc = 1;
   HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
   c->mvalid = true;
   return LB_OK;
@@ -1143,6 +1167,7 @@ lb_status lb_ensemble_admit(lb_ensemble* e, const lb_grid* g, const lb_params* p
   if (g->wall_y) return efail(e, LB_EINVAL, "ensemble members are periodic boxes");
   if (p->coupling == LB_COUPLE_IB || p->mts_substeps != 0)
     return efail(e, LB_EINVAL, "ensemble members use FC, EBF or no coupling without sub-steps");
+  if (p->kT != 0.0) return efail(e, LB_EINVAL, "ensemble members are deterministic (kT = 0)");
   if (lim->max_bonds != 0 || lim->max_shells != 0)
     return efail(e, LB_EINVAL, "ensemble members carry free particles only");
   if (p->storage != e->storage || p->kernel != e->kernel)

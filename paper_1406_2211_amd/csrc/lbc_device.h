@@ -29,6 +29,59 @@ __device__ __forceinline__ R wgt(int i) {
   return WCLASS[i] == 0 ? R(1) / R(3) : (WCLASS[i] == 1 ? R(1) / R(18) : R(1) / R(36));
 }
 
+// ------------------------------------------------------------ random numbers
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011): ten rounds, each
+// multiplying words 0 and 2 by the published constants (full 64-bit products)
+// and mixing the halves with words 1 and 3 and the key, which advances by the
+// published Weyl increments between rounds.
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+
+// Uniform in (0, 1) from the top 24 bits (exact in FP32 and FP64), and four
+// normal deviates by the Box-Muller transform of the pairs (x, y), (z, w).
+template <typename R>
+__device__ __forceinline__ R unit24(uint32_t x) {
+  return (R(x >> 8) + R(0.5)) * R(5.9604644775390625e-08);  // 2^-24
+}
+
+template <typename R>
+__device__ __forceinline__ void normals4(uint4 b, R g[4]) {
+  const uint32_t w[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const R r = sqrt(R(-2) * log(unit24<R>(w[2 * p])));
+    const R th = R(6.283185307179586) * unit24<R>(w[2 * p + 1]);
+    g[2 * p] = r * cos(th);
+    g[2 * p + 1] = r * sin(th);
+  }
+}
+
+// Deviate index of velocity c_i: its rank in increasing 9(cx+1) + 3(cy+1) + (cz+1).
+struct VelRank {
+  int r[Q];
+  constexpr VelRank() : r() {
+    for (int i = 0; i < Q; ++i) {
+      int n = 0;
+      for (int j = 0; j < Q; ++j)
+        n += (9 * (CX[j] + 1) + 3 * (CY[j] + 1) + CZ[j] + 1) <
+             (9 * (CX[i] + 1) + 3 * (CY[i] + 1) + CZ[i] + 1);
+      r[i] = n;
+    }
+  }
+};
+constexpr VelRank kVelRank{};
+
 // Storage reference in the comoving frame: e_i(U) = f^eq_i(rho0, U) - w_i rho0
 // (zero density deviation); stored value = f - w rho0 - e_i(U_ref).
 template <typename R>
@@ -228,7 +281,50 @@ struct PassK {
   R hp, hm;         // (1 - lambda+)/2 and (1 - lambda-)/2
   R ui[3];          // reference velocity of the input buffer (comoving frame)
   const R* cm;      // comoving reference terms per pair, see comoving_terms
+  // fluctuating collision: S sqrt(mu lambda (2 - lambda)) for the even / odd
+  // moments, the generator key and the step index
+  R ap, am;
+  uint32_t k0, k1, t0, t1;
 };
+
+// Thermal noise of the fluctuating collision (Eq. mrt-fluct) at one site, in
+// population form and storage units.  With g_i the site's normal deviates
+// (five Philox blocks with counter (site, step low, block, step high)),
+// z_i = sqrt(w_i) g_i has every moment m_k(z) / sqrt(b_k) standard normal and
+// independent; removing its density and momentum,
+//   zc_i = z_i - w_i (m0(z) + 3 c_i . j(z)),
+// and scaling the parts even and odd over opposite pairs by
+// sqrt(rho mu lambda+- (2 - lambda+-)) adds to each non-conserved moment
+// sqrt(rho) phi_k r_k with phi_k = sqrt(mu b_k lambda_k (2 - lambda_k)), the
+// amplitude that keeps its variance at the equilibrium mu rho b_k.
+template <typename R>
+__device__ __forceinline__ void site_noise(const PassK<R>& k, uint32_t site, R rho, R n[Q]) {
+  R g[20];
+#pragma unroll
+  for (int b = 0; b < 5; ++b) normals4<R>(philox(make_uint4(site, k.t0, b, k.t1), k.k0, k.k1), g + 4 * b);
+  const R s0 = sqrt(R(1) / R(3)), s1 = sqrt(R(1) / R(18)), s2 = sqrt(R(1) / R(36));
+  R z[Q], m0 = 0, mx = 0, my = 0, mz = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    z[i] = (WCLASS[i] == 0 ? s0 : (WCLASS[i] == 1 ? s1 : s2)) * g[kVelRank.r[i]];
+    m0 += z[i];
+    if (CX[i]) mx += R(CX[i]) * z[i];
+    if (CY[i]) my += R(CY[i]) * z[i];
+    if (CZ[i]) mz += R(CZ[i]) * z[i];
+  }
+  const R sr = sqrt(rho);
+  const R ep = sr * k.ap, om = sr * k.am;
+  n[0] = ep * (z[0] - wgt<R>(0) * m0);
+#pragma unroll
+  for (int i = 1; i < Q; i += 2) {
+    const R w = wgt<R>(i);
+    const R cm = R(3) * (R(CX[i]) * mx + R(CY[i]) * my + R(CZ[i]) * mz);
+    const R a = z[i] - w * (m0 + cm), b = z[i + 1] - w * (m0 - cm);
+    const R e = R(0.5) * (a + b), o = R(0.5) * (a - b);
+    n[i] = ep * e + om * o;
+    n[i + 1] = ep * e - om * o;
+  }
+}
 
 // Comoving frame: the reference parts of the storage-unit equilibria, the same
 // for every site of a box in one pass.  Pair p = 1..9 is (2p-1, 2p), p = 0 the
@@ -285,7 +381,8 @@ __host__ __device__ inline const float* pick_terms<float>(const double*, const f
 //   odd:  3 B (c.u) - 3 B0 (c.U)
 // so neither the loads nor the stores need the scale; the U terms are
 // per-pass constants (comoving_terms).
-template <int S, bool CM>
+// With NS the thermal noise of site_noise is added to every stored value.
+template <int S, bool CM, bool NS = false>
 __device__ __forceinline__ void fused_site(const typename Store<S>::R f[Q], typename Store<S>::R Fx,
                                            typename Store<S>::R Fy, typename Store<S>::R Fz,
                                            const PassK<typename Store<S>::R>& k,
@@ -315,6 +412,8 @@ __device__ __forceinline__ void fused_site(const typename Store<S>::R f[Q], type
   const R hx = ux + hf * Fx, hy = uy + hf * Fy, hz = uz + hf * Fz;
   const R usq = ux * ux + uy * uy + uz * uz, hsq = hx * hx + hy * hy + hz * hz;
   const R rs = rho * k.sc;
+  R nz[Q];
+  if (NS) site_noise<R>(k, (uint32_t)own, rho, nz);
   {
     const R w = wgt<R>(0);
     R eb = w * (d - R(1.5) * rs * usq), eh = w * (d - R(1.5) * rs * hsq);
@@ -322,7 +421,9 @@ __device__ __forceinline__ void fused_site(const typename Store<S>::R f[Q], type
       eb -= k.cm[0];
       eh -= k.cm[20];
     }
-    St::st_raw(fo + own, eh + R(2) * k.hp * (f[0] - eb));
+    R v = eh + R(2) * k.hp * (f[0] - eb);
+    if (NS) v += nz[0];
+    St::st_raw(fo + own, v);
   }
 #pragma unroll
   for (int i = 1; i < Q; i += 2) {
@@ -341,8 +442,13 @@ __device__ __forceinline__ void fused_site(const typename Store<S>::R f[Q], type
     }
     const R ni = f[i] - Eb - Ob, nj = f[i + 1] - Eb + Ob;
     const R sym = k.hp * (ni + nj), anti = k.hm * (ni - nj);
-    St::st_raw(fo + (size_t)i * P + own, Eh + Oh + sym + anti);
-    St::st_raw(fo + (size_t)(i + 1) * P + own, Eh - Oh + sym - anti);
+    R vi = Eh + Oh + sym + anti, vj = Eh - Oh + sym - anti;
+    if (NS) {
+      vi += nz[i];
+      vj += nz[i + 1];
+    }
+    St::st_raw(fo + (size_t)i * P + own, vi);
+    St::st_raw(fo + (size_t)(i + 1) * P + own, vj);
   }
 }
 

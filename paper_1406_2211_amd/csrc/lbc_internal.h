@@ -38,6 +38,11 @@ struct LatArgs {
   double rnx, rny;    // 1/nx, 1/ny (linear-site pass)
   int clear_mask;     // clear the force mask after reading it (every kMaskKeep steps)
   int ib_copy;        // immersed boundary: FA becomes the pending FB (same spread)
+  // fluctuating collision (noise != 0): S sqrt(mu lambda (2 - lambda)) for the
+  // even / odd moments, generator key, step index
+  int noise;
+  double ap, am;
+  uint32_t key0, key1, t0, t1;
 };
 
 struct InitArgs {
@@ -79,6 +84,11 @@ struct PartArgs {
   int target;       // spread into FA (0) or FB (1)
   int drift_before;  // first P^1/2 of Alg. 3 (when no intrinsic forces sit between)
   int drift_after;   // final P^1/2 of Alg. 3
+  // random force of the force coupling (kT > 0): generator key, step index and
+  // the index of this coupling step within the step
+  double kT;
+  uint32_t key0, key1, t0, t1;
+  int jc;
   double hh;         // coupling step length: h/2 (half steps) or h/2n (coupled sub-steps)
   double hd;         // length of drift_before / drift_after
   int fa_rd;         // the interpolated momentum also takes (h/2) FA (earlier sub-steps)

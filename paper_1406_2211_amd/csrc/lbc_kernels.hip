@@ -80,7 +80,7 @@ __device__ __forceinline__ void take_forces_ib(uint64_t word, uint64_t* mp, size
   if (lane == 0 && keep != word) *mp = keep;
 }
 
-template <int S, bool CM, bool WALL>
+template <int S, bool CM, bool WALL, bool NS = false>
 __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
   using St = Store<S>;
   using T = typename St::T;
@@ -125,7 +125,15 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
   k.hm = R(0.5) * R(a.omm);
   for (int c = 0; c < 3; ++c) k.ui[c] = R(a.uin[c]);
   k.cm = pick_terms<R>(a.cm, a.cmf);
-  fused_site<S, CM>(f, Fx, Fy, Fz, k, (T*)a.fout, N, own);
+  if (NS) {
+    k.ap = R(a.ap);
+    k.am = R(a.am);
+    k.k0 = a.key0;
+    k.k1 = a.key1;
+    k.t0 = a.t0;
+    k.t1 = a.t1;
+  }
+  fused_site<S, CM, NS>(f, Fx, Fy, Fz, k, (T*)a.fout, N, own);
 }
 
 // ======================================================================
@@ -459,8 +467,19 @@ __global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
   double Fh[3];
   if (a.coupling == LB_COUPLE_FC) {
     const double den = 1.0 + 0.5 * al + 0.5 * be;
+    double zeta[4] = {0, 0, 0, 0};
+    if (a.kT > 0.0) {
+      // random force of Eq. viscous-coupling: variance 2 k_B T gamma / hh per
+      // component, entering the implicit solution like the drag; deviates from
+      // the Philox block (particle, step low, 2^16 + coupling step, step high)
+      normals4<double>(philox(make_uint4((uint32_t)p, a.t0, 65536u + (uint32_t)a.jc, a.t1),
+                              a.key0, a.key1), zeta);
+      const double sig = sqrt(2.0 * a.kT * a.gamma / hh);
+      for (int k = 0; k < 3; ++k) zeta[k] = sig * zeta[k] / den;
+    }
     for (int k = 0; k < 3; ++k) {
       Fh[k] = -(a.gamma * (v[k] - up[k]) + 0.5 * al * Fi[k]) / den;
+      if (a.kT > 0.0) Fh[k] += zeta[k];
       v[k] += hh / m * (Fh[k] + Fi[k]);
     }
   } else {
@@ -802,16 +821,16 @@ static dim3 lattice_grid(const Geo& g, dim3 b) {
     default: { constexpr int SS = LB_BF16; CALL; } break;           \
   }
 
-template <int S, bool CM, bool WALL>
+template <int S, bool CM, bool WALL, bool NS>
 __global__ __launch_bounds__(256) void k_stream_collide_lin(LatArgs a);
 
-template <bool CM, bool WALL>
+template <bool CM, bool WALL, bool NS = false>
 static void launch_sc(int storage, const LatArgs& a, dim3 gr, dim3 b, hipStream_t st) {
   if (a.g.wpr == 0) {  // linear mask: x extent not a multiple of 64
     const unsigned nb = (unsigned)((a.g.N + 255) / 256);
-    LBC_STORAGE_SWITCH(storage, (k_stream_collide_lin<SS, CM, WALL><<<nb, 256, 0, st>>>(a)));
+    LBC_STORAGE_SWITCH(storage, (k_stream_collide_lin<SS, CM, WALL, NS><<<nb, 256, 0, st>>>(a)));
   } else {
-    LBC_STORAGE_SWITCH(storage, (k_stream_collide<SS, CM, WALL><<<gr, b, 0, st>>>(a)));
+    LBC_STORAGE_SWITCH(storage, (k_stream_collide<SS, CM, WALL, NS><<<gr, b, 0, st>>>(a)));
   }
 }
 
@@ -820,7 +839,10 @@ static void launch_sc(int storage, const LatArgs& a, dim3 gr, dim3 b, hipStream_
 // carries none of its arithmetic.
 hipError_t launch_stream_collide(int storage, bool comoving, const LatArgs& a, hipStream_t st) {
   const dim3 b = lattice_block(a.g), gr = lattice_grid(a.g, b);
-  if (comoving) {
+  if (a.noise) {  // fluctuating collision (the comoving frame is not combined with it)
+    if (a.g.wall) launch_sc<false, true, true>(storage, a, gr, b, st);
+    else launch_sc<false, false, true>(storage, a, gr, b, st);
+  } else if (comoving) {
     if (a.g.wall) launch_sc<true, true>(storage, a, gr, b, st);
     else launch_sc<true, false>(storage, a, gr, b, st);
   } else {
@@ -971,6 +993,15 @@ struct LatView {
   __device__ const float* cmf() const { return a.cmf; }
   __device__ bool ib_copy() const { return a.ib_copy != 0; }
   __device__ bool clear_mask() const { return a.clear_mask != 0; }
+  template <typename R>
+  __device__ void noise(PassK<R>& k) const {
+    k.ap = R(a.ap);
+    k.am = R(a.am);
+    k.k0 = a.key0;
+    k.k1 = a.key1;
+    k.t0 = a.t0;
+    k.t1 = a.t1;
+  }
 };
 
 struct SlotView {
@@ -996,9 +1027,11 @@ struct SlotView {
   __device__ const float* cmf() const { return s.cmf; }
   __device__ bool ib_copy() const { return false; }
   __device__ bool clear_mask() const { return s.steps_done % kMaskKeep == 0; }
+  template <typename R>
+  __device__ void noise(PassK<R>&) const {}  // ensemble members are deterministic
 };
 
-template <int S, bool CM, bool WALL, class V>
+template <int S, bool CM, bool WALL, class V, bool NS = false>
 __device__ __forceinline__ void linear_site(const V& v, uint32_t s) {
   using St = Store<S>;
   using T = typename St::T;
@@ -1042,12 +1075,13 @@ __device__ __forceinline__ void linear_site(const V& v, uint32_t s) {
     for (int c = 0; c < 3; ++c) k.ui[c] = R(v.uin(c));
   }
   k.cm = pick_terms<R>(v.cm(), v.cmf());
-  fused_site<S, CM>(f, Fx, Fy, Fz, k, (T*)v.fout(), P, s);
+  if (NS) v.noise(k);
+  fused_site<S, CM, NS>(f, Fx, Fy, Fz, k, (T*)v.fout(), P, s);
 }
 
-template <int S, bool CM, bool WALL>
+template <int S, bool CM, bool WALL, bool NS>
 __global__ __launch_bounds__(256) void k_stream_collide_lin(LatArgs a) {
-  linear_site<S, CM, WALL>(LatView{a}, blockIdx.x * 256u + threadIdx.x);
+  linear_site<S, CM, WALL, LatView, NS>(LatView{a}, blockIdx.x * 256u + threadIdx.x);
 }
 
 // The slot table is read-only during the lattice pass (only k_ens_advance

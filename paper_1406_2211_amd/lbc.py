@@ -42,7 +42,8 @@ class lb_params(C.Structure):
                 ("coupling", C.c_int32), ("gamma", C.c_double), ("kernel", C.c_int32),
                 ("storage", C.c_int32), ("f16_scale_log2", C.c_int32),
                 ("mts_substeps", C.c_int32), ("deterministic", C.c_int32),
-                ("comoving", C.c_int32), ("csc", C.c_int32), ("mts_inside", C.c_int32)]
+                ("comoving", C.c_int32), ("csc", C.c_int32), ("mts_inside", C.c_int32),
+                ("kT", C.c_double), ("seed", C.c_uint64)]
 
 
 class lb_limits(C.Structure):
@@ -128,7 +129,8 @@ def lattice_velocities():
 
 def make_params(tau, rho0=1.0, body_force=(0.0, 0.0, 0.0), collision=LB_BGK, trt_magic=3.0 / 16.0,
                 coupling=LB_COUPLE_NONE, gamma=0.0, kernel=LB_PHI2, storage=LB_F64,
-                f16_scale_log2=0, mts_substeps=0, comoving=0, csc=0, mts_inside=0):
+                f16_scale_log2=0, mts_substeps=0, comoving=0, csc=0, mts_inside=0, kT=0.0,
+                seed=0):
     p = lb_params()
     p.tau, p.rho0 = float(tau), float(rho0)
     for a in range(3):
@@ -138,6 +140,7 @@ def make_params(tau, rho0=1.0, body_force=(0.0, 0.0, 0.0), collision=LB_BGK, trt
     p.storage, p.f16_scale_log2 = int(storage), int(f16_scale_log2)
     p.mts_substeps, p.deterministic = int(mts_substeps), 0
     p.comoving, p.csc, p.mts_inside = int(comoving), int(csc), int(mts_inside)
+    p.kT, p.seed = float(kT), int(seed)
     return p
 
 

@@ -65,7 +65,8 @@ def run_oracle(c: Case):
                  bond_type=c.bond_type, nshell=c.nshell, shell_template=c.template,
                  tether_k=c.tether_k, magic=c.extra.get("magic", 3.0 / 16.0),
                  csc=c.extra.get("csc", 0), mts_inside=c.extra.get("mts_inside", 0),
-                 rho0=c.extra.get("rho0", 1.0))
+                 rho0=c.extra.get("rho0", 1.0), kT=c.extra.get("kT", 0.0),
+                 seed=c.extra.get("seed", 0))
     rho, u = initial_fields(c)
     df = o.init_fluid(rho, u)
     pos = None if c.pos is None else np.array(c.pos, dtype=np.float64, copy=True)
@@ -104,7 +105,8 @@ def make_gpu(c: Case):
                     storage=c.storage, mts_substeps=c.mts, f16_scale_log2=c.f16_scale_log2,
                     comoving=c.extra.get("comoving", 0), csc=c.extra.get("csc", 0),
                     trt_magic=c.extra.get("magic", 3.0 / 16.0),
-                    mts_inside=c.extra.get("mts_inside", 0), rho0=c.extra.get("rho0", 1.0))
+                    mts_inside=c.extra.get("mts_inside", 0), rho0=c.extra.get("rho0", 1.0),
+                    kT=c.extra.get("kT", 0.0), seed=c.extra.get("seed", 0))
     rho, u = initial_fields(c)
     lat.lb_init_fluid(None if rho is None else torch.from_numpy(rho),
                       None if u is None else torch.from_numpy(np.ascontiguousarray(u)))
