@@ -47,6 +47,12 @@ def workload(name):
                         mts_substeps=5),
             pos=pos, vel=vel, mass=np.ones(len(pos)), bonds=bonds, bond_k=30.0, bond_r0=1.0,
             bytes_per_site=152, dtype="f32")
+    if name == "c2thermal":
+        wl = workload("c2")
+        wl["desc"] = ("thermal c2: " + wl["desc"] + "; fluctuating collision and random coupling "
+                      "force at kT=1e-5 (Philox4x32-10, seed 2)")
+        wl["params"] = dict(wl["params"], kT=1e-5, seed=2)
+        return wl
     if name in ("c3", "c3phi2"):
         box = (128, 128, 256)
         T = I.icosphere(3, 6.0)
@@ -109,7 +115,7 @@ def cpu_baseline(wl, steps):
                  fext=p.get("body_force", (0, 0, 0)), bonds=wl.get("bonds"),
                  bond_k=wl.get("bond_k", 0.0), bond_r0=wl.get("bond_r0", 1.0),
                  nshell=wl.get("nshell", 0), shell_template=wl.get("template"),
-                 tether_k=wl.get("tether_k", 0.0))
+                 tether_k=wl.get("tether_k", 0.0), kT=p.get("kT", 0.0), seed=p.get("seed", 0))
     df = o.init_fluid()
     pos = None if wl.get("pos") is None else wl["pos"].copy()
     vel = None if pos is None or wl.get("vel") is None else wl["vel"].copy()

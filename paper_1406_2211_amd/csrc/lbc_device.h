@@ -41,30 +41,43 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+    // three-input exclusive or in one instruction (truth table 0x96)
+    c = make_uint4(__builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96), (uint32_t)p1,
+                   __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96),
+                   (uint32_t)p0);
   }
   return c;
 }
 
 // Uniform in (0, 1) from the top 24 bits (exact in FP32 and FP64), and four
-// normal deviates by the Box-Muller transform of the pairs (x, y), (z, w).
+// normal deviates by the Box-Muller transform of the pairs (x, y), (z, w):
+// r = sqrt(-2 ln u1), (r cos 2 pi u2, r sin 2 pi u2).  FP64 uses the library
+// functions (the angle through sincospi, an exact argument reduction).  FP32
+// uses the hardware transcendentals: log2, square root, and sine and cosine
+// of a whole number of revolutions (u2 in (0, 1)), each within a few ulp.
 template <typename R>
 __device__ __forceinline__ R unit24(uint32_t x) {
   return (R(x >> 8) + R(0.5)) * R(5.9604644775390625e-08);  // 2^-24
 }
 
+__device__ __forceinline__ void box_muller(float u1, float u2, float& a, float& b) {
+  const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+  a = r * __builtin_amdgcn_cosf(u2);
+  b = r * __builtin_amdgcn_sinf(u2);
+}
+__device__ __forceinline__ void box_muller(double u1, double u2, double& a, double& b) {
+  const double r = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincospi(2.0 * u2, &sn, &cs);
+  a = r * cs;
+  b = r * sn;
+}
+
 template <typename R>
 __device__ __forceinline__ void normals4(uint4 b, R g[4]) {
-  const uint32_t w[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    const R r = sqrt(R(-2) * log(unit24<R>(w[2 * p])));
-    const R th = R(6.283185307179586) * unit24<R>(w[2 * p + 1]);
-    g[2 * p] = r * cos(th);
-    g[2 * p + 1] = r * sin(th);
-  }
+  box_muller(unit24<R>(b.x), unit24<R>(b.y), g[0], g[1]);
+  box_muller(unit24<R>(b.z), unit24<R>(b.w), g[2], g[3]);
 }
 
 // Deviate index of velocity c_i: its rank in increasing 9(cx+1) + 3(cy+1) + (cz+1).
