@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liblbo.so")
 _lib = None
 
-BGK, TRT = 0, 1
+BGK, TRT, MRT = 0, 1, 2
 NONE, FC, EBF, IB = 0, 1, 2, 3
 HARMONIC, FENE = 0, 1
 Q = 19
@@ -44,6 +44,7 @@ class _Cfg(C.Structure):
         ("csc", C.c_int),
         ("mts_inside", C.c_int),
         ("kT", C.c_double), ("seed", C.c_uint64), ("step0", C.c_int64),
+        ("mrt_rates", C.c_double * 5),
     ]
 
 
@@ -63,6 +64,7 @@ def lib():
         "lbo_feq_dev": (None, [C.c_double, C.c_double, _dp, _dp]),
         "lbo_force_term": (None, [_dp, _dp, _dp]),
         "lbo_mrt_basis": (None, [_dp, _dp]),
+        "lbo_group_basis": (None, [_dp, _dp]),
         "lbo_rates": (None, [P, _dp]),
         "lbo_collide_site": (None, [P, _dp]),
         "lbo_init_fluid": (None, [P, _dp, vp, vp]),
@@ -135,6 +137,14 @@ def mrt_basis():
     return E.reshape(Q, Q), b
 
 
+def group_basis():
+    """Rows E[k, i] and norms b[k] of the general MRT basis (moment groups)."""
+    E = np.zeros(Q * Q)
+    b = np.zeros(Q)
+    lib().lbo_group_basis(E, b)
+    return E.reshape(Q, Q), b
+
+
 def phi(kernel, r):
     return lib().lbo_phi(int(kernel), float(r))
 
@@ -173,7 +183,9 @@ class Oracle:
     bonds [None: int32 [nb,2]], bond_k, bond_r0, bond_type [HARMONIC],
     nshell [0], shell_template [None: [M,3]], tether_k, csc [0: the C S form; 1: C^1/2 S C^1/2],
     mts_inside [0: coupling outside the sub-steps; 1: inside every sub-step], kT [0: no
-    fluctuations], seed [0], step0 [0: index of the first step in the random streams]."""
+    fluctuations], seed [0], step0 [0: index of the first step in the random streams],
+    mrt_rates [5 x 1.0: bulk, vector ghosts, pseudo-vector ghosts, scalar and tensor ghosts;
+    collision MRT]."""
 
     def __init__(self, **cfg):
         self.nx, self.ny, self.nz = int(cfg["nx"]), int(cfg["ny"]), int(cfg["nz"])
@@ -212,6 +224,8 @@ class Oracle:
         c.kT = float(cfg.get("kT", 0.0))
         c.seed = int(cfg.get("seed", 0))
         c.step0 = int(cfg.get("step0", 0))
+        for k, r in enumerate(cfg.get("mrt_rates", (1.0,) * 5)):
+            c.mrt_rates[k] = float(r)
         self.cfg = c
         self.N = self.nx * self.ny * self.nz
         self.shape = (self.nz, self.ny, self.nx)

@@ -173,12 +173,73 @@ void lbo_mrt_basis(double E[LBO_Q * LBO_Q], double b[LBO_Q]) {
   }
 }
 
+/* Moment basis of the general MRT collision (Eq. mrt-coll with a rate per
+ * moment group): the polynomials of the D3Q19 basis of Duenweg, Schiller and
+ * Ladd (2007), w-orthogonal, whose rows span the subspaces that the cubic
+ * symmetry leaves invariant: 1; c_a; bulk c^2 - 1; shear 3cx^2 - c^2,
+ * cy^2 - cz^2, cx cy, cy cz, cz cx; vector ghosts c_a (3c^2 - 5); pseudo-vector
+ * ghosts cx (cy^2 - cz^2) and cyclic; scalar ghost 3c^4 - 6c^2 + 1; tensor
+ * ghosts (2c^2 - 3)(3cx^2 - c^2), (2c^2 - 3)(cy^2 - cz^2).  A rate per group
+ * keeps the collision isotropic. */
+void lbo_group_basis(double E[LBO_Q * LBO_Q], double b[LBO_Q]) {
+  lattice_init();
+  for (int i = 0; i < LBO_Q; ++i) {
+    const double x = C[i][0], y = C[i][1], z = C[i][2];
+    const double c2 = x * x + y * y + z * z, c4 = c2 * c2;
+    const double row[LBO_Q] = {1.0,
+                               x,
+                               y,
+                               z,
+                               c2 - 1.0,
+                               3.0 * x * x - c2,
+                               y * y - z * z,
+                               x * y,
+                               y * z,
+                               z * x,
+                               x * (3.0 * c2 - 5.0),
+                               y * (3.0 * c2 - 5.0),
+                               z * (3.0 * c2 - 5.0),
+                               x * (y * y - z * z),
+                               y * (z * z - x * x),
+                               z * (x * x - y * y),
+                               3.0 * c4 - 6.0 * c2 + 1.0,
+                               (2.0 * c2 - 3.0) * (3.0 * x * x - c2),
+                               (2.0 * c2 - 3.0) * (y * y - z * z)};
+    for (int k = 0; k < LBO_Q; ++k) E[k * LBO_Q + i] = row[k];
+  }
+  for (int k = 0; k < LBO_Q; ++k) {
+    double nrm = 0.0;
+    for (int i = 0; i < LBO_Q; ++i) nrm += W[i] * E[k * LBO_Q + i] * E[k * LBO_Q + i];
+    b[k] = nrm;
+  }
+}
+
+/* The basis a configuration relaxes in: the group basis for the general MRT,
+ * the Gram-Schmidt basis otherwise (any w-orthogonal basis with the same
+ * even and odd subspaces gives the same two-rate collision). */
+static void basis_for(const lbo_cfg *cfg, double *E, double *b) {
+  if (cfg->collision == LBO_MRT)
+    lbo_group_basis(E, b);
+  else
+    lbo_mrt_basis(E, b);
+}
+
 /* Relaxation rates per basis row.  BGK: lambda = 1/tau for every row (R2).
  * Two-rate MRT: even rows at lp = 1/tau, odd rows at lm from the magic
  * parameter (1/lp - 1/2)(1/lm - 1/2) = magic.  Rows 0..3 are conserved, so
  * their rate is irrelevant. */
 void lbo_rates(const lbo_cfg *cfg, double lam[LBO_Q]) {
   const double lp = 1.0 / cfg->tau;
+  if (cfg->collision == LBO_MRT) { /* rows of lbo_group_basis */
+    const double *r = cfg->mrt_rates;
+    for (int k = 0; k < LBO_Q; ++k) lam[k] = lp; /* conserved rows and shear */
+    lam[4] = r[0];
+    for (int k = 10; k < 13; ++k) lam[k] = r[1];
+    for (int k = 13; k < 16; ++k) lam[k] = r[2];
+    lam[16] = r[3];
+    lam[17] = lam[18] = r[4];
+    return;
+  }
   double lm = lp;
   if (cfg->collision == LBO_TRT) lm = 1.0 / (0.5 + cfg->magic / (cfg->tau - 0.5));
   for (int k = 0; k < LBO_Q; ++k) {
@@ -336,7 +397,7 @@ static void collide_site_with(const lbo_cfg *cfg, double df[LBO_Q], const double
 
 void lbo_collide_site(const lbo_cfg *cfg, double df[LBO_Q]) {
   double E[LBO_Q * LBO_Q], b[LBO_Q], lam[LBO_Q];
-  lbo_mrt_basis(E, b);
+  basis_for(cfg, E, b);
   lbo_rates(cfg, lam);
   collide_site_with(cfg, df, E, b, lam);
 }
@@ -408,7 +469,7 @@ void lbo_force_half(const lbo_cfg *cfg, double *df, const double *Fc) {
 void lbo_collide_noisy(const lbo_cfg *cfg, double *df, int64_t step) {
   lattice_init();
   double E[LBO_Q * LBO_Q], b[LBO_Q], lam[LBO_Q];
-  lbo_mrt_basis(E, b);
+  basis_for(cfg, E, b);
   lbo_rates(cfg, lam);
   const long N = nsites(cfg);
 #pragma omp parallel for schedule(static)
@@ -436,7 +497,7 @@ void lbo_collide(const lbo_cfg *cfg, double *df) { lbo_collide_noisy(cfg, df, cf
 void lbo_collide_half(const lbo_cfg *cfg, double *df) {
   lattice_init();
   double E[LBO_Q * LBO_Q], b[LBO_Q], lam[LBO_Q];
-  lbo_mrt_basis(E, b);
+  basis_for(cfg, E, b);
   lbo_rates(cfg, lam);
   for (int k = 0; k < LBO_Q; ++k) lam[k] = 1.0 - sqrt(1.0 - lam[k]);
   const long N = nsites(cfg);
@@ -966,6 +1027,9 @@ static int check_cfg(const lbo_cfg *cfg, int np, const double *mass) {
   if (cfg->coupling == LBO_IB && cfg->mts_n > 0) return -1;
   if (cfg->mts_inside != 0 && cfg->mts_inside != 1) return -1;
   if (!(cfg->kT >= 0.0)) return -1;
+  if (cfg->collision == LBO_MRT)
+    for (int k = 0; k < 5; ++k)
+      if (!(cfg->mrt_rates[k] > 0.0 && cfg->mrt_rates[k] < 2.0)) return -1;
   if (cfg->kT > 0.0 && cfg->csc) return -1; /* C^1/2 of a fluctuating state is not the
                                                fluctuating half step (Sec. 3.2) */
   if ((cfg->coupling == LBO_FC || cfg->coupling == LBO_EBF) && np > 0 && !mass) return -1;

@@ -24,7 +24,7 @@
 
 #define LBO_Q 19
 
-enum { LBO_BGK = 0, LBO_TRT = 1 };
+enum { LBO_BGK = 0, LBO_TRT = 1, LBO_MRT = 2 };
 enum { LBO_NONE = 0, LBO_FC = 1, LBO_EBF = 2, LBO_IB = 3 };
 enum { LBO_HARMONIC = 0, LBO_FENE = 1 };
 
@@ -34,7 +34,8 @@ typedef struct lbo_cfg {
   double tau;            /* tau_LB, must be > 1/2 */
   double rho0;
   double fext[3];        /* constant body-force density */
-  int collision;         /* LBO_BGK or LBO_TRT (MRT with two rates) */
+  int collision;         /* LBO_BGK, LBO_TRT (MRT with two rates) or LBO_MRT (a rate per
+                            moment group, see mrt_rates) */
   double magic;          /* TRT magic parameter (1/lp - 1/2)(1/lm - 1/2) */
   int coupling;          /* LBO_NONE, LBO_FC, LBO_EBF (modified EBF), LBO_IB */
   double gamma;          /* friction for FC / EBF */
@@ -58,6 +59,9 @@ typedef struct lbo_cfg {
                                   force zeta of Eq. viscous-coupling */
   uint64_t seed;               /* key of the counter-based generator */
   int64_t step0;               /* index of the first step of a run in the random streams */
+  double mrt_rates[5];         /* LBO_MRT: rates of the bulk stress, the vector and the
+                                  pseudo-vector third-order ghosts, the scalar and the tensor
+                                  fourth-order ghosts (the shear stress relaxes at 1/tau) */
 } lbo_cfg;
 
 /* lattice and local operators */
@@ -65,6 +69,7 @@ int lbo_d3q19(int32_t c[LBO_Q * 3], double w[LBO_Q], int32_t opp[LBO_Q]);
 void lbo_feq_dev(double drho, double rho, const double u[3], double out[LBO_Q]);
 void lbo_force_term(const double u[3], const double F[3], double G[LBO_Q]);
 void lbo_mrt_basis(double E[LBO_Q * LBO_Q], double b[LBO_Q]);
+void lbo_group_basis(double E[LBO_Q * LBO_Q], double b[LBO_Q]);
 void lbo_rates(const lbo_cfg *cfg, double lam[LBO_Q]);
 void lbo_collide_site(const lbo_cfg *cfg, double df[LBO_Q]);
 
