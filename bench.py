@@ -53,6 +53,12 @@ def workload(name):
                       "force at kT=1e-5 (Philox4x32-10, seed 2)")
         wl["params"] = dict(wl["params"], kT=1e-5, seed=2)
         return wl
+    if name == "c2mrt":
+        wl = workload("c2")
+        wl["desc"] = ("c2 with the general MRT collision: " + wl["desc"] + "; group rates bulk 1.4, "
+                      "ghosts 1.2 (vector), 1.2 (pseudo-vector), 1.5 (scalar), 1.5 (tensor)")
+        wl["params"] = dict(wl["params"], collision=2, mrt_rates=(1.4, 1.2, 1.2, 1.5, 1.5))
+        return wl
     if name in ("c3", "c3phi2"):
         box = (128, 128, 256)
         T = I.icosphere(3, 6.0)
@@ -115,7 +121,8 @@ def cpu_baseline(wl, steps):
                  fext=p.get("body_force", (0, 0, 0)), bonds=wl.get("bonds"),
                  bond_k=wl.get("bond_k", 0.0), bond_r0=wl.get("bond_r0", 1.0),
                  nshell=wl.get("nshell", 0), shell_template=wl.get("template"),
-                 tether_k=wl.get("tether_k", 0.0), kT=p.get("kT", 0.0), seed=p.get("seed", 0))
+                 tether_k=wl.get("tether_k", 0.0), kT=p.get("kT", 0.0), seed=p.get("seed", 0),
+                 mrt_rates=p.get("mrt_rates", (1.0,) * 5))
     df = o.init_fluid()
     pos = None if wl.get("pos") is None else wl["pos"].copy()
     vel = None if pos is None or wl.get("vel") is None else wl["vel"].copy()

@@ -53,7 +53,7 @@ typedef enum lb_status {
   LB_ESTATE = 5   /* call not valid in the current state */
 } lb_status;
 
-enum lb_collision { LB_BGK = 0, LB_TRT = 1 };
+enum lb_collision { LB_BGK = 0, LB_TRT = 1, LB_MRT = 2 };
 enum lb_forcing { LB_FORCING_SPLIT2 = 0 };
 enum lb_coupling { LB_COUPLE_NONE = 0, LB_COUPLE_FC = 1, LB_COUPLE_EBF = 2, LB_COUPLE_IB = 3 };
 enum lb_kernel { LB_PHI2 = 2, LB_PHI3 = 3, LB_PHI4 = 4 };
@@ -69,7 +69,8 @@ typedef struct lb_params {
   double tau;            /* lattice relaxation time (> 1/2), see above */
   double rho0;           /* reference density; populations are stored as f - w rho0 */
   double body_force[3];  /* constant body-force density F_ext */
-  int32_t collision;     /* LB_BGK, or LB_TRT: MRT with the two rates of Eq. mrt-coll */
+  int32_t collision;     /* LB_BGK; LB_TRT: MRT with the two rates of Eq. mrt-coll; LB_MRT:
+                            Eq. mrt-coll with a rate per moment group (mrt_rates) */
   double trt_magic;      /* (1/l+ - 1/2)(1/l- - 1/2) for LB_TRT; 3/16 if <= 0 */
   int32_t forcing;       /* LB_FORCING_SPLIT2: midpoint half forces around C S */
   int32_t coupling;      /* LB_COUPLE_* (Sec. 5.1 IB, 5.2 FC, 5.3 modified EBF) */
@@ -107,6 +108,14 @@ typedef struct lb_params {
   uint64_t seed;         /* key of the Philox4x32-10 streams; the random numbers of a step
                             depend only on (seed, step index, site or particle), not on the
                             launch configuration */
+  double mrt_rates[5];   /* LB_MRT: relaxation rates in (0, 2) of the moment groups of the
+                            D3Q19 basis of Duenweg, Schiller and Ladd (2007), each invariant
+                            under the cubic symmetry: [0] bulk stress c^2 - 1 (bulk viscosity
+                            (2/3) rho c_s^2 (1/rate - 1/2)), [1] vector ghosts c_a(3c^2 - 5),
+                            [2] pseudo-vector ghosts cx(cy^2 - cz^2) and cyclic, [3] scalar
+                            ghost 3c^4 - 6c^2 + 1, [4] tensor ghosts (2c^2 - 3)(3cx^2 - c^2),
+                            (2c^2 - 3)(cy^2 - cz^2).  The shear stress relaxes at 1/tau.  Not
+                            with csc or comoving, nor in ensembles (LB_EINVAL). */
 } lb_params;
 
 typedef struct lb_limits {
@@ -184,7 +193,7 @@ lb_status lb_populations(lb_ctx* ctx, double* d_df);
  * d_sigma [6][nz][ny][nx] in the order xx, yy, zz, xy, xz, yz:
  * sigma = (1 - lambda_+/2) sum_i (f_i - f^eq_i(rho, u)) c_i c_i of the
  * standard physical populations, lambda_+ = 1/tau the rate of the stress
- * modes.  This equals (1/2)((1 - lambda_1/2)^-1 + (1 - lambda_1/2)) times the
+ * modes (with LB_MRT the trace part takes (1 - lambda_bulk/2) instead).  This equals (1/2)((1 - lambda_1/2)^-1 + (1 - lambda_1/2)) times the
  * same sum over the collide-stream-collide populations, and -rho nu
  * (grad u + grad u^T) with nu = (tau - 1/2)/3 up to second-order terms.  The
  * same physical quantity in both forms; the half forces are equilibrium

@@ -113,7 +113,15 @@ bool check_params(const lb_grid* g, const lb_params* p, const lb_limits* lim, st
   if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return err = "rho0 must be > 0", false;
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(p->body_force[a])) return err = "body force must be finite", false;
-  if (p->collision != LB_BGK && p->collision != LB_TRT) return err = "unknown collision", false;
+  if (p->collision != LB_BGK && p->collision != LB_TRT && p->collision != LB_MRT)
+    return err = "unknown collision", false;
+  if (p->collision == LB_MRT) {
+    for (int k = 0; k < 5; ++k)
+      if (!(p->mrt_rates[k] > 0.0 && p->mrt_rates[k] < 2.0))
+        return err = "mrt_rates must lie in (0, 2)", false;
+    if (p->csc) return err = "the collide-stream-collide output takes the two-rate collision", false;
+    if (p->comoving) return err = "the comoving storage frame takes the two-rate collision", false;
+  }
   if (p->forcing != LB_FORCING_SPLIT2) return err = "unknown forcing scheme", false;
   if (p->coupling < LB_COUPLE_NONE || p->coupling > LB_COUPLE_IB)
     return err = "unknown coupling", false;
@@ -417,6 +425,15 @@ static lb_status lattice_pass(lb_ctx* c) {
   a.key1 = (uint32_t)(c->p.seed >> 32);
   a.t0 = (uint32_t)c->steps;
   a.t1 = (uint32_t)((uint64_t)c->steps >> 32);
+  a.mrt = c->p.collision == LB_MRT ? 1 : 0;
+  {  // group rates: bulk, shear, vector, pseudo-vector, scalar and tensor ghosts
+    const double* r = c->p.mrt_rates;
+    const double lg[6] = {r[0], 1.0 - c->omp, r[1], r[2], r[3], r[4]};
+    for (int g = 0; g < 6; ++g) {
+      a.lg[g] = lg[g];
+      a.ag[g] = c->scale * std::sqrt(3.0 * c->p.kT * lg[g] * (2.0 - lg[g]));
+    }
+  }
   for (int k = 0; k < 3; ++k) {
     a.uin[k] = c->uref[k];
     a.uout[k] = c->uref[k] + (c->p.comoving ? c->p.body_force[k] / c->p.rho0 : 0.0);
@@ -806,8 +823,10 @@ lb_status lb_populations(lb_ctx* c, double* d_df) {
 lb_status lb_stress(lb_ctx* c, double* d_sigma) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
   if (!d_sigma) return fail(c, LB_EINVAL, "null output");
-  // 1 - lambda+/2 with 1 - lambda+ = omp
-  HIPCHK(c, launch_stress(c->p.storage, site_args(c), d_sigma, 0.5 * (1.0 + c->omp), c->st));
+  // 1 - lambda+/2 with 1 - lambda+ = omp; the trace part relaxes at the bulk rate for LB_MRT
+  const double ps = 0.5 * (1.0 + c->omp);
+  const double pb = c->p.collision == LB_MRT ? 1.0 - 0.5 * c->p.mrt_rates[0] : ps;
+  HIPCHK(c, launch_stress(c->p.storage, site_args(c), d_sigma, ps, pb, c->st));
   return LB_OK;
 }
 
@@ -1168,6 +1187,8 @@ lb_status lb_ensemble_admit(lb_ensemble* e, const lb_grid* g, const lb_params* p
   if (p->coupling == LB_COUPLE_IB || p->mts_substeps != 0)
     return efail(e, LB_EINVAL, "ensemble members use FC, EBF or no coupling without sub-steps");
   if (p->kT != 0.0) return efail(e, LB_EINVAL, "ensemble members are deterministic (kT = 0)");
+  if (p->collision == LB_MRT)
+    return efail(e, LB_EINVAL, "ensemble members use the BGK or two-rate collision");
   if (lim->max_bonds != 0 || lim->max_shells != 0)
     return efail(e, LB_EINVAL, "ensemble members carry free particles only");
   if (p->storage != e->storage || p->kernel != e->kernel)

@@ -298,6 +298,10 @@ struct PassK {
   // moments, the generator key and the step index
   R ap, am;
   uint32_t k0, k1, t0, t1;
+  // general MRT: rate of each moment group (bulk, shear, vector ghosts,
+  // pseudo-vector ghosts, scalar ghost, tensor ghosts) and, with noise, the
+  // amplitude S sqrt(mu lambda (2 - lambda)) of each group
+  R lg[6], ag[6];
 };
 
 // Thermal noise of the fluctuating collision (Eq. mrt-fluct) at one site, in
@@ -462,6 +466,170 @@ __device__ __forceinline__ void fused_site(const typename Store<S>::R f[Q], type
     }
     St::st_raw(fo + (size_t)i * P + own, vi);
     St::st_raw(fo + (size_t)(i + 1) * P + own, vj);
+  }
+}
+
+// ------------------------------------------------------------- general MRT
+// Moment rows of the general MRT collision (Eq. mrt-coll with a rate per
+// moment group): the D3Q19 polynomials of Duenweg, Schiller and Ladd (2007),
+// w-orthogonal, each group spanning a subspace the cubic symmetry leaves
+// invariant.  Rows 0..3 (density, momentum) are conserved; row k >= 4 belongs
+// to group mrt_group(k): 0 bulk, 1 shear, 2 vector ghosts, 3 pseudo-vector
+// ghosts, 4 scalar ghost, 5 tensor ghosts.  Evaluated at compile time.
+constexpr int mrt_row(int k, int i) {
+  const int x = CX[i], y = CY[i], z = CZ[i], c2 = x * x + y * y + z * z;
+  switch (k) {
+    case 4: return c2 - 1;
+    case 5: return 3 * x * x - c2;
+    case 6: return y * y - z * z;
+    case 7: return x * y;
+    case 8: return y * z;
+    case 9: return z * x;
+    case 10: return x * (3 * c2 - 5);
+    case 11: return y * (3 * c2 - 5);
+    case 12: return z * (3 * c2 - 5);
+    case 13: return x * (y * y - z * z);
+    case 14: return y * (z * z - x * x);
+    case 15: return z * (x * x - y * y);
+    case 16: return 3 * c2 * c2 - 6 * c2 + 1;
+    case 17: return (2 * c2 - 3) * (3 * x * x - c2);
+    case 18: return (2 * c2 - 3) * (y * y - z * z);
+  }
+  return 0;
+}
+constexpr int mrt_group(int k) {
+  return k == 4 ? 0 : (k <= 9 ? 1 : (k <= 12 ? 2 : (k <= 15 ? 3 : (k == 16 ? 4 : 5))));
+}
+constexpr bool mrt_odd(int k) { return k >= 10 && k <= 15; }
+// 1 / b_k with b_k = sum_i w_i e_k(c_i)^2
+constexpr double mrt_inv_b(int k) {
+  double b = 0.0;
+  for (int i = 0; i < Q; ++i) {
+    const double w = WCLASS[i] == 0 ? 1.0 / 3.0 : (WCLASS[i] == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+    b += w * mrt_row(k, i) * mrt_row(k, i);
+  }
+  return 1.0 / b;
+}
+
+// One site of the fused pass with the general MRT collision (no comoving
+// frame):
+//   f*_i = f^eq_i(rho, u + F/2rho) + n_i - w_i sum_k e_k(c_i) (lambda_k m_k - xi_k) / b_k
+// with n = f - f^eq(rho, u), m_k = sum_i e_k(c_i) n_i over the non-conserved
+// rows and, with NS, the thermal noise xi_k = sqrt(rho) S sqrt(mu lambda_k
+// (2 - lambda_k)) m_k(z) of z_i = sqrt(w_i) g_i (Eq. mrt-fluct).  Sums run
+// over the opposite pairs: even rows see n_i + n_j, odd rows n_i - n_j.  The
+// row coefficients are compile-time integers, so only their nonzero terms
+// are formed.
+template <int S, bool NS>
+__device__ __forceinline__ void fused_site_mrt(const typename Store<S>::R f[Q],
+                                               typename Store<S>::R Fx, typename Store<S>::R Fy,
+                                               typename Store<S>::R Fz,
+                                               const PassK<typename Store<S>::R>& k,
+                                               typename Store<S>::T* __restrict__ fo, size_t P,
+                                               size_t own) {
+  using St = Store<S>;
+  using R = typename St::R;
+  R d = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    d += f[i];
+    if (CX[i]) jx += R(CX[i]) * f[i];
+    if (CY[i]) jy += R(CY[i]) * f[i];
+    if (CZ[i]) jz += R(CZ[i]) * f[i];
+  }
+  const R rho = k.rho0 + d * k.inv;
+  const R ir = R(1) / rho;
+  const R js = k.inv * ir;
+  const R ux = jx * js, uy = jy * js, uz = jz * js;
+  const R hf = R(0.5) * ir;
+  const R hx = ux + hf * Fx, hy = uy + hf * Fy, hz = uz + hf * Fz;
+  const R usq = ux * ux + uy * uy + uz * uz, hsq = hx * hx + hy * hy + hz * hz;
+  const R rs = rho * k.sc;
+  // equilibria (storage units) and non-equilibrium parts; pair p = (2p+1, 2p+2)
+  R n0, eh0, Eh[9], Oh[9], nI[9], nJ[9], sp[9], ap[9];
+  {
+    const R w = wgt<R>(0);
+    n0 = f[0] - w * (d - R(1.5) * rs * usq);
+    eh0 = w * (d - R(1.5) * rs * hsq);
+  }
+#pragma unroll
+  for (int p = 0; p < 9; ++p) {
+    const int i = 2 * p + 1;
+    const R w = wgt<R>(i);
+    const R A = w * d, B = w * rs;
+    const R cb = R(CX[i]) * ux + R(CY[i]) * uy + R(CZ[i]) * uz;
+    const R ch = R(CX[i]) * hx + R(CY[i]) * hy + R(CZ[i]) * hz;
+    const R Eb = A + B * (R(4.5) * cb * cb - R(1.5) * usq), Ob = R(3) * B * cb;
+    Eh[p] = A + B * (R(4.5) * ch * ch - R(1.5) * hsq);
+    Oh[p] = R(3) * B * ch;
+    nI[p] = f[i] - Eb - Ob;
+    nJ[p] = f[i + 1] - Eb + Ob;
+    sp[p] = nI[p] + nJ[p];
+    ap[p] = nI[p] - nJ[p];
+  }
+  // noise moments m_k(z), z_i = sqrt(w_i) g_i, paired like n
+  R zs[9], za[9], z0 = 0;
+  if (NS) {
+    R g[20];
+#pragma unroll
+    for (int b = 0; b < 5; ++b)
+      normals4<R>(philox(make_uint4((uint32_t)own, k.t0, b, k.t1), k.k0, k.k1), g + 4 * b);
+    const R s0 = sqrt(R(1) / R(3)), s1 = sqrt(R(1) / R(18)), s2 = sqrt(R(1) / R(36));
+    z0 = s0 * g[kVelRank.r[0]];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+      const int i = 2 * p + 1;
+      const R sw = WCLASS[i] == 1 ? s1 : s2;
+      const R zi = sw * g[kVelRank.r[i]], zj = sw * g[kVelRank.r[i + 1]];
+      zs[p] = zi + zj;
+      za[p] = zi - zj;
+    }
+  }
+  const R sr = NS ? sqrt(rho) : R(0);
+  // relaxation amounts D_k = (lambda_k m_k - xi_k) / b_k
+  R D[Q];
+#pragma unroll
+  for (int q = 4; q < Q; ++q) {
+    R m = 0, mz = 0;
+    if (!mrt_odd(q) && mrt_row(q, 0) != 0) {
+      m += R(mrt_row(q, 0)) * n0;
+      if (NS) mz += R(mrt_row(q, 0)) * z0;
+    }
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+      const int c = mrt_row(q, 2 * p + 1);
+      if (c != 0) {
+        m += R(c) * (mrt_odd(q) ? ap[p] : sp[p]);
+        if (NS) mz += R(c) * (mrt_odd(q) ? za[p] : zs[p]);
+      }
+    }
+    R v = k.lg[mrt_group(q)] * m;
+    if (NS) v -= sr * k.ag[mrt_group(q)] * mz;
+    D[q] = v * R(mrt_inv_b(q));
+  }
+  {
+    R c = 0;
+#pragma unroll
+    for (int q = 4; q < Q; ++q)
+      if (!mrt_odd(q) && mrt_row(q, 0) != 0) c += R(mrt_row(q, 0)) * D[q];
+    St::st_raw(fo + own, eh0 + n0 - wgt<R>(0) * c);
+  }
+#pragma unroll
+  for (int p = 0; p < 9; ++p) {
+    const int i = 2 * p + 1;
+    R ce = 0, co = 0;
+#pragma unroll
+    for (int q = 4; q < Q; ++q) {
+      const int c = mrt_row(q, i);
+      if (c == 0) continue;
+      if (mrt_odd(q))
+        co += R(c) * D[q];
+      else
+        ce += R(c) * D[q];
+    }
+    const R w = wgt<R>(i);
+    St::st_raw(fo + (size_t)i * P + own, Eh[p] + Oh[p] + nI[p] - w * (ce + co));
+    St::st_raw(fo + (size_t)(i + 1) * P + own, Eh[p] - Oh[p] + nJ[p] - w * (ce - co));
   }
 }
 

@@ -43,6 +43,11 @@ struct LatArgs {
   int noise;
   double ap, am;
   uint32_t key0, key1, t0, t1;
+  // general MRT (mrt != 0): rate of each moment group (bulk, shear, vector
+  // ghosts, pseudo-vector ghosts, scalar ghost, tensor ghosts) and the noise
+  // amplitude S sqrt(mu lambda (2 - lambda)) of each group
+  int mrt;
+  double lg[6], ag[6];
 };
 
 struct InitArgs {
@@ -201,7 +206,9 @@ hipError_t launch_moments(int storage, const SiteArgs& a, double* rho, double* u
 // physical populations; sqrt(1 - lambda+-): the collide-stream-collide state).
 hipError_t launch_populations(int storage, const SiteArgs& a, double* out, double gp, double gm,
                               hipStream_t st);
-hipError_t launch_stress(int storage, const SiteArgs& a, double* out, double pref, hipStream_t st);
+// pref: factor of the traceless part; prefb: factor of the trace part
+hipError_t launch_stress(int storage, const SiteArgs& a, double* out, double pref, double prefb,
+                         hipStream_t st);
 hipError_t launch_totals(int storage, const SiteArgs& a, double* partial, int nblk,
                          const double* vel, const double* mass, long long np, double* out,
                          hipStream_t st);

@@ -80,7 +80,7 @@ __device__ __forceinline__ void take_forces_ib(uint64_t word, uint64_t* mp, size
   if (lane == 0 && keep != word) *mp = keep;
 }
 
-template <int S, bool CM, bool WALL, bool NS = false>
+template <int S, bool CM, bool WALL, bool NS = false, bool MRT = false>
 __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
   using St = Store<S>;
   using T = typename St::T;
@@ -133,7 +133,15 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
     k.t0 = a.t0;
     k.t1 = a.t1;
   }
-  fused_site<S, CM, NS>(f, Fx, Fy, Fz, k, (T*)a.fout, N, own);
+  if (MRT) {
+    for (int c = 0; c < 6; ++c) {
+      k.lg[c] = R(a.lg[c]);
+      k.ag[c] = R(a.ag[c]);
+    }
+    fused_site_mrt<S, NS>(f, Fx, Fy, Fz, k, (T*)a.fout, N, own);
+  } else {
+    fused_site<S, CM, NS>(f, Fx, Fy, Fz, k, (T*)a.fout, N, own);
+  }
 }
 
 // ======================================================================
@@ -227,7 +235,7 @@ __global__ void k_populations(SiteArgs a, double* out, double gp, double gm, int
 // yy, zz, xy, xz, yz).  The pending half force is an equilibrium shift and
 // drops out, so the stored populations and their own velocity give it.
 template <int S>
-__global__ void k_stress(SiteArgs a, double* out, double pref) {
+__global__ void k_stress(SiteArgs a, double* out, double pref, double prefb) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y, z = blockIdx.z;
   if (x >= a.g.nx) return;
@@ -248,6 +256,13 @@ __global__ void k_stress(SiteArgs a, double* out, double pref) {
     p[5] += ne * (CY[i] * CZ[i]);
   }
   const long long s = site_index(a.g, x, y, z);
+  if (prefb != pref) {  // general MRT: the trace part relaxes at its own rate
+    const double tr = (p[0] + p[1] + p[2]) / 3.0;
+    for (int q = 0; q < 3; ++q) p[q] = pref * (p[q] - tr) + prefb * tr;
+    for (int q = 3; q < 6; ++q) p[q] *= pref;
+    for (int q = 0; q < 6; ++q) out[(long long)q * a.g.N + s] = p[q];
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < 6; ++q) out[(long long)q * a.g.N + s] = pref * p[q];
 }
@@ -821,16 +836,17 @@ static dim3 lattice_grid(const Geo& g, dim3 b) {
     default: { constexpr int SS = LB_BF16; CALL; } break;           \
   }
 
-template <int S, bool CM, bool WALL, bool NS>
+template <int S, bool CM, bool WALL, bool NS, bool MRT>
 __global__ __launch_bounds__(256) void k_stream_collide_lin(LatArgs a);
 
-template <bool CM, bool WALL, bool NS = false>
+template <bool CM, bool WALL, bool NS = false, bool MRT = false>
 static void launch_sc(int storage, const LatArgs& a, dim3 gr, dim3 b, hipStream_t st) {
   if (a.g.wpr == 0) {  // linear mask: x extent not a multiple of 64
     const unsigned nb = (unsigned)((a.g.N + 255) / 256);
-    LBC_STORAGE_SWITCH(storage, (k_stream_collide_lin<SS, CM, WALL, NS><<<nb, 256, 0, st>>>(a)));
+    LBC_STORAGE_SWITCH(storage,
+                       (k_stream_collide_lin<SS, CM, WALL, NS, MRT><<<nb, 256, 0, st>>>(a)));
   } else {
-    LBC_STORAGE_SWITCH(storage, (k_stream_collide<SS, CM, WALL, NS><<<gr, b, 0, st>>>(a)));
+    LBC_STORAGE_SWITCH(storage, (k_stream_collide<SS, CM, WALL, NS, MRT><<<gr, b, 0, st>>>(a)));
   }
 }
 
@@ -839,7 +855,15 @@ static void launch_sc(int storage, const LatArgs& a, dim3 gr, dim3 b, hipStream_
 // carries none of its arithmetic.
 hipError_t launch_stream_collide(int storage, bool comoving, const LatArgs& a, hipStream_t st) {
   const dim3 b = lattice_block(a.g), gr = lattice_grid(a.g, b);
-  if (a.noise) {  // fluctuating collision (the comoving frame is not combined with it)
+  if (a.mrt) {  // general MRT (not with the comoving frame), with or without noise
+    if (a.noise) {
+      if (a.g.wall) launch_sc<false, true, true, true>(storage, a, gr, b, st);
+      else launch_sc<false, false, true, true>(storage, a, gr, b, st);
+    } else {
+      if (a.g.wall) launch_sc<false, true, false, true>(storage, a, gr, b, st);
+      else launch_sc<false, false, false, true>(storage, a, gr, b, st);
+    }
+  } else if (a.noise) {  // fluctuating collision (the comoving frame is not combined with it)
     if (a.g.wall) launch_sc<false, true, true>(storage, a, gr, b, st);
     else launch_sc<false, false, true>(storage, a, gr, b, st);
   } else if (comoving) {
@@ -872,9 +896,10 @@ hipError_t launch_populations(int storage, const SiteArgs& a, double* out, doubl
   return hipGetLastError();
 }
 
-hipError_t launch_stress(int storage, const SiteArgs& a, double* out, double pref, hipStream_t st) {
+hipError_t launch_stress(int storage, const SiteArgs& a, double* out, double pref, double prefb,
+                         hipStream_t st) {
   const dim3 b = lattice_block(a.g), gr = lattice_grid(a.g, b);
-  LBC_STORAGE_SWITCH(storage, (k_stress<SS><<<gr, b, 0, st>>>(a, out, pref)));
+  LBC_STORAGE_SWITCH(storage, (k_stress<SS><<<gr, b, 0, st>>>(a, out, pref, prefb)));
   return hipGetLastError();
 }
 
@@ -1002,6 +1027,13 @@ struct LatView {
     k.t0 = a.t0;
     k.t1 = a.t1;
   }
+  template <typename R>
+  __device__ void mrt(PassK<R>& k) const {
+    for (int c = 0; c < 6; ++c) {
+      k.lg[c] = R(a.lg[c]);
+      k.ag[c] = R(a.ag[c]);
+    }
+  }
 };
 
 struct SlotView {
@@ -1029,9 +1061,11 @@ struct SlotView {
   __device__ bool clear_mask() const { return s.steps_done % kMaskKeep == 0; }
   template <typename R>
   __device__ void noise(PassK<R>&) const {}  // ensemble members are deterministic
+  template <typename R>
+  __device__ void mrt(PassK<R>&) const {}  // ... and use the two-rate collision
 };
 
-template <int S, bool CM, bool WALL, class V, bool NS = false>
+template <int S, bool CM, bool WALL, class V, bool NS = false, bool MRT = false>
 __device__ __forceinline__ void linear_site(const V& v, uint32_t s) {
   using St = Store<S>;
   using T = typename St::T;
@@ -1076,12 +1110,17 @@ __device__ __forceinline__ void linear_site(const V& v, uint32_t s) {
   }
   k.cm = pick_terms<R>(v.cm(), v.cmf());
   if (NS) v.noise(k);
-  fused_site<S, CM, NS>(f, Fx, Fy, Fz, k, (T*)v.fout(), P, s);
+  if (MRT) {
+    v.mrt(k);
+    fused_site_mrt<S, NS>(f, Fx, Fy, Fz, k, (T*)v.fout(), P, s);
+  } else {
+    fused_site<S, CM, NS>(f, Fx, Fy, Fz, k, (T*)v.fout(), P, s);
+  }
 }
 
-template <int S, bool CM, bool WALL, bool NS>
+template <int S, bool CM, bool WALL, bool NS, bool MRT>
 __global__ __launch_bounds__(256) void k_stream_collide_lin(LatArgs a) {
-  linear_site<S, CM, WALL, LatView, NS>(LatView{a}, blockIdx.x * 256u + threadIdx.x);
+  linear_site<S, CM, WALL, LatView, NS, MRT>(LatView{a}, blockIdx.x * 256u + threadIdx.x);
 }
 
 // The slot table is read-only during the lattice pass (only k_ens_advance

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbc.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EBUSY, LB_EDEVICE, LB_ESTATE = range(6)
-LB_BGK, LB_TRT = 0, 1
+LB_BGK, LB_TRT, LB_MRT = 0, 1, 2
 LB_FORCING_SPLIT2 = 0
 LB_COUPLE_NONE, LB_COUPLE_FC, LB_COUPLE_EBF, LB_COUPLE_IB = 0, 1, 2, 3
 LB_PHI2, LB_PHI3, LB_PHI4 = 2, 3, 4
@@ -43,7 +43,7 @@ class lb_params(C.Structure):
                 ("storage", C.c_int32), ("f16_scale_log2", C.c_int32),
                 ("mts_substeps", C.c_int32), ("deterministic", C.c_int32),
                 ("comoving", C.c_int32), ("csc", C.c_int32), ("mts_inside", C.c_int32),
-                ("kT", C.c_double), ("seed", C.c_uint64)]
+                ("kT", C.c_double), ("seed", C.c_uint64), ("mrt_rates", C.c_double * 5)]
 
 
 class lb_limits(C.Structure):
@@ -130,7 +130,7 @@ def lattice_velocities():
 def make_params(tau, rho0=1.0, body_force=(0.0, 0.0, 0.0), collision=LB_BGK, trt_magic=3.0 / 16.0,
                 coupling=LB_COUPLE_NONE, gamma=0.0, kernel=LB_PHI2, storage=LB_F64,
                 f16_scale_log2=0, mts_substeps=0, comoving=0, csc=0, mts_inside=0, kT=0.0,
-                seed=0):
+                seed=0, mrt_rates=(1.0, 1.0, 1.0, 1.0, 1.0)):
     p = lb_params()
     p.tau, p.rho0 = float(tau), float(rho0)
     for a in range(3):
@@ -141,6 +141,8 @@ def make_params(tau, rho0=1.0, body_force=(0.0, 0.0, 0.0), collision=LB_BGK, trt
     p.mts_substeps, p.deterministic = int(mts_substeps), 0
     p.comoving, p.csc, p.mts_inside = int(comoving), int(csc), int(mts_inside)
     p.kT, p.seed = float(kT), int(seed)
+    for k in range(5):
+        p.mrt_rates[k] = float(mrt_rates[k])
     return p
 
 

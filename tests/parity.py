@@ -66,7 +66,7 @@ def run_oracle(c: Case):
                  tether_k=c.tether_k, magic=c.extra.get("magic", 3.0 / 16.0),
                  csc=c.extra.get("csc", 0), mts_inside=c.extra.get("mts_inside", 0),
                  rho0=c.extra.get("rho0", 1.0), kT=c.extra.get("kT", 0.0),
-                 seed=c.extra.get("seed", 0))
+                 seed=c.extra.get("seed", 0), mrt_rates=c.extra.get("mrt_rates", (1.0,) * 5))
     rho, u = initial_fields(c)
     df = o.init_fluid(rho, u)
     pos = None if c.pos is None else np.array(c.pos, dtype=np.float64, copy=True)
@@ -77,7 +77,16 @@ def run_oracle(c: Case):
     rho_o, u_o = o.moments(df)
     out = dict(df=df, rho=rho_o, u=u_o, pos=pos, vel=vel, totals=o.totals(df, vel, c.mass))
     if c.extra.get("stress"):
-        out["sigma"] = stress_prefactor(c) * o.stress(df)
+        pi = o.stress(df)
+        if c.collision == 2:  # general MRT: the trace relaxes at the bulk rate
+            tr = (pi[0] + pi[1] + pi[2]) / 3.0
+            ps, pb = 1.0 - 0.5 / c.tau, 1.0 - 0.5 * c.extra["mrt_rates"][0]
+            sig = ps * pi
+            for q in range(3):
+                sig[q] = ps * (pi[q] - tr) + pb * tr
+            out["sigma"] = sig
+        else:
+            out["sigma"] = stress_prefactor(c) * pi
     return out
 
 
@@ -106,7 +115,8 @@ def make_gpu(c: Case):
                     comoving=c.extra.get("comoving", 0), csc=c.extra.get("csc", 0),
                     trt_magic=c.extra.get("magic", 3.0 / 16.0),
                     mts_inside=c.extra.get("mts_inside", 0), rho0=c.extra.get("rho0", 1.0),
-                    kT=c.extra.get("kT", 0.0), seed=c.extra.get("seed", 0))
+                    kT=c.extra.get("kT", 0.0), seed=c.extra.get("seed", 0),
+                    mrt_rates=c.extra.get("mrt_rates", (1.0,) * 5))
     rho, u = initial_fields(c)
     lat.lb_init_fluid(None if rho is None else torch.from_numpy(rho),
                       None if u is None else torch.from_numpy(np.ascontiguousarray(u)))

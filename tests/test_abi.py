@@ -63,6 +63,10 @@ def test_workspace_size_scales_with_storage():
     dict(tau=0.8, csc=1), dict(tau=1.2, collision=1, trt_magic=3.0 / 16.0, csc=1),
     dict(tau=1.2, csc=2), dict(tau=0.8, coupling=1, gamma=1.0, mts_inside=1),
     dict(tau=0.8, coupling=1, gamma=1.0, mts_substeps=2, mts_inside=2),
+    dict(tau=0.8, collision=2, mrt_rates=(1.0, 2.0, 1.0, 1.0, 1.0)),
+    dict(tau=0.8, collision=2, mrt_rates=(0.0, 1.0, 1.0, 1.0, 1.0)),
+    dict(tau=1.2, collision=2, csc=1), dict(tau=0.8, collision=2, comoving=1),
+    dict(tau=0.8, kT=-1.0), dict(tau=1.2, kT=1e-4, csc=1), dict(tau=0.8, kT=1e-4, comoving=1),
 ])
 def test_invalid_parameters_rejected(bad):
     with pytest.raises(L.LbcError) as e:

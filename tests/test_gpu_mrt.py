@@ -1,0 +1,140 @@
+"""GPU parity of the general MRT collision (Eq. mrt-coll with a rate per
+moment group) against the FP64 oracle, which relaxes in moment space with a
+dense 19 x 19 transform.  Tolerances as in the other parity tests (FP64
+storage 1e-12, for bonded chains 20 times the oracle's one-ulp sensitivity if
+larger; FP32 storage 1e-5).  Also: the two-rate special case against the GPU
+two-rate path, and the sound attenuation set by the bulk rate (independent
+of the oracle)."""
+import numpy as np
+import pytest
+
+from paper_1406_2211_amd import inputs as I
+from parity import Case, compare, run_gpu, run_oracle, ulp_sensitivity
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+RATES = (0.8, 1.3, 0.7, 1.9, 1.1)  # bulk, vector ghosts, pseudo-vector ghosts, scalar, tensor
+
+
+def _mrt(c, rates=RATES):
+    c.collision = 2
+    c.extra["mrt_rates"] = rates
+    return c
+
+
+def _check(c, tol):
+    o = run_oracle(c)
+    sens = ulp_sensitivity(c, o) if c.bonds is not None else 0.0
+    return compare(c, run_gpu(c), o, tol, sens=sens)
+
+
+def test_ragged_box_body_force_fp64():
+    c = Case(name="mrt_ragged", nx=13, ny=9, nz=11, tau=0.7, steps=40, fext=(1e-6, -2e-6, 0.0),
+             u_noise=1e-3)
+    _check(_mrt(c), TOL64)
+
+
+def test_row_layout_walls_fp64():
+    c = Case(name="mrt_row_walls", nx=64, ny=10, nz=6, tau=0.9, steps=30, wall_y=1,
+             fext=(0.0, 0.0, 1e-6), u_noise=1e-3)
+    _check(_mrt(c), TOL64)
+
+
+def test_force_coupling_phi3_fp64():
+    pos = I.uniform_positions(20, (16, 16, 16), 3)
+    c = Case(name="mrt_fc", nx=16, ny=16, nz=16, tau=0.6, steps=30, coupling=1, gamma=1.5,
+             kernel=3, pos=pos, vel=np.random.default_rng(3).normal(0, 1e-3, (20, 3)),
+             mass=np.ones(20))
+    _check(_mrt(c), TOL64)
+
+
+def test_chains_coupling_inside_fp64():
+    pos, vel, bonds = I.chains(2, 10, (20, 20, 20), 1.0, 1e-3, 3)
+    c = Case(name="mrt_mts", nx=20, ny=20, nz=20, tau=0.7, steps=20, coupling=1, gamma=2.0,
+             mts=3, pos=pos, vel=vel, mass=np.ones(len(pos)), bonds=bonds, bond_k=2.0,
+             bond_r0=1.0)
+    c.extra["mts_inside"] = 1
+    _check(_mrt(c), TOL64)
+
+
+def test_ib_shells_fp64():
+    T = I.icosphere(1, 3.0)
+    # markers off the template shape, as in the other IB cases: with the
+    # markers exactly on it the rigid fit is ill-conditioned
+    X = np.array([8.0, 8.2, 9.1]) + T + 0.15 * np.random.default_rng(5).standard_normal(T.shape)
+    c = Case(name="mrt_ib", nx=16, ny=16, nz=18, tau=0.8, steps=20, wall_y=1, coupling=3,
+             kernel=4, u_noise=0.0, pos=X, nshell=1, template=T, tether_k=0.05,
+             fext=(0.0, 0.0, 1e-6))
+    _check(_mrt(c), TOL64)
+
+
+@pytest.mark.parametrize("nx", [12, 64])
+def test_fluctuating_mrt_fp64(nx):
+    """Noise per moment group (amplitude sqrt(mu lambda_g (2 - lambda_g)))."""
+    c = Case(name=f"mrt_fluct_{nx}", nx=nx, ny=10, nz=8, tau=0.8, steps=25)
+    c.extra.update(kT=1e-5, seed=77)
+    _check(_mrt(c), TOL64)
+
+
+def test_force_coupling_fp32():
+    pos = I.uniform_positions(30, (32, 32, 32), 4)
+    c = Case(name="mrt_fc32", nx=32, ny=32, nz=32, tau=0.6, steps=60, coupling=1, gamma=2.0,
+             storage=1, pos=pos, vel=np.zeros((30, 3)), mass=np.ones(30), fext=(1e-6, 0, 0))
+    _check(_mrt(c), TOL32)
+
+
+def test_stress_with_bulk_rate_fp64():
+    c = Case(name="mrt_stress", nx=12, ny=16, nz=10, tau=0.8, steps=40, u_noise=1e-3, seed=3)
+    c.extra.update(shear=2e-2, stress=1)
+    c = _mrt(c)
+    g, o = run_gpu(c), run_oracle(c)
+    err = np.abs(g["sigma"] - o["sigma"]).max()
+    assert np.abs(o["sigma"]).max() > 1e-4
+    assert err <= 19 * TOL64 * np.abs(o["df"]).max()
+
+
+def test_two_rate_special_case_matches_two_rate_path():
+    """Group rates (l+, l-, l-, l+, l+) on the MRT path give the two-rate
+    path's result (different arithmetic, same collision)."""
+    tau, magic = 0.7, 3.0 / 16.0
+    lp, lm = 1.0 / tau, 1.0 / (0.5 + magic / (tau - 0.5))
+    a = Case(name="trt_path", nx=20, ny=12, nz=14, tau=tau, steps=30, collision=1,
+             fext=(1e-6, 0, 0), u_noise=1e-3)
+    b = _mrt(Case(name="mrt_path", nx=20, ny=12, nz=14, tau=tau, steps=30,
+                  fext=(1e-6, 0, 0), u_noise=1e-3), (lp, lm, lm, lp, lp))
+    ga, gb = run_gpu(a), run_gpu(b)
+    assert np.abs(ga["df"] - gb["df"]).max() < 1e-13 * np.abs(ga["df"]).max()
+
+
+@pytest.mark.parametrize("lb", [0.8, 1.6])
+def test_bulk_rate_sets_sound_attenuation(lb):
+    """Independent of the oracle: a standing sound wave on the GPU decays at
+    Gamma = (k^2/2rho)(4 eta/3 + eta_b), eta_b = (2/3) rho c_s^2 (1/l_b - 1/2)."""
+    import torch
+    from paper_1406_2211_amd import lbc as L
+    n, tau = 64, 0.8
+    lat = L.Lattice(n, 1, 1, tau=tau, collision=2, mrt_rates=(lb, 1.3, 0.7, 1.9, 1.1), storage=0)
+    x = np.arange(n)
+    k = 2 * np.pi / n
+    rho = 1.0 + 1e-5 * np.cos(k * x)
+    lat.lb_init_fluid(torch.from_numpy(rho.reshape(1, 1, n)), None)
+    cs = np.sqrt(1.0 / 3.0)
+    ts, es = [], []
+    for t in range(0, 1200, 10):
+        r, u = lat.lb_moments()
+        r, u = r.cpu().numpy(), u.cpu().numpy()
+        ar = np.sum((r[0, 0] - 1.0) * np.cos(k * x)) * 2.0 / n
+        au = np.sum(u[0, 0, 0] * np.sin(k * x)) * 2.0 / n
+        ts.append(t)
+        es.append(ar * ar + (au / cs) ** 2)
+        lat.lb_step(10)
+    torch.cuda.synchronize()
+    lat.lb_destroy()
+    gam = -0.5 * np.polyfit(np.array(ts), np.log(np.array(es)), 1)[0]
+    cs2 = 1.0 / 3.0
+    # eta / rho c_s^2 = 1/l_s - 1/2 = tau - 1/2
+    expect = 0.5 * k * k * (4.0 / 3.0 * cs2 * (tau - 0.5) + 2.0 / 3.0 * cs2 * (1.0 / lb - 0.5))
+    print(f"[mrt] bulk rate {lb}: Gamma {gam:.5e}, expected {expect:.5e}", flush=True)
+    assert abs(gam / expect - 1.0) < 0.03
