@@ -188,6 +188,7 @@ struct lb_ctx {
   bool member = false;  // slot of an ensemble: stepped only by lb_ensemble_step
   bool running = false;  // ensemble slot whose device record has been uploaded
   bool mvalid = false;   // coupling moment cache holds the state of f[cur]
+  int lds_cu = 0;        // LDS bytes per compute unit (for the lattice-pass occupancy cap)
   int nshell = 0, shell_size = 0;
   double k_tether = 0;
   double omp = 0, omm = 0;
@@ -425,6 +426,20 @@ static lb_status lattice_pass(lb_ctx* c) {
   a.key1 = (uint32_t)(c->p.seed >> 32);
   a.t0 = (uint32_t)c->steps;
   a.t1 = (uint32_t)((uint64_t)c->steps >> 32);
+  // Occupancy cap of the pass.  Fewer resident wavefronts per CU keep fewer
+  // of the 19 population streams open at once, which raised the streaming
+  // rate of the deterministic pass: 20 waves per CU for FP32 (256^3: 452 ->
+  // 435 us; 250^3 on the linear-site pass: 427 -> 408 us), 24 for 16-bit
+  // storage (256^3 FP16: 229 -> 225 us).  The cap is an unused dynamic LDS
+  // reservation per workgroup.  Not for FP64 (no gain measured) nor with
+  // thermal noise (its arithmetic needs the occupancy).
+  a.occ_lds = 0;
+  if (c->lds_cu > 0 && c->p.kT == 0.0 && c->p.storage != LB_F64) {
+    const int waves_cu = c->p.storage == LB_F32 ? 20 : 24;
+    const int bx = c->geo.wpr == 0 ? 256 : std::min(256, (c->geo.nx + 63) / 64 * 64);
+    const int groups = std::max(1, waves_cu / (bx / 64));
+    a.occ_lds = (c->lds_cu / groups) & ~1023;
+  }
   a.mrt = c->p.collision == LB_MRT ? 1 : 0;
   {  // group rates: bulk, shear, vector, pseudo-vector, scalar and tensor ghosts
     const double* r = c->p.mrt_rates;
@@ -687,6 +702,13 @@ static lb_status create_ctx(const lb_grid* g, const lb_params* p, const lb_limit
   if (p->storage == LB_F16 || p->storage == LB_BF16) {
     c->scale = std::ldexp(1.0f, p->f16_scale_log2);
     c->inv = std::ldexp(1.0f, -p->f16_scale_log2);
+  }
+  {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+            hipSuccess)
+      c->lds_cu = v;
   }
   lb_status s = lb_init_fluid(c, nullptr, nullptr);
   if (s != LB_OK) {

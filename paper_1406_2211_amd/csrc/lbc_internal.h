@@ -48,6 +48,7 @@ struct LatArgs {
   // amplitude S sqrt(mu lambda (2 - lambda)) of each group
   int mrt;
   double lg[6], ag[6];
+  int occ_lds;  // dynamic LDS bytes reserved per workgroup (occupancy cap), 0: none
 };
 
 struct InitArgs {

@@ -843,10 +843,11 @@ template <bool CM, bool WALL, bool NS = false, bool MRT = false>
 static void launch_sc(int storage, const LatArgs& a, dim3 gr, dim3 b, hipStream_t st) {
   if (a.g.wpr == 0) {  // linear mask: x extent not a multiple of 64
     const unsigned nb = (unsigned)((a.g.N + 255) / 256);
-    LBC_STORAGE_SWITCH(storage,
-                       (k_stream_collide_lin<SS, CM, WALL, NS, MRT><<<nb, 256, 0, st>>>(a)));
+    LBC_STORAGE_SWITCH(storage, (k_stream_collide_lin<SS, CM, WALL, NS, MRT>
+                                 <<<nb, 256, a.occ_lds, st>>>(a)));
   } else {
-    LBC_STORAGE_SWITCH(storage, (k_stream_collide<SS, CM, WALL, NS, MRT><<<gr, b, 0, st>>>(a)));
+    LBC_STORAGE_SWITCH(storage,
+                       (k_stream_collide<SS, CM, WALL, NS, MRT><<<gr, b, a.occ_lds, st>>>(a)));
   }
 }
 
