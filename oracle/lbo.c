@@ -271,7 +271,8 @@ static void site_rho_u(const lbo_cfg *cfg, const double df[LBO_Q], double *drho,
 /* multipliers and mixing their halves with words 1 and 3 and the key; the  */
 /* key advances by the published Weyl increments between rounds.  Normal    */
 /* deviates by the Box-Muller transform (Box and Muller 1958) of uniforms   */
-/* u = (x / 2^8 + 1/2) / 2^24 in (0, 1) made from the top 24 bits.          */
+/* u = (x / 2^9 + 1/2) / 2^23 in (0, 1) made from the top 23 bits (a value */
+/* with 24 significant bits, exact in single precision as well).            */
 /* ------------------------------------------------------------------------ */
 void lbo_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
   uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1];
@@ -294,14 +295,14 @@ void lbo_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
   out[3] = c3;
 }
 
-static double unit24(uint32_t x) { return ((double)(x >> 8) + 0.5) / 16777216.0; }
+static double unit23(uint32_t x) { return ((double)(x >> 9) + 0.5) / 8388608.0; }
 
 void lbo_normals4(const uint32_t ctr[4], const uint32_t key[2], double g[4]) {
   uint32_t x[4];
   lbo_philox(ctr, key, x);
   for (int p = 0; p < 2; ++p) {
-    const double r = sqrt(-2.0 * log(unit24(x[2 * p])));
-    const double th = 6.283185307179586 * unit24(x[2 * p + 1]);
+    const double r = sqrt(-2.0 * log(unit23(x[2 * p])));
+    const double th = 6.283185307179586 * unit23(x[2 * p + 1]);
     g[2 * p] = r * cos(th);
     g[2 * p + 1] = r * sin(th);
   }

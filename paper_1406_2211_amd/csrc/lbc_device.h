@@ -50,15 +50,18 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
   return c;
 }
 
-// Uniform in (0, 1) from the top 24 bits (exact in FP32 and FP64), and four
+// Uniform in (0, 1) from the top 23 bits, u = (x / 2^9 + 1/2) / 2^23: 24
+// significant bits, exact in FP32 and FP64 (a 24-bit version would need 25
+// and round in FP32 for half of the values, which moves u near 1 and with it
+// the small radii sqrt(-2 ln u) of the transform), and four
 // normal deviates by the Box-Muller transform of the pairs (x, y), (z, w):
 // r = sqrt(-2 ln u1), (r cos 2 pi u2, r sin 2 pi u2).  FP64 uses the library
 // functions (the angle through sincospi, an exact argument reduction).  FP32
 // uses the hardware transcendentals: log2, square root, and sine and cosine
 // of a whole number of revolutions (u2 in (0, 1)), each within a few ulp.
 template <typename R>
-__device__ __forceinline__ R unit24(uint32_t x) {
-  return (R(x >> 8) + R(0.5)) * R(5.9604644775390625e-08);  // 2^-24
+__device__ __forceinline__ R unit23(uint32_t x) {
+  return (R(x >> 9) + R(0.5)) * R(1.1920928955078125e-07);  // 2^-23
 }
 
 __device__ __forceinline__ void box_muller(float u1, float u2, float& a, float& b) {
@@ -76,8 +79,8 @@ __device__ __forceinline__ void box_muller(double u1, double u2, double& a, doub
 
 template <typename R>
 __device__ __forceinline__ void normals4(uint4 b, R g[4]) {
-  box_muller(unit24<R>(b.x), unit24<R>(b.y), g[0], g[1]);
-  box_muller(unit24<R>(b.z), unit24<R>(b.w), g[2], g[3]);
+  box_muller(unit23<R>(b.x), unit23<R>(b.y), g[0], g[1]);
+  box_muller(unit23<R>(b.z), unit23<R>(b.w), g[2], g[3]);
 }
 
 // Deviate index of velocity c_i: its rank in increasing 9(cx+1) + 3(cy+1) + (cz+1).

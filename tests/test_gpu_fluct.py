@@ -126,3 +126,15 @@ def test_thermal_equilibrium_populations_64cubed_fp32(collision, tau):
           flush=True)
     assert np.all(np.abs(ratio - 1.0) < 0.02), ratio
     assert abs(cross / nsamp) < 0.02 * 3 * kT / 18
+
+
+def test_full_size_thermal_force_coupling_fp32():
+    """The thermal force-coupling workload at full size, in the launch
+    configuration the benchmark times: 256^3 two-rate MRT, FP32 storage,
+    10^4 bonded particles with the multiple time-step split, kT = 1e-5; every
+    output compared with the oracle after 2 steps."""
+    pos, vel, bonds = I.chains(100, 100, (256, 256, 256), 1.0, 1e-3, 2)
+    c = Case(name="c2thermal_full", nx=256, ny=256, nz=256, tau=0.6, steps=2, collision=1,
+             coupling=1, gamma=2.0, kernel=2, storage=1, mts=5, u_noise=0.0, pos=pos, vel=vel,
+             mass=np.ones(len(pos)), bonds=bonds, bond_k=30.0, bond_r0=1.0)
+    _check(_fl(c, kT=1e-5, seed=2), TOL32)

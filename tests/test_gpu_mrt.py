@@ -138,3 +138,14 @@ def test_bulk_rate_sets_sound_attenuation(lb):
     expect = 0.5 * k * k * (4.0 / 3.0 * cs2 * (tau - 0.5) + 2.0 / 3.0 * cs2 * (1.0 / lb - 0.5))
     print(f"[mrt] bulk rate {lb}: Gamma {gam:.5e}, expected {expect:.5e}", flush=True)
     assert abs(gam / expect - 1.0) < 0.03
+
+
+def test_full_size_force_coupling_fp32():
+    """The force-coupling workload with the general MRT at full size, in the
+    launch configuration the benchmark times (256^3, FP32, 10^4 bonded
+    particles, multiple time steps); every output compared after 2 steps."""
+    pos, vel, bonds = I.chains(100, 100, (256, 256, 256), 1.0, 1e-3, 2)
+    c = Case(name="c2mrt_full", nx=256, ny=256, nz=256, tau=0.6, steps=2, coupling=1,
+             gamma=2.0, kernel=2, storage=1, mts=5, u_noise=0.0, pos=pos, vel=vel,
+             mass=np.ones(len(pos)), bonds=bonds, bond_k=30.0, bond_r0=1.0)
+    _check(_mrt(c, (1.4, 1.2, 1.2, 1.5, 1.5)), TOL32)
