@@ -116,6 +116,8 @@ struct Store<LB_F64> {
   using V4 = double4;
   static __device__ __forceinline__ R ld(const T* p, R) { return *p; }
   static __device__ __forceinline__ R raw(const T* p) { return *p; }
+  // non-temporal load (the row-mapped pass reads each population once)
+  static __device__ __forceinline__ R raw_nt(const T* p) { return __builtin_nontemporal_load(p); }
   // populations are written once per pass and not re-read by it: non-temporal
   static __device__ __forceinline__ void st(T* p, R v, R) { __builtin_nontemporal_store(v, p); }
   static __device__ __forceinline__ void st_raw(T* p, R v) { __builtin_nontemporal_store(v, p); }
@@ -127,6 +129,7 @@ struct Store<LB_F32> {
   using V4 = float4;
   static __device__ __forceinline__ R ld(const T* p, R) { return *p; }
   static __device__ __forceinline__ R raw(const T* p) { return *p; }
+  static __device__ __forceinline__ R raw_nt(const T* p) { return __builtin_nontemporal_load(p); }
   static __device__ __forceinline__ void st(T* p, R v, R) { __builtin_nontemporal_store(v, p); }
   static __device__ __forceinline__ void st_raw(T* p, R v) { __builtin_nontemporal_store(v, p); }
 };
@@ -138,6 +141,9 @@ struct Store<LB_F16> {
   // stored value is scale * (f - w rho0); inv is 1/scale (a power of two)
   static __device__ __forceinline__ R ld(const T* p, R inv) { return __half2float(*p) * inv; }
   static __device__ __forceinline__ R raw(const T* p) { return __half2float(*p); }
+  static __device__ __forceinline__ R raw_nt(const T* p) {
+    return __half2float(__ushort_as_half(__builtin_nontemporal_load((const unsigned short*)p)));
+  }
   static __device__ __forceinline__ void st(T* p, R v, R scale) { st_raw(p, v * scale); }
   static __device__ __forceinline__ void st_raw(T* p, R v) {
     __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)), (unsigned short*)p);
@@ -150,6 +156,10 @@ struct Store<LB_BF16> {
   using V4 = float4;
   static __device__ __forceinline__ R ld(const T* p, R inv) { return __bfloat162float(*p) * inv; }
   static __device__ __forceinline__ R raw(const T* p) { return __bfloat162float(*p); }
+  static __device__ __forceinline__ R raw_nt(const T* p) {
+    // bf16 is the top half of an FP32 word
+    return __uint_as_float((uint32_t)__builtin_nontemporal_load((const unsigned short*)p) << 16);
+  }
   static __device__ __forceinline__ void st(T* p, R v, R scale) { st_raw(p, v * scale); }
   static __device__ __forceinline__ void st_raw(T* p, R v) {
     const __hip_bfloat16 b = __float2bfloat16(v);
