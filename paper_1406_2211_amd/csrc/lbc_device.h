@@ -289,6 +289,36 @@ __device__ __forceinline__ void site_phys(const SiteArgs& a, int x, int y, int z
   if (phys) add_pending<S>(a, site_index(a.g, x, y, z), j);
 }
 
+// Physical moments at one site in the compute type R, for kernels that stage
+// many sites and round the moments to R anyway (R = float for FP32 and 16-bit
+// storage keeps the 19 gathered values in half the registers).
+template <int S, typename R>
+__device__ __forceinline__ void site_phys_r(const SiteArgs& a, int x, int y, int z, R& drho,
+                                            R j[3]) {
+  using St = Store<S>;
+  using V4 = typename St::V4;
+  R fl[Q];
+  pull<S, R>((const typename St::T*)a.f, a.g, x, y, z, (R)a.inv, fl);
+  if (a.uref[0] != 0.0 || a.uref[1] != 0.0 || a.uref[2] != 0.0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      fl[i] += eref<R>(i, (R)a.rho0, (R)a.uref[0], (R)a.uref[1], (R)a.uref[2]);
+  }
+  drho = 0;
+  j[0] = j[1] = j[2] = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += fl[i];
+    if (CX[i]) j[0] += R(CX[i]) * fl[i];
+    if (CY[i]) j[1] += R(CY[i]) * fl[i];
+    if (CZ[i]) j[2] += R(CZ[i]) * fl[i];
+  }
+  const V4 fb = ((const V4*)a.FB)[site_index(a.g, x, y, z)];
+  j[0] += R(0.5) * ((R)fb.x + (R)a.pfx);
+  j[1] += R(0.5) * ((R)fb.y + (R)a.pfy);
+  j[2] += R(0.5) * ((R)fb.z + (R)a.pfz);
+}
+
 // deviation equilibrium f^eq_i(rho,u) - w_i rho0 = w_i [drho + rho P_i(u)],
 // P_i(u) = 3 c.u + 9/2 (c.u)^2 - 3/2 u.u
 template <typename R>

@@ -707,32 +707,43 @@ __global__ void k_bond_groups(BondArgs b, int mode, int acc, int nsub, double dt
 // first marker, centred, the least-squares rotation of the template onto
 // them is found from the dominant eigenvector of Horn's symmetric 4x4
 // quaternion matrix (cyclic Jacobi), and F_j = -k (y_j - c - R t_j).
-__device__ void sym4_eig_max(double A[4][4], double q[4]) {
+// Every index below is a compile-time constant after unrolling, so A and V
+// stay in registers (indexed at run time they went to scratch memory).
+__device__ __forceinline__ void sym4_eig_max(double A[4][4], double q[4]) {
   double V[4][4];
+#pragma unroll
   for (int i = 0; i < 4; ++i)
+#pragma unroll
     for (int j = 0; j < 4; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
   for (int it = 0; it < 50; ++it) {
     double off = 0, dia = 0;
+#pragma unroll
     for (int i = 0; i < 4; ++i)
+#pragma unroll
       for (int j = 0; j < 4; ++j) (i == j ? dia : off) += A[i][j] * A[i][j];
     if (off == 0.0 || off < 1e-32 * dia) break;
+#pragma unroll
     for (int p = 0; p < 3; ++p)
+#pragma unroll
       for (int r = p + 1; r < 4; ++r) {
         const double apr = A[p][r];
         if (apr == 0.0) continue;
         const double theta = 0.5 * (A[r][r] - A[p][p]) / apr;
         const double t = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
         const double c = rsqrt(t * t + 1.0), s = t * c;
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
           const double x = A[k][p], y = A[k][r];
           A[k][p] = c * x - s * y;
           A[k][r] = s * x + c * y;
         }
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
           const double x = A[p][k], y = A[r][k];
           A[p][k] = c * x - s * y;
           A[r][k] = s * x + c * y;
         }
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
           const double x = V[k][p], y = V[k][r];
           V[k][p] = c * x - s * y;
@@ -740,10 +751,16 @@ __device__ void sym4_eig_max(double A[4][4], double q[4]) {
         }
       }
   }
-  int best = 0;
-  for (int k = 1; k < 4; ++k)
-    if (A[k][k] > A[best][best]) best = k;
-  for (int k = 0; k < 4; ++k) q[k] = V[k][best];
+  double bv = A[0][0];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] = V[k][0];
+#pragma unroll
+  for (int j = 1; j < 4; ++j)
+    if (A[j][j] > bv) {
+      bv = A[j][j];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) q[k] = V[k][j];
+    }
 }
 
 __global__ __launch_bounds__(256) void k_shell_forces(ShellArgs sa) {

@@ -262,12 +262,12 @@ __device__ __forceinline__ void row_interp(const SiteArgs& s, const Region& r,
         if (Wt == W(0)) continue;
         const int x = wrap_idx(j0[0] + k, s.g.nx), z = wrap_idx(j0[2] + kz, s.g.nz);
         const int y = s.g.wall ? jy : wrap_idx(jy, s.g.ny);
-        double fl[Q], drho, j[3];
-        site_phys<S>(s, x, y, z, fl, drho, j, true);
-        const double rr = s.rho0 + drho;
-        ux += Wt * (W)(j[0] / rr);
-        uy += Wt * (W)(j[1] / rr);
-        uz += Wt * (W)(j[2] / rr);
+        W drho, j[3];
+        site_phys_r<S, W>(s, x, y, z, drho, j);
+        const W rr = W(s.rho0) + drho;
+        ux += Wt * (j[0] / rr);
+        uy += Wt * (j[1] / rr);
+        uz += Wt * (j[2] / rr);
       }
     }
   }
@@ -319,13 +319,13 @@ __global__ __launch_bounds__(1024) void k_tile_interp(TileArgs t, SiteArgs s, co
       M4 m;
       m.x = m.y = m.z = m.w = W(0);
       if (slot_site(s.g, r, ix, iy, iz, x, y, z)) {
-        double fl[Q], drho, j[3];
-        site_phys<S>(s, x, y, z, fl, drho, j, true);
-        const double rr = s.rho0 + drho;
-        m.x = (W)rr;
-        m.y = (W)(j[0] / rr);
-        m.z = (W)(j[1] / rr);
-        m.w = (W)(j[2] / rr);
+        W drho, j[3];
+        site_phys_r<S, W>(s, x, y, z, drho, j);
+        const W rr = W(s.rho0) + drho;
+        m.x = rr;
+        m.y = j[0] / rr;
+        m.z = j[1] / rr;
+        m.w = j[2] / rr;
       }
       mom[k] = m;
     }
