@@ -1300,7 +1300,7 @@ lb_status lb_ensemble_autotune(lb_ensemble* e, int32_t steps_per_candidate, int3
   lb_status s;
   if (e->dirty && (s = ens_refresh(e)) != LB_OK) return s;
   const int cus = e->cus;
-  const int lat_c[] = {cus * 4, cus * 8, cus * 16};
+  const int lat_c[] = {cus * 4, cus * 6, cus * 8, cus * 16};
   const int part_c[] = {cus, cus * 2, cus * 4};
   hipEvent_t t0, t1;
   EHIPCHK(e, hipEventCreate(&t0));
