@@ -211,6 +211,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="c2")
+    ap.add_argument("--timing-stride", type=int, default=8,
+                    help="time one lattice pass in every k of the timed steps with HIP events")
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=256, help="c5: number of requests")
@@ -255,7 +257,7 @@ def main():
         lat.lb_set_shells(nshell, tmpl, wl["tether_k"])
     lat.lb_step(args.warmup)
     torch.cuda.synchronize()
-    lat.lb_timing(args.steps)
+    lat.lb_timing(args.steps, args.timing_stride)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lat.lb_step(args.steps)
@@ -283,6 +285,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_stream_collide", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "avg_launch_us": round(kern_s * 1e6, 2),
+                     "timed_launches": int(passes),
                      "algorithmic_bytes_per_launch": bps * N},
     }
     lat.lb_destroy()

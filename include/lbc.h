@@ -208,12 +208,16 @@ lb_status lb_get_particles(lb_ctx* ctx, double* d_pos, double* d_vel);
  * h_out[4..6] = particle momentum sum_p m_p v_p (0 for IB).  Synchronous. */
 lb_status lb_totals(lb_ctx* ctx, double h_out[7]);
 
-/* Kernel timing for measurement: with max_passes > 0 the next max_passes
- * fused lattice passes are each bracketed by a pair of HIP events recorded on
- * the context stream (host-side event objects; no device memory); 0 disables.
+/* Kernel timing for measurement: with max_passes > 0, of the fused lattice
+ * passes that follow, the first and then one in every `stride` (>= 1) is
+ * bracketed by a pair of HIP events recorded on the context stream, up to
+ * max_passes timed passes (host-side event objects; no device memory); 0
+ * disables.  Each event pair costs a few microseconds of idle pipeline, so a
+ * stride above 1 keeps the measurement from slowing the run it measures.
  * lb_timing_read waits for the stream and returns the summed event time of
- * the recorded passes (ms) and their number, then resets the count. */
-lb_status lb_timing(lb_ctx* ctx, int32_t max_passes);
+ * the timed passes (ms) and their number, then resets the count.  EINVAL for
+ * a negative or huge max_passes or a stride outside [1, 2^20]. */
+lb_status lb_timing(lb_ctx* ctx, int32_t max_passes, int32_t stride);
 lb_status lb_timing_read(lb_ctx* ctx, double* lattice_ms, int64_t* passes);
 
 /* Number of particles, steps taken so far. */

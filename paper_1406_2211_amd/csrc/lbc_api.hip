@@ -196,6 +196,8 @@ struct lb_ctx {
   double uref[3] = {0, 0, 0};  // storage reference velocity of f[cur] (comoving frame)
   std::vector<hipEvent_t> ev;  // timing event pairs
   int32_t ev_used = 0;
+  int32_t ev_stride = 1;   // time one pass in every ev_stride
+  int64_t ev_seen = 0;     // passes since timing was armed
   std::string err;
 };
 
@@ -454,7 +456,8 @@ static lb_status lattice_pass(lb_ctx* c) {
     a.uout[k] = c->uref[k] + (c->p.comoving ? c->p.body_force[k] / c->p.rho0 : 0.0);
   }
   comoving_terms(c->scale, c->p.rho0, a.uin, a.uout, a.cm, a.cmf);
-  const bool timed = 2 * (size_t)c->ev_used + 1 < c->ev.size();
+  const bool timed =
+      2 * (size_t)c->ev_used + 1 < c->ev.size() && c->ev_seen++ % c->ev_stride == 0;
   if (timed) HIPCHK(c, hipEventRecord(c->ev[2 * c->ev_used], c->st));
   HIPCHK(c, launch_stream_collide(c->p.storage, c->p.comoving != 0, a, c->st));
   if (timed) HIPCHK(c, hipEventRecord(c->ev[2 * c->ev_used++ + 1], c->st));
@@ -879,11 +882,13 @@ static void free_events(lb_ctx* c) {
   for (auto e : c->ev) (void)hipEventDestroy(e);
   c->ev.clear();
   c->ev_used = 0;
+  c->ev_seen = 0;
 }
 
-lb_status lb_timing(lb_ctx* c, int32_t max_passes) {
+lb_status lb_timing(lb_ctx* c, int32_t max_passes, int32_t stride) {
   if (!c) return fail(nullptr, LB_EINVAL, "null context");
   if (max_passes < 0 || max_passes > (1 << 20)) return fail(c, LB_EINVAL, "invalid pass count");
+  if (stride < 1 || stride > (1 << 20)) return fail(c, LB_EINVAL, "invalid timing stride");
   HIPCHK(c, hipStreamSynchronize(c->st));
   free_events(c);
   for (int32_t k = 0; k < 2 * max_passes; ++k) {
@@ -891,6 +896,7 @@ lb_status lb_timing(lb_ctx* c, int32_t max_passes) {
     HIPCHK(c, hipEventCreate(&e));
     c->ev.push_back(e);
   }
+  c->ev_stride = stride;
   return LB_OK;
 }
 

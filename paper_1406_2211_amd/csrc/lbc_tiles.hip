@@ -4,24 +4,28 @@
 // Markers are binned into 8x8x8 lattice tiles by the cell containing them
 // (counting sort: count, single-block scan that also lists the occupied tiles
 // in increasing order, scatter).  Workgroups loop over the occupied tiles;
-// for each they work on a staged region of 12^3 sites: the tile and two sites
-// on each side.  That covers the 2-, 3- and 4-point stencils of every marker
-// binned into the tile, also after it has moved down by up to one lattice
-// spacing or up within its cell.  A marker whose stencil leaves the region
-// (it crossed the upper cell face or a periodic seam, or the binning is a few
-// steps old) takes the direct path that gathers from global memory.  The
-// markers of a tile are staged in LDS too, in chunks.
+// for each they work on a region of 13^3 sites: the tile, two sites below it
+// and three above.  That covers the 2-, 3- and 4-point stencils of every
+// marker binned into the tile, also after it has moved by up to one lattice
+// spacing in any direction since the binning (the 4-point stencil reaches one
+// node below the marker's cell and two above it).  A marker whose stencil
+// leaves the region (it moved further, or across a periodic seam) takes the
+// direct path that gathers from global memory.  The markers of a tile are
+// staged in LDS too, in chunks.
 //
-//   interpolation (Eq. IBM-interpolation): physical moments rho, u of every
-//   region site are computed once (pull gather + pending half force) into LDS
-//   in FP64; each marker then sums K^3 weighted LDS entries, one lane per
-//   x-row of stencil nodes and a butterfly reduction over the lane group.
+//   interpolation (Eq. IBM-interpolation): the region sites that some marker
+//   stencil covers are marked in an LDS bitmap and listed; their physical
+//   velocities u are computed once (pull gather + pending half force) into
+//   LDS (FP64 with FP64 storage, FP32 otherwise); each marker then sums K^3
+//   weighted LDS entries, one lane per z-plane of stencil nodes and a butterfly
+//   reduction over the lane group.
 //   spreading (Eq. IBM-spreading): markers add W F into an FP64 LDS
 //   accumulator of the region (LDS atomics, one lane per stencil site); the
 //   workgroup then adds every nonzero region site to the global force field
 //   once and flags it for the lattice pass.
-// Workgroups have 1024 lanes so that staging and flushing a region take two
-// rounds of loads with sixteen wavefronts in flight.
+// Interpolation workgroups have 256 lanes, so that nearly every tile of a
+// dense marker set is worked on at once; spreading workgroups have 1024 lanes
+// so that flushing a region takes few rounds of loads.
 #include <algorithm>
 
 #include "lbc_device.h"
@@ -31,7 +35,7 @@ namespace lbc {
 
 constexpr int kTile = 8;
 constexpr int kLo = 2;     // region starts two sites below the tile
-constexpr int kReg = 12;   // region edge: tile + 2 below + 2 above
+constexpr int kReg = 13;   // region edge: tile + 2 below + 3 above
 constexpr int kRegSites = kReg * kReg * kReg;
 
 __device__ __forceinline__ int tile_of(const TileArgs& t, const double X[3], int c[3]) {
@@ -192,41 +196,41 @@ __device__ __forceinline__ bool node_site(const Geo& g, const int j[3], int& x, 
 template <int S>
 struct TileT {
   using W = double;
-  using M4 = double4;
 };
 template <>
 struct TileT<LB_F32> {
   using W = float;
-  using M4 = float4;
 };
 template <>
 struct TileT<LB_F16> {
   using W = float;
-  using M4 = float4;
 };
 template <>
 struct TileT<LB_BF16> {
   using W = float;
-  using M4 = float4;
 };
 
-// Interpolation lane groups: one lane per x-row of stencil nodes (ky, kz),
-// K^2 rows rounded up to a power of two (4 lanes for K = 2, 16 for K = 3, 4).
+// Interpolation lane groups: one lane per z-plane of stencil nodes, K planes
+// rounded up to a power of two (2 lanes for K = 2, 4 for K = 3, 4), so that a
+// 256-lane workgroup interpolates 64 markers at once and the group reduction
+// takes one or two butterfly levels.
 template <int K>
 struct RowLanes {
-  static constexpr int L = K == 2 ? 4 : 16;
+  static constexpr int L = K == 2 ? 2 : 4;
 };
 
-// Weighted sum over the lane's row of K nodes of the region moments (or of
-// gathered moments when the stencil leaves the region), reduced over the
-// marker's lane group: u_p = sum_nodes W u(node), W = phi(x) phi(y) phi(z).
+// Weighted sum over the lane's plane of K x K nodes of the region moments (or
+// of gathered moments for a row with a node that was not staged), reduced
+// over the marker's lane group: u_p = sum_nodes W u(node),
+// W = phi(x) phi(y) phi(z).
 template <int S, int K>
 __device__ __forceinline__ void row_interp(const SiteArgs& s, const Region& r,
-                                           const typename TileT<S>::M4* mom, const double X[3],
-                                           int lane, double up[3]) {
+                                           const typename TileT<S>::W* mu,
+                                           const uint32_t* rowm, const double X[3], int lane,
+                                           double up[3]) {
   using W = typename TileT<S>::W;
   constexpr int L = RowLanes<K>::L;
-  const int ky = lane % K, kz = lane / K;
+  const int kz = lane;
   int j0[3];
   bool inside = true;
 #pragma unroll
@@ -235,35 +239,53 @@ __device__ __forceinline__ void row_interp(const SiteArgs& s, const Region& r,
     inside = inside && j0[a] - r.o[a] >= 0 && j0[a] - r.o[a] + K <= kReg;
   }
   W ux = 0, uy = 0, uz = 0;
-  if (lane < K * K) {
-    W wx[K];
+  if (kz < K) {
+    W wx[K], wy[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) wx[k] = phi_eval_t<W>(K, (W)((double)(j0[0] + k) - X[0]));
-    const W wy = phi_eval_t<W>(K, (W)((double)(j0[1] + ky) - X[1]));
+    for (int k = 0; k < K; ++k) {
+      wx[k] = phi_eval_t<W>(K, (W)((double)(j0[0] + k) - X[0]));
+      wy[k] = phi_eval_t<W>(K, (W)((double)(j0[1] + k) - X[1]));
+    }
     const W wz = phi_eval_t<W>(K, (W)((double)(j0[2] + kz) - X[2]));
-    if (inside) {
-      const typename TileT<S>::M4* row =
-          mom + ((j0[2] + kz - r.o[2]) * kReg + (j0[1] + ky - r.o[1])) * kReg + (j0[0] - r.o[0]);
+    constexpr uint32_t km = (1u << K) - 1u;
+    uint32_t miss = 0;  // rows with a node that was not staged
+#pragma unroll
+    for (int ky = 0; ky < K; ++ky) {
+      const int jy = j0[1] + ky;
+      if (s.g.wall && (jy < 0 || jy >= s.g.ny)) continue;  // beyond a wall: no node
+      bool staged = inside;  // the row's K nodes must all have been staged
+      if (staged) {
+        const uint32_t bits = rowm[(j0[2] + kz - r.o[2]) * kReg + (jy - r.o[1])];
+        staged = ((bits >> (j0[0] - r.o[0])) & km) == km;
+      }
+      if (!staged) {
+        miss |= 1u << ky;
+        continue;
+      }
+      const W* row = mu + ((j0[2] + kz - r.o[2]) * kReg + (jy - r.o[1])) * kReg + (j0[0] - r.o[0]);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const W Wt = wx[k] * wy * wz;
+        const W Wt = wx[k] * (wy[ky] * wz);
         if (Wt == W(0)) continue;
-        const typename TileT<S>::M4 m = row[k];
-        if (m.x == W(0)) continue;  // beyond a wall
-        ux += Wt * m.y;
-        uy += Wt * m.z;
-        uz += Wt * m.w;
+        ux += Wt * row[k];
+        uy += Wt * row[kRegSites + k];
+        uz += Wt * row[2 * kRegSites + k];
       }
-    } else {
+    }
+    // direct path (rare): gather the missing rows' nodes from global memory,
+    // weights recomputed so that no array is indexed at run time
+#pragma unroll 1
+    for (int ky = 0; miss != 0u && ky < K; ++ky) {
       const int jy = j0[1] + ky;
-      const bool in_y = !s.g.wall || (jy >= 0 && jy < s.g.ny);
-      for (int k = 0; k < K && in_y; ++k) {
-        const W Wt = wx[k] * wy * wz;
+      if (!((miss >> ky) & 1u)) continue;
+      const W wyz = phi_eval_t<W>(K, (W)((double)jy - X[1])) * wz;
+      const int y = s.g.wall ? jy : wrap_idx(jy, s.g.ny), z = wrap_idx(j0[2] + kz, s.g.nz);
+#pragma unroll 1
+      for (int k = 0; k < K; ++k) {
+        const W Wt = phi_eval_t<W>(K, (W)((double)(j0[0] + k) - X[0])) * wyz;
         if (Wt == W(0)) continue;
-        const int x = wrap_idx(j0[0] + k, s.g.nx), z = wrap_idx(j0[2] + kz, s.g.nz);
-        const int y = s.g.wall ? jy : wrap_idx(jy, s.g.ny);
         W drho, j[3];
-        site_phys_r<S, W>(s, x, y, z, drho, j);
+        site_phys_r<S, W>(s, wrap_idx(j0[0] + k, s.g.nx), y, z, drho, j);
         const W rr = W(s.rho0) + drho;
         ux += Wt * (j[0] / rr);
         uy += Wt * (j[1] / rr);
@@ -276,16 +298,65 @@ __device__ __forceinline__ void row_interp(const SiteArgs& s, const Region& r,
   up[2] = (double)group_sum_t<L, W>(uz);
 }
 
-// Markers of the tile being processed, staged in LDS in chunks of kChunk
+// Markers of the tile being processed, staged in LDS in chunks of C
 // (index and the positions and forces the kernel reads), so that the marker
 // loops never wait on dependent global loads.
-constexpr int kChunk = 256;
+// Interpolation workgroups are small (256 lanes) so that the occupied tiles
+// of a dense marker set are worked on nearly all at once: three are resident
+// per CU (registers; the staged velocities, one marker chunk and the staging
+// lists take 38 KB of LDS in FP32), and the grid holds four per CU so that
+// the last start as the first finish.  Capping the registers for four
+// resident workgroups spills and was measured slower.  Spreading keeps
+// 1024-lane workgroups, two per CU.
+constexpr int kInterpLanes = 256;
+constexpr int kInterpWgPerCu = 4;
+constexpr int kInterpChunk = 128;
+constexpr int kSpreadChunk = 256;
 
+template <int C>
 struct MarkerLds {
-  int p[kChunk];
-  double X[kChunk][3];  // position the stencil is built at
-  double Y[kChunk][3];  // second vector: pos (interpolation) or force (spreading)
+  static constexpr int kChunk = C;
+  int p[C];
+  double X[C][3];  // position the stencil is built at
+  double Y[C][3];  // second vector: pos (interpolation) or force (spreading)
 };
+
+// Which region slots the interpolation stages.  Only the slots inside some
+// marker's stencil are read, about a quarter of the region for markers on a
+// surface, so the workgroup first marks the stencils of its markers (at the
+// positions it knows, widened by kMarkDelta for the drifts of the pass) in a
+// bitmap with one kReg-bit x mask per (y, z) row, then lists the marked slots
+// and stages only those.  A stencil row with an unstaged node takes the
+// direct path, so the bitmap decides speed, not results.
+constexpr double kMarkDelta = 0.05;
+constexpr int kRows = kReg * kReg;
+constexpr int kListWaves = (kRegSites + 63) / 64;
+static_assert(kListWaves <= 64, "segment offsets are scanned by one wavefront");
+
+struct StageLds {
+  uint32_t rowm[kRows];         // x mask of marked slots per (y, z) row
+  int cnt[kListWaves];          // marked slots per 64-slot segment, then their offsets
+  unsigned short list[kRegSites];  // marked slots, increasing
+  int nlist;
+};
+
+// Mark the slots of the K-point stencils of X - d .. X + d (d = kMarkDelta
+// per axis), clipped to the region; g16 lanes cover the rows.
+template <int K>
+__device__ __forceinline__ void mark_stencil(const Region& r, const double X[3], uint32_t* rowm,
+                                             int g, int G) {
+  int lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = max(first_node<K>(X[a] - kMarkDelta) - r.o[a], 0);
+    hi[a] = min(first_node<K>(X[a] + kMarkDelta) + K - 1 - r.o[a], kReg - 1);
+  }
+  if (lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2]) return;
+  const uint32_t xb = ((1u << (hi[0] - lo[0] + 1)) - 1u) << lo[0];
+  const int ny = hi[1] - lo[1] + 1, nrow = ny * (hi[2] - lo[2] + 1);
+  for (int q = g; q < nrow; q += G)
+    atomicOr(rowm + (lo[2] + q / ny) * kReg + lo[1] + q % ny, xb);
+}
 
 // ------------------------------------------------------------- interpolation
 // mode 0: IB predictor       aux = wrap(pos + h/2 u(pos))
@@ -300,37 +371,111 @@ struct MarkerLds {
 // memory instead (same arithmetic per node).  Workgroups loop over the
 // occupied tiles (persistent grid).
 template <int S, int K>
-__global__ __launch_bounds__(1024) void k_tile_interp(TileArgs t, SiteArgs s, const double* at,
-                                                      double* pos, double* aux, int mode) {
+__global__ __launch_bounds__(kInterpLanes) void k_tile_interp(TileArgs t, SiteArgs s,
+                                                              const double* at, double* pos,
+                                                              double* aux, int mode) {
   constexpr int L = RowLanes<K>::L;
+  constexpr int G = 16;  // lanes per marker while marking
   using W = typename TileT<S>::W;
-  using M4 = typename TileT<S>::M4;
+  using MK = MarkerLds<kInterpChunk>;
+  constexpr int kChunk = MK::kChunk;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  M4* mom = (M4*)lds_raw;                                          // kRegSites
-  MarkerLds* mk = (MarkerLds*)(lds_raw + sizeof(M4) * kRegSites);  // one chunk
+  W* mu = (W*)lds_raw;                                                // 3 * kRegSites
+  MK* mk = (MK*)(lds_raw + sizeof(W) * 3 * kRegSites);                // one chunk
+  StageLds* sg = (StageLds*)(lds_raw + sizeof(W) * 3 * kRegSites + sizeof(MK));
   const int lane = threadIdx.x % L;
   const int nocc = t.nocc[0];
+  const bool two = mode == 1 || mode == 3;  // pos is read as well as at
+  auto load_chunk = [&](int c0, int nc) {
+    for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+      const int p = t.sorted[c0 + i];
+      mk->p[i] = p;
+      for (int a = 0; a < 3; ++a) {
+        mk->X[i][a] = at[3 * (long long)p + a];
+        mk->Y[i][a] = two ? pos[3 * (long long)p + a] : 0.0;
+      }
+    }
+  };
   for (int ot = blockIdx.x; ot < nocc; ot += gridDim.x) {
     const int tl = t.occ[ot];
     const Region r = region_of(t, tl);
-    for (int k = threadIdx.x; k < kRegSites; k += blockDim.x) {
+    const int b0 = t.start[tl], b1 = t.start[tl + 1];
+    // first marker chunk, and a cleared bitmap
+    load_chunk(b0, min(kChunk, b1 - b0));
+    for (int k = threadIdx.x; k < kRows; k += blockDim.x) sg->rowm[k] = 0u;
+    __syncthreads();
+    // mark the stencils the pass will read: at at and, where it is also
+    // interpolated from, at pos (mode 3: the final advection starts there)
+    for (int i = (int)threadIdx.x / G; i < b1 - b0; i += (int)blockDim.x / G) {
+      double X[3], Y[3];
+      if (i < kChunk) {
+        for (int a = 0; a < 3; ++a) {
+          X[a] = mk->X[i][a];
+          Y[a] = mk->Y[i][a];
+        }
+      } else {
+        const long long p = t.sorted[b0 + i];
+        for (int a = 0; a < 3; ++a) {
+          X[a] = at[3 * p + a];
+          Y[a] = two ? pos[3 * p + a] : 0.0;
+        }
+      }
+      mark_stencil<K>(r, X, sg->rowm, (int)threadIdx.x % G, G);
+      if (mode == 3) mark_stencil<K>(r, Y, sg->rowm, (int)threadIdx.x % G, G);
+    }
+    __syncthreads();
+    // list the marked slots in increasing order (wave ballots, then offsets)
+    const int wv = (int)threadIdx.x / 64;
+    for (int k0 = 0; k0 < kRegSites; k0 += (int)blockDim.x) {
+      const int seg = k0 / 64 + wv, k = k0 + (int)threadIdx.x;  // wave wv: slots 64 seg ..
+      if (seg >= kListWaves) continue;  // (uniform over the wave)
+      const bool on = k < kRegSites && ((sg->rowm[k / kReg] >> (k % kReg)) & 1u);
+      const uint64_t b = __ballot(on);
+      if (threadIdx.x % 64 == 0) sg->cnt[seg] = (int)__popcll(b);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {  // segment counts -> exclusive offsets (one wave)
+      const int l = (int)threadIdx.x, v = l < kListWaves ? sg->cnt[l] : 0;
+      int incl = v;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(incl, d, 64);
+        if (l >= d) incl += u;
+      }
+      if (l < kListWaves) sg->cnt[l] = incl - v;
+      if (l == 63) sg->nlist = incl;
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < kRegSites; k0 += (int)blockDim.x) {
+      const int seg = k0 / 64 + wv, k = k0 + (int)threadIdx.x;
+      if (seg >= kListWaves) continue;
+      const bool on = k < kRegSites && ((sg->rowm[k / kReg] >> (k % kReg)) & 1u);
+      const uint64_t b = __ballot(on);
+      const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+      if (on) sg->list[sg->cnt[seg] + below] = (unsigned short)k;
+    }
+    __syncthreads();
+    const int nlist = sg->nlist;
+    for (int i = threadIdx.x; i < nlist; i += blockDim.x) {
+      const int k = sg->list[i];
       const int ix = k % kReg, iy = (k / kReg) % kReg, iz = k / (kReg * kReg);
       int x, y, z;
-      M4 m;
-      m.x = m.y = m.z = m.w = W(0);
+      W u0 = W(0), u1 = W(0), u2 = W(0);  // beyond a wall: never read
       if (slot_site(s.g, r, ix, iy, iz, x, y, z)) {
         W drho, j[3];
         site_phys_r<S, W>(s, x, y, z, drho, j);
         const W rr = W(s.rho0) + drho;
-        m.x = rr;
-        m.y = j[0] / rr;
-        m.z = j[1] / rr;
-        m.w = j[2] / rr;
+        u0 = j[0] / rr;
+        u1 = j[1] / rr;
+        u2 = j[2] / rr;
       }
-      mom[k] = m;
+      mu[k] = u0;
+      mu[kRegSites + k] = u1;
+      mu[2 * kRegSites + k] = u2;
     }
     auto interp_at = [&](const double X[3], double up[3]) {
-      row_interp<S, K>(s, r, mom, X, lane, up);
+      row_interp<S, K>(s, r, mu, sg->rowm, X, lane, up);
     };
     auto half_drift = [&](const double from[3], const double u[3], double to[3]) {
       for (int a = 0; a < 3; ++a) to[a] = from[a] + 0.5 * u[a];
@@ -338,59 +483,53 @@ __global__ __launch_bounds__(1024) void k_tile_interp(TileArgs t, SiteArgs s, co
       if (!s.g.wall) to[1] = wrap_pos(to[1], (double)s.g.ny);
       to[2] = wrap_pos(to[2], (double)s.g.nz);
     };
-    const int b0 = t.start[tl], b1 = t.start[tl + 1];
     for (int c0 = b0; c0 < b1; c0 += kChunk) {
       const int nc = min(kChunk, b1 - c0);
-      __syncthreads();  // previous chunk (or region staging) done with mk
-      for (int i = threadIdx.x; i < nc; i += blockDim.x) {
-        const int p = t.sorted[c0 + i];
-        mk->p[i] = p;
-        for (int a = 0; a < 3; ++a) {
-          mk->X[i][a] = at[3 * (long long)p + a];
-          mk->Y[i][a] = (mode == 1 || mode == 3) ? pos[3 * (long long)p + a] : 0.0;
-        }
+      if (c0 != b0) {
+        __syncthreads();  // previous chunk done with mk
+        load_chunk(c0, nc);
       }
-      __syncthreads();
+      __syncthreads();  // staged moments (first chunk) or the new chunk ready
       for (int i = (int)threadIdx.x / L; i < nc; i += (int)blockDim.x / L) {  // groups leave together
         const long long p = mk->p[i];
         const double X[3] = {mk->X[i][0], mk->X[i][1], mk->X[i][2]};
-        double up[3], Y[3];
-        interp_at(X, up);
+        const double P[3] = {mk->Y[i][0], mk->Y[i][1], mk->Y[i][2]};
+        // Interpolation points in order (one call site, so the interpolation
+        // is compiled once): mode 0, 1: X; mode 2: X, then X~ = X + h/2 u(X);
+        // mode 3: X (= X~ of the previous step), then Xs = P + h/2 u(X), then
+        // X~ = Xs + h/2 u(Xs).  Xs is the point the last half drift starts from.
+        const int nint = mode == 3 ? 3 : (mode == 2 ? 2 : 1);
+        double q[3] = {X[0], X[1], X[2]}, Xs[3] = {X[0], X[1], X[2]}, u[3], Y[3];
+#pragma unroll 1
+        for (int it = 0; it < nint; ++it) {
+          interp_at(q, u);
+          if (it + 1 == nint) break;
+          if (mode == 3 && it == 0) {
+            half_drift(P, u, Xs);
+            for (int a = 0; a < 3; ++a) q[a] = Xs[a];
+          } else {
+            half_drift(Xs, u, q);
+          }
+        }
         if (mode == 0) {  // predictor only
-          half_drift(X, up, Y);
+          half_drift(X, u, Y);
           if (lane == 0)
             for (int a = 0; a < 3; ++a) aux[3 * p + a] = Y[a];
         } else if (mode == 1) {  // advection with the velocity at X~ = at
-          const double P[3] = {mk->Y[i][0], mk->Y[i][1], mk->Y[i][2]};
-          half_drift(P, up, Y);
+          half_drift(P, u, Y);
           if (lane == 0)
             for (int a = 0; a < 3; ++a) pos[3 * p + a] = Y[a];
-        } else {
-          // mode 2: predictor, then the first advection from the same staged
-          // state; mode 3: first the final advection of the previous step
-          double Xs[3], Xt[3], u0[3], u2[3];
-          if (mode == 3) {
-            const double P[3] = {mk->Y[i][0], mk->Y[i][1], mk->Y[i][2]};
-            half_drift(P, up, Xs);
-            interp_at(Xs, u0);
-          } else {
-            for (int a = 0; a < 3; ++a) {
-              Xs[a] = X[a];
-              u0[a] = up[a];
-            }
-          }
-          half_drift(Xs, u0, Xt);
-          interp_at(Xt, u2);
-          half_drift(Xs, u2, Y);
+        } else {  // X~ = q, and X <- Xs + h/2 u(X~)
+          half_drift(Xs, u, Y);
           if (lane == 0)
             for (int a = 0; a < 3; ++a) {
-              aux[3 * p + a] = Xt[a];
+              aux[3 * p + a] = q[a];
               pos[3 * p + a] = Y[a];
             }
         }
       }
     }
-    __syncthreads();  // region moments are overwritten by the next tile
+    __syncthreads();  // region moments and bitmap are overwritten by the next tile
   }
 }
 
@@ -402,8 +541,10 @@ __global__ __launch_bounds__(1024) void k_tile_spread(TileArgs t, const double* 
                                                       const double* F, void* field) {
   constexpr int L = Lanes<K>::L;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  MarkerLds* mk = (MarkerLds*)lds_raw;                     // one chunk
-  double* acc = (double*)(lds_raw + sizeof(MarkerLds));    // 3 * kRegSites
+  using MK = MarkerLds<kSpreadChunk>;
+  constexpr int kChunk = MK::kChunk;
+  MK* mk = (MK*)lds_raw;                                   // one chunk
+  double* acc = (double*)(lds_raw + sizeof(MK));           // 3 * kRegSites
   E* Fd = (E*)field;
   const int lane = threadIdx.x % L;
   const int nocc = t.nocc[0];
@@ -477,7 +618,7 @@ hipError_t launch_bin(const TileArgs& t, const double* pos, long long n, hipStre
 
 // Persistent grid over the occupied tiles (their number is only known on the
 // device): two 1024-lane workgroups per CU, at most one per tile.
-static unsigned tile_grid(const TileArgs& t) {
+static unsigned tile_grid(const TileArgs& t, int per_cu) {
   static int cus = 0;
   if (cus == 0) {
     int dev = 0;
@@ -486,7 +627,7 @@ static unsigned tile_grid(const TileArgs& t) {
               ? prop.multiProcessorCount
               : 256;
   }
-  return (unsigned)std::min(t.ntiles, 2 * cus);
+  return (unsigned)std::min(t.ntiles, per_cu * cus);
 }
 
 #define LBC_TILE_K_SWITCH(K, CALL)                        \
@@ -508,19 +649,21 @@ hipError_t launch_tile_interp(int storage, int K, const TileArgs& t, const SiteA
                               hipStream_t st) {
   if (n <= 0) return hipSuccess;
   LBC_TILE_K_SWITCH(K, LBC_TILE_S_SWITCH(storage, (k_tile_interp<SS, KK>
-      <<<tile_grid(t), 1024, sizeof(typename TileT<SS>::M4) * kRegSites + sizeof(MarkerLds), st>>>(
-          t, s, at, pos, aux, mode))));
+      <<<tile_grid(t, kInterpWgPerCu), kInterpLanes,
+         sizeof(typename TileT<SS>::W) * 3 * kRegSites + sizeof(MarkerLds<kInterpChunk>) +
+             sizeof(StageLds), st>>>(t, s, at, pos, aux, mode))));
   return hipGetLastError();
 }
 
 hipError_t launch_tile_spread(int storage, int K, const TileArgs& t, const double* at,
                               const double* F, void* field, long long n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const size_t lds = sizeof(MarkerLds) + sizeof(double) * 3 * kRegSites;
+  const size_t lds = sizeof(MarkerLds<kSpreadChunk>) + sizeof(double) * 3 * kRegSites;
+  const unsigned gr = tile_grid(t, 2);
   if (storage == LB_F64) {
-    LBC_TILE_K_SWITCH(K, (k_tile_spread<double, KK><<<tile_grid(t), 1024, lds, st>>>(t, at, F, field)));
+    LBC_TILE_K_SWITCH(K, (k_tile_spread<double, KK><<<gr, 1024, lds, st>>>(t, at, F, field)));
   } else {
-    LBC_TILE_K_SWITCH(K, (k_tile_spread<float, KK><<<tile_grid(t), 1024, lds, st>>>(t, at, F, field)));
+    LBC_TILE_K_SWITCH(K, (k_tile_spread<float, KK><<<gr, 1024, lds, st>>>(t, at, F, field)));
   }
   return hipGetLastError();
 }

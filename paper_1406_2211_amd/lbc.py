@@ -90,7 +90,7 @@ def load():
         "lb_stress": (i32, [vp, vp]),
         "lb_get_particles": (i32, [vp, vp, vp]),
         "lb_totals": (i32, [vp, C.POINTER(dbl)]),
-        "lb_timing": (i32, [vp, i32]),
+        "lb_timing": (i32, [vp, i32, i32]),
         "lb_timing_read": (i32, [vp, C.POINTER(dbl), C.POINTER(i64)]),
         "lb_info": (i32, [vp, C.POINTER(i64), C.POINTER(i64)]),
         "lb_destroy": (i32, [vp]),
@@ -264,8 +264,8 @@ class Lattice:
         self._call("lb_totals", out)
         return np.array(out[:])
 
-    def lb_timing(self, max_passes):
-        self._call("lb_timing", int(max_passes))
+    def lb_timing(self, max_passes, stride=1):
+        self._call("lb_timing", int(max_passes), int(stride))
 
     def lb_timing_read(self):
         ms, n = C.c_double(), C.c_int64()

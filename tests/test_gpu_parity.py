@@ -245,3 +245,29 @@ def test_ib_markers_crossing_tiles_and_seam(kernel):
              fext=(1e-6, 0.0, -1e-6))
     c.extra["u0"] = u0
     check(c, TOL64)
+
+
+def test_timing_stride_counts_timed_passes():
+    """Timing brackets the first lattice pass and then one in every `stride`,
+    up to the number of event pairs armed; the stepping itself is unchanged
+    (the timed and untimed runs give bit-identical states)."""
+    from paper_1406_2211_amd import lbc as L
+    import torch
+    res = []
+    for stride in (1, 3, 8):
+        lat = L.Lattice(16, 16, 16, tau=0.8, storage=L.LB_F32, body_force=(1e-5, 0.0, 2e-6))
+        lat.lb_init_fluid()
+        lat.lb_timing(100, stride)
+        lat.lb_step(20)
+        ms, n = lat.lb_timing_read()
+        assert n == (20 + stride - 1) // stride and ms > 0.0
+        lat.lb_timing(2, stride)
+        lat.lb_step(20)
+        _, n2 = lat.lb_timing_read()
+        assert n2 == 2
+        res.append(lat.lb_populations().cpu().numpy())
+        with pytest.raises(L.LbcError):
+            lat.lb_timing(1, 0)
+        lat.lb_destroy()
+    torch.cuda.synchronize()
+    assert np.array_equal(res[0], res[1]) and np.array_equal(res[0], res[2])
