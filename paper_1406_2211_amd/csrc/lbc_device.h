@@ -319,6 +319,48 @@ __device__ __forceinline__ void site_phys_r(const SiteArgs& a, int x, int y, int
   j[2] += R(0.5) * ((R)fb.z + (R)a.pfz);
 }
 
+// site_phys_r with the populations loaded one after another (a rolled loop):
+// the same operations in the same order, for a rarely taken path whose 19
+// loads in flight would otherwise set the register budget of a whole kernel.
+template <int S, typename R>
+__device__ __forceinline__ void site_phys_r_seq(const SiteArgs& a, int x, int y, int z, R& drho,
+                                                R j[3]) {
+  using St = Store<S>;
+  using V4 = typename St::V4;
+  const typename St::T* __restrict__ f = (const typename St::T*)a.f;
+  const Geo& g = a.g;
+  const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+  const long long own = site_index(g, x, y, z);
+  const bool ref = a.uref[0] != 0.0 || a.uref[1] != 0.0 || a.uref[2] != 0.0;
+  drho = 0;
+  j[0] = j[1] = j[2] = 0;
+#pragma unroll 1
+  for (int i = 0; i < Q; ++i) {
+    long long src;
+    const bool bb = g.wall && ((CY[i] == 1 && y == 0) || (CY[i] == -1 && y == g.ny - 1));
+    if (bb) {
+      src = (long long)OPP[i] * g.ps + own;
+    } else {
+      const int xs = CX[i] == 1 ? xm : (CX[i] == -1 ? xp : x);
+      const int ys = CY[i] == 1 ? ym : (CY[i] == -1 ? yp : y);
+      const int zs = CZ[i] == 1 ? zm : (CZ[i] == -1 ? zp : z);
+      src = (long long)i * g.ps + site_index(g, xs, ys, zs);
+    }
+    R fl = St::ld(f + src, (R)a.inv);
+    if (ref) fl += eref<R>(i, (R)a.rho0, (R)a.uref[0], (R)a.uref[1], (R)a.uref[2]);
+    drho += fl;
+    if (CX[i]) j[0] += R(CX[i]) * fl;
+    if (CY[i]) j[1] += R(CY[i]) * fl;
+    if (CZ[i]) j[2] += R(CZ[i]) * fl;
+  }
+  const V4 fb = ((const V4*)a.FB)[own];
+  j[0] += R(0.5) * ((R)fb.x + (R)a.pfx);
+  j[1] += R(0.5) * ((R)fb.y + (R)a.pfy);
+  j[2] += R(0.5) * ((R)fb.z + (R)a.pfz);
+}
+
 // deviation equilibrium f^eq_i(rho,u) - w_i rho0 = w_i [drho + rho P_i(u)],
 // P_i(u) = 3 c.u + 9/2 (c.u)^2 - 3/2 u.u
 template <typename R>

@@ -19,13 +19,13 @@
 //   LDS (FP64 with FP64 storage, FP32 otherwise); each marker then sums K^3
 //   weighted LDS entries, one lane per z-plane of stencil nodes and a butterfly
 //   reduction over the lane group.
-//   spreading (Eq. IBM-spreading): markers add W F into an FP64 LDS
-//   accumulator of the region (LDS atomics, one lane per stencil site); the
-//   workgroup then adds every nonzero region site to the global force field
-//   once and flags it for the lattice pass.
-// Interpolation workgroups have 256 lanes, so that nearly every tile of a
-// dense marker set is worked on at once; spreading workgroups have 1024 lanes
-// so that flushing a region takes few rounds of loads.
+//   spreading (Eq. IBM-spreading): the stencil sites are listed the same way;
+//   markers add W F into an FP64 LDS accumulator of the listed sites (LDS
+//   atomics, one lane per z-plane of stencil nodes); the workgroup then adds
+//   every nonzero listed site to the global force field once and flags it for
+//   the lattice pass.
+// Workgroups have 256 lanes, four per CU in the grid, so that nearly every
+// tile of a dense marker set is worked on at once.
 #include <algorithm>
 
 #include "lbc_device.h"
@@ -147,39 +147,6 @@ __device__ __forceinline__ bool slot_site(const Geo& g, const Region& r, int ix,
   return true;
 }
 
-// One lane of a marker's lane group: stencil node (kx, ky, kz) = lane
-// (x fastest) of the K-point stencil whose first node is j0 (Appendix A
-// kernels), its weight (evaluated in T), and the node's region slot.
-template <int K>
-struct Node {
-  bool on;       // lane carries a node of nonzero weight
-  bool inside;   // the whole stencil lies in the staged region (same for the group)
-  double W;
-  int j[3];      // unwrapped node coordinates
-  int slot;      // region slot (when inside)
-};
-
-template <int K, typename T>
-__device__ __forceinline__ Node<K> node_of(const Region& r, const double X[3], int lane) {
-  Node<K> n;
-  const int k[3] = {lane % K, (lane / K) % K, lane / (K * K)};
-  n.inside = true;
-  T w = T(1);
-  int rel[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int j0 = first_node<K>(X[a]);
-    n.inside = n.inside && j0 - r.o[a] >= 0 && j0 - r.o[a] + K <= kReg;
-    n.j[a] = j0 + k[a];
-    rel[a] = n.j[a] - r.o[a];
-    w *= phi_eval_t<T>(K, (T)((double)n.j[a] - X[a]));
-  }
-  n.W = (double)w;
-  n.on = lane < K * K * K && n.W != 0.0;
-  n.slot = (rel[2] * kReg + rel[1]) * kReg + rel[0];
-  return n;
-}
-
 // Wrapped site of a node; false beyond a wall.
 __device__ __forceinline__ bool node_site(const Geo& g, const int j[3], int& x, int& y, int& z) {
   x = wrap_idx(j[0], g.nx);
@@ -285,7 +252,7 @@ __device__ __forceinline__ void row_interp(const SiteArgs& s, const Region& r,
         const W Wt = phi_eval_t<W>(K, (W)((double)(j0[0] + k) - X[0])) * wyz;
         if (Wt == W(0)) continue;
         W drho, j[3];
-        site_phys_r<S, W>(s, wrap_idx(j0[0] + k, s.g.nx), y, z, drho, j);
+        site_phys_r_seq<S, W>(s, wrap_idx(j0[0] + k, s.g.nx), y, z, drho, j);
         const W rr = W(s.rho0) + drho;
         ux += Wt * (j[0] / rr);
         uy += Wt * (j[1] / rr);
@@ -298,21 +265,23 @@ __device__ __forceinline__ void row_interp(const SiteArgs& s, const Region& r,
   up[2] = (double)group_sum_t<L, W>(uz);
 }
 
-// Markers of the tile being processed, staged in LDS in chunks of C
-// (index and the positions and forces the kernel reads), so that the marker
-// loops never wait on dependent global loads.
-// Interpolation workgroups are small (256 lanes) so that the occupied tiles
-// of a dense marker set are worked on nearly all at once: three are resident
-// per CU (registers; the staged velocities, one marker chunk and the staging
-// lists take 38 KB of LDS in FP32), and the grid holds four per CU so that
-// the last start as the first finish.  Capping the registers for four
-// resident workgroups spills and was measured slower.  Spreading keeps
-// 1024-lane workgroups, two per CU.
+// Interpolation and spreading workgroups are small (256 lanes) so that the
+// occupied tiles of a dense marker set are worked on nearly all at once: the
+// grid holds four per CU.  In FP32 four interpolation workgroups are resident
+// per CU (128 registers, which the rolled direct-path gather keeps within
+// reach; the staged velocities, one marker chunk and the staging lists take
+// 38 KB of LDS) and three spreading ones (40 KB of LDS each).
 constexpr int kInterpLanes = 256;
 constexpr int kInterpWgPerCu = 4;
 constexpr int kInterpChunk = 128;
-constexpr int kSpreadChunk = 256;
+constexpr int kSpreadLanes = 256;
+constexpr int kSpreadWgPerCu = 4;
+constexpr int kSpreadChunk = 128;
+constexpr int kSpreadCap = 1024;  // accumulated sites per tile
 
+// Markers of the tile being processed, staged in LDS in chunks of C
+// (index and the positions and forces the kernel reads), so that the marker
+// loops never wait on dependent global loads.
 template <int C>
 struct MarkerLds {
   static constexpr int kChunk = C;
@@ -340,22 +309,65 @@ struct StageLds {
   int nlist;
 };
 
-// Mark the slots of the K-point stencils of X - d .. X + d (d = kMarkDelta
-// per axis), clipped to the region; g16 lanes cover the rows.
+// Mark the slots of the K-point stencils of X - d .. X + d (per axis),
+// clipped to the region; lanes g of a group of G cover the rows.
 template <int K>
-__device__ __forceinline__ void mark_stencil(const Region& r, const double X[3], uint32_t* rowm,
-                                             int g, int G) {
+__device__ __forceinline__ void mark_stencil(const Region& r, const double X[3], double d,
+                                             uint32_t* rowm, int g, int G) {
   int lo[3], hi[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    lo[a] = max(first_node<K>(X[a] - kMarkDelta) - r.o[a], 0);
-    hi[a] = min(first_node<K>(X[a] + kMarkDelta) + K - 1 - r.o[a], kReg - 1);
+    lo[a] = max(first_node<K>(X[a] - d) - r.o[a], 0);
+    hi[a] = min(first_node<K>(X[a] + d) + K - 1 - r.o[a], kReg - 1);
   }
   if (lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2]) return;
   const uint32_t xb = ((1u << (hi[0] - lo[0] + 1)) - 1u) << lo[0];
   const int ny = hi[1] - lo[1] + 1, nrow = ny * (hi[2] - lo[2] + 1);
   for (int q = g; q < nrow; q += G)
     atomicOr(rowm + (lo[2] + q / ny) * kReg + lo[1] + q % ny, xb);
+}
+
+// List the slots marked in sg->rowm in increasing order: per 64-slot segment
+// a wave ballot counts them, one wavefront scans the counts into offsets, and
+// every marked slot writes itself at its offset plus its rank in the ballot.
+// idx (optional) receives each listed slot's list position.  Called after a
+// barrier that follows the marking; ends with a barrier.
+__device__ __forceinline__ void list_marked(StageLds* sg, unsigned short* idx) {
+  const int wv = (int)threadIdx.x / 64;
+  for (int k0 = 0; k0 < kRegSites; k0 += (int)blockDim.x) {
+    const int seg = k0 / 64 + wv, k = k0 + (int)threadIdx.x;  // wave wv: slots 64 seg ..
+    if (seg >= kListWaves) continue;  // (uniform over the wave)
+    const bool on = k < kRegSites && ((sg->rowm[k / kReg] >> (k % kReg)) & 1u);
+    const uint64_t b = __ballot(on);
+    if (threadIdx.x % 64 == 0) sg->cnt[seg] = (int)__popcll(b);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {  // segment counts -> exclusive offsets (one wave)
+    const int l = (int)threadIdx.x, v = l < kListWaves ? sg->cnt[l] : 0;
+    int incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int u = __shfl_up(incl, d, 64);
+      if (l >= d) incl += u;
+    }
+    if (l < kListWaves) sg->cnt[l] = incl - v;
+    if (l == 63) sg->nlist = incl;
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < kRegSites; k0 += (int)blockDim.x) {
+    const int seg = k0 / 64 + wv, k = k0 + (int)threadIdx.x;
+    if (seg >= kListWaves) continue;
+    const bool on = k < kRegSites && ((sg->rowm[k / kReg] >> (k % kReg)) & 1u);
+    const uint64_t b = __ballot(on);
+    const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+    if (on) {
+      const int at = sg->cnt[seg] + below;
+      sg->list[at] = (unsigned short)k;
+      if (idx) idx[k] = (unsigned short)at;
+    }
+  }
+  __syncthreads();
 }
 
 // ------------------------------------------------------------- interpolation
@@ -420,42 +432,11 @@ __global__ __launch_bounds__(kInterpLanes) void k_tile_interp(TileArgs t, SiteAr
           Y[a] = two ? pos[3 * p + a] : 0.0;
         }
       }
-      mark_stencil<K>(r, X, sg->rowm, (int)threadIdx.x % G, G);
-      if (mode == 3) mark_stencil<K>(r, Y, sg->rowm, (int)threadIdx.x % G, G);
+      mark_stencil<K>(r, X, kMarkDelta, sg->rowm, (int)threadIdx.x % G, G);
+      if (mode == 3) mark_stencil<K>(r, Y, kMarkDelta, sg->rowm, (int)threadIdx.x % G, G);
     }
     __syncthreads();
-    // list the marked slots in increasing order (wave ballots, then offsets)
-    const int wv = (int)threadIdx.x / 64;
-    for (int k0 = 0; k0 < kRegSites; k0 += (int)blockDim.x) {
-      const int seg = k0 / 64 + wv, k = k0 + (int)threadIdx.x;  // wave wv: slots 64 seg ..
-      if (seg >= kListWaves) continue;  // (uniform over the wave)
-      const bool on = k < kRegSites && ((sg->rowm[k / kReg] >> (k % kReg)) & 1u);
-      const uint64_t b = __ballot(on);
-      if (threadIdx.x % 64 == 0) sg->cnt[seg] = (int)__popcll(b);
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {  // segment counts -> exclusive offsets (one wave)
-      const int l = (int)threadIdx.x, v = l < kListWaves ? sg->cnt[l] : 0;
-      int incl = v;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const int u = __shfl_up(incl, d, 64);
-        if (l >= d) incl += u;
-      }
-      if (l < kListWaves) sg->cnt[l] = incl - v;
-      if (l == 63) sg->nlist = incl;
-    }
-    __syncthreads();
-    for (int k0 = 0; k0 < kRegSites; k0 += (int)blockDim.x) {
-      const int seg = k0 / 64 + wv, k = k0 + (int)threadIdx.x;
-      if (seg >= kListWaves) continue;
-      const bool on = k < kRegSites && ((sg->rowm[k / kReg] >> (k % kReg)) & 1u);
-      const uint64_t b = __ballot(on);
-      const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
-                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-      if (on) sg->list[sg->cnt[seg] + below] = (unsigned short)k;
-    }
-    __syncthreads();
+    list_marked(sg, nullptr);
     const int nlist = sg->nlist;
     for (int i = threadIdx.x; i < nlist; i += blockDim.x) {
       const int k = sg->list[i];
@@ -534,64 +515,125 @@ __global__ __launch_bounds__(kInterpLanes) void k_tile_interp(TileArgs t, SiteAr
 }
 
 // ------------------------------------------------------------------ spreading
-// The region accumulator is FP64 whatever the field precision: LDS atomic
-// adds run several times faster in FP64 than in FP32 on this device.
+// The accumulator is FP64 whatever the field precision: LDS atomic adds run
+// several times faster in FP64 than in FP32 on this device.  It holds only
+// the region sites the tile's stencils cover (listed as in the
+// interpolation, at most kSpreadCap of them; a node listed beyond that adds
+// to the global field directly), so that the workgroup's LDS stays small.
+// Global adds go through atomics: the regions of neighbouring tiles overlap.
 template <typename E, int K>
-__global__ __launch_bounds__(1024) void k_tile_spread(TileArgs t, const double* at,
-                                                      const double* F, void* field) {
-  constexpr int L = Lanes<K>::L;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
+__global__ __launch_bounds__(kSpreadLanes) void k_tile_spread(TileArgs t, const double* at,
+                                                              const double* F, void* field) {
+  constexpr int L = RowLanes<K>::L;
+  constexpr int G = 16;  // lanes per marker while marking
   using MK = MarkerLds<kSpreadChunk>;
   constexpr int kChunk = MK::kChunk;
-  MK* mk = (MK*)lds_raw;                                   // one chunk
-  double* acc = (double*)(lds_raw + sizeof(MK));           // 3 * kRegSites
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double* acc = (double*)lds_raw;                                    // 3 * kSpreadCap
+  MK* mk = (MK*)(lds_raw + sizeof(double) * 3 * kSpreadCap);        // one chunk
+  StageLds* sg = (StageLds*)((unsigned char*)mk + sizeof(MK));
+  unsigned short* idx = (unsigned short*)((unsigned char*)sg + sizeof(StageLds));  // kRegSites
   E* Fd = (E*)field;
   const int lane = threadIdx.x % L;
   const int nocc = t.nocc[0];
+  auto load_chunk = [&](int c0, int nc) {
+    for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+      const int p = t.sorted[c0 + i];
+      mk->p[i] = p;
+      for (int a = 0; a < 3; ++a) {
+        mk->X[i][a] = at[3 * (long long)p + a];
+        mk->Y[i][a] = F[3 * (long long)p + a];
+      }
+    }
+  };
+  auto global_add = [&](int jx, int jy, int jz, double f0, double f1, double f2) {
+    const int j[3] = {jx, jy, jz};
+    int x, y, z;
+    if (!node_site(t.g, j, x, y, z)) return;  // beyond a wall
+    const long long sidx = site_index(t.g, x, y, z);
+    unsafeAtomicAdd(Fd + 4 * sidx + 0, (E)f0);
+    unsafeAtomicAdd(Fd + 4 * sidx + 1, (E)f1);
+    unsafeAtomicAdd(Fd + 4 * sidx + 2, (E)f2);
+    uint64_t bit;
+    flag_site(mask_word(t.mask, t.g, x, y, z, bit), bit);
+  };
   for (int ot = blockIdx.x; ot < nocc; ot += gridDim.x) {
     const int tl = t.occ[ot];
     const Region r = region_of(t, tl);
-    for (int k = threadIdx.x; k < 3 * kRegSites; k += blockDim.x) acc[k] = 0.0;
     const int b0 = t.start[tl], b1 = t.start[tl + 1];
+    load_chunk(b0, min(kChunk, b1 - b0));
+    for (int k = threadIdx.x; k < kRows; k += blockDim.x) sg->rowm[k] = 0u;
+    __syncthreads();
+    for (int i = (int)threadIdx.x / G; i < b1 - b0; i += (int)blockDim.x / G) {
+      double X[3];
+      if (i < kChunk) {
+        for (int a = 0; a < 3; ++a) X[a] = mk->X[i][a];
+      } else {
+        const long long p = t.sorted[b0 + i];
+        for (int a = 0; a < 3; ++a) X[a] = at[3 * p + a];
+      }
+      mark_stencil<K>(r, X, 0.0, sg->rowm, (int)threadIdx.x % G, G);
+    }
+    __syncthreads();
+    list_marked(sg, idx);
+    const int nacc = min(sg->nlist, kSpreadCap);
+    for (int k = threadIdx.x; k < 3 * nacc; k += blockDim.x) acc[k] = 0.0;
     for (int c0 = b0; c0 < b1; c0 += kChunk) {
       const int nc = min(kChunk, b1 - c0);
-      __syncthreads();  // previous chunk done with mk (and acc cleared)
-      for (int i = threadIdx.x; i < nc; i += blockDim.x) {
-        const int p = t.sorted[c0 + i];
-        mk->p[i] = p;
-        for (int a = 0; a < 3; ++a) {
-          mk->X[i][a] = at[3 * (long long)p + a];
-          mk->Y[i][a] = F[3 * (long long)p + a];
-        }
+      if (c0 != b0) {
+        __syncthreads();  // previous chunk done with mk
+        load_chunk(c0, nc);
       }
-      __syncthreads();
+      __syncthreads();  // accumulator cleared (first chunk) or the new chunk ready
       for (int i = (int)threadIdx.x / L; i < nc; i += (int)blockDim.x / L) {
+        const int kz = lane;
+        if (kz >= K) continue;
         const double X[3] = {mk->X[i][0], mk->X[i][1], mk->X[i][2]};
-        const Node<K> n = node_of<K, E>(r, X, lane);  // weights in the field precision
-        if (!n.on) continue;
-        if (t.g.wall && (n.j[1] < 0 || n.j[1] >= t.g.ny)) continue;  // beyond a wall
-        const double f0 = n.W * mk->Y[i][0], f1 = n.W * mk->Y[i][1], f2 = n.W * mk->Y[i][2];
-        if (n.inside) {
-          double* a = acc + 3 * n.slot;
-          atomicAdd(a + 0, f0);
-          atomicAdd(a + 1, f1);
-          atomicAdd(a + 2, f2);
-        } else {
-          int x, y, z;
-          node_site(t.g, n.j, x, y, z);
-          const long long sidx = site_index(t.g, x, y, z);
-          unsafeAtomicAdd(Fd + 4 * sidx + 0, (E)f0);
-          unsafeAtomicAdd(Fd + 4 * sidx + 1, (E)f1);
-          unsafeAtomicAdd(Fd + 4 * sidx + 2, (E)f2);
-          uint64_t bit;
-          flag_site(mask_word(t.mask, t.g, x, y, z, bit), bit);
+        const double Fp[3] = {mk->Y[i][0], mk->Y[i][1], mk->Y[i][2]};
+        int j0[3];
+        bool inside = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          j0[a] = first_node<K>(X[a]);
+          inside = inside && j0[a] - r.o[a] >= 0 && j0[a] - r.o[a] + K <= kReg;
+        }
+        E wx[K], wy[K];  // weights in the field precision
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          wx[k] = phi_eval_t<E>(K, (E)((double)(j0[0] + k) - X[0]));
+          wy[k] = phi_eval_t<E>(K, (E)((double)(j0[1] + k) - X[1]));
+        }
+        const E wz = phi_eval_t<E>(K, (E)((double)(j0[2] + kz) - X[2]));
+#pragma unroll
+        for (int ky = 0; ky < K; ++ky) {
+          const int jy = j0[1] + ky;
+          if (t.g.wall && (jy < 0 || jy >= t.g.ny)) continue;  // beyond a wall
+          const int rowslot = inside ? ((j0[2] + kz - r.o[2]) * kReg + (jy - r.o[1])) * kReg +
+                                           (j0[0] - r.o[0])
+                                     : 0;
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const double W = (double)(wx[k] * wy[ky] * wz);
+            if (W == 0.0) continue;
+            const double f0 = W * Fp[0], f1 = W * Fp[1], f2 = W * Fp[2];
+            const int q = inside ? (int)idx[rowslot + k] : kSpreadCap;
+            if (q < kSpreadCap) {
+              double* a = acc + 3 * q;
+              atomicAdd(a + 0, f0);
+              atomicAdd(a + 1, f1);
+              atomicAdd(a + 2, f2);
+            } else {
+              global_add(j0[0] + k, jy, j0[2] + kz, f0, f1, f2);
+            }
+          }
         }
       }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < kRegSites; k += blockDim.x) {
-      const E a0 = (E)acc[3 * k], a1 = (E)acc[3 * k + 1], a2 = (E)acc[3 * k + 2];
+    for (int q = threadIdx.x; q < nacc; q += blockDim.x) {
+      const E a0 = (E)acc[3 * q], a1 = (E)acc[3 * q + 1], a2 = (E)acc[3 * q + 2];
       if (a0 == E(0) && a1 == E(0) && a2 == E(0)) continue;
+      const int k = sg->list[q];
       const int ix = k % kReg, iy = (k / kReg) % kReg, iz = k / (kReg * kReg);
       int x, y, z;
       if (!slot_site(t.g, r, ix, iy, iz, x, y, z)) continue;
@@ -602,7 +644,7 @@ __global__ __launch_bounds__(1024) void k_tile_spread(TileArgs t, const double* 
       uint64_t bit;
       flag_site(mask_word(t.mask, t.g, x, y, z, bit), bit);
     }
-    __syncthreads();  // acc is cleared for the next tile
+    __syncthreads();  // accumulator, lists and chunk are reused by the next tile
   }
 }
 
@@ -617,7 +659,7 @@ hipError_t launch_bin(const TileArgs& t, const double* pos, long long n, hipStre
 }
 
 // Persistent grid over the occupied tiles (their number is only known on the
-// device): two 1024-lane workgroups per CU, at most one per tile.
+// device): per_cu workgroups per CU, at most one per tile.
 static unsigned tile_grid(const TileArgs& t, int per_cu) {
   static int cus = 0;
   if (cus == 0) {
@@ -658,12 +700,13 @@ hipError_t launch_tile_interp(int storage, int K, const TileArgs& t, const SiteA
 hipError_t launch_tile_spread(int storage, int K, const TileArgs& t, const double* at,
                               const double* F, void* field, long long n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const size_t lds = sizeof(MarkerLds<kSpreadChunk>) + sizeof(double) * 3 * kRegSites;
-  const unsigned gr = tile_grid(t, 2);
+  const size_t lds = sizeof(double) * 3 * kSpreadCap + sizeof(MarkerLds<kSpreadChunk>) +
+                     sizeof(StageLds) + sizeof(unsigned short) * kRegSites;
+  const unsigned gr = tile_grid(t, kSpreadWgPerCu);
   if (storage == LB_F64) {
-    LBC_TILE_K_SWITCH(K, (k_tile_spread<double, KK><<<gr, 1024, lds, st>>>(t, at, F, field)));
+    LBC_TILE_K_SWITCH(K, (k_tile_spread<double, KK><<<gr, kSpreadLanes, lds, st>>>(t, at, F, field)));
   } else {
-    LBC_TILE_K_SWITCH(K, (k_tile_spread<float, KK><<<gr, 1024, lds, st>>>(t, at, F, field)));
+    LBC_TILE_K_SWITCH(K, (k_tile_spread<float, KK><<<gr, kSpreadLanes, lds, st>>>(t, at, F, field)));
   }
   return hipGetLastError();
 }
