@@ -763,6 +763,100 @@ __device__ __forceinline__ void sym4_eig_max(double A[4][4], double q[4]) {
     }
 }
 
+// Dominant eigenvector of Horn's traceless symmetric 4x4 matrix A without an
+// iterative eigen-solve: the largest root of the characteristic polynomial
+// p(l) = l^4 - (tr A^2 / 2) l^2 - (tr A^3 / 3) l + det A by Newton's method
+// from the upper bound ||A||_F (p is convex above its largest root, so the
+// iterates decrease monotonically onto it; the same idea as Theobald's
+// quaternion characteristic polynomial method), then the column of
+// adj(A - l I) with the largest diagonal entry, which is proportional to the
+// eigenvector of a simple root.  Returns false when the eigen-residual is not
+// at rounding level (a near-degenerate top eigenvalue); the caller then uses
+// the Jacobi solve.  Every index is a compile-time constant after unrolling.
+__device__ __forceinline__ int skip_idx(int i, int k) { return k < i ? k : k + 1; }
+
+__device__ __forceinline__ bool quat_top(const double A[4][4], double q[4]) {
+  double fro2 = 0, tr3 = 0;
+  double B[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      fro2 += A[i][j] * A[i][j];
+      double b = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) b += A[i][k] * A[k][j];
+      B[i][j] = b;
+    }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tr3 += B[i][j] * A[j][i];
+  if (!(fro2 > 0.0)) {  // A = 0: any rotation fits; the identity, as the Jacobi solve gives
+    q[0] = 1.0;
+    q[1] = q[2] = q[3] = 0.0;
+    return true;
+  }
+  // det A by cofactors along row 0
+  double det = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c0 = skip_idx(j, 0), c1 = skip_idx(j, 1), c2 = skip_idx(j, 2);
+    const double m = A[1][c0] * (A[2][c1] * A[3][c2] - A[2][c2] * A[3][c1]) -
+                     A[1][c1] * (A[2][c0] * A[3][c2] - A[2][c2] * A[3][c0]) +
+                     A[1][c2] * (A[2][c0] * A[3][c1] - A[2][c1] * A[3][c0]);
+    det += ((j & 1) ? -1.0 : 1.0) * A[0][j] * m;
+  }
+  const double a2 = 0.5 * fro2, a1 = tr3 / 3.0;
+  double l = sqrt(fro2);
+  for (int it = 0; it < 60; ++it) {
+    const double l2 = l * l;
+    const double p = (l2 - a2) * l2 - a1 * l + det;
+    const double dp = (4.0 * l2 - 2.0 * a2) * l - a1;
+    if (!(dp > 0.0)) break;
+    const double dl = p / dp;
+    l -= dl;
+    if (fabs(dl) <= 1e-15 * fabs(l)) break;
+  }
+  // adjugate of M = A - l I: adj[i][j] = (-1)^(i+j) det(M without row j, column i)
+  double M[4][4], best = -1.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) M[i][j] = A[i][j] - (i == j ? l : 0.0);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double col[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r0 = skip_idx(c, 0), r1 = skip_idx(c, 1), r2 = skip_idx(c, 2);
+      const int k0 = skip_idx(i, 0), k1 = skip_idx(i, 1), k2 = skip_idx(i, 2);
+      const double m = M[r0][k0] * (M[r1][k1] * M[r2][k2] - M[r1][k2] * M[r2][k1]) -
+                       M[r0][k1] * (M[r1][k0] * M[r2][k2] - M[r1][k2] * M[r2][k0]) +
+                       M[r0][k2] * (M[r1][k0] * M[r2][k1] - M[r1][k1] * M[r2][k0]);
+      col[i] = (((i + c) & 1) ? -1.0 : 1.0) * m;
+    }
+    if (fabs(col[c]) > best) {
+      best = fabs(col[c]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) q[i] = col[i];
+    }
+  }
+  const double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  if (!(nq > 0.0)) return false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) q[i] /= nq;
+  double res = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double r = -l * q[i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r += A[i][j] * q[j];
+    res = fmax(res, fabs(r));
+  }
+  return res <= 1e-12 * sqrt(fro2);
+}
+
 __global__ __launch_bounds__(256) void k_shell_forces(ShellArgs sa) {
   __shared__ double red[16 * 4];
   __shared__ double sh_c[3], sh_R[9];
@@ -809,7 +903,7 @@ __global__ __launch_bounds__(256) void k_shell_forces(ShellArgs sa) {
                       {Szx - Sxz, Sxy + Syx, -Sxx + Syy - Szz, Syz + Szy},
                       {Sxy - Syx, Szx + Sxz, Syz + Szy, -Sxx - Syy + Szz}};
     double q[4];
-    sym4_eig_max(A, q);
+    if (!quat_top(A, q)) sym4_eig_max(A, q);
     const double w = q[0], x = q[1], y = q[2], z = q[3];
     sh_R[0] = w * w + x * x - y * y - z * z;
     sh_R[1] = 2 * (x * y - w * z);

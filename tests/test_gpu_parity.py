@@ -247,6 +247,26 @@ def test_ib_markers_crossing_tiles_and_seam(kernel):
     check(c, TOL64)
 
 
+@pytest.mark.parametrize("kernel,storage", [(4, 0), (3, 0), (4, 1)])
+def test_ib_dense_tile_overflows_spread_accumulator(kernel, storage):
+    """400 IB markers (bonded in pairs) packed into one 8^3 tile: their
+    stencils cover most of the 13^3 region, more sites than the spreading
+    workgroup accumulates in LDS, so the sites listed beyond that add to the
+    global field directly; every interpolation row stays staged.  A uniform
+    flow carries the markers across the tile's upper faces."""
+    rng = np.random.default_rng(21)
+    n = 200
+    a = rng.uniform(8.0, 16.0, (n, 3))
+    b = a + rng.uniform(-0.4, 0.4, (n, 3))
+    pos = np.vstack([a, b]) % 24.0
+    bonds = np.array([[i, i + n] for i in range(n)])
+    c = Case(name=f"ib_dense_k{kernel}_s{storage}", nx=24, ny=24, nz=24, tau=0.7, steps=12,
+             coupling=3, kernel=kernel, storage=storage, u_noise=0.0, pos=pos, bonds=bonds,
+             bond_k=0.05, bond_r0=0.4, fext=(1e-6, 0.0, -1e-6))
+    c.extra["u0"] = np.array([0.03, 0.02, -0.025])
+    check(c, TOL64 if storage == 0 else TOL32)
+
+
 def test_timing_stride_counts_timed_passes():
     """Timing brackets the first lattice pass and then one in every `stride`,
     up to the number of event pairs armed; the stepping itself is unchanged
