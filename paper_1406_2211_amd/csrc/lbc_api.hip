@@ -397,8 +397,21 @@ static lb_status enqueue_fint(lb_ctx* c, double* pos, bool& any) {
   return LB_OK;
 }
 
-static lb_status lattice_pass(lb_ctx* c) {
-  LatArgs a;
+// Whether the 2n intrinsic-force sub-steps of the multiple time-step split can
+// run as extra workgroups of the lattice launch: row-mapped deterministic
+// pass, a bond group fits a workgroup, and the groups fit one z slab of
+// workgroups.
+static bool bonds_in_pass(const lb_ctx* c) {
+  if (c->geo.wpr == 0 || c->ngroups <= 0 || c->p.kT > 0.0) return false;
+  const int bx = std::min(256, (c->geo.nx + 63) / 64 * 64);
+  const long long slab = (long long)((c->geo.nx + bx - 1) / bx) * c->geo.ny;
+  return c->gcap <= bx && c->ngroups <= slab;
+}
+
+// bond_nsub > 0: the launch also runs bond_nsub sub-steps of bond_dt of every
+// bond group (bonds_in_pass must hold).
+static lb_status lattice_pass(lb_ctx* c, int bond_nsub = 0, double bond_dt = 0.0) {
+  LatArgs a{};
   a.g = c->geo;
   a.fin = c->L.f[c->cur];
   a.fout = c->L.f[1 - c->cur];
@@ -456,6 +469,14 @@ static lb_status lattice_pass(lb_ctx* c) {
     a.uout[k] = c->uref[k] + (c->p.comoving ? c->p.body_force[k] / c->p.rho0 : 0.0);
   }
   comoving_terms(c->scale, c->p.rho0, a.uin, a.uout, a.cm, a.cmf);
+  if (bond_nsub > 0) {
+    a.bond = bond_args(c, c->L.pos);
+    a.bond_groups = c->ngroups;
+    a.bond_nsub = bond_nsub;
+    a.bond_dt = bond_dt;
+    a.bond_cap = c->gcap;
+    a.occ_lds = std::max(a.occ_lds, c->gcap * 3 * (int)sizeof(double));
+  }
   const bool timed =
       2 * (size_t)c->ev_used + 1 < c->ev.size() && c->ev_seen++ % c->ev_stride == 0;
   if (timed) HIPCHK(c, hipEventRecord(c->ev[2 * c->ev_used], c->st));
@@ -594,12 +615,18 @@ static lb_status step_once(lb_ctx* c) {
     HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
     // The 2n intrinsic-force sub-steps between the two coupling halves touch
     // only particle state and the lattice pass only fluid state, so all 2n
-    // run as one launch before the pass (bitwise the same as n, pass, n).
-    // Running them beside the pass on a second stream was measured slower:
-    // they take CUs from the bandwidth-bound pass.
-    HIPCHK(c, launch_bond_groups(bond_args(c, c->L.pos), c->ngroups, c->gcap, 1, 0, 2 * n, dt,
-                                 c->st));
-    if ((s = lattice_pass(c)) != LB_OK) return s;
+    // run together (bitwise the same as n, pass, n): as extra workgroups of
+    // the lattice launch where they fit (they then cost the pass about one
+    // percent of its CU time instead of a launch of their own), else as one
+    // launch before the pass.  Running them on a second stream beside the
+    // pass was measured slower.
+    if (bonds_in_pass(c)) {
+      if ((s = lattice_pass(c, 2 * n, dt)) != LB_OK) return s;
+    } else {
+      HIPCHK(c, launch_bond_groups(bond_args(c, c->L.pos), c->ngroups, c->gcap, 1, 0, 2 * n, dt,
+                                   c->st));
+      if ((s = lattice_pass(c)) != LB_OK) return s;
+    }
     a = part_args(c);
     a.phys = 0;
     a.target = 1;

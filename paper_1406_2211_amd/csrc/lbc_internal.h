@@ -19,6 +19,21 @@ struct Geo {
                  // every population array starts on a 256-byte boundary
 };
 
+struct BondArgs {
+  Geo g;
+  const int32_t* perm;   // particles ordered by group
+  const int32_t* loc;    // slot of each particle inside its group
+  const int32_t* goff;   // group offsets into perm
+  const int32_t* start;  // CSR of bond partners (global particle indices)
+  const int32_t* nbr;
+  double* pos;
+  double* vel;
+  const double* mass;
+  double* fint;
+  double k, r0;
+  int type;
+};
+
 // Fused lattice pass (stream, both pending half forces, collide).
 struct LatArgs {
   Geo g;
@@ -49,6 +64,16 @@ struct LatArgs {
   int mrt;
   double lg[6], ag[6];
   int occ_lds;  // dynamic LDS bytes reserved per workgroup (occupancy cap), 0: none
+  // Intrinsic-force sub-steps run by extra workgroups of the same launch
+  // (bond_groups > 0; row-mapped pass only): the workgroups of the first z
+  // slab (blockIdx.z == 0) take bond group blockIdx.y * gridDim.x + blockIdx.x
+  // and do bond_nsub velocity-Verlet sub-steps of bond_dt; the lattice rows
+  // are at blockIdx.z - 1.  They touch only particle state, the pass only
+  // fluid state.
+  BondArgs bond;
+  int bond_groups, bond_nsub;
+  int bond_cap;  // particles per bond group at most (needs that many lanes and 24 B of LDS each)
+  double bond_dt;
 };
 
 struct InitArgs {
@@ -110,21 +135,6 @@ struct PartArgs {
   int4* mbase;      // [n] first stencil node (x, y, z) of the cached entries
   int cache_use;    // first half: cached entries are current
   int cache_fill;   // second half: store the gathered moments
-};
-
-struct BondArgs {
-  Geo g;
-  const int32_t* perm;   // particles ordered by group
-  const int32_t* loc;    // slot of each particle inside its group
-  const int32_t* goff;   // group offsets into perm
-  const int32_t* start;  // CSR of bond partners (global particle indices)
-  const int32_t* nbr;
-  double* pos;
-  double* vel;
-  const double* mass;
-  double* fint;
-  double k, r0;
-  int type;
 };
 
 struct ShellArgs {

@@ -80,14 +80,31 @@ __device__ __forceinline__ void take_forces_ib(uint64_t word, uint64_t* mp, size
   if (lane == 0 && keep != word) *mp = keep;
 }
 
+// Intrinsic-force sub-steps of one bond group (defined with the particle
+// kernels below); the lattice pass may run them in extra workgroups.
+__device__ void bond_group(const BondArgs& b, int grp, int mode, int acc, int nsub, double dt,
+                           double* lds);
+
 template <int S, bool CM, bool WALL, bool NS = false, bool MRT = false>
 __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
+  // Intrinsic-force sub-steps (workgroup-uniform branch).  Not compiled into
+  // the noisy pass: its registers would cost that uncapped pass occupancy.
+  if constexpr (!NS) {
+    if (a.bond_groups > 0 && blockIdx.z == 0) {
+      const int grp = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+      if (grp < a.bond_groups) {
+        extern __shared__ double bond_lds[];
+        bond_group(a.bond, grp, 1, 0, a.bond_nsub, a.bond_dt, bond_lds);
+      }
+      return;
+    }
+  }
   const uint32_t nx = (uint32_t)a.g.nx, ny = (uint32_t)a.g.ny, nz = (uint32_t)a.g.nz;
   const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t y = blockIdx.y, z = blockIdx.z;
+  const uint32_t y = blockIdx.y, z = blockIdx.z - ((!NS && a.bond_groups > 0) ? 1u : 0u);
   if (x >= nx) return;
   const uint32_t ys[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
   const uint32_t zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
@@ -647,9 +664,9 @@ __device__ __forceinline__ void bond_force(const BondArgs& b, const Partners& P,
   }
 }
 
-__global__ void k_bond_groups(BondArgs b, int mode, int acc, int nsub, double dt) {
-  extern __shared__ double lds[];
-  const int g0 = b.goff[blockIdx.x], cnt = b.goff[blockIdx.x + 1] - g0;
+__device__ __forceinline__ void bond_group(const BondArgs& b, int grp, int mode, int acc, int nsub,
+                                           double dt, double* lds) {
+  const int g0 = b.goff[grp], cnt = b.goff[grp + 1] - g0;
   const int t = threadIdx.x;
   const bool on = t < cnt;
   const long long p = on ? b.perm[g0 + t] : 0;
@@ -701,6 +718,11 @@ __global__ void k_bond_groups(BondArgs b, int mode, int acc, int nsub, double dt
       b.pos[3 * p + k] = r[k];
       b.vel[3 * p + k] = v[k];
     }
+}
+
+__global__ void k_bond_groups(BondArgs b, int mode, int acc, int nsub, double dt) {
+  extern __shared__ double lds[];
+  bond_group(b, blockIdx.x, mode, acc, nsub, dt, lds);
 }
 
 // Rigid-shell tethers: block per shell.  Markers are unwrapped around the
@@ -967,8 +989,16 @@ static void launch_sc(int storage, const LatArgs& a, dim3 gr, dim3 b, hipStream_
 // BGK and the two-rate collision share one kernel (BGK: equal rates); the
 // comoving storage frame is a compile-time switch so that the rest frame
 // carries none of its arithmetic.
-hipError_t launch_stream_collide(int storage, bool comoving, const LatArgs& a, hipStream_t st) {
-  const dim3 b = lattice_block(a.g), gr = lattice_grid(a.g, b);
+hipError_t launch_stream_collide(int storage, bool comoving, const LatArgs& a_in, hipStream_t st) {
+  const dim3 b = lattice_block(a_in.g);
+  dim3 gr = lattice_grid(a_in.g, b);
+  LatArgs a = a_in;
+  if (a.bond_groups > 0) {  // one more z slab of workgroups runs the bond groups
+    if (a.g.wpr == 0 || a.noise || (unsigned)a.bond_groups > gr.x * gr.y ||
+        a.bond_cap > (int)b.x || a.occ_lds < a.bond_cap * 3 * (int)sizeof(double))
+      return hipErrorInvalidValue;
+    gr.z += 1;
+  }
   if (a.mrt) {  // general MRT (not with the comoving frame), with or without noise
     if (a.noise) {
       if (a.g.wall) launch_sc<false, true, true, true>(storage, a, gr, b, st);
