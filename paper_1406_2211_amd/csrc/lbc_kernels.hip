@@ -434,9 +434,24 @@ __device__ __forceinline__ void group_interp(const PartArgs& a, const double X[3
   up[2] = group_sum<L>(uz);
 }
 
+// The mask word of the lane's stencil node at X, loaded ahead of the
+// spreading so that its latency overlaps the gathers: bits are only set while
+// a coupling kernel runs (the lattice pass clears them between kernels), so a
+// bit seen set stays set, and one seen clear is set with an atomic.
+template <int K>
+__device__ __forceinline__ uint64_t mask_preload(const PartArgs& a, const double X[3], int lane) {
+  const SiteSlot sl = slot_of<K>(a.s.g, X, lane);
+  if (!sl.valid) return ~0ull;
+  uint64_t bit;
+  return __atomic_load_n(mask_word(a.mask, a.s.g, sl.x, sl.y, sl.z, bit), __ATOMIC_RELAXED);
+}
+
+// Spread W F to the lane's stencil node; pre: the node's mask word from
+// mask_preload at the same X (nullptr: load it here).
 template <typename E, int K>
 __device__ __forceinline__ void group_spread(const PartArgs& a, const double X[3],
-                                             const double F[3], void* field, int lane) {
+                                             const double F[3], void* field, int lane,
+                                             const uint64_t* pre = nullptr) {
   const SiteSlot sl = slot_of<K>(a.s.g, X, lane);
   if (!sl.valid) return;
   E* Fd = (E*)field;
@@ -445,7 +460,12 @@ __device__ __forceinline__ void group_spread(const PartArgs& a, const double X[3
   unsafeAtomicAdd(Fd + 4 * s + 1, (E)(sl.W * F[1]));
   unsafeAtomicAdd(Fd + 4 * s + 2, (E)(sl.W * F[2]));
   uint64_t bit;
-  flag_site(mask_word(a.mask, a.s.g, sl.x, sl.y, sl.z, bit), bit);
+  uint64_t* mw = mask_word(a.mask, a.s.g, sl.x, sl.y, sl.z, bit);
+  if (pre) {
+    if (!(*pre & bit)) atomicOr((unsigned long long*)mw, bit);
+  } else {
+    flag_site(mw, bit);
+  }
 }
 
 __device__ __forceinline__ void wrap3(const Geo& g, double r[3]) {
@@ -494,6 +514,7 @@ __global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
     for (int k = 0; k < 3; ++k) r[k] += a.hd * v[k];
     wrap3(a.s.g, r);
   }
+  const uint64_t mpre = a.defer ? ~0ull : mask_preload<K>(a, r, lane);
   const double m = a.mass[p];
   double rp, up[3];
   group_interp<S, K>(a, r, a.phys != 0, lane, rp, up, p);
@@ -529,7 +550,7 @@ __global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
     if (lane == 0)
       for (int k = 0; k < 3; ++k) a.defer[3 * p + k] = Ff[k];
   } else {
-    group_spread<E, K>(a, r, Ff, a.target ? a.FB : a.FA, lane);
+    group_spread<E, K>(a, r, Ff, a.target ? a.FB : a.FA, lane, &mpre);
   }
   if (lane == 0) {
     if (a.drift_after) {
@@ -1336,6 +1357,7 @@ __global__ __launch_bounds__(256) void k_ens_couple(EnsArgs e, int half) {
       for (int k = 0; k < 3; ++k) r[k] += hh * v[k];
       wrap3(sl.g, r);
     }
+    const uint64_t mpre = mask_preload<K>(a, r, lane);
     const double m = sl.mass[p];
     double rp, up[3];
     group_interp<S, K>(a, r, half == 0, lane, rp, up, p);
@@ -1356,7 +1378,7 @@ __global__ __launch_bounds__(256) void k_ens_couple(EnsArgs e, int half) {
       }
     }
     const double Ff[3] = {-Fh[0], -Fh[1], -Fh[2]};
-    group_spread<E, K>(a, r, Ff, half == 0 ? sl.FA : sl.FB, lane);
+    group_spread<E, K>(a, r, Ff, half == 0 ? sl.FA : sl.FB, lane, &mpre);
     if (lane == 0) {
       if (half == 1) {
         for (int k = 0; k < 3; ++k) r[k] += hh * v[k];
