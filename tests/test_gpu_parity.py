@@ -154,6 +154,25 @@ def test_mts_soft_chains_fp64_strict():
     check(c, TOL64)
 
 
+@pytest.mark.parametrize("nx,walls", [(128, 0), (320, 1)])
+def test_mts_bond_substeps_inside_the_lattice_launch_fp64(nx, walls):
+    """Rows of 128 or more sites use the row-mapped pass, whose first z slab of
+    workgroups then runs the bond sub-steps of the multiple time-step split
+    (a bond group of 128 particles fits a workgroup); 320 sites make two row
+    chunks (256 and a ragged 64), and y walls select the other pass variant.
+    Soft bonds keep the trajectory well conditioned, so the plain 1e-12 bound
+    applies."""
+    rng = np.random.default_rng(11)
+    pos = np.array([[5.0 + 40.0 * c + 0.95 * k, 5.0 + 3.0 * c, 6.0] for c in range(3)
+                    for k in range(12)]) + rng.uniform(-0.2, 0.2, (36, 3))
+    vel = rng.normal(0.0, 2e-2, (36, 3))
+    bonds = np.array([[12 * c + k, 12 * c + k + 1] for c in range(3) for k in range(11)])
+    c = Case(name=f"mts_row{nx}", nx=nx, ny=16, nz=12, tau=0.7, steps=10, collision=1,
+             coupling=1, gamma=1.0, kernel=2, storage=0, mts=3, u_noise=1e-3, pos=pos, vel=vel,
+             mass=np.full(len(pos), 2.0), bonds=bonds, bond_k=0.02, bond_r0=1.0, wall_y=walls)
+    check(c, TOL64)
+
+
 def _soft_alg3_case(name="alg3", steps=25):
     pos, vel, bonds = I.chains(2, 8, (20, 20, 20), 1.0, 2e-2, 8)
     return Case(name=name, nx=20, ny=20, nz=20, tau=0.6, steps=steps, collision=1, coupling=1,
