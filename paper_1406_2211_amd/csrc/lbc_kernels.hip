@@ -468,6 +468,65 @@ __device__ __forceinline__ void group_spread(const PartArgs& a, const double X[3
   }
 }
 
+// Spreading of the 2-point kernel with the contributions of consecutive
+// particles combined inside the wavefront before the atomics.  A wavefront
+// holds 8 particles (8 lanes each, one per stencil node); consecutive
+// particles of a chain sit about one spacing apart, so particle q + 1 shares
+// on average three to four of its nodes with particle q.  From the last
+// particle of the wavefront down to the second, each particle hands the
+// (already combined) contribution of every node it shares with its
+// predecessor to the predecessor's lane for that node, which adds it in FP64;
+// only nodes that are not handed on issue the three float atomics.  The sum at
+// a site is the same set of terms as with one atomic per contribution (the
+// order of atomic additions is unspecified either way).  pre: the node's mask
+// word from mask_preload.
+template <typename E>
+__device__ __forceinline__ void group_spread_k2(const PartArgs& a, const double X[3],
+                                                const double F[3], void* field, int lane,
+                                                long long p, uint64_t pre) {
+  const SiteSlot sl = slot_of<2>(a.s.g, X, lane);
+  long long sidx = sl.valid ? site_index(a.s.g, sl.x, sl.y, sl.z) : -1;
+  double c0 = sl.valid ? sl.W * F[0] : 0.0, c1 = sl.valid ? sl.W * F[1] : 0.0,
+         c2 = sl.valid ? sl.W * F[2] : 0.0;
+  const int wl = (int)(threadIdx.x & 63), qi = wl >> 3;
+  const int kx = lane & 1, ky = (lane >> 1) & 1, kz = lane >> 2;
+#pragma unroll 1
+  for (int i = 7; i >= 1; --i) {
+    // first node of particle i and of particle i - 1 (uniform over each group)
+    const int ax = __shfl(sl.j0[0], 8 * i, 64), ay = __shfl(sl.j0[1], 8 * i, 64),
+              az = __shfl(sl.j0[2], 8 * i, 64);
+    const int bx = __shfl(sl.j0[0], 8 * (i - 1), 64), by = __shfl(sl.j0[1], 8 * (i - 1), 64),
+              bz = __shfl(sl.j0[2], 8 * (i - 1), 64);
+    const int dx = ax - bx, dy = ay - by, dz = az - bz;
+    // receiver (particle i - 1, node k'): its node k' - d of particle i
+    const int sx = kx - dx, sy = ky - dy, sz = kz - dz;
+    const bool rin = qi == i - 1 && p + 1 < a.n && sx >= 0 && sx <= 1 && sy >= 0 && sy <= 1 &&
+                     sz >= 0 && sz <= 1;
+    const int src = rin ? 8 * i + sx + 2 * sy + 4 * sz : wl;
+    // donor (particle i, node k): the receiver's node k + d of particle i - 1
+    const int tx = kx + dx, ty = ky + dy, tz = kz + dz;
+    const bool din = qi == i && tx >= 0 && tx <= 1 && ty >= 0 && ty <= 1 && tz >= 0 && tz <= 1;
+    const int dst = din ? 8 * (i - 1) + tx + 2 * ty + 4 * tz : wl;
+    const long long s_src = __shfl(sidx, src, 64);
+    const double g0 = __shfl(c0, src, 64), g1 = __shfl(c1, src, 64), g2 = __shfl(c2, src, 64);
+    const long long s_dst = __shfl(sidx, dst, 64);
+    if (rin && sidx >= 0 && s_src == sidx) {
+      c0 += g0;
+      c1 += g1;
+      c2 += g2;
+    }
+    if (din && sidx >= 0 && s_dst == sidx) sidx = -1;  // handed on to particle i - 1
+  }
+  if (sidx < 0) return;
+  E* Fd = (E*)field;
+  unsafeAtomicAdd(Fd + 4 * sidx + 0, (E)c0);
+  unsafeAtomicAdd(Fd + 4 * sidx + 1, (E)c1);
+  unsafeAtomicAdd(Fd + 4 * sidx + 2, (E)c2);
+  uint64_t bit;
+  uint64_t* mw = mask_word(a.mask, a.s.g, sl.x, sl.y, sl.z, bit);
+  if (!(pre & bit)) atomicOr((unsigned long long*)mw, bit);
+}
+
 __device__ __forceinline__ void wrap3(const Geo& g, double r[3]) {
   r[0] = wrap_pos(r[0], (double)g.nx);
   if (!g.wall) r[1] = wrap_pos(r[1], (double)g.ny);
@@ -550,7 +609,10 @@ __global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
     if (lane == 0)
       for (int k = 0; k < 3; ++k) a.defer[3 * p + k] = Ff[k];
   } else {
-    group_spread<E, K>(a, r, Ff, a.target ? a.FB : a.FA, lane, &mpre);
+    if constexpr (K == 2)
+      group_spread_k2<E>(a, r, Ff, a.target ? a.FB : a.FA, lane, p, mpre);
+    else
+      group_spread<E, K>(a, r, Ff, a.target ? a.FB : a.FA, lane, &mpre);
   }
   if (lane == 0) {
     if (a.drift_after) {
