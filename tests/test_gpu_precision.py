@@ -72,3 +72,25 @@ def test_comoving_frame_keeps_fp16_increments():
     print(f"[precision] forced uniform flow, FP16: rest frame u err {e_rest:.3e}, "
           f"comoving frame {e_com:.3e}", flush=True)
     assert e_com < e_rest / 10
+
+
+@pytest.mark.parametrize("storage,scale,limit", [(2, 20, 5e-3), (3, 0, 5e-2)])
+def test_16bit_storage_ib_tiles_error_reported(storage, scale, limit):
+    """The binned immersed-boundary path (4-point kernel, staged velocities in
+    FP32 from 16-bit populations) on the wall-bounded shell case, against the
+    FP64 oracle; the bound catches a broken 16-bit staging path, the measured
+    errors are printed."""
+    T = I.icosphere(1, 4.0)
+    cen = I.shell_centres(2, 4.0, (24, 24, 32), True, 2.0, 3.0, seed=3)
+    X = np.vstack([c + T for c in cen])
+    X = X + 0.15 * np.random.default_rng(5).standard_normal(X.shape)
+    c = Case(name=f"ib16_s{storage}", nx=24, ny=24, nz=32, tau=0.8, steps=30, wall_y=1,
+             fext=(0.0, 0.0, 1e-5), coupling=3, kernel=4, storage=storage, u_noise=1e-4,
+             pos=X, nshell=2, template=T, tether_k=0.05, f16_scale_log2=scale)
+    o = run_oracle(c)
+    g = run_gpu(c)
+    e = errors(c, g, o)
+    print(f"[precision] IB tiles storage={storage} scale=2^{scale}: " +
+          ", ".join(f"{k}={v:.3e}" for k, v in e.items()), flush=True)
+    assert np.all(np.isfinite(g["u"])) and np.all(np.isfinite(g["pos"]))
+    assert e["u"] < limit and e["pos"] < 1e-6
