@@ -90,21 +90,18 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
-  // Intrinsic-force sub-steps (workgroup-uniform branch).  Not compiled into
-  // the noisy pass: its registers would cost that uncapped pass occupancy.
-  if constexpr (!NS) {
-    if (a.bond_groups > 0 && blockIdx.z == 0) {
-      const int grp = (int)(blockIdx.y * gridDim.x + blockIdx.x);
-      if (grp < a.bond_groups) {
-        extern __shared__ double bond_lds[];
-        bond_group(a.bond, grp, 1, 0, a.bond_nsub, a.bond_dt, bond_lds);
-      }
-      return;
+  // Intrinsic-force sub-steps (workgroup-uniform branch).
+  if (a.bond_groups > 0 && blockIdx.z == 0) {
+    const int grp = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    if (grp < a.bond_groups) {
+      extern __shared__ double bond_lds[];
+      bond_group(a.bond, grp, 1, 0, a.bond_nsub, a.bond_dt, bond_lds);
     }
+    return;
   }
   const uint32_t nx = (uint32_t)a.g.nx, ny = (uint32_t)a.g.ny, nz = (uint32_t)a.g.nz;
   const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t y = blockIdx.y, z = blockIdx.z - ((!NS && a.bond_groups > 0) ? 1u : 0u);
+  const uint32_t y = blockIdx.y, z = blockIdx.z - (a.bond_groups > 0 ? 1u : 0u);
   if (x >= nx) return;
   const uint32_t ys[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
   const uint32_t zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
@@ -1077,8 +1074,8 @@ hipError_t launch_stream_collide(int storage, bool comoving, const LatArgs& a_in
   dim3 gr = lattice_grid(a_in.g, b);
   LatArgs a = a_in;
   if (a.bond_groups > 0) {  // one more z slab of workgroups runs the bond groups
-    if (a.g.wpr == 0 || a.noise || (unsigned)a.bond_groups > gr.x * gr.y ||
-        a.bond_cap > (int)b.x || a.occ_lds < a.bond_cap * 3 * (int)sizeof(double))
+    if (a.g.wpr == 0 || (unsigned)a.bond_groups > gr.x * gr.y || a.bond_cap > (int)b.x ||
+        a.occ_lds < a.bond_cap * 3 * (int)sizeof(double))
       return hipErrorInvalidValue;
     gr.z += 1;
   }
