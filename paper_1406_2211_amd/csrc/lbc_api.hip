@@ -398,10 +398,12 @@ static lb_status enqueue_fint(lb_ctx* c, double* pos, bool& any) {
 }
 
 // Whether the 2n intrinsic-force sub-steps of the multiple time-step split can
-// run as extra workgroups of the lattice launch: row-mapped pass, a bond group
-// fits a workgroup, and the groups fit one z slab of workgroups.
+// run as extra workgroups of the lattice launch: a bond group fits a
+// workgroup, and on the row-mapped pass the groups fit one z slab of
+// workgroups.
 static bool bonds_in_pass(const lb_ctx* c) {
-  if (c->geo.wpr == 0 || c->ngroups <= 0) return false;
+  if (c->ngroups <= 0) return false;
+  if (c->geo.wpr == 0) return c->gcap <= 256;  // linear-site pass: 256-lane workgroups
   const int bx = std::min(256, (c->geo.nx + 63) / 64 * 64);
   const long long slab = (long long)((c->geo.nx + bx - 1) / bx) * c->geo.ny;
   return c->gcap <= bx && c->ngroups <= slab;

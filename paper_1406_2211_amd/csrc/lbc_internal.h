@@ -65,11 +65,12 @@ struct LatArgs {
   double lg[6], ag[6];
   int occ_lds;  // dynamic LDS bytes reserved per workgroup (occupancy cap), 0: none
   // Intrinsic-force sub-steps run by extra workgroups of the same launch
-  // (bond_groups > 0; row-mapped pass only): the workgroups of the first z
-  // slab (blockIdx.z == 0) take bond group blockIdx.y * gridDim.x + blockIdx.x
-  // and do bond_nsub velocity-Verlet sub-steps of bond_dt; the lattice rows
-  // are at blockIdx.z - 1.  They touch only particle state, the pass only
-  // fluid state.
+  // (bond_groups > 0), each doing bond_nsub velocity-Verlet sub-steps of
+  // bond_dt for one bond group.  Row-mapped pass: the workgroups of the first
+  // z slab (blockIdx.z == 0) take group blockIdx.y * gridDim.x + blockIdx.x
+  // and the lattice rows are at blockIdx.z - 1; linear-site pass: workgroup b
+  // < bond_groups takes group b and the sites start at workgroup bond_groups.
+  // They touch only particle state, the pass only fluid state.
   BondArgs bond;
   int bond_groups, bond_nsub;
   int bond_cap;  // particles per bond group at most (needs that many lanes and 24 B of LDS each)

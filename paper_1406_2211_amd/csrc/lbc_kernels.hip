@@ -1057,7 +1057,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_lin(LatArgs a);
 template <bool CM, bool WALL, bool NS = false, bool MRT = false>
 static void launch_sc(int storage, const LatArgs& a, dim3 gr, dim3 b, hipStream_t st) {
   if (a.g.wpr == 0) {  // linear mask: x extent not a multiple of 64
-    const unsigned nb = (unsigned)((a.g.N + 255) / 256);
+    const unsigned nb = (unsigned)((a.g.N + 255) / 256) + (unsigned)a.bond_groups;
     LBC_STORAGE_SWITCH(storage, (k_stream_collide_lin<SS, CM, WALL, NS, MRT>
                                  <<<nb, 256, a.occ_lds, st>>>(a)));
   } else {
@@ -1073,11 +1073,14 @@ hipError_t launch_stream_collide(int storage, bool comoving, const LatArgs& a_in
   const dim3 b = lattice_block(a_in.g);
   dim3 gr = lattice_grid(a_in.g, b);
   LatArgs a = a_in;
-  if (a.bond_groups > 0) {  // one more z slab of workgroups runs the bond groups
-    if (a.g.wpr == 0 || (unsigned)a.bond_groups > gr.x * gr.y || a.bond_cap > (int)b.x ||
-        a.occ_lds < a.bond_cap * 3 * (int)sizeof(double))
-      return hipErrorInvalidValue;
-    gr.z += 1;
+  if (a.bond_groups > 0) {  // extra workgroups run the bond groups
+    if (a.occ_lds < a.bond_cap * 3 * (int)sizeof(double)) return hipErrorInvalidValue;
+    if (a.g.wpr == 0) {  // linear-site pass: bond_groups workgroups in front
+      if (a.bond_cap > 256) return hipErrorInvalidValue;
+    } else {  // row-mapped pass: one more z slab of workgroups in front
+      if ((unsigned)a.bond_groups > gr.x * gr.y || a.bond_cap > (int)b.x) return hipErrorInvalidValue;
+      gr.z += 1;
+    }
   }
   if (a.mrt) {  // general MRT (not with the comoving frame), with or without noise
     if (a.noise) {
@@ -1344,7 +1347,16 @@ __device__ __forceinline__ void linear_site(const V& v, uint32_t s) {
 
 template <int S, bool CM, bool WALL, bool NS, bool MRT>
 __global__ __launch_bounds__(256) void k_stream_collide_lin(LatArgs a) {
-  linear_site<S, CM, WALL, LatView, NS, MRT>(LatView{a}, blockIdx.x * 256u + threadIdx.x);
+  uint32_t b = blockIdx.x;
+  if (a.bond_groups > 0) {  // the first bond_groups workgroups run the intrinsic-force sub-steps
+    if (b < (uint32_t)a.bond_groups) {
+      extern __shared__ double bond_lds[];
+      bond_group(a.bond, (int)b, 1, 0, a.bond_nsub, a.bond_dt, bond_lds);
+      return;
+    }
+    b -= (uint32_t)a.bond_groups;
+  }
+  linear_site<S, CM, WALL, LatView, NS, MRT>(LatView{a}, b * 256u + threadIdx.x);
 }
 
 // The slot table is read-only during the lattice pass (only k_ens_advance
