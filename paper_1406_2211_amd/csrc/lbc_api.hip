@@ -397,6 +397,19 @@ static lb_status enqueue_fint(lb_ctx* c, double* pos, bool& any) {
   return LB_OK;
 }
 
+// P^(hd): r <- wrap(r + hd v) for every particle, then F_int at the new
+// positions.  With bonds and no shells both run in one launch of the bond
+// groups (every particle belongs to a group), else as a drift and enqueue_fint.
+static lb_status drift_and_fint(lb_ctx* c, double hd, bool& any) {
+  if (c->nshell == 0 && c->nbond > 0 && c->ngroups > 0) {
+    HIPCHK(c, launch_bond_groups(bond_args(c, c->L.pos), c->ngroups, c->gcap, 2, 0, 0, hd, c->st));
+    any = true;
+    return LB_OK;
+  }
+  HIPCHK(c, launch_drift(c->geo, c->np, c->L.pos, c->L.vel, hd, c->st));
+  return enqueue_fint(c, c->L.pos, any);
+}
+
 // Whether the 2n intrinsic-force sub-steps of the multiple time-step split can
 // run as extra workgroups of the lattice launch: a bond group fits a
 // workgroup, and on the row-mapped pass the groups fit one z slab of
@@ -520,10 +533,7 @@ static lb_status step_mts_inside(lb_ctx* c) {
     if (side == 1 && (s = lattice_pass(c)) != LB_OK) return s;
     for (int k = 0; k < n; ++k) {
       bool any = false;
-      if (fint) {
-        HIPCHK(c, launch_drift(c->geo, c->np, c->L.pos, c->L.vel, 0.5 * dt, c->st));
-        if ((s = enqueue_fint(c, c->L.pos, any)) != LB_OK) return s;
-      }
+      if (fint && (s = drift_and_fint(c, 0.5 * dt, any)) != LB_OK) return s;
       PartArgs a = part_args(c);
       a.hh = dt;
       a.hd = 0.5 * dt;
@@ -641,10 +651,7 @@ static lb_status step_once(lb_ctx* c) {
   // Without intrinsic forces the first P^1/2 is done by the coupling kernel.
   const bool fint = c->nshell > 0 || c->nbond > 0;
   bool any = false;
-  if (fint) {
-    HIPCHK(c, launch_drift(c->geo, c->np, c->L.pos, c->L.vel, 0.5, c->st));
-    if ((s = enqueue_fint(c, c->L.pos, any)) != LB_OK) return s;
-  }
+  if (fint && (s = drift_and_fint(c, 0.5, any)) != LB_OK) return s;
   PartArgs a = part_args(c);
   a.use_fint = any ? 1 : 0;
   a.drift_before = fint ? 0 : 1;

@@ -698,6 +698,7 @@ __global__ __launch_bounds__(256) void k_ib_advect(PartArgs a, int spread_fint) 
 // LDS.  mode 0: F_int at the current positions (stored, or added with acc).
 // mode 1: nsub velocity-Verlet sub-steps of length dt with F_int only
 // (the [P F_int P]^n factor of the multiple time-step split, Sec. 6).
+// mode 2: the positions drift by dt (r <- wrap(r + dt v)), then mode 0.
 // Bond partners of one particle, held in registers across the sub-steps
 // (up to kMaxBondsReg; a particle with more partners reads the CSR list).
 constexpr int kMaxBondsReg = 6;
@@ -762,7 +763,12 @@ __device__ __forceinline__ void bond_group(const BondArgs& b, int grp, int mode,
     if (b.mass) m = b.mass[p];
     load_partners(b, p, P);
   }
-  if (mode == 0) {
+  if (mode == 0 || mode == 2) {
+    if (mode == 2 && on) {  // drift by dt first (as k_drift does), store the positions
+      for (int k = 0; k < 3; ++k) r[k] = r[k] + dt * v[k];
+      wrap3(b.g, r);
+      for (int k = 0; k < 3; ++k) b.pos[3 * p + k] = r[k];
+    }
     if (on)
       for (int k = 0; k < 3; ++k) lds[3 * t + k] = r[k];
     __syncthreads();
