@@ -45,6 +45,7 @@ class _Cfg(C.Structure):
         ("mts_inside", C.c_int),
         ("kT", C.c_double), ("seed", C.c_uint64), ("step0", C.c_int64),
         ("mrt_rates", C.c_double * 5),
+        ("order", C.c_int),
     ]
 
 
@@ -185,7 +186,8 @@ class Oracle:
     mts_inside [0: coupling outside the sub-steps; 1: inside every sub-step], kT [0: no
     fluctuations], seed [0], step0 [0: index of the first step in the random streams],
     mrt_rates [5 x 1.0: bulk, vector ghosts, pseudo-vector ghosts, scalar and tensor ghosts;
-    collision MRT]."""
+    collision MRT], order [0: the second-order splitting; test-only alternatives: 1 the
+    first-order P S C F sequence, 2 a planted misordering (see lbo.h)]."""
 
     def __init__(self, **cfg):
         self.nx, self.ny, self.nz = int(cfg["nx"]), int(cfg["ny"]), int(cfg["nz"])
@@ -226,6 +228,7 @@ class Oracle:
         c.step0 = int(cfg.get("step0", 0))
         for k, r in enumerate(cfg.get("mrt_rates", (1.0,) * 5)):
             c.mrt_rates[k] = float(r)
+        c.order = int(cfg.get("order", 0))
         self.cfg = c
         self.N = self.nx * self.ny * self.nz
         self.shape = (self.nz, self.ny, self.nx)

@@ -707,7 +707,9 @@ void lbo_bond_forces(const lbo_cfg *cfg, int np, const double *pos, double *F) {
     const double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     double s; /* F_i = s d */
     if (cfg->bond_type == LBO_FENE) {
-      s = cfg->bond_k / (1.0 - L * L / (cfg->bond_r0 * cfg->bond_r0));
+      /* U = -k r0^2/2 ln(1 - L^2/r0^2) is infinite from L = r0 on: the force
+       * there is NaN, not the sign-flipped value of the formula */
+      s = L < cfg->bond_r0 ? cfg->bond_k / (1.0 - L * L / (cfg->bond_r0 * cfg->bond_r0)) : NAN;
     } else {
       s = L > 0.0 ? cfg->bond_k * (L - cfg->bond_r0) / L : 0.0;
     }
@@ -883,6 +885,16 @@ static void coupling_step(const lbo_cfg *cfg, int np, const double *pos, double 
     double *Fh = w->Fh + 3 * p, *v = vel + 3 * p;
     if (cfg->coupling == LBO_FC) {
       lbo_fc_force(cfg->gamma, mass[p], w->rho_p[p], hh, v, w->u_p + 3 * p, Fint + 3 * p, Fh);
+      {
+        /* The fluid at the particle also feels the body force over the coupling
+         * step: Eq. fc-vel with du/dt = [gamma (v - u) + F_ext] / (rho a^3).
+         * The Crank-Nicolson solution then gains +(beta/2) F_ext in the bracket
+         * of Eq. modified-force (R6b), which keeps the step second order under a
+         * body force (it is first order when the body force stays outside). */
+        const double al = cfg->gamma * hh / mass[p], be = cfg->gamma * hh / w->rho_p[p];
+        for (int a = 0; a < 3; ++a)
+          Fh[a] += 0.5 * be * cfg->fext[a] / (1.0 + 0.5 * al + 0.5 * be);
+      }
       if (cfg->kT > 0.0) {
         /* random force zeta of Eq. viscous-coupling, variance 2 k_B T gamma / hh
          * per component over a coupling step of length hh, entering the implicit
@@ -919,12 +931,34 @@ static double *step_fc(const lbo_cfg *cfg, double *df, int np, double *pos, doub
   }
   lbo_force_half(cfg, df, part ? w->Fc : NULL);
   df = collide_stream(cfg, df, w);
+  const int planted = part && cfg->order == 2; /* TEST ONLY: final P^1/2 misplaced */
+  if (planted) drift(cfg, np, pos, vel, 0.5);
   if (part) {
     lbo_moments(cfg, df, w->rho, w->u); /* post-stream, before the half force (R6) */
     coupling_step(cfg, np, pos, vel, mass, w->Fint, 0.5, 1, w);
   }
   lbo_force_half(cfg, df, part ? w->Fc : NULL);
-  if (part) drift(cfg, np, pos, vel, 0.5);
+  if (part && !planted) drift(cfg, np, pos, vel, 0.5);
+  return df;
+}
+
+/* TEST ONLY (order = 1).  The first-order sequence P S C F of Sec. 5.1,
+ * applied right to left: the force operator over a full step h (the coupling
+ * of Sec. 5.2 with h' = h at the current positions, the kick, the lattice
+ * force with the body force), the collision, streaming, then the full
+ * position update with the new velocities.  The second-order pins measure the
+ * splitting of Eq. fc-splitting against this sequence. */
+static double *step_fc_first_order(const lbo_cfg *cfg, double *df, int np, double *pos,
+                                   double *vel, const double *mass, work *w) {
+  const int part = cfg->coupling != LBO_NONE && np > 0;
+  if (part) {
+    lbo_intrinsic(cfg, np, pos, w->Fint);
+    lbo_moments(cfg, df, w->rho, w->u);
+    coupling_step(cfg, np, pos, vel, mass, w->Fint, 1.0, 0, w);
+  }
+  lbo_force_dt(cfg, df, part ? w->Fc : NULL, 1.0);
+  df = collide_stream(cfg, df, w);
+  if (part) drift(cfg, np, pos, vel, 1.0);
   return df;
 }
 
@@ -997,7 +1031,9 @@ static double *step_ib(const lbo_cfg *cfg, double *df, int np, double *X, work *
   double *Xt = w->X1;
   lbo_moments(cfg, df, w->rho, w->u);
   lbo_interp(cfg, np, X, w->rho, w->u, w->rho_p, w->u_p);
-  for (int p = 0; p < 3 * np; ++p) Xt[p] = X[p] + 0.5 * w->u_p[p];
+  /* order = 2 (TEST ONLY) plants a mistake: no predictor, X~ = X(t) */
+  const double pred = cfg->order == 2 ? 0.0 : 0.5;
+  for (int p = 0; p < 3 * np; ++p) Xt[p] = X[p] + pred * w->u_p[p];
   wrap_positions(cfg, np, Xt);
   lbo_intrinsic(cfg, np, Xt, w->Fint);
   lbo_interp(cfg, np, Xt, w->rho, w->u, w->rho_p, w->u_p);
@@ -1015,6 +1051,24 @@ static double *step_ib(const lbo_cfg *cfg, double *df, int np, double *X, work *
   return df;
 }
 
+/* TEST ONLY (order = 1).  The first-order IB sequence P S C F of Sec. 5.1:
+ * the intrinsic forces at X(t) spread and applied over a full step, the
+ * collision, streaming, then X(t+h) = X(t) + h I[X(t)] u(t+h). */
+static double *step_ib_first_order(const lbo_cfg *cfg, double *df, int np, double *X,
+                                   work *w) {
+  const long N = nsites(cfg);
+  lbo_intrinsic(cfg, np, X, w->Fint);
+  memset(w->Fc, 0, sizeof(double) * 3 * N);
+  lbo_spread(cfg, np, X, w->Fint, w->Fc);
+  lbo_force_dt(cfg, df, w->Fc, 1.0);
+  df = collide_stream(cfg, df, w);
+  lbo_moments(cfg, df, w->rho, w->u);
+  lbo_interp(cfg, np, X, w->rho, w->u, w->rho_p, w->u_p);
+  for (int p = 0; p < 3 * np; ++p) X[p] += w->u_p[p];
+  wrap_positions(cfg, np, X);
+  return df;
+}
+
 static int check_cfg(const lbo_cfg *cfg, int np, const double *mass) {
   if (cfg->nx <= 0 || cfg->ny <= 0 || cfg->nz <= 0) return -1;
   if (!(cfg->tau > 0.5)) return -1;
@@ -1027,6 +1081,8 @@ static int check_cfg(const lbo_cfg *cfg, int np, const double *mass) {
   if (cfg->kernel < 2 || cfg->kernel > 4) return -1;
   if (cfg->coupling == LBO_IB && cfg->mts_n > 0) return -1;
   if (cfg->mts_inside != 0 && cfg->mts_inside != 1) return -1;
+  if (cfg->order < 0 || cfg->order > 2) return -1;
+  if (cfg->order != 0 && (cfg->mts_n > 0 || cfg->csc || cfg->kT > 0.0)) return -1;
   if (!(cfg->kT >= 0.0)) return -1;
   if (cfg->collision == LBO_MRT)
     for (int k = 0; k < 5; ++k)
@@ -1054,7 +1110,10 @@ int lbo_run(const lbo_cfg *cfg, int nsteps, double *df, int np, double *pos, dou
     double *out;
     w.t = cfg->step0 + t;
     if (cfg->coupling == LBO_IB)
-      out = step_ib(cfg, cur, np, pos, &w);
+      out = cfg->order == 1 ? step_ib_first_order(cfg, cur, np, pos, &w)
+                            : step_ib(cfg, cur, np, pos, &w);
+    else if (cfg->order == 1)
+      out = step_fc_first_order(cfg, cur, np, pos, vel, mass, &w);
     else if (cfg->mts_n > 0 && cfg->coupling != LBO_NONE && np > 0)
       out = cfg->mts_inside ? step_mts_inside(cfg, cur, np, pos, vel, mass, &w)
                             : step_mts(cfg, cur, np, pos, vel, mass, &w);

@@ -62,6 +62,14 @@ typedef struct lbo_cfg {
   double mrt_rates[5];         /* LBO_MRT: rates of the bulk stress, the vector and the
                                   pseudo-vector third-order ghosts, the scalar and the tensor
                                   fourth-order ghosts (the shear stress relaxes at 1/tau) */
+  int order;                   /* TEST ONLY, the orderings the second-order pins are checked
+                                  against: 0 the second-order splitting (Eq. fc-splitting in
+                                  the order of Alg. 3; Eq. IBM-scheme in the order of Alg. 2);
+                                  1 the first-order sequence P S C F that Sec. 5.1 contrasts it
+                                  with (full-step force and coupling, collision, streaming,
+                                  full-step position update); 2 a planted mistake: FC/EBF with
+                                  the final P^1/2 moved before the second coupling half, IB
+                                  without the predictor (forces and interpolation at X(t)) */
 } lbo_cfg;
 
 /* lattice and local operators */

@@ -176,6 +176,18 @@ def test_zero_mass_limit_is_immersed_boundary():
 
 
 # ---------------------------------------------------------------- intrinsic forces
+def test_fene_bond_at_maximum_extension_is_nan():
+    """FENE's energy -k r0^2/2 ln(1 - |d|^2/r0^2) is infinite from |d| = r0 on:
+    the force of such a bond is NaN (not the sign-flipped value of the
+    formula), the bond just inside r0 is finite and pulls the pair together."""
+    o = O.Oracle(nx=10, ny=10, nz=10, tau=0.8, bonds=np.array([[0, 1], [2, 3]]), bond_k=1.0,
+                 bond_r0=1.5, bond_type=O.FENE)
+    pos = np.array([[1.0, 1.0, 1.0], [2.4, 1.0, 1.0], [5.0, 5.0, 5.0], [6.6, 5.0, 5.0]])
+    F = o.bond_forces(pos)
+    assert np.all(np.isfinite(F[:2])) and F[0, 0] > 0 and F[1, 0] < 0
+    assert np.all(np.isnan(F[2:, 0]))
+
+
 @pytest.mark.parametrize("btype", [O.HARMONIC, O.FENE])
 def test_bond_forces_are_minus_energy_gradient(btype):
     k, r0 = 30.0, (1.0 if btype == O.HARMONIC else 1.5)
