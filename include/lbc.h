@@ -158,10 +158,16 @@ lb_status lb_init_fluid(lb_ctx* ctx, const double* d_rho, const double* d_u);
 lb_status lb_set_particles(lb_ctx* ctx, int64_t n, const double* d_pos, const double* d_vel,
                            const double* d_mass);
 
-/* Bonds between particles (intrinsic forces, "CalculateForces" of Alg. 3):
- * harmonic U = k/2 (|d| - r0)^2 or FENE U = -k r0^2/2 ln(1 - |d|^2/r0^2)
- * with d the minimum-image separation.  h_pairs [nb][2] host int32 particle
- * indices.  Bonded clusters must not exceed 1024 particles.  Synchronous. */
+/* Bonds between particles (intrinsic forces, "CalculateForces" of Alg. 3
+ * and Alg. 2; the paper leaves their model open): harmonic
+ * U = k/2 (|d| - r0)^2 or FENE U = -k r0^2/2 ln(1 - |d|^2/r0^2) with d the
+ * minimum-image separation.  A FENE bond stretched to |d| >= r0 has infinite
+ * energy: its force is NaN, which propagates into the particles and the
+ * fluid (the run is not stopped; lb_totals then reports non-finite sums).
+ * h_pairs [nb][2] host int32 particle indices, copied.  Bonded clusters must
+ * not exceed 1024 particles.  Errors: LB_ENOMEM beyond max_bonds, LB_EINVAL
+ * for an unknown type, non-finite k or r0, or FENE with r0 <= 0.
+ * Synchronous. */
 lb_status lb_set_bonds(lb_ctx* ctx, int64_t nb, const int32_t* h_pairs, double k, double r0,
                        int32_t type);
 

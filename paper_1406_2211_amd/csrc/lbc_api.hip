@@ -246,6 +246,7 @@ static PartArgs part_args(const lb_ctx* c) {
   a.fint = c->L.fint;
   a.aux = c->L.aux;
   a.gamma = c->p.gamma;
+  for (int k = 0; k < 3; ++k) a.fext[k] = c->p.body_force[k];
   a.coupling = c->p.coupling;
   a.use_fint = 0;
   a.phys = 1;
@@ -384,7 +385,7 @@ static lb_status enqueue_fint(lb_ctx* c, double* pos, bool& any) {
   if (c->nshell > 0) {
     const int64_t nm = (int64_t)c->nshell * c->shell_size;
     if (nm < c->np)
-      HIPCHK(c, hipMemsetAsync(c->L.fint + 3 * nm, 0, (size_t)(c->np - nm) * 24, c->st));
+      HIPCHK(c, launch_zero(c->L.fint + 3 * nm, (size_t)(c->np - nm) * 24, c->st));
     ShellArgs s{c->geo, pos, c->L.tmpl, c->L.fint, c->L.rot, c->shell_size, c->k_tether};
     HIPCHK(c, launch_shell_forces(s, c->nshell, c->st));
     any = true;
@@ -596,7 +597,7 @@ static lb_status step_once(lb_ctx* c) {
                                    c->st));
     bool any;
     if ((s = enqueue_fint(c, c->L.aux, any)) != LB_OK) return s;
-    if (!any) HIPCHK(c, hipMemsetAsync(c->L.fint, 0, (size_t)c->np * 24, c->st));
+    if (!any) HIPCHK(c, launch_zero(c->L.fint, (size_t)c->np * 24, c->st));
     HIPCHK(c, launch_tile_spread(S, K, t, c->L.aux, c->L.fint, c->L.FA, c->np, c->st));
     // The second half force is the same spread of the same F_int at X~: the
     // lattice pass keeps the first-half field as the pending one (ib_copy).
@@ -609,7 +610,7 @@ static lb_status step_once(lb_ctx* c) {
     HIPCHK(c, launch_ib_predict(c->p.storage, a, c->st));
     bool any;
     if ((s = enqueue_fint(c, c->L.aux, any)) != LB_OK) return s;
-    if (!any) HIPCHK(c, hipMemsetAsync(c->L.fint, 0, (size_t)c->np * 24, c->st));
+    if (!any) HIPCHK(c, launch_zero(c->L.fint, (size_t)c->np * 24, c->st));
     HIPCHK(c, launch_ib_advect(c->p.storage, a, 1, c->st));
     if ((s = lattice_pass(c)) != LB_OK) return s;  // FB <- FA (ib_copy)
     a = part_args(c);
@@ -767,9 +768,9 @@ lb_status lb_init_fluid(lb_ctx* c, const double* d_rho, const double* d_u) {
   c->cur = 0;
   HIPCHK(c, launch_init(c->p.storage, a, c->st));
   const size_t vb = (size_t)c->geo.N * force_vec_bytes(c->p.storage);
-  HIPCHK(c, hipMemsetAsync(c->L.FA, 0, vb, c->st));
-  HIPCHK(c, hipMemsetAsync(c->L.FB, 0, vb, c->st));
-  HIPCHK(c, hipMemsetAsync(c->L.mask, 0, mask_words(c->g) * 8, c->st));
+  HIPCHK(c, launch_zero(c->L.FA, vb, c->st));
+  HIPCHK(c, launch_zero(c->L.FB, vb, c->st));
+  HIPCHK(c, launch_zero(c->L.mask, mask_words(c->g) * 8, c->st));
   c->pend = 0;
   c->mvalid = false;
   c->uref[0] = c->uref[1] = c->uref[2] = 0.0;
@@ -791,7 +792,7 @@ lb_status lb_set_particles(lb_ctx* c, int64_t n, const double* d_pos, const doub
     if (d_vel)
       HIPCHK(c, hipMemcpyAsync(c->L.vel, d_vel, n * 24, hipMemcpyDeviceToDevice, c->st));
     else
-      HIPCHK(c, hipMemsetAsync(c->L.vel, 0, n * 24, c->st));
+      HIPCHK(c, launch_zero(c->L.vel, n * 24, c->st));
     if (d_mass) {
       HIPCHK(c, hipMemcpyAsync(c->L.mass, d_mass, n * 8, hipMemcpyDeviceToDevice, c->st));
     } else {

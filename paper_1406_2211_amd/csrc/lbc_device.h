@@ -737,14 +737,22 @@ __device__ __forceinline__ T phi_eval_t(int K, T r) {
 
 __device__ __forceinline__ double phi_eval(int K, double r) { return phi_eval_t<double>(K, r); }
 
+// floor(X) as an int for any X: the argument is first clamped to [-2^30, 2^30]
+// (a NaN becomes -2^30), so a non-finite or runaway position (an unstable run,
+// an over-stretched FENE bond) still maps to an in-range integer that the
+// periodic wrap or the wall test below can handle; its weights stay NaN.
+__device__ __forceinline__ int safe_floor(double X) {
+  return (int)floor(fmin(fmax(X, -1073741824.0), 1073741824.0));
+}
+
 // First node of the K-point stencil of X: nodes j0 .. j0+K-1.
 template <int K>
 __device__ __forceinline__ int first_node(double X) {
-  return K == 3 ? (int)floor(X + 0.5) - 1 : (K == 2 ? (int)floor(X) : (int)floor(X) - 1);
+  return K == 3 ? safe_floor(X + 0.5) - 1 : (K == 2 ? safe_floor(X) : safe_floor(X) - 1);
 }
 
 __device__ __forceinline__ int stencil(int K, double X, double w[4]) {
-  const int j0 = K == 3 ? (int)floor(X + 0.5) - 1 : (K == 2 ? (int)floor(X) : (int)floor(X) - 1);
+  const int j0 = K == 3 ? safe_floor(X + 0.5) - 1 : (K == 2 ? safe_floor(X) : safe_floor(X) - 1);
 #pragma unroll
   for (int k = 0; k < 4; ++k) w[k] = k < K ? phi_eval(K, (double)(j0 + k) - X) : 0.0;
   return j0;

@@ -110,6 +110,8 @@ struct PartArgs {
   double* fint;
   double* aux;  // IB predictor positions
   double gamma;
+  double fext[3];   // body-force density the fluid feels over the coupling step; it
+                    // enters the implicit force-coupling solve as +(beta/2) F_ext
   int coupling;
   int use_fint;     // F_int enters the coupling force and the kick (Alg. 3)
   int phys;         // interpolate the physical velocity (with pending FB)
@@ -227,6 +229,8 @@ hipError_t launch_totals(int storage, const SiteArgs& a, double* partial, int nb
 hipError_t launch_drift(const Geo& g, long long n, double* pos, const double* vel, double dt,
                         hipStream_t st);
 hipError_t launch_wrap(const Geo& g, long long n, double* pos, hipStream_t st);
+// Zeroes bytes (a multiple of 8) at p with a fill kernel.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_couple_half(int storage, const PartArgs& a, hipStream_t st);
 hipError_t launch_spread_deferred(int storage, const PartArgs& a, hipStream_t st);
 hipError_t launch_ib_predict(int storage, const PartArgs& a, hipStream_t st);

@@ -588,8 +588,10 @@ __global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
       const double sig = sqrt(2.0 * a.kT * a.gamma / hh);
       for (int k = 0; k < 3; ++k) zeta[k] = sig * zeta[k] / den;
     }
+    // Crank-Nicolson solution of Eq. fc-vel over hh (Eq. modified-force), the
+    // fluid at the particle also accelerated by the body force: +(beta/2) F_ext
     for (int k = 0; k < 3; ++k) {
-      Fh[k] = -(a.gamma * (v[k] - up[k]) + 0.5 * al * Fi[k]) / den;
+      Fh[k] = -(a.gamma * (v[k] - up[k]) + 0.5 * al * Fi[k] - 0.5 * be * a.fext[k]) / den;
       if (a.kT > 0.0) Fh[k] += zeta[k];
       v[k] += hh / m * (Fh[k] + Fi[k]);
     }
@@ -726,8 +728,8 @@ __device__ __forceinline__ void bond_pair(const BondArgs& b, const double r[3], 
   d[2] -= b.g.nz * floor(d[2] / b.g.nz + 0.5);
   const double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   double s;
-  if (b.type == LB_FENE)
-    s = b.k / (1.0 - L * L / (b.r0 * b.r0));
+  if (b.type == LB_FENE)  // infinite energy from L = r0 on: NaN, not the formula's sign flip
+    s = L < b.r0 ? b.k / (1.0 - L * L / (b.r0 * b.r0)) : __builtin_nan("");
   else
     s = L > 0.0 ? b.k * (L - b.r0) / L : 0.0;
   for (int k = 0; k < 3; ++k) F[k] += s * d[k];
@@ -1157,6 +1159,21 @@ hipError_t launch_wrap(const Geo& g, long long n, double* pos, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Zero fill of n 8-byte words (a kernel, so that a caller capturing the
+// library's calls in a HIP graph records kernel nodes only).
+__global__ void k_zero(unsigned long long* p, long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0ull;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const long long n = (long long)(bytes / 8);
+  if (n <= 0) return hipSuccess;
+  const long long blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+  k_zero<<<(unsigned)blocks, 256, 0, st>>>((unsigned long long*)p, n);
+  return hipGetLastError();
+}
+
 #define LBC_KERNEL_SWITCH(K, CALL)                        \
   switch (K) {                                            \
     case 2: { constexpr int KK = 2; CALL; } break;        \
@@ -1442,8 +1459,9 @@ __global__ __launch_bounds__(256) void k_ens_couple(EnsArgs e, int half) {
     double Fh[3];
     if (sl.coupling == LB_COUPLE_FC) {
       const double den = 1.0 + 0.5 * al + 0.5 * be;
+      const double fe[3] = {sl.fx, sl.fy, sl.fz};
       for (int k = 0; k < 3; ++k) {
-        Fh[k] = -(sl.gamma * (v[k] - up[k])) / den;
+        Fh[k] = -(sl.gamma * (v[k] - up[k]) - 0.5 * be * fe[k]) / den;
         v[k] += hh / m * Fh[k];
       }
     } else {

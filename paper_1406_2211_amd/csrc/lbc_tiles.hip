@@ -41,7 +41,7 @@ constexpr int kRegSites = kReg * kReg * kReg;
 __device__ __forceinline__ int tile_of(const TileArgs& t, const double X[3], int c[3]) {
   const int n[3] = {t.g.nx, t.g.ny, t.g.nz};
   for (int a = 0; a < 3; ++a) {
-    int j = (int)floor(X[a]);
+    int j = safe_floor(X[a]);
     if (j < 0) j = 0;
     if (j >= n[a]) j = n[a] - 1;
     c[a] = j / kTile;
