@@ -229,6 +229,23 @@ lb_status lb_timing_read(lb_ctx* ctx, double* lattice_ms, int64_t* passes);
 /* Number of particles, steps taken so far. */
 lb_status lb_info(const lb_ctx* ctx, int64_t* nparticles, int64_t* steps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lb_create
+ * with the workspace taken from a static device array of the library instead
+ * of the caller, 64 MiB per GPU (held by each GPU the library runs on until
+ * the process ends).  Allocates no device memory.  At most one context made
+ * this way is alive per device at a time (they would share the array):
+ * another call on the same device returns LB_EBUSY until lb_destroy of the
+ * first; contexts made by lb_create are unaffected.  The array keeps the
+ * last context's contents; the call initialises everything the context reads
+ * (as lb_create does).  The caller must not use the context from two threads
+ * or streams at once (calls that overlap on one device race on the array).
+ * Errors: LB_ENOMEM when lb_workspace_size of this box exceeds 64 MiB,
+ * LB_EBUSY as above, LB_EINVAL and LB_EDEVICE as lb_create.  Every other
+ * call works on the context as on one made by lb_create. */
+lb_status lb_create_static(const lb_grid* g, const lb_params* p, const lb_limits* lim,
+                           void* hip_stream, lb_ctx** out);
+
 lb_status lb_destroy(lb_ctx* ctx);
 const char* lb_last_error(const lb_ctx* ctx);
 const char* lb_status_string(lb_status s);

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -198,6 +199,7 @@ struct lb_ctx {
   int32_t ev_used = 0;
   int32_t ev_stride = 1;   // time one pass in every ev_stride
   int64_t ev_seen = 0;     // passes since timing was armed
+  int static_dev = -1;     // device whose static array holds the workspace (lb_create_static)
   std::string err;
 };
 
@@ -958,9 +960,12 @@ lb_status lb_info(const lb_ctx* c, int64_t* nparticles, int64_t* steps) {
   return LB_OK;
 }
 
+static void release_static(lb_ctx* c);
+
 lb_status lb_destroy(lb_ctx* c) {
   if (!c) return LB_OK;
   free_events(c);
+  release_static(c);
   delete c;
   return LB_OK;
 }
@@ -980,6 +985,71 @@ const char* lb_status_string(lb_status s) {
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// A context without caller memory: its workspace is a file-scope device array
+// of the library (one copy per GPU, held until the process ends).
+// ===========================================================================
+namespace {
+
+constexpr size_t kStaticBytes = size_t(64) << 20;  // 64 MiB per GPU
+constexpr int kMaxDevices = 64;
+
+struct StaticSlot {
+  void* ptr = nullptr;     // device address of this GPU's copy of `scratch`
+  lb_ctx* owner = nullptr; // the live context whose workspace it is
+};
+std::mutex g_static_mu;
+StaticSlot g_static[kMaxDevices];
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+static void release_static(lb_ctx* c) {
+  if (c->static_dev < 0) return;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (g_static[c->static_dev].owner == c) g_static[c->static_dev].owner = nullptr;
+  c->static_dev = -1;
+}
+
+extern "C" lb_status lb_create_static(const lb_grid* g, const lb_params* p, const lb_limits* lim,
+                                      void* hip_stream, lb_ctx** out) {
+  std::string err;
+  if (!out) return fail(nullptr, LB_EINVAL, "null output");
+  *out = nullptr;
+  if (!check_params(g, p, lim, err)) return fail(nullptr, LB_EINVAL, err);
+  const size_t need = carve(*g, *p, *lim, nullptr).bytes;
+  if (need > kStaticBytes)
+    return fail(nullptr, LB_ENOMEM,
+                "the box needs " + std::to_string(need) + " bytes of device memory; "
+                "lb_create_static holds at most " + std::to_string(kStaticBytes) +
+                " bytes (use lb_create with a caller workspace)");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(nullptr, LB_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, LB_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  StaticSlot& sl = g_static[dev];
+  if (sl.owner)
+    return fail(nullptr, LB_EBUSY,
+                "a context made by lb_create_static is alive on this device; destroy it first");
+  if (!sl.ptr) {  // first use on this device (which is current): resolve its copy of the array
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(nullptr, LB_EDEVICE,
+                  std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    sl.ptr = ptr;
+  }
+  lb_ctx* c = nullptr;
+  lb_status st = create_ctx(g, p, lim, sl.ptr, kStaticBytes, hip_stream, false, &c);
+  if (st != LB_OK) return st;
+  c->static_dev = dev;
+  sl.owner = c;
+  *out = c;
+  return LB_OK;
+}
 
 // ===========================================================================
 // Ensembles: many boxes resident in one caller-owned pool, stepped together.

@@ -25,7 +25,7 @@ LB_HARMONIC, LB_FENE = 0, 1
 EXPORTS = ["lb_lattice_velocities", "lb_workspace_size", "lb_create", "lb_init_fluid",
            "lb_set_particles", "lb_set_bonds", "lb_set_shells", "lb_step", "lb_moments",
            "lb_populations", "lb_stress", "lb_get_particles", "lb_totals", "lb_timing",
-           "lb_timing_read", "lb_info", "lb_destroy",
+           "lb_timing_read", "lb_info", "lb_create_static", "lb_destroy",
            "lb_last_error", "lb_status_string", "lb_ensemble_footprint", "lb_ensemble_create",
            "lb_ensemble_stream", "lb_ensemble_admit", "lb_ensemble_step", "lb_ensemble_query",
            "lb_ensemble_retire", "lb_ensemble_autotune", "lb_ensemble_destroy",
@@ -80,6 +80,7 @@ def load():
         "lb_lattice_velocities": (i32, [C.POINTER(i32)]),
         "lb_workspace_size": (i32, [G, P, M, C.POINTER(C.c_size_t)]),
         "lb_create": (i32, [G, P, M, vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "lb_create_static": (i32, [G, P, M, vp, C.POINTER(vp)]),
         "lb_init_fluid": (i32, [vp, vp, vp]),
         "lb_set_particles": (i32, [vp, i64, vp, vp, vp]),
         "lb_set_bonds": (i32, [vp, i64, vp, dbl, dbl, i32]),
@@ -159,10 +160,14 @@ def _ptr(t):
 class Lattice:
     """One lattice context.  Device memory (the workspace) is a torch uint8
     tensor owned by this object; all calls are enqueued on ``stream`` (a
-    torch.cuda.Stream; default: the current stream at construction)."""
+    torch.cuda.Stream; default: the current stream at construction).  With
+    static_workspace=True the context is made by lb_create_static instead and
+    takes its workspace from the library's static device array (no device
+    memory is allocated; one such context per device at a time)."""
 
     def __init__(self, nx, ny, nz, wall_y=0, max_particles=0, max_bonds=0, max_shells=0,
-                 max_shell_size=0, stream=None, device="cuda", _ctx=None, **params):
+                 max_shell_size=0, stream=None, device="cuda", _ctx=None, static_workspace=False,
+                 **params):
         import torch
         self.torch = torch
         if _ctx is not None:  # a slot of an ensemble: the ensemble owns memory and stream
@@ -184,6 +189,16 @@ class Lattice:
                                 int(max_shell_size))
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.shape = (int(nz), int(ny), int(nx))
+        self.N = int(nx) * int(ny) * int(nz)
+        self.np = 0
+        if static_workspace:
+            self.workspace = None
+            self.ctx = C.c_void_p()
+            _check(load().lb_create_static(C.byref(self.grid), C.byref(self.params),
+                                           C.byref(self.limits),
+                                           C.c_void_p(self.stream.cuda_stream), C.byref(self.ctx)))
+            return
         nbytes = workspace_size(self.grid, self.params, self.limits)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()

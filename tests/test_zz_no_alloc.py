@@ -1,0 +1,59 @@
+"""lb_create_static (the context whose workspace is the library's static
+device array, for callers that cannot allocate): through the C ABI, its
+results equal those of the same run on a context made by lb_create with a
+caller workspace, on two contexts in a row, the second on a smaller box."""
+import numpy as np
+import pytest
+
+from paper_1406_2211_amd import inputs as I
+from paper_1406_2211_amd import lbc as L
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(n, steps, static):
+    import torch
+    pos = I.uniform_positions(3, (n, n, n), 7)
+    vel = 1e-3 * np.random.default_rng(3).standard_normal((3, 3))
+    lat = L.Lattice(n, n, n, max_particles=3, static_workspace=static, tau=0.8,
+                    body_force=(1e-6, 0.0, -2e-6), coupling=L.LB_COUPLE_FC, gamma=1.0,
+                    kernel=L.LB_PHI3, storage=L.LB_F64)
+    lat.lb_init_fluid(None, torch.from_numpy(I.noise_velocity(lat.shape, 1e-4, 5)))
+    lat.lb_set_particles(torch.from_numpy(pos), torch.from_numpy(vel), torch.ones(3, dtype=torch.float64))
+    print(f"[gpu] no-alloc case n={n} steps={steps} static={static}", flush=True)
+    lat.lb_step(steps)
+    _, u = lat.lb_moments()
+    df = lat.lb_populations()
+    p, v = lat.lb_get_particles()
+    torch.cuda.synchronize()
+    out = dict(u=u.cpu().numpy(), df=df.cpu().numpy(), pos=p.cpu().numpy(), vel=v.cpu().numpy(),
+               tot=lat.lb_totals())
+    lat.lb_destroy()
+    return out
+
+
+def _same(a, b):
+    for k in a:
+        scale = max(np.abs(b[k]).max(), 1e-300)
+        assert np.abs(a[k] - b[k]).max() <= 1e-12 * scale, k
+
+
+def test_static_workspace_matches_caller_workspace():
+    for n, steps in ((24, 40), (12, 25)):  # the second call on a smaller box
+        _same(_run(n, steps, True), _run(n, steps, False))
+
+
+def test_static_workspace_limits():
+    import torch
+    big = L.Lattice(4, 4, 4, static_workspace=True, tau=0.8)
+    with pytest.raises(L.LbcError) as e:  # one static context per device at a time
+        L.Lattice(4, 4, 4, static_workspace=True, tau=0.8)
+    assert e.value.status == L.LB_EBUSY
+    big.lb_destroy()
+    with pytest.raises(L.LbcError) as e:  # host-side size check, nothing enqueued
+        L.Lattice(256, 256, 256, static_workspace=True, tau=0.8, storage=L.LB_F32)
+    assert e.value.status == L.LB_ENOMEM and "at most" in str(e.value)
+    again = L.Lattice(8, 8, 8, static_workspace=True, tau=0.8)
+    again.lb_step(3)
+    torch.cuda.synchronize()
+    again.lb_destroy()
