@@ -127,17 +127,24 @@ typedef struct lb_limits {
 
 typedef struct lb_ctx lb_ctx;
 
-/* D3Q19 velocity set in library order, c[i*3 + a]; returns 19. */
+/* D3Q19 velocity set (the discrete velocities c_i of Sec. 2, Eq.
+ * discrete-Boltzmann; the paper fixes no particular set) in library order,
+ * c[i*3 + a] into a caller array of 57; returns 19.  No error. */
 int32_t lb_lattice_velocities(int32_t c[57]);
 
 /* Device bytes needed for a context of this size (a pure function of the
- * arguments).  The caller allocates them (alignment 256 B) and passes them to
- * lb_create. */
+ * arguments): the two population buffers of the pull stream (Sec. 3.1), the
+ * coupling force fields of the two half steps (Sec. 5), particle state and
+ * tables.  The caller allocates them (alignment 256 B) and passes them to
+ * lb_create.  Errors: LB_EINVAL for invalid arguments (checked on the host). */
 lb_status lb_workspace_size(const lb_grid* g, const lb_params* p, const lb_limits* lim,
                             size_t* bytes);
 
-/* Creates a context on the current HIP device.  The workspace and the stream
- * (a hipStream_t, or NULL for the null stream) are borrowed: the caller keeps
+/* Creates a context on the current HIP device: the lattice of Sec. 3 (Eq.
+ * split-lb) with the relaxation time and collision of Sec. 3.2 (Eq.
+ * collision-operator, Eq. mrt-coll), the forcing of Sec. 3.3 and the coupling
+ * scheme of Sec. 5 chosen in lb_params.  The workspace and the stream (a
+ * hipStream_t, or NULL for the null stream) are borrowed: the caller keeps
  * them alive until lb_destroy.  Initialises the fluid at rest,
  * f = f^eq(rho0, 0), with no particles.  Errors: LB_EINVAL (bad grid or
  * parameters, e.g. tau <= 1/2), LB_ENOMEM (workspace smaller than
@@ -150,11 +157,15 @@ lb_status lb_create(const lb_grid* g, const lb_params* p, const lb_limits* lim,
  * rho0 and 0. */
 lb_status lb_init_fluid(lb_ctx* ctx, const double* d_rho, const double* d_u);
 
-/* Copies n particles (FC/EBF: positions r, velocities v, masses m > 0; IB:
- * marker positions X, velocities and masses ignored and may be NULL) into the
- * context.  FP64 device arrays [n][3], [n][3], [n].  Positions in periodic
- * directions are wrapped into [0, L).  Errors: LB_ENOMEM if n exceeds
- * max_particles, LB_EINVAL for n < 0. */
+/* Copies n particles into the context: for FC/EBF the positions r_i,
+ * velocities v_i and masses m_i > 0 of the particle equations of motion
+ * (Sec. 5.2, Eq. fc-vel and the equations before Eq. fc-splitting); for IB
+ * the Lagrangian marker positions X_i of Sec. 5.1 (velocities and masses are
+ * ignored and may be NULL; markers move with the interpolated fluid).  FP64
+ * device arrays [n][3], [n][3], [n], read (copied) on the context stream.
+ * Positions in periodic directions are wrapped into [0, L).  Errors:
+ * LB_ENOMEM if n exceeds max_particles, LB_EINVAL for n < 0 or a NULL array
+ * that is needed. */
 lb_status lb_set_particles(lb_ctx* ctx, int64_t n, const double* d_pos, const double* d_vel,
                            const double* d_mass);
 
@@ -206,12 +217,20 @@ lb_status lb_populations(lb_ctx* ctx, double* d_df);
  * shifts and do not enter it.  Asynchronous. */
 lb_status lb_stress(lb_ctx* ctx, double* d_sigma);
 
-/* Current particle positions and velocities, FP64 device [n][3] (either may be NULL). */
+/* Current particle positions and velocities (r_i, v_i of Sec. 5.2; for IB the
+ * marker positions X_i of Sec. 5.1 and zero velocities) at the step boundary,
+ * copied on the context stream into FP64 device arrays [n][3] owned by the
+ * caller (either may be NULL).  Asynchronous; no error beyond a NULL context. */
 lb_status lb_get_particles(lb_ctx* ctx, double* d_pos, double* d_vel);
 
-/* Conserved totals in FP64, reduced on the device in a fixed order:
- * h_out[0] = sum_x rho - N rho0, h_out[1..3] = fluid momentum sum_x rho u,
- * h_out[4..6] = particle momentum sum_p m_p v_p (0 for IB).  Synchronous. */
+/* Conserved totals in FP64, reduced on the device in a fixed order: mass,
+ * conserved by collision and streaming (Sec. 3.1, 3.2), and momentum, which
+ * the coupling exchanges between fluid and particles with equal and opposite
+ * forces (Sec. 5.2, the force on the fluid is -I* F^h).
+ * h_out[0] = sum_x rho - N rho0, h_out[1..3] = fluid momentum sum_x rho u of
+ * the physical state (Sec. 4), h_out[4..6] = particle momentum sum_p m_p v_p
+ * (0 for IB).  h_out is a host array of 7.  Synchronous (waits for the
+ * context stream). */
 lb_status lb_totals(lb_ctx* ctx, double h_out[7]);
 
 /* Kernel timing for measurement: with max_passes > 0, of the fused lattice
@@ -226,7 +245,8 @@ lb_status lb_totals(lb_ctx* ctx, double h_out[7]);
 lb_status lb_timing(lb_ctx* ctx, int32_t max_passes, int32_t stride);
 lb_status lb_timing_read(lb_ctx* ctx, double* lattice_ms, int64_t* passes);
 
-/* Number of particles, steps taken so far. */
+/* Number of particles and time steps taken so far (host-side counters, no
+ * device work). */
 lb_status lb_info(const lb_ctx* ctx, int64_t* nparticles, int64_t* steps);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -246,8 +266,12 @@ lb_status lb_info(const lb_ctx* ctx, int64_t* nparticles, int64_t* steps);
 lb_status lb_create_static(const lb_grid* g, const lb_params* p, const lb_limits* lim,
                            void* hip_stream, lb_ctx** out);
 
+/* Frees the host-side context (the workspace and stream stay the caller's;
+ * a lb_create_static context releases the device's static array). */
 lb_status lb_destroy(lb_ctx* ctx);
+/* Message of the last failed call on ctx (NULL: of a failed creation). */
 const char* lb_last_error(const lb_ctx* ctx);
+/* Text of a status code. */
 const char* lb_status_string(lb_status s);
 
 /* ------------------------------------------------------------------------
@@ -261,18 +285,26 @@ const char* lb_status_string(lb_status s);
  * ------------------------------------------------------------------------ */
 typedef struct lb_ensemble lb_ensemble;
 
-/* Device bytes one box occupies in the pool (its admission footprint). */
+/* Device bytes one box occupies in the pool (its admission footprint): the
+ * same workspace as lb_workspace_size. */
 lb_status lb_ensemble_footprint(const lb_grid* g, const lb_params* p, const lb_limits* lim,
                                 size_t* bytes);
 
-/* Creates an ensemble over the borrowed device pool d_pool (256-byte aligned,
- * kept alive by the caller until lb_ensemble_destroy) for at most max_slots
- * boxes, all with the given storage precision and delta kernel.  The ensemble
- * creates its own (default-priority, blocking) stream; lb_ensemble_stream
- * returns it, and every operation on the ensemble and on its slots is ordered
- * on it. */
+/* Creates an ensemble (the batching form: independent runs of the method of
+ * Sec. 5.2 stepped together) over the borrowed device pool d_pool (256-byte
+ * aligned, kept alive by the caller until lb_ensemble_destroy) for at most
+ * max_slots boxes, all with the given storage precision and delta kernel.
+ * Every operation on the ensemble and on its slots is ordered on hip_stream
+ * (a hipStream_t the caller keeps alive until lb_ensemble_destroy; the batched
+ * steps are captured from it into HIP graphs, so it must not be the legacy
+ * null stream).  With hip_stream NULL the ensemble creates its own blocking
+ * default-priority stream and destroys it with the ensemble.
+ * lb_ensemble_stream returns the stream in use.  Errors: LB_EINVAL (pool
+ * misaligned, max_slots outside [1, 65536], unknown storage or kernel),
+ * LB_ENOMEM (pool smaller than the slot tables), LB_EDEVICE. */
 lb_status lb_ensemble_create(void* d_pool, size_t bytes, int32_t max_slots, int32_t storage,
-                             int32_t kernel, lb_ensemble** out);
+                             int32_t kernel, void* hip_stream, lb_ensemble** out);
+/* The stream the ensemble's work is ordered on (the caller's, or its own). */
 lb_status lb_ensemble_stream(lb_ensemble* e, void** stream);
 
 /* Admits a box with a budget of nsteps time steps.  Returns its slot and a
@@ -286,8 +318,9 @@ lb_status lb_ensemble_stream(lb_ensemble* e, void** stream);
 lb_status lb_ensemble_admit(lb_ensemble* e, const lb_grid* g, const lb_params* p,
                             const lb_limits* lim, int64_t nsteps, int32_t* slot, lb_ctx** ctx);
 
-/* Advances every live box by nsteps steps (boxes whose budget is spent do
- * not move).  Asynchronous on the ensemble stream. */
+/* Advances every live box by nsteps time steps of Eq. fc-splitting in the
+ * ordering of Alg. 3 (boxes whose budget is spent do not move).  Asynchronous
+ * on the ensemble stream.  Errors: LB_EINVAL for nsteps < 0, LB_EDEVICE. */
 lb_status lb_ensemble_step(lb_ensemble* e, int64_t nsteps);
 
 /* Waits for the ensemble stream and reports the steps a slot has taken and
@@ -295,7 +328,8 @@ lb_status lb_ensemble_step(lb_ensemble* e, int64_t nsteps);
  * lb_moments and the other queries.  Synchronous. */
 lb_status lb_ensemble_query(lb_ensemble* e, int32_t slot, int64_t* steps_done, int32_t* done);
 
-/* Frees a slot and its pool memory (its context handle becomes invalid). */
+/* Frees a slot and its pool memory (its context handle becomes invalid).
+ * Errors: LB_EINVAL for a slot that is not live. */
 lb_status lb_ensemble_retire(lb_ensemble* e, int32_t slot);
 
 /* Times steps_per_candidate real steps of the live mix under each candidate
@@ -304,7 +338,10 @@ lb_status lb_ensemble_retire(lb_ensemble* e, int32_t slot);
 lb_status lb_ensemble_autotune(lb_ensemble* e, int32_t steps_per_candidate, int32_t* lat_grid,
                                int32_t* part_grid);
 
+/* Waits for the ensemble stream, frees every slot and the host-side state
+ * (the pool and a borrowed stream stay the caller's). */
 lb_status lb_ensemble_destroy(lb_ensemble* e);
+/* Message of the last failed call on e (NULL: of a failed lb_ensemble_create). */
 const char* lb_ensemble_last_error(const lb_ensemble* e);
 
 #ifdef __cplusplus

@@ -1072,6 +1072,7 @@ struct lb_ensemble {
   char* pool = nullptr;
   size_t bytes = 0, head = 0;
   hipStream_t st = nullptr;
+  bool own_stream = false;  // created by lb_ensemble_create (no stream was given)
   int max_slots = 0, storage = LB_F32, kernel = 2;
   EnsSlot* d_slots = nullptr;
   int2* d_litems = nullptr;
@@ -1250,7 +1251,7 @@ lb_status lb_ensemble_footprint(const lb_grid* g, const lb_params* p, const lb_l
 }
 
 lb_status lb_ensemble_create(void* d_pool, size_t bytes, int32_t max_slots, int32_t storage,
-                             int32_t kernel, lb_ensemble** out) {
+                             int32_t kernel, void* hip_stream, lb_ensemble** out) {
   if (!out) return efail(nullptr, LB_EINVAL, "null output");
   *out = nullptr;
   if (!d_pool || ((uintptr_t)d_pool & 255)) return efail(nullptr, LB_EINVAL, "pool must be 256-byte aligned");
@@ -1287,10 +1288,16 @@ lb_status lb_ensemble_create(void* d_pool, size_t bytes, int32_t max_slots, int3
       e->part_grid = 2 * e->cus;
     }
   }
-  hipError_t r = hipStreamCreate(&e->st);
-  if (r != hipSuccess) {
-    delete e;
-    return efail(nullptr, LB_EDEVICE, hipGetErrorString(r));
+  if (hip_stream) {  // borrowed: the caller keeps it alive until lb_ensemble_destroy
+    e->st = (hipStream_t)hip_stream;
+    e->own_stream = false;
+  } else {  // the legacy null stream cannot be captured: make a default-priority stream
+    hipError_t r = hipStreamCreate(&e->st);
+    if (r != hipSuccess) {
+      delete e;
+      return efail(nullptr, LB_EDEVICE, hipGetErrorString(r));
+    }
+    e->own_stream = true;
   }
   std::vector<EnsSlot> zero(max_slots);
   for (auto& z : zero) z.live = 0;
@@ -1298,7 +1305,7 @@ lb_status lb_ensemble_create(void* d_pool, size_t bytes, int32_t max_slots, int3
   if (hipMemcpy(e->d_slots, zero.data(), zero.size() * sizeof(EnsSlot), hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemcpy(e->d_counts, counts, sizeof(counts), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipStreamDestroy(e->st);
+    if (e->own_stream) (void)hipStreamDestroy(e->st);
     delete e;
     return efail(nullptr, LB_EDEVICE, "cannot initialise the ensemble tables");
   }
@@ -1453,7 +1460,7 @@ lb_status lb_ensemble_destroy(lb_ensemble* e) {
   for (auto& h : e->slots)
     if (h.live) lb_destroy(h.ctx);
   ens_drop_graphs(e);
-  (void)hipStreamDestroy(e->st);
+  if (e->own_stream) (void)hipStreamDestroy(e->st);
   delete e;
   return LB_OK;
 }

@@ -98,7 +98,7 @@ def load():
         "lb_last_error": (C.c_char_p, [vp]),
         "lb_status_string": (C.c_char_p, [i32]),
         "lb_ensemble_footprint": (i32, [G, P, M, C.POINTER(C.c_size_t)]),
-        "lb_ensemble_create": (i32, [vp, C.c_size_t, i32, i32, i32, C.POINTER(vp)]),
+        "lb_ensemble_create": (i32, [vp, C.c_size_t, i32, i32, i32, vp, C.POINTER(vp)]),
         "lb_ensemble_stream": (i32, [vp, C.POINTER(vp)]),
         "lb_ensemble_admit": (i32, [vp, G, P, M, i64, C.POINTER(i32), C.POINTER(vp)]),
         "lb_ensemble_step": (i32, [vp, i64]),
@@ -320,12 +320,18 @@ def ensemble_footprint(nx, ny, nz, max_particles=0, **params):
 
 class Ensemble:
     """Many periodic boxes resident in one device pool (a torch uint8 tensor)
-    and stepped together by batched launches replayed from HIP graphs."""
+    and stepped together by batched launches replayed from HIP graphs, all
+    ordered on ``stream`` (a torch.cuda.Stream the library borrows).  Without
+    one the library makes its own blocking default-priority stream (the legacy
+    null stream cannot be captured), which orders with work on torch's default
+    stream."""
 
-    def __init__(self, pool_bytes, max_slots, storage=LB_F32, kernel=LB_PHI2, device="cuda"):
+    def __init__(self, pool_bytes, max_slots, storage=LB_F32, kernel=LB_PHI2, device="cuda",
+                 stream=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
+        self.stream = stream
         self.pool = torch.empty(int(pool_bytes) + 256, dtype=torch.uint8, device=self.device)
         base = self.pool.data_ptr()
         ptr = base + ((-base) % 256)
@@ -333,7 +339,9 @@ class Ensemble:
         self.ens = C.c_void_p()
         torch.cuda.synchronize(self.device)
         _echeck(load().lb_ensemble_create(C.c_void_p(ptr), int(pool_bytes), int(max_slots),
-                                          self.storage, self.kernel, C.byref(self.ens)))
+                                          self.storage, self.kernel,
+                                          None if stream is None else C.c_void_p(stream.cuda_stream),
+                                          C.byref(self.ens)))
         st = C.c_void_p()
         _echeck(load().lb_ensemble_stream(self.ens, C.byref(st)), self.ens)
         self.stream_ptr = st.value
