@@ -80,7 +80,14 @@ typedef struct lb_params {
   int32_t f16_scale_log2;/* LB_F16/LB_BF16: stored value is 2^p (f - w rho0) */
   int32_t mts_substeps;  /* 0: Alg. 3 ordering; n > 0: Sec. 6 split with the coupling
                             outside and n velocity-Verlet sub-steps on each side */
-  int32_t deterministic; /* reserved, must be 0 */
+  int32_t deterministic; /* 0: spreading (Eq. IBM-spreading, the adjoint of interpolation) adds
+                            each contribution W F to its site with a floating-point atomic, so
+                            the order of the additions, and the rounding of the sum, varies
+                            from run to run.  1: the sum at each site is formed exactly in
+                            128-bit fixed point (resolution 2^-96, contributions below 2^20)
+                            with integer atomics and then rounded once, so every run gives
+                            bitwise the same result, alone or in an ensemble mix.  Slower
+                            (two extra launches per spread, 48 B of accumulator per site). */
   int32_t comoving;      /* 0: store f - w rho0; 1: store f - f^eq(rho0, U_ref) with U_ref
                             advancing by F_ext/rho0 per step (the mean velocity a uniform body
                             force gives the fluid); an exact change of variables that keeps
@@ -293,7 +300,9 @@ lb_status lb_ensemble_footprint(const lb_grid* g, const lb_params* p, const lb_l
 /* Creates an ensemble (the batching form: independent runs of the method of
  * Sec. 5.2 stepped together) over the borrowed device pool d_pool (256-byte
  * aligned, kept alive by the caller until lb_ensemble_destroy) for at most
- * max_slots boxes, all with the given storage precision and delta kernel.
+ * max_slots boxes, all with the given storage precision and delta kernel and
+ * the given spreading mode (deterministic 0 or 1, which every admitted box's
+ * lb_params.deterministic must match, see there).
  * Every operation on the ensemble and on its slots is ordered on hip_stream
  * (a hipStream_t the caller keeps alive until lb_ensemble_destroy; the batched
  * steps are captured from it into HIP graphs, so it must not be the legacy
@@ -303,7 +312,8 @@ lb_status lb_ensemble_footprint(const lb_grid* g, const lb_params* p, const lb_l
  * misaligned, max_slots outside [1, 65536], unknown storage or kernel),
  * LB_ENOMEM (pool smaller than the slot tables), LB_EDEVICE. */
 lb_status lb_ensemble_create(void* d_pool, size_t bytes, int32_t max_slots, int32_t storage,
-                             int32_t kernel, void* hip_stream, lb_ensemble** out);
+                             int32_t kernel, int32_t deterministic, void* hip_stream,
+                             lb_ensemble** out);
 /* The stream the ensemble's work is ordered on (the caller's, or its own). */
 lb_status lb_ensemble_stream(lb_ensemble* e, void** stream);
 

@@ -46,6 +46,7 @@ struct Layout {
   int *tcount, *tstart, *tcursor, *tocc, *tnocc, *ptile, *psorted;
   double4* mcache;
   int4* mbase;
+  uint64_t* det;  // fixed-point spreading accumulator [N][3][2] (deterministic mode)
   size_t bytes;
 };
 
@@ -98,6 +99,7 @@ Layout carve(const lb_grid& g, const lb_params& p, const lb_limits& lim, void* b
   const bool cached = p.coupling == LB_COUPLE_FC || p.coupling == LB_COUPLE_EBF;
   L.mcache = c.take<double4>(cached ? np * kernel_lanes(p.kernel) * 32 : 32);
   L.mbase = c.take<int4>(cached ? np * 16 : 16);
+  L.det = c.take<uint64_t>(p.deterministic ? (size_t)N * 48 : 64);
   L.bytes = c.off;
   return L;
 }
@@ -144,7 +146,7 @@ bool check_params(const lb_grid* g, const lb_params* p, const lb_limits* lim, st
     return err = "the comoving storage frame is not combined with thermal fluctuations", false;
   if (p->mts_inside && p->mts_substeps < 1)
     return err = "mts_inside needs mts_substeps >= 1", false;
-  if (p->deterministic != 0) return err = "deterministic mode is not available", false;
+  if (p->deterministic != 0 && p->deterministic != 1) return err = "deterministic must be 0 or 1", false;
   if (p->comoving != 0 && p->comoving != 1) return err = "comoving must be 0 or 1", false;
   if (p->comoving && g->wall_y)
     return err = "the comoving storage frame needs a periodic box (walls break uniform flow)", false;
@@ -516,6 +518,37 @@ static lb_status finish_step(lb_ctx* c) {
   return LB_OK;
 }
 
+// One coupling step (k_couple_half).  In the deterministic mode the kernel
+// stores each particle's lattice force instead of spreading it (into aux,
+// unused by force coupling), and the fixed-point spread (with the closing
+// drift, if any) and its finalize into the target field follow.
+static lb_status couple(lb_ctx* c, const PartArgs& a) {
+  if (!c->p.deterministic) {
+    HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
+    return LB_OK;
+  }
+  PartArgs b = a;
+  b.defer = c->L.aux;
+  b.drift_after = 0;
+  HIPCHK(c, launch_couple_half(c->p.storage, b, c->st));
+  PartArgs d = a;
+  d.defer = nullptr;
+  HIPCHK(c, launch_spread_det(d, c->L.pos, c->L.aux, c->L.det, c->st));
+  HIPCHK(c, launch_det_finalize(c->p.storage, c->geo, c->L.mask, c->L.det,
+                                a.target ? c->L.FB : c->L.FA, c->st));
+  return LB_OK;
+}
+
+// Deterministic spread of the intrinsic forces at the IB predictor positions
+// X~ (aux) into FA.
+static lb_status spread_fint_det(lb_ctx* c) {
+  PartArgs a = part_args(c);
+  a.drift_after = 0;
+  HIPCHK(c, launch_spread_det(a, c->L.aux, c->L.fint, c->L.det, c->st));
+  HIPCHK(c, launch_det_finalize(c->p.storage, c->geo, c->L.mask, c->L.det, c->L.FA, c->st));
+  return LB_OK;
+}
+
 // Multiple time stepping with the coupling inside (Eq. multistep): n coupled
 // sub-steps of dt = h/2n on each side of the lattice pass.  A sub-step drifts
 // dt/2, takes the intrinsic force at the midpoint, couples over dt (F^h, kick,
@@ -554,8 +587,8 @@ static lb_status step_mts_inside(lb_ctx* c) {
       a.fa_rd = (side == 0 && k > 0) ? 1 : 0;
       a.cache_fill = (side == 1 && k == 0) ? 1 : 0;
       a.cache_use = (side == 1 && k > 0) || (side == 0 && c->mvalid) ? 1 : 0;
-      if (k == 0) {
-        HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
+      if (k == 0 || c->p.deterministic) {  // (the deterministic spread is a launch of its own)
+        if ((s = couple(c, a)) != LB_OK) return s;
       } else {  // spread and closing drift in a second launch, from the midpoint positions
         a.defer = c->L.aux;
         PartArgs b = a;
@@ -600,7 +633,11 @@ static lb_status step_once(lb_ctx* c) {
     bool any;
     if ((s = enqueue_fint(c, c->L.aux, any)) != LB_OK) return s;
     if (!any) HIPCHK(c, launch_zero(c->L.fint, (size_t)c->np * 24, c->st));
-    HIPCHK(c, launch_tile_spread(S, K, t, c->L.aux, c->L.fint, c->L.FA, c->np, c->st));
+    if (c->p.deterministic) {
+      if ((s = spread_fint_det(c)) != LB_OK) return s;
+    } else {
+      HIPCHK(c, launch_tile_spread(S, K, t, c->L.aux, c->L.fint, c->L.FA, c->np, c->st));
+    }
     // The second half force is the same spread of the same F_int at X~: the
     // lattice pass keeps the first-half field as the pending one (ib_copy).
     if ((s = lattice_pass(c)) != LB_OK) return s;
@@ -613,7 +650,8 @@ static lb_status step_once(lb_ctx* c) {
     bool any;
     if ((s = enqueue_fint(c, c->L.aux, any)) != LB_OK) return s;
     if (!any) HIPCHK(c, launch_zero(c->L.fint, (size_t)c->np * 24, c->st));
-    HIPCHK(c, launch_ib_advect(c->p.storage, a, 1, c->st));
+    HIPCHK(c, launch_ib_advect(c->p.storage, a, c->p.deterministic ? 0 : 1, c->st));
+    if (c->p.deterministic && (s = spread_fint_det(c)) != LB_OK) return s;
     if ((s = lattice_pass(c)) != LB_OK) return s;  // FB <- FA (ib_copy)
     a = part_args(c);
     HIPCHK(c, launch_ib_advect(c->p.storage, a, 0, c->st));
@@ -626,7 +664,7 @@ static lb_status step_once(lb_ctx* c) {
     PartArgs a = part_args(c);
     a.target = 0;
     a.cache_use = c->mvalid ? 1 : 0;
-    HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
+    if ((s = couple(c, a)) != LB_OK) return s;
     // The 2n intrinsic-force sub-steps between the two coupling halves touch
     // only particle state and the lattice pass only fluid state, so all 2n
     // run together (bitwise the same as n, pass, n): as extra workgroups of
@@ -646,7 +684,7 @@ static lb_status step_once(lb_ctx* c) {
     a.target = 1;
     a.cache_fill = 1;
     a.jc = 1;
-    HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
+    if ((s = couple(c, a)) != LB_OK) return s;
     c->mvalid = true;
     return LB_OK;
   }
@@ -660,7 +698,7 @@ static lb_status step_once(lb_ctx* c) {
   a.drift_before = fint ? 0 : 1;
   a.target = 0;
   a.cache_use = c->mvalid ? 1 : 0;
-  HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
+  if ((s = couple(c, a)) != LB_OK) return s;
   if ((s = lattice_pass(c)) != LB_OK) return s;
   a = part_args(c);
   a.use_fint = any ? 1 : 0;
@@ -669,7 +707,7 @@ static lb_status step_once(lb_ctx* c) {
   a.drift_after = 1;
   a.cache_fill = 1;
   a.jc = 1;
-  HIPCHK(c, launch_couple_half(c->p.storage, a, c->st));
+  if ((s = couple(c, a)) != LB_OK) return s;
   c->mvalid = true;
   return LB_OK;
 }
@@ -773,6 +811,7 @@ lb_status lb_init_fluid(lb_ctx* c, const double* d_rho, const double* d_u) {
   HIPCHK(c, launch_zero(c->L.FA, vb, c->st));
   HIPCHK(c, launch_zero(c->L.FB, vb, c->st));
   HIPCHK(c, launch_zero(c->L.mask, mask_words(c->g) * 8, c->st));
+  if (c->p.deterministic) HIPCHK(c, launch_zero(c->L.det, (size_t)c->geo.N * 48, c->st));
   c->pend = 0;
   c->mvalid = false;
   c->uref[0] = c->uref[1] = c->uref[2] = 0.0;
@@ -1074,6 +1113,7 @@ struct lb_ensemble {
   hipStream_t st = nullptr;
   bool own_stream = false;  // created by lb_ensemble_create (no stream was given)
   int max_slots = 0, storage = LB_F32, kernel = 2;
+  int det = 0;  // deterministic spreading in every slot
   EnsSlot* d_slots = nullptr;
   int2* d_litems = nullptr;
   int2* d_pitems = nullptr;
@@ -1138,6 +1178,9 @@ static EnsSlot slot_from_ctx(const lb_ctx* c) {
   s.omp = c->omp;
   s.omm = c->omm;
   s.gamma = c->p.gamma;
+  s.det_on = c->p.deterministic;
+  s.aux = c->L.aux;
+  s.det = c->L.det;
   s.scale = c->scale;
   s.inv = c->inv;
   s.collision = c->p.collision;
@@ -1215,7 +1258,7 @@ static lb_status ens_build_graphs(lb_ensemble* e) {
     hipGraph_t graph;
     EHIPCHK(e, hipStreamBeginCapture(e->st, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < n; ++k) {
-      hipError_t r = launch_ens_step(e->storage, e->kernel, a, e->lat_grid, e->part_grid, e->st);
+      hipError_t r = launch_ens_step(e->storage, e->kernel, a, e->lat_grid, e->part_grid, e->det, e->st);
       if (r != hipSuccess) {
         (void)hipStreamEndCapture(e->st, &graph);
         e->err = std::string("capture: ") + hipGetErrorString(r);
@@ -1251,7 +1294,8 @@ lb_status lb_ensemble_footprint(const lb_grid* g, const lb_params* p, const lb_l
 }
 
 lb_status lb_ensemble_create(void* d_pool, size_t bytes, int32_t max_slots, int32_t storage,
-                             int32_t kernel, void* hip_stream, lb_ensemble** out) {
+                             int32_t kernel, int32_t deterministic, void* hip_stream,
+                             lb_ensemble** out) {
   if (!out) return efail(nullptr, LB_EINVAL, "null output");
   *out = nullptr;
   if (!d_pool || ((uintptr_t)d_pool & 255)) return efail(nullptr, LB_EINVAL, "pool must be 256-byte aligned");
@@ -1259,7 +1303,10 @@ lb_status lb_ensemble_create(void* d_pool, size_t bytes, int32_t max_slots, int3
   if (storage != LB_F32 && storage != LB_F16 && storage != LB_BF16 && storage != LB_F64)
     return efail(nullptr, LB_EINVAL, "unknown storage");
   if (kernel < 2 || kernel > 4) return efail(nullptr, LB_EINVAL, "kernel must be 2, 3 or 4");
+  if (deterministic != 0 && deterministic != 1)
+    return efail(nullptr, LB_EINVAL, "deterministic must be 0 or 1");
   lb_ensemble* e = new lb_ensemble();
+  e->det = deterministic;
   e->pool = (char*)d_pool;
   e->bytes = bytes;
   e->max_slots = max_slots;
@@ -1328,6 +1375,8 @@ lb_status lb_ensemble_admit(lb_ensemble* e, const lb_grid* g, const lb_params* p
   if (p->coupling == LB_COUPLE_IB || p->mts_substeps != 0)
     return efail(e, LB_EINVAL, "ensemble members use FC, EBF or no coupling without sub-steps");
   if (p->kT != 0.0) return efail(e, LB_EINVAL, "ensemble members are deterministic (kT = 0)");
+  if (p->deterministic != e->det)
+    return efail(e, LB_EINVAL, "deterministic spreading must match the ensemble's");
   if (p->collision == LB_MRT)
     return efail(e, LB_EINVAL, "ensemble members use the BGK or two-rate collision");
   if (lim->max_bonds != 0 || lim->max_shells != 0)
@@ -1431,7 +1480,7 @@ lb_status lb_ensemble_autotune(lb_ensemble* e, int32_t steps_per_candidate, int3
     for (int pg : part_c) {
       EHIPCHK(e, hipEventRecord(t0, e->st));
       for (int k = 0; k < steps_per_candidate; ++k)
-        EHIPCHK(e, launch_ens_step(e->storage, e->kernel, a, lg, pg, e->st));
+        EHIPCHK(e, launch_ens_step(e->storage, e->kernel, a, lg, pg, e->det, e->st));
       EHIPCHK(e, hipEventRecord(t1, e->st));
       EHIPCHK(e, hipEventSynchronize(t1));
       float ms;

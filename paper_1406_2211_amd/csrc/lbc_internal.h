@@ -199,6 +199,9 @@ struct EnsSlot {
   int mvalid;       // the cache holds the state of f[cur]
   double cm[40];    // comoving reference terms of the next pass (comoving_terms)
   float cmf[40];    // the same in FP32
+  int det_on;       // deterministic spreading: lattice forces stored in aux, summed in det
+  double* aux;      // [np][3]
+  uint64_t* det;    // [N][3][2] fixed-point accumulator
 };
 
 struct EnsArgs {
@@ -210,8 +213,9 @@ struct EnsArgs {
   const int* npitems;
 };
 
+// det: the deterministic spreading kernels run after each coupling half
 hipError_t launch_ens_step(int storage, int K, const EnsArgs& e, int lat_grid, int part_grid,
-                           hipStream_t st);
+                           int det, hipStream_t st);
 
 hipError_t launch_stream_collide(int storage, bool comoving, const LatArgs& a, hipStream_t st);
 hipError_t launch_init(int storage, const InitArgs& a, hipStream_t st);
@@ -233,6 +237,14 @@ hipError_t launch_wrap(const Geo& g, long long n, double* pos, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_couple_half(int storage, const PartArgs& a, hipStream_t st);
 hipError_t launch_spread_deferred(int storage, const PartArgs& a, hipStream_t st);
+// Deterministic spreading: W F of every particle (positions X, lattice forces
+// F [n][3]) into the 128-bit fixed-point accumulator acc [N][3][2], flagging
+// the sites (and the closing drift if a.drift_after); then field += the sums
+// at every flagged site and acc back to zero there.
+hipError_t launch_spread_det(const PartArgs& a, const double* X, const double* F, uint64_t* acc,
+                             hipStream_t st);
+hipError_t launch_det_finalize(int storage, const Geo& g, const uint64_t* mask, uint64_t* acc,
+                               void* field, hipStream_t st);
 hipError_t launch_ib_predict(int storage, const PartArgs& a, hipStream_t st);
 hipError_t launch_ib_advect(int storage, const PartArgs& a, int spread_fint, hipStream_t st);
 hipError_t launch_bond_groups(const BondArgs& b, int ngroups, int gcap, int mode, int acc,

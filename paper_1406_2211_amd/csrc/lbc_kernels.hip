@@ -649,6 +649,123 @@ __global__ __launch_bounds__(256) void k_spread_deferred(PartArgs a) {
   }
 }
 
+// ----------------------------------------------- deterministic spreading
+// Spreading (Eq. IBM-spreading) as an exact sum: every contribution W F is
+// converted to a 128-bit fixed-point number q 2^-96 (two's complement, words
+// lo and hi) and added to the site's accumulator with 64-bit integer
+// atomics.  Integer addition is associative, so the sum does not depend on
+// the order in which the contributions arrive; a finalize pass then adds the
+// converted sum to the force field.  Range: contributions below 2^20 in
+// magnitude (larger or non-finite ones become a marker that reads back as
+// NaN), resolution 2^-96.
+constexpr int kFixShift = 96;
+
+__device__ __forceinline__ void to_fixed(double c, uint64_t& lo, uint64_t& hi) {
+  const double a = fabs(c);
+  if (!(a < 1048576.0)) {  // non-finite or beyond any force of a stable run
+    lo = 0ull;
+    hi = 1ull << 56;
+    return;
+  }
+  lo = hi = 0ull;
+  if (a == 0.0) return;
+  int e;
+  const double m = frexp(a, &e);                     // a = m 2^e, m in [1/2, 1)
+  const uint64_t mant = (uint64_t)ldexp(m, 53);      // exact 53-bit integer
+  const int sh = e - 53 + kFixShift;                 // a 2^96 = mant 2^sh, sh < 64
+  if (sh > 0) {
+    lo = mant << sh;
+    hi = mant >> (64 - sh);
+  } else if (sh > -64) {
+    lo = mant >> (-sh);  // truncation below the resolution
+  }
+  if (c < 0.0) {
+    lo = ~lo + 1ull;
+    hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+  }
+}
+
+__device__ __forceinline__ double from_fixed(uint64_t lo, uint64_t hi) {
+  const bool neg = (int64_t)hi < 0;
+  if (neg) {
+    lo = ~lo + 1ull;
+    hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+  }
+  if (hi >= (1ull << 54)) return __builtin_nan("");  // the marker of a non-finite contribution
+  const double v = ldexp((double)hi, 64 - kFixShift) + ldexp((double)lo, -kFixShift);
+  return neg ? -v : v;
+}
+
+// q += (lo, hi) modulo 2^128: the carry out of the low word is known from the
+// value the low atomic returns, so the result is exact whatever the order.
+__device__ __forceinline__ void fixed_add(uint64_t* q, uint64_t lo, uint64_t hi) {
+  const uint64_t old = (uint64_t)atomicAdd((unsigned long long*)q, (unsigned long long)lo);
+  const uint64_t h = hi + (old + lo < old ? 1ull : 0ull);
+  if (h) atomicAdd((unsigned long long*)(q + 1), (unsigned long long)h);
+}
+
+// Adds W F of every particle (positions X, lattice forces F [n][3]) to the
+// fixed-point accumulator acc [N][3][2] at its stencil nodes and flags them;
+// then the closing drift of the coupling step when a.drift_after (X = a.pos).
+template <int K>
+__global__ __launch_bounds__(256) void k_spread_det(PartArgs a, const double* X, const double* F,
+                                                    uint64_t* acc) {
+  constexpr int L = Lanes<K>::L;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long p = gid / L;
+  const int lane = (int)(gid % L);
+  if (p >= a.n) return;  // whole groups leave together
+  double r[3], f[3];
+  for (int k = 0; k < 3; ++k) {
+    r[k] = X[3 * p + k];
+    f[k] = F[3 * p + k];
+  }
+  const SiteSlot sl = slot_of<K>(a.s.g, r, lane);
+  if (sl.valid) {
+    const long long s = site_index(a.s.g, sl.x, sl.y, sl.z);
+    for (int k = 0; k < 3; ++k) {
+      uint64_t lo, hi;
+      to_fixed(sl.W * f[k], lo, hi);
+      if (lo | hi) fixed_add(acc + 6 * s + 2 * k, lo, hi);
+    }
+    uint64_t bit;
+    flag_site(mask_word(a.mask, a.s.g, sl.x, sl.y, sl.z, bit), bit);
+  }
+  if (lane == 0 && a.drift_after) {
+    for (int k = 0; k < 3; ++k) r[k] += a.hd * a.vel[3 * p + k];
+    wrap3(a.s.g, r);
+    for (int k = 0; k < 3; ++k) a.pos[3 * p + k] = r[k];
+  }
+}
+
+// field += the accumulated sum at site s if it is flagged, and the
+// accumulator back to zero there (one lane per site: no two lanes touch a site).
+template <typename E>
+__device__ __forceinline__ void det_finalize_site(const Geo& g, const uint64_t* mask,
+                                                  uint64_t* acc, E* field, long long s) {
+  const int x = (int)(s % g.nx);
+  const long long r = s / g.nx;
+  const int y = (int)(r % g.ny), z = (int)(r / g.ny);
+  uint64_t bit;
+  const uint64_t w = *mask_word(const_cast<uint64_t*>(mask), g, x, y, z, bit);
+  if (!(w & bit)) return;
+  uint64_t* q = acc + 6 * s;
+  for (int k = 0; k < 3; ++k) {
+    const uint64_t lo = q[2 * k], hi = q[2 * k + 1];
+    if (!(lo | hi)) continue;
+    field[4 * s + k] += (E)from_fixed(lo, hi);
+    q[2 * k] = 0ull;
+    q[2 * k + 1] = 0ull;
+  }
+}
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_det_finalize(Geo g, const uint64_t* mask, uint64_t* acc,
+                                                      E* field) {
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < g.N) det_finalize_site<E>(g, mask, acc, field, s);
+}
+
 // IB (Alg. 2): predictor X~ = X + (h/2) I[X] u(t)
 template <int S, int K>
 __global__ __launch_bounds__(256) void k_ib_predict(PartArgs a) {
@@ -1200,6 +1317,23 @@ hipError_t launch_spread_deferred(int storage, const PartArgs& a, hipStream_t st
   return hipGetLastError();
 }
 
+hipError_t launch_spread_det(const PartArgs& a, const double* X, const double* F, uint64_t* acc,
+                             hipStream_t st) {
+  if (a.n > 0)
+    LBC_KERNEL_SWITCH(a.K, (k_spread_det<KK><<<gblocks(a.n, KK), 256, 0, st>>>(a, X, F, acc)));
+  return hipGetLastError();
+}
+
+hipError_t launch_det_finalize(int storage, const Geo& g, const uint64_t* mask, uint64_t* acc,
+                               void* field, hipStream_t st) {
+  const unsigned nb = (unsigned)((g.N + 255) / 256);
+  if (storage == LB_F64)
+    k_det_finalize<double><<<nb, 256, 0, st>>>(g, mask, acc, (double*)field);
+  else
+    k_det_finalize<float><<<nb, 256, 0, st>>>(g, mask, acc, (float*)field);
+  return hipGetLastError();
+}
+
 hipError_t launch_ib_predict(int storage, const PartArgs& a, hipStream_t st) {
   if (a.n > 0)
     LBC_KERNEL_SWITCH(a.K, LBC_STORAGE_SWITCH(storage, (k_ib_predict<SS, KK>
@@ -1473,9 +1607,14 @@ __global__ __launch_bounds__(256) void k_ens_couple(EnsArgs e, int half) {
       }
     }
     const double Ff[3] = {-Fh[0], -Fh[1], -Fh[2]};
-    group_spread<E, K>(a, r, Ff, half == 0 ? sl.FA : sl.FB, lane, &mpre);
+    if (sl.det_on) {  // stored; k_ens_spread_det spreads it (and drifts after half 1)
+      if (lane == 0)
+        for (int k = 0; k < 3; ++k) sl.aux[3 * p + k] = Ff[k];
+    } else {
+      group_spread<E, K>(a, r, Ff, half == 0 ? sl.FA : sl.FB, lane, &mpre);
+    }
     if (lane == 0) {
-      if (half == 1) {
+      if (half == 1 && !sl.det_on) {
         for (int k = 0; k < 3; ++k) r[k] += hh * v[k];
         wrap3(sl.g, r);
       }
@@ -1484,6 +1623,59 @@ __global__ __launch_bounds__(256) void k_ens_couple(EnsArgs e, int half) {
         sl.vel[3 * p + k] = v[k];
       }
     }
+  }
+}
+
+// Deterministic spreading of the stored lattice forces of one coupling half
+// of every deterministic slot (fixed-point accumulation, see k_spread_det),
+// then the final P^1/2 after half 1.
+template <int K>
+__global__ __launch_bounds__(256) void k_ens_spread_det(EnsArgs e, int half) {
+  constexpr int L = Lanes<K>::L;
+  const int n = *e.npitems;
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int2 w = e.pitems[it];
+    const EnsSlot& sl = e.slots[w.x];
+    if (!ens_active(sl) || sl.coupling == LB_COUPLE_NONE || !sl.det_on) continue;
+    const long long p = (long long)w.y + threadIdx.x / L;
+    const int lane = threadIdx.x % L;
+    if (p >= sl.np) continue;  // whole lane groups leave together
+    double r[3], f[3];
+    for (int k = 0; k < 3; ++k) {
+      r[k] = sl.pos[3 * p + k];
+      f[k] = sl.aux[3 * p + k];
+    }
+    const SiteSlot ss = slot_of<K>(sl.g, r, lane);
+    if (ss.valid) {
+      const long long s = site_index(sl.g, ss.x, ss.y, ss.z);
+      for (int k = 0; k < 3; ++k) {
+        uint64_t lo, hi;
+        to_fixed(ss.W * f[k], lo, hi);
+        if (lo | hi) fixed_add(sl.det + 6 * s + 2 * k, lo, hi);
+      }
+      uint64_t bit;
+      flag_site(mask_word(sl.mask, sl.g, ss.x, ss.y, ss.z, bit), bit);
+    }
+    if (lane == 0 && half == 1) {
+      for (int k = 0; k < 3; ++k) r[k] += 0.5 * sl.vel[3 * p + k];
+      wrap3(sl.g, r);
+      for (int k = 0; k < 3; ++k) sl.pos[3 * p + k] = r[k];
+    }
+  }
+}
+
+// The finalize of the deterministic spread for every deterministic slot, over
+// the lattice work list (one lane per site).
+template <int S>
+__global__ __launch_bounds__(256) void k_ens_det_finalize(EnsArgs e, int half) {
+  using E = typename Store<S>::R;
+  const int n = *e.nlitems;
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int2 w = e.litems[it];
+    const EnsSlot& sl = e.slots[w.x];
+    if (!ens_active(sl) || sl.coupling == LB_COUPLE_NONE || !sl.det_on || sl.np == 0) continue;
+    const long long s = (long long)w.y * 256 + threadIdx.x;
+    if (s < sl.g.N) det_finalize_site<E>(sl.g, sl.mask, sl.det, (E*)(half ? sl.FB : sl.FA), s);
   }
 }
 
@@ -1507,10 +1699,17 @@ __global__ void k_ens_advance(EnsArgs e) {
 }
 
 hipError_t launch_ens_step(int storage, int K, const EnsArgs& e, int lat_grid, int part_grid,
-                           hipStream_t st) {
-  LBC_KERNEL_SWITCH(K, LBC_STORAGE_SWITCH(storage, (k_ens_couple<SS, KK><<<part_grid, 256, 0, st>>>(e, 0))));
-  LBC_STORAGE_SWITCH(storage, (k_ens_lattice<SS><<<lat_grid, 256, 0, st>>>(e.slots, e.litems, e.nlitems)));
-  LBC_KERNEL_SWITCH(K, LBC_STORAGE_SWITCH(storage, (k_ens_couple<SS, KK><<<part_grid, 256, 0, st>>>(e, 1))));
+                           int det, hipStream_t st) {
+  for (int half = 0; half < 2; ++half) {
+    if (half == 1)
+      LBC_STORAGE_SWITCH(storage, (k_ens_lattice<SS><<<lat_grid, 256, 0, st>>>(e.slots, e.litems,
+                                                                              e.nlitems)));
+    LBC_KERNEL_SWITCH(K, LBC_STORAGE_SWITCH(storage, (k_ens_couple<SS, KK><<<part_grid, 256, 0, st>>>(e, half))));
+    if (det) {
+      LBC_KERNEL_SWITCH(K, (k_ens_spread_det<KK><<<part_grid, 256, 0, st>>>(e, half)));
+      LBC_STORAGE_SWITCH(storage, (k_ens_det_finalize<SS><<<lat_grid, 256, 0, st>>>(e, half)));
+    }
+  }
   k_ens_advance<<<(e.nslots + 63) / 64, 64, 0, st>>>(e);
   return hipGetLastError();
 }

@@ -98,7 +98,7 @@ def load():
         "lb_last_error": (C.c_char_p, [vp]),
         "lb_status_string": (C.c_char_p, [i32]),
         "lb_ensemble_footprint": (i32, [G, P, M, C.POINTER(C.c_size_t)]),
-        "lb_ensemble_create": (i32, [vp, C.c_size_t, i32, i32, i32, vp, C.POINTER(vp)]),
+        "lb_ensemble_create": (i32, [vp, C.c_size_t, i32, i32, i32, i32, vp, C.POINTER(vp)]),
         "lb_ensemble_stream": (i32, [vp, C.POINTER(vp)]),
         "lb_ensemble_admit": (i32, [vp, G, P, M, i64, C.POINTER(i32), C.POINTER(vp)]),
         "lb_ensemble_step": (i32, [vp, i64]),
@@ -131,7 +131,7 @@ def lattice_velocities():
 def make_params(tau, rho0=1.0, body_force=(0.0, 0.0, 0.0), collision=LB_BGK, trt_magic=3.0 / 16.0,
                 coupling=LB_COUPLE_NONE, gamma=0.0, kernel=LB_PHI2, storage=LB_F64,
                 f16_scale_log2=0, mts_substeps=0, comoving=0, csc=0, mts_inside=0, kT=0.0,
-                seed=0, mrt_rates=(1.0, 1.0, 1.0, 1.0, 1.0)):
+                seed=0, mrt_rates=(1.0, 1.0, 1.0, 1.0, 1.0), deterministic=0):
     p = lb_params()
     p.tau, p.rho0 = float(tau), float(rho0)
     for a in range(3):
@@ -139,7 +139,7 @@ def make_params(tau, rho0=1.0, body_force=(0.0, 0.0, 0.0), collision=LB_BGK, trt
     p.collision, p.trt_magic, p.forcing = int(collision), float(trt_magic), LB_FORCING_SPLIT2
     p.coupling, p.gamma, p.kernel = int(coupling), float(gamma), int(kernel)
     p.storage, p.f16_scale_log2 = int(storage), int(f16_scale_log2)
-    p.mts_substeps, p.deterministic = int(mts_substeps), 0
+    p.mts_substeps, p.deterministic = int(mts_substeps), int(deterministic)
     p.comoving, p.csc, p.mts_inside = int(comoving), int(csc), int(mts_inside)
     p.kT, p.seed = float(kT), int(seed)
     for k in range(5):
@@ -327,7 +327,7 @@ class Ensemble:
     stream."""
 
     def __init__(self, pool_bytes, max_slots, storage=LB_F32, kernel=LB_PHI2, device="cuda",
-                 stream=None):
+                 stream=None, deterministic=0):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -336,10 +336,11 @@ class Ensemble:
         base = self.pool.data_ptr()
         ptr = base + ((-base) % 256)
         self.storage, self.kernel = int(storage), int(kernel)
+        self.deterministic = int(deterministic)
         self.ens = C.c_void_p()
         torch.cuda.synchronize(self.device)
         _echeck(load().lb_ensemble_create(C.c_void_p(ptr), int(pool_bytes), int(max_slots),
-                                          self.storage, self.kernel,
+                                          self.storage, self.kernel, self.deterministic,
                                           None if stream is None else C.c_void_p(stream.cuda_stream),
                                           C.byref(self.ens)))
         st = C.c_void_p()
@@ -353,6 +354,7 @@ class Ensemble:
         g = lb_grid(int(nx), int(ny), int(nz), 0)
         params.setdefault("storage", self.storage)
         params.setdefault("kernel", self.kernel)
+        params.setdefault("deterministic", self.deterministic)
         p = make_params(**params)
         m = lb_limits(int(max_particles), 0, 0, 0)
         slot, ctx = C.c_int32(), C.c_void_p()

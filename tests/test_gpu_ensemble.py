@@ -82,27 +82,36 @@ def test_ensemble_slots_match_oracle_fp64():
     ens.destroy()
 
 
-@pytest.mark.parametrize("storage,tol", [(1, 1e-5), (2, 2e-3)])
-def test_same_alone_and_in_the_mix(storage, tol):
+@pytest.mark.parametrize("det", [1, 0])
+@pytest.mark.parametrize("storage,tol", [(1, 1e-6), (2, 1e-4)])
+def test_same_alone_and_in_the_mix(storage, tol, det):
+    """Each request run alone and in a mix of uneven boxes.  With the
+    deterministic spread (det = 1) the results are bitwise equal, particles
+    included; with atomic spreading only boxes without particles are, and the
+    others agree to the storage precision's round-off (measured up to about
+    1e-7 in FP32 and 2e-5 in FP16)."""
     from paper_1406_2211_amd import lbc as L
     cases = [_case(s, storage=storage) for s in SPECS]
     for c in cases:
         c.f16_scale_log2 = 20
-    mix = L.Ensemble(_pool_for(cases), max_slots=8, storage=storage, kernel=2)
+    mix = L.Ensemble(_pool_for(cases), max_slots=8, storage=storage, kernel=2, deterministic=det)
     hs = [_admit(mix, c) for c in cases]
     mix.step(40)
     for i, c in enumerate(cases):
-        alone = L.Ensemble(_pool_for([c]), max_slots=1, storage=storage, kernel=2)
+        alone = L.Ensemble(_pool_for([c]), max_slots=1, storage=storage, kernel=2,
+                           deterministic=det)
         slot, lat = _admit(alone, c)
         alone.step(40)
         a = _read(alone, slot, lat, c)
         m = _read(mix, hs[i][0], hs[i][1], c)
         scale = np.abs(a["u"]).max()
         err = np.abs(a["u"] - m["u"]).max() / scale
-        print(f"[ensemble] storage={storage} slot {i}: alone vs mix u err {err:.2e}", flush=True)
+        print(f"[ensemble] storage={storage} det={det} slot {i}: alone vs mix u err {err:.2e}",
+              flush=True)
         assert err <= tol
-        if c.pos is None:  # no atomics involved: identical
-            assert np.array_equal(a["df"], m["df"])
+        if det or c.pos is None:  # no order-dependent sums: identical
+            for k in ("df", "u", "pos", "vel"):
+                assert a[k] is None or np.array_equal(a[k], m[k]), (i, k)
         alone.destroy()
     mix.destroy()
 

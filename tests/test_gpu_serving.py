@@ -29,15 +29,19 @@ def test_batched_server_matches_fifo_per_request():
     pool = 2 * big + 400_000  # about two boxes at a time: forces queueing
     print("[gpu] serving test with pool", pool, flush=True)
     seen = []
-    bat, _ = S.serve_batched(reqs, pool, max_slots=8, storage=L.LB_F64, chunk=7, comoving=0,
-                             autotune=False, log=seen.append)
-    fifo, _ = S.serve_fifo(reqs, storage=L.LB_F64)
+    every = {r.rid for r in reqs}
+    bat, fb = S.serve_batched(reqs, pool, max_slots=8, storage=L.LB_F64, chunk=7, comoving=0,
+                              autotune=False, log=seen.append, keep=every)
+    fifo, ff = S.serve_fifo(reqs, storage=L.LB_F64, keep=every)
     assert len(bat) == len(fifo) == len(reqs)
     a = {r.rid: r.totals for r in bat}
     b = {r.rid: r.totals for r in fifo}
     for rid in a:
         scale = np.abs(b[rid]).max()
         assert np.abs(a[rid] - b[rid]).max() <= 1e-12 * max(scale, 1e-300), rid
+        # the whole velocity field of each request, not only its sums
+        us = np.abs(ff[rid]).max()
+        assert np.abs(fb[rid] - ff[rid]).max() <= 1e-12 * max(us, 1e-300), rid
     # requests were admitted after earlier ones finished, i.e. the pool bounded concurrency
     s = S.summarize(bat)
     print("[serving]", s, flush=True)
