@@ -224,6 +224,18 @@ lb_status lb_populations(lb_ctx* ctx, double* d_df);
  * shifts and do not enter it.  Asynchronous. */
 lb_status lb_stress(lb_ctx* ctx, double* d_sigma);
 
+/* Viscous stress in the sweep (Sec. 4: in the collide-stream-collide form the
+ * stress is available locally at every step): with d_sigma non-NULL, every
+ * fused lattice pass that follows also writes, at every site, the viscous
+ * stress of Eq. viscstress (the quantity lb_stress returns) of the physical
+ * state the pass starts from, i.e. lb_step(1) leaves in d_sigma the stress of
+ * the state it was called on, at the cost of the stores only (no extra read
+ * pass).  d_sigma is [6][nz][ny][nx] (xx, yy, zz, xy, xz, yz) in the compute
+ * precision: FP64 with LB_F64 storage, FP32 otherwise; owned by the caller,
+ * who keeps it alive while attached.  NULL detaches.  Errors: LB_EINVAL with
+ * LB_MRT or kT > 0 (not supported), LB_ESTATE on an ensemble slot. */
+lb_status lb_stress_sweep(lb_ctx* ctx, void* d_sigma);
+
 /* Current particle positions and velocities (r_i, v_i of Sec. 5.2; for IB the
  * marker positions X_i of Sec. 5.1 and zero velocities) at the step boundary,
  * copied on the context stream into FP64 device arrays [n][3] owned by the

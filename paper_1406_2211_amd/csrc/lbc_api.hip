@@ -202,6 +202,7 @@ struct lb_ctx {
   int32_t ev_stride = 1;   // time one pass in every ev_stride
   int64_t ev_seen = 0;     // passes since timing was armed
   int static_dev = -1;     // device whose static array holds the workspace (lb_create_static)
+  void* sweep = nullptr;   // lb_stress_sweep output: stress of each pass's starting state
   std::string err;
 };
 
@@ -488,6 +489,8 @@ static lb_status lattice_pass(lb_ctx* c, int bond_nsub = 0, double bond_dt = 0.0
     a.uout[k] = c->uref[k] + (c->p.comoving ? c->p.body_force[k] / c->p.rho0 : 0.0);
   }
   comoving_terms(c->scale, c->p.rho0, a.uin, a.uout, a.cm, a.cmf);
+  a.sigma = c->sweep;
+  a.sp = 0.5 * (1.0 + c->omp);  // 1 - lambda_+/2
   if (bond_nsub > 0) {
     a.bond = bond_args(c, c->L.pos);
     a.bond_groups = c->ngroups;
@@ -929,6 +932,15 @@ lb_status lb_stress(lb_ctx* c, double* d_sigma) {
   const double ps = 0.5 * (1.0 + c->omp);
   const double pb = c->p.collision == LB_MRT ? 1.0 - 0.5 * c->p.mrt_rates[0] : ps;
   HIPCHK(c, launch_stress(c->p.storage, site_args(c), d_sigma, ps, pb, c->st));
+  return LB_OK;
+}
+
+lb_status lb_stress_sweep(lb_ctx* c, void* d_sigma) {
+  if (!c) return fail(nullptr, LB_EINVAL, "null context");
+  if (c->member) return fail(c, LB_ESTATE, "ensemble slots have no stress sweep");
+  if (d_sigma && (c->p.collision == LB_MRT || c->p.kT > 0.0))
+    return fail(c, LB_EINVAL, "the stress sweep takes the BGK or two-rate collision without noise");
+  c->sweep = d_sigma;
   return LB_OK;
 }
 

@@ -484,12 +484,14 @@ __host__ __device__ inline const float* pick_terms<float>(const double*, const f
 // so neither the loads nor the stores need the scale; the U terms are
 // per-pass constants (comoving_terms).
 // With NS the thermal noise of site_noise is added to every stored value.
-template <int S, bool CM, bool NS = false>
+template <int S, bool CM, bool NS = false, bool SG = false>
 __device__ __forceinline__ void fused_site(const typename Store<S>::R f[Q], typename Store<S>::R Fx,
                                            typename Store<S>::R Fy, typename Store<S>::R Fz,
                                            const PassK<typename Store<S>::R>& k,
                                            typename Store<S>::T* __restrict__ fo, size_t P,
-                                           size_t own) {
+                                           size_t own,
+                                           typename Store<S>::R* __restrict__ sgo = nullptr,
+                                           size_t sN = 0, typename Store<S>::R sp = 0) {
   using St = Store<S>;
   using R = typename St::R;
   R d = 0, jx = 0, jy = 0, jz = 0;
@@ -516,6 +518,7 @@ __device__ __forceinline__ void fused_site(const typename Store<S>::R f[Q], type
   const R rs = rho * k.sc;
   R nz[Q];
   if (NS) site_noise<R>(k, (uint32_t)own, rho, nz);
+  R pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;  // non-equilibrium stress (SG)
   {
     const R w = wgt<R>(0);
     R eb = w * (d - R(1.5) * rs * usq), eh = w * (d - R(1.5) * rs * hsq);
@@ -549,8 +552,26 @@ __device__ __forceinline__ void fused_site(const typename Store<S>::R f[Q], type
       vi += nz[i];
       vj += nz[i + 1];
     }
+    if (SG) {  // sum_i (f_i - f^eq_i) c_i c_i over the opposite pair (c_j = -c_i)
+      const R s2 = ni + nj;
+      if (CX[i]) pxx += s2;
+      if (CY[i]) pyy += s2;
+      if (CZ[i]) pzz += s2;
+      if (CX[i] && CY[i]) pxy += R(CX[i] * CY[i]) * s2;
+      if (CX[i] && CZ[i]) pxz += R(CX[i] * CZ[i]) * s2;
+      if (CY[i] && CZ[i]) pyz += R(CY[i] * CZ[i]) * s2;
+    }
     St::st_raw(fo + (size_t)i * P + own, vi);
     St::st_raw(fo + (size_t)(i + 1) * P + own, vj);
+  }
+  if (SG) {  // viscous stress of the state this pass started from (Eq. viscstress)
+    const R pf = sp * k.inv;
+    sgo[own] = pf * pxx;
+    sgo[sN + own] = pf * pyy;
+    sgo[2 * sN + own] = pf * pzz;
+    sgo[3 * sN + own] = pf * pxy;
+    sgo[4 * sN + own] = pf * pxz;
+    sgo[5 * sN + own] = pf * pyz;
   }
 }
 

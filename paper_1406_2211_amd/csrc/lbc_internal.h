@@ -71,6 +71,10 @@ struct LatArgs {
   // and the lattice rows are at blockIdx.z - 1; linear-site pass: workgroup b
   // < bond_groups takes group b and the sites start at workgroup bond_groups.
   // They touch only particle state, the pass only fluid state.
+  // Viscous stress output (non-null): sigma [6][N] in the compute precision,
+  // (1 - lambda_+/2) sum_i (f_i - f^eq_i) c_i c_i of the pulled state, sp = 1 - lambda_+/2
+  void* sigma;
+  double sp;
   BondArgs bond;
   int bond_groups, bond_nsub;
   int bond_cap;  // particles per bond group at most (needs that many lanes and 24 B of LDS each)

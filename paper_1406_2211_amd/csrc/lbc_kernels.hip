@@ -85,7 +85,7 @@ __device__ __forceinline__ void take_forces_ib(uint64_t word, uint64_t* mp, size
 __device__ void bond_group(const BondArgs& b, int grp, int mode, int acc, int nsub, double dt,
                            double* lds);
 
-template <int S, bool CM, bool WALL, bool NS = false, bool MRT = false>
+template <int S, bool CM, bool WALL, bool NS = false, bool MRT = false, bool SG = false>
 __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
   using St = Store<S>;
   using T = typename St::T;
@@ -156,7 +156,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(LatArgs a) {
     }
     fused_site_mrt<S, NS>(f, Fx, Fy, Fz, k, (T*)a.fout, N, own);
   } else {
-    fused_site<S, CM, NS>(f, Fx, Fy, Fz, k, (T*)a.fout, N, own);
+    fused_site<S, CM, NS, SG>(f, Fx, Fy, Fz, k, (T*)a.fout, N, own, (R*)a.sigma, (size_t)a.g.N,
+                              R(a.sp));
   }
 }
 
@@ -1176,18 +1177,18 @@ static dim3 lattice_grid(const Geo& g, dim3 b) {
     default: { constexpr int SS = LB_BF16; CALL; } break;           \
   }
 
-template <int S, bool CM, bool WALL, bool NS, bool MRT>
+template <int S, bool CM, bool WALL, bool NS, bool MRT, bool SG>
 __global__ __launch_bounds__(256) void k_stream_collide_lin(LatArgs a);
 
-template <bool CM, bool WALL, bool NS = false, bool MRT = false>
+template <bool CM, bool WALL, bool NS = false, bool MRT = false, bool SG = false>
 static void launch_sc(int storage, const LatArgs& a, dim3 gr, dim3 b, hipStream_t st) {
   if (a.g.wpr == 0) {  // linear mask: x extent not a multiple of 64
     const unsigned nb = (unsigned)((a.g.N + 255) / 256) + (unsigned)a.bond_groups;
-    LBC_STORAGE_SWITCH(storage, (k_stream_collide_lin<SS, CM, WALL, NS, MRT>
+    LBC_STORAGE_SWITCH(storage, (k_stream_collide_lin<SS, CM, WALL, NS, MRT, SG>
                                  <<<nb, 256, a.occ_lds, st>>>(a)));
   } else {
     LBC_STORAGE_SWITCH(storage,
-                       (k_stream_collide<SS, CM, WALL, NS, MRT><<<gr, b, a.occ_lds, st>>>(a)));
+                       (k_stream_collide<SS, CM, WALL, NS, MRT, SG><<<gr, b, a.occ_lds, st>>>(a)));
   }
 }
 
@@ -1218,6 +1219,14 @@ hipError_t launch_stream_collide(int storage, bool comoving, const LatArgs& a_in
   } else if (a.noise) {  // fluctuating collision (the comoving frame is not combined with it)
     if (a.g.wall) launch_sc<false, true, true>(storage, a, gr, b, st);
     else launch_sc<false, false, true>(storage, a, gr, b, st);
+  } else if (a.sigma) {  // the viscous stress of the state the pass starts from, written out
+    if (comoving) {
+      if (a.g.wall) launch_sc<true, true, false, false, true>(storage, a, gr, b, st);
+      else launch_sc<true, false, false, false, true>(storage, a, gr, b, st);
+    } else {
+      if (a.g.wall) launch_sc<false, true, false, false, true>(storage, a, gr, b, st);
+      else launch_sc<false, false, false, false, true>(storage, a, gr, b, st);
+    }
   } else if (comoving) {
     if (a.g.wall) launch_sc<true, true>(storage, a, gr, b, st);
     else launch_sc<true, false>(storage, a, gr, b, st);
@@ -1402,6 +1411,8 @@ struct LatView {
   __device__ const float* cmf() const { return a.cmf; }
   __device__ bool ib_copy() const { return a.ib_copy != 0; }
   __device__ bool clear_mask() const { return a.clear_mask != 0; }
+  __device__ void* sigma() const { return a.sigma; }
+  __device__ double sp() const { return a.sp; }
   template <typename R>
   __device__ void noise(PassK<R>& k) const {
     k.ap = R(a.ap);
@@ -1443,13 +1454,15 @@ struct SlotView {
   __device__ const float* cmf() const { return s.cmf; }
   __device__ bool ib_copy() const { return false; }
   __device__ bool clear_mask() const { return s.steps_done % kMaskKeep == 0; }
+  __device__ void* sigma() const { return nullptr; }
+  __device__ double sp() const { return 0.0; }
   template <typename R>
   __device__ void noise(PassK<R>&) const {}  // ensemble members are deterministic
   template <typename R>
   __device__ void mrt(PassK<R>&) const {}  // ... and use the two-rate collision
 };
 
-template <int S, bool CM, bool WALL, class V, bool NS = false, bool MRT = false>
+template <int S, bool CM, bool WALL, class V, bool NS = false, bool MRT = false, bool SG = false>
 __device__ __forceinline__ void linear_site(const V& v, uint32_t s) {
   using St = Store<S>;
   using T = typename St::T;
@@ -1498,11 +1511,12 @@ __device__ __forceinline__ void linear_site(const V& v, uint32_t s) {
     v.mrt(k);
     fused_site_mrt<S, NS>(f, Fx, Fy, Fz, k, (T*)v.fout(), P, s);
   } else {
-    fused_site<S, CM, NS>(f, Fx, Fy, Fz, k, (T*)v.fout(), P, s);
+    fused_site<S, CM, NS, SG>(f, Fx, Fy, Fz, k, (T*)v.fout(), P, s, (R*)v.sigma(), (size_t)g.N,
+                              R(v.sp()));
   }
 }
 
-template <int S, bool CM, bool WALL, bool NS, bool MRT>
+template <int S, bool CM, bool WALL, bool NS, bool MRT, bool SG>
 __global__ __launch_bounds__(256) void k_stream_collide_lin(LatArgs a) {
   uint32_t b = blockIdx.x;
   if (a.bond_groups > 0) {  // the first bond_groups workgroups run the intrinsic-force sub-steps
@@ -1513,7 +1527,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_lin(LatArgs a) {
     }
     b -= (uint32_t)a.bond_groups;
   }
-  linear_site<S, CM, WALL, LatView, NS, MRT>(LatView{a}, b * 256u + threadIdx.x);
+  linear_site<S, CM, WALL, LatView, NS, MRT, SG>(LatView{a}, b * 256u + threadIdx.x);
 }
 
 // The slot table is read-only during the lattice pass (only k_ens_advance

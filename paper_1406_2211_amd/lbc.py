@@ -24,7 +24,7 @@ LB_HARMONIC, LB_FENE = 0, 1
 
 EXPORTS = ["lb_lattice_velocities", "lb_workspace_size", "lb_create", "lb_init_fluid",
            "lb_set_particles", "lb_set_bonds", "lb_set_shells", "lb_step", "lb_moments",
-           "lb_populations", "lb_stress", "lb_get_particles", "lb_totals", "lb_timing",
+           "lb_populations", "lb_stress", "lb_stress_sweep", "lb_get_particles", "lb_totals", "lb_timing",
            "lb_timing_read", "lb_info", "lb_create_static", "lb_destroy",
            "lb_last_error", "lb_status_string", "lb_ensemble_footprint", "lb_ensemble_create",
            "lb_ensemble_stream", "lb_ensemble_admit", "lb_ensemble_step", "lb_ensemble_query",
@@ -89,6 +89,7 @@ def load():
         "lb_moments": (i32, [vp, vp, vp]),
         "lb_populations": (i32, [vp, vp]),
         "lb_stress": (i32, [vp, vp]),
+        "lb_stress_sweep": (i32, [vp, vp]),
         "lb_get_particles": (i32, [vp, vp, vp]),
         "lb_totals": (i32, [vp, C.POINTER(dbl)]),
         "lb_timing": (i32, [vp, i32, i32]),
@@ -266,6 +267,20 @@ class Lattice:
         sigma = self.torch.empty((6,) + self.shape, dtype=self.torch.float64, device=self.device)
         self._call("lb_stress", _ptr(sigma))
         return sigma
+
+    def lb_stress_sweep(self, attach=True):
+        """Attach (or detach) a [6, nz, ny, nx] tensor that every following
+        lattice pass fills with the viscous stress of the state it starts
+        from; FP64 with FP64 storage, FP32 otherwise.  Returns the tensor."""
+        if not attach:
+            self._call("lb_stress_sweep", None)
+            self._sweep = None
+            return None
+        dt = self.torch.float64 if self.params.storage == LB_F64 else self.torch.float32
+        self._sweep = self.torch.zeros((6,) + self.shape, dtype=dt, device=self.device)
+        self.torch.cuda.synchronize(self.device)
+        self._call("lb_stress_sweep", _ptr(self._sweep))
+        return self._sweep
 
     def lb_get_particles(self):
         pos = self.torch.empty((self.np, 3), dtype=self.torch.float64, device=self.device)

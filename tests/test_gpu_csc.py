@@ -201,3 +201,52 @@ def test_csc_and_stress_in_an_ensemble():
         assert np.abs(df - o["df"]).max() <= TOL64 * np.abs(o["df"]).max()
         assert np.abs(sig - o["sigma"]).max() <= 19 * TOL64 * np.abs(o["df"]).max()
     ens.destroy()
+
+
+def _sweep_run(c):
+    """Runs c.steps steps with the stress sweep attached; returns the sweep
+    buffer, which holds the stress of the state after c.steps - 1 steps."""
+    import torch
+    from parity import make_gpu
+    lat = make_gpu(c)
+    print(f"[gpu] stress sweep {c.name}: {c.nx}x{c.ny}x{c.nz} steps={c.steps} "
+          f"storage={c.storage}", flush=True)
+    buf = lat.lb_stress_sweep()
+    lat.lb_step(c.steps)
+    torch.cuda.synchronize()
+    out = buf.double().cpu().numpy()
+    lat.lb_destroy()
+    return out
+
+
+@pytest.mark.parametrize("collision,tau,csc,wall_y,particles", [
+    (0, 1.5, 1, 0, 1), (1, 1.25, 1, 1, 0), (1, 0.8, 0, 0, 1), (0, 1.1, 0, 1, 0)])
+def test_stress_in_the_sweep_fp64(collision, tau, csc, wall_y, particles):
+    """The stress written by the lattice pass (lb_stress_sweep) is that of the
+    state the pass starts from: after n steps it equals the oracle's stress
+    after n - 1 steps, in both forms, with walls, forces and coupling."""
+    c = _stress_case(collision, tau, csc, wall_y=wall_y, steps=31)
+    if particles:
+        c.pos, c.vel, c.mass = _parts(3, (c.nx, c.ny, c.nz), 11)
+        c.coupling, c.gamma = 1, 1.2
+    sweep = _sweep_run(c)
+    c.steps -= 1
+    o = run_oracle(c)
+    err = np.abs(sweep - o["sigma"]).max()
+    print(f"[stress] sweep {c.name}: max|sigma| {np.abs(o['sigma']).max():.3e}, abs err "
+          f"{err:.3e}", flush=True)
+    assert np.abs(o["sigma"]).max() > 1e-4
+    assert err <= 19 * TOL64 * np.abs(o["df"]).max()
+
+
+def test_stress_in_the_sweep_fp32_row_layout():
+    """FP32 storage on the row-mapped pass (nx = 64): the FP32 stress of the
+    sweep against the FP64 stress lb_stress returns for the same state."""
+    c = _stress_case(1, 1.25, 1, storage=1, steps=41)
+    c.nx = 64
+    sweep = _sweep_run(c)
+    c.steps -= 1
+    g = run_gpu(c)
+    err = np.abs(sweep - g["sigma"]).max() / np.abs(g["sigma"]).max()
+    print(f"[stress] sweep fp32 row layout: relative {err:.3e}", flush=True)
+    assert err < 1e-5

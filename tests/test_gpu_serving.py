@@ -46,3 +46,27 @@ def test_batched_server_matches_fifo_per_request():
     s = S.summarize(bat)
     print("[serving]", s, flush=True)
     assert any(r.admitted > min(x.completed for x in bat) for r in bat)
+
+
+def test_fp16_served_runs_within_the_stated_velocity_bound():
+    """The serving form's precision claim on a sample of the serving request
+    mix (the same generator, 12 requests, boxes of side 32-96 and the full
+    step range): every batched FP16 run (comoving frame) against the same
+    request run alone with FP32 storage, relative max-norm velocity error
+    within the bound bench.py states and enforces (1e-4)."""
+    import bench
+    from paper_1406_2211_amd import inputs as I
+    from paper_1406_2211_amd import lbc as L
+    from paper_1406_2211_amd import serving as S
+    reqs = [I.Request(r.rid, 0.0, r.side, r.nparticles, r.tau, r.fext, r.steps, r.seed)
+            for r in I.serving_requests(12, 1.0, seed=5, side_range=(32, 96))]
+    every = {r.rid for r in reqs}
+    print("[gpu] serving precision sample of", len(reqs), "requests", flush=True)
+    _, f16 = S.serve_batched(reqs, 8 << 30, max_slots=16, storage=L.LB_F16, keep=every)
+    _, f32 = S.serve_fifo(reqs, storage=L.LB_F32, keep=every)
+    worst = 0.0
+    for rid in every:
+        e = np.abs(f16[rid] - f32[rid]).max() / max(np.abs(f32[rid]).max(), 1e-300)
+        worst = max(worst, e)
+    print(f"[serving] FP16 vs FP32 velocity error, worst of {len(every)}: {worst:.2e}", flush=True)
+    assert worst <= bench.SERVING_VEL_BOUND
