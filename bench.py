@@ -54,6 +54,15 @@ def workload(name):
                         mts_substeps=5),
             pos=pos, vel=vel, mass=np.ones(len(pos)), bonds=bonds, bond_k=30.0, bond_r0=1.0,
             bytes_per_site=152, dtype="f32")
+    if name == "c2inside":
+        wl = workload("c2")
+        wl["desc"] = wl["desc"].replace(
+            "multiple time-step split with the coupling outside the sub-steps (Sec. 6, second "
+            "decomposition), n=5 sub-steps per side",
+            "multiple time-step split with the coupling inside every sub-step (Eq. multistep), "
+            "n=5 sub-steps per side")
+        wl["params"] = dict(wl["params"], mts_inside=1)
+        return wl
     if name == "c2thermal":
         wl = workload("c2")
         wl["desc"] = ("thermal c2: " + wl["desc"] + "; fluctuating collision and random coupling "

@@ -642,7 +642,12 @@ __global__ __launch_bounds__(256) void k_spread_deferred(PartArgs a) {
     r[k] = a.pos[3 * p + k];
     F[k] = a.defer[3 * p + k];
   }
-  group_spread<E, K>(a, r, F, a.target ? a.FB : a.FA, lane);
+  if constexpr (K == 2) {  // contributions of consecutive beads combined before the atomics
+    const uint64_t mpre = mask_preload<K>(a, r, lane);
+    group_spread_k2<E>(a, r, F, a.target ? a.FB : a.FA, lane, p, mpre);
+  } else {
+    group_spread<E, K>(a, r, F, a.target ? a.FB : a.FA, lane);
+  }
   if (lane == 0 && a.drift_after) {
     for (int k = 0; k < 3; ++k) r[k] += a.hd * a.vel[3 * p + k];
     wrap3(a.s.g, r);
