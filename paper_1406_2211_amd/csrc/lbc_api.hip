@@ -47,6 +47,8 @@ struct Layout {
   double4* mcache;
   int4* mbase;
   uint64_t* det;  // fixed-point spreading accumulator [N][3][2] (deterministic mode)
+  void* U;        // velocity at the flagged sites [N][4] (binned immersed boundary)
+  int* miss;      // markers left to the gathering interpolation: 2 counters, then the list
   size_t bytes;
 };
 
@@ -100,6 +102,9 @@ Layout carve(const lb_grid& g, const lb_params& p, const lb_limits& lim, void* b
   L.mcache = c.take<double4>(cached ? np * kernel_lanes(p.kernel) * 32 : 32);
   L.mbase = c.take<int4>(cached ? np * 16 : 16);
   L.det = c.take<uint64_t>(p.deterministic ? (size_t)N * 48 : 64);
+  const bool binned = p.coupling == LB_COUPLE_IB && p.kernel >= 3;
+  L.U = c.take<void>(binned ? (size_t)N * 4 * (p.storage == LB_F64 ? 8 : 4) : 64);
+  L.miss = c.take<int>(binned ? (np + 2) * 4 : 64);
   L.bytes = c.off;
   return L;
 }
@@ -188,6 +193,8 @@ struct lb_ctx {
   bool tiled = false;   // binned LDS-staged particle path (dense IB markers)
   int64_t binned_at = -1;  // step of the last marker binning (-1: markers changed since)
   bool adv_pending = false;  // tiled IB: the final half advection of the last step is due
+  uint32_t ustamp = 0;  // tiled IB: stamp of the last velocity pass over the flagged sites
+  bool flags_follow = false;  // tiled IB: the force mask holds the markers' last stencils
   bool member = false;  // slot of an ensemble: stepped only by lb_ensemble_step
   bool running = false;  // ensemble slot whose device record has been uploaded
   bool mvalid = false;   // coupling moment cache holds the state of f[cur]
@@ -510,13 +517,27 @@ static lb_status lattice_pass(lb_ctx* c, int bond_nsub = 0, double bond_dt = 0.0
   return LB_OK;
 }
 
+// Interpolation of the tiled IB path (modes of launch_flag_interp): the
+// velocity pass over the flagged sites under a new stamp, then the markers.
+// The field is cleared before a stamp is reused (every 2^32 - 1 calls), so
+// that an entry carries the current stamp only if this call wrote it.
+static lb_status flag_interp(lb_ctx* c, const double* at, double* pos, double* aux, int mode) {
+  if (++c->ustamp == 0xffffffffu) {
+    HIPCHK(c, launch_zero(c->L.U, (size_t)c->geo.N * 4 * (c->p.storage == LB_F64 ? 8 : 4), c->st));
+    c->ustamp = 1;
+  }
+  HIPCHK(c, launch_flag_interp(c->p.storage, c->p.kernel, site_args(c), c->L.mask, c->L.U,
+                               c->ustamp, at, pos, aux, mode, c->np, c->L.miss, !c->flags_follow,
+                               c->st));
+  return LB_OK;
+}
+
 // Complete a deferred final half advection of the tiled IB path, so that
 // lb_step returns at a step boundary.
 static lb_status finish_step(lb_ctx* c) {
   if (!c->adv_pending) return LB_OK;
-  const TileArgs t = tile_args(c);
-  HIPCHK(c, launch_tile_interp(c->p.storage, c->p.kernel, t, site_args(c), c->L.aux, c->L.pos,
-                               c->L.aux, 1, c->np, c->st));
+  const lb_status s = flag_interp(c, c->L.aux, c->L.pos, c->L.aux, 1);
+  if (s != LB_OK) return s;
   c->adv_pending = false;
   return LB_OK;
 }
@@ -613,26 +634,26 @@ static lb_status step_once(lb_ctx* c) {
     return lattice_pass(c);
   }
   if (c->p.coupling == LB_COUPLE_IB && c->tiled) {
-    // binned, LDS-staged interpolation and spreading (dense markers)
+    // dense markers: interpolation from the velocity of the flagged sites,
+    // binned LDS-accumulated spreading
     const TileArgs t = tile_args(c);
     const int S = c->p.storage, K = c->p.kernel;
-    // The binning only decides which workgroup stages a marker; a marker whose
-    // stencil has left its tile's region takes the direct path, so results do
-    // not depend on how fresh the binning is.  Markers move far less than a
-    // site per step: rebin every kRebin steps.
+    // The binning only decides which workgroup accumulates a marker's force;
+    // a marker whose stencil has left its tile's region adds to the field
+    // directly, so results do not depend on how fresh the binning is.
+    // Markers move far less than a site per step: rebin every kRebin steps.
     if (c->binned_at < 0 || c->steps - c->binned_at >= kRebin) {
       HIPCHK(c, launch_bin(t, c->L.pos, c->np, c->st));
       c->binned_at = c->steps;
     }
-    // X~ = X + h/2 I[X]u(t), then X <- X + h/2 I[X~]u(t): one staged pass.
-    // The final advection of the previous step, X <- X + h/2 I[X~]u(t), reads
-    // the same state and is done first in the same pass (mode 3).
+    // X~ = X + h/2 I[X]u(t), then X <- X + h/2 I[X~]u(t), from one velocity
+    // pass.  The final advection of the previous step, X <- X + h/2 I[X~]u(t),
+    // reads the same state and is done first (mode 3).
     if (c->adv_pending)
-      HIPCHK(c, launch_tile_interp(S, K, t, site_args(c), c->L.aux, c->L.pos, c->L.aux, 3, c->np,
-                                   c->st));
+      s = flag_interp(c, c->L.aux, c->L.pos, c->L.aux, 3);
     else
-      HIPCHK(c, launch_tile_interp(S, K, t, site_args(c), c->L.pos, c->L.pos, c->L.aux, 2, c->np,
-                                   c->st));
+      s = flag_interp(c, c->L.pos, c->L.pos, c->L.aux, 2);
+    if (s != LB_OK) return s;
     bool any;
     if ((s = enqueue_fint(c, c->L.aux, any)) != LB_OK) return s;
     if (!any) HIPCHK(c, launch_zero(c->L.fint, (size_t)c->np * 24, c->st));
@@ -645,6 +666,7 @@ static lb_status step_once(lb_ctx* c) {
     // lattice pass keeps the first-half field as the pending one (ib_copy).
     if ((s = lattice_pass(c)) != LB_OK) return s;
     c->adv_pending = true;  // X <- X + h/2 I[X~]u(t+h): with the next step, or finish_step
+    c->flags_follow = true;  // the mask now holds the stencils at X~
     return LB_OK;
   }
   if (c->p.coupling == LB_COUPLE_IB) {
@@ -815,6 +837,12 @@ lb_status lb_init_fluid(lb_ctx* c, const double* d_rho, const double* d_u) {
   HIPCHK(c, launch_zero(c->L.FB, vb, c->st));
   HIPCHK(c, launch_zero(c->L.mask, mask_words(c->g) * 8, c->st));
   if (c->p.deterministic) HIPCHK(c, launch_zero(c->L.det, (size_t)c->geo.N * 48, c->st));
+  if (c->tiled) {
+    HIPCHK(c, launch_zero(c->L.U, (size_t)c->geo.N * 4 * (c->p.storage == LB_F64 ? 8 : 4), c->st));
+    HIPCHK(c, launch_zero(c->L.miss, 8, c->st));
+    c->ustamp = 0;
+    c->flags_follow = false;
+  }
   c->pend = 0;
   c->mvalid = false;
   c->uref[0] = c->uref[1] = c->uref[2] = 0.0;
@@ -849,6 +877,7 @@ lb_status lb_set_particles(lb_ctx* c, int64_t n, const double* d_pos, const doub
   c->np = n;
   c->groups_dirty = true;
   c->binned_at = -1;
+  c->flags_follow = false;
   c->mvalid = false;
   return LB_OK;
 }

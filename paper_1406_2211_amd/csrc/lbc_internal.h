@@ -170,9 +170,9 @@ struct TileArgs {
 };
 
 hipError_t launch_bin(const TileArgs& t, const double* pos, long long n, hipStream_t st);
-hipError_t launch_tile_interp(int storage, int K, const TileArgs& t, const SiteArgs& s,
-                              const double* at, double* pos, double* aux, int mode, long long n,
-                              hipStream_t st);
+hipError_t launch_flag_interp(int storage, int K, const SiteArgs& s, const uint64_t* mask,
+                              void* U, uint32_t stamp, const double* at, double* pos, double* aux,
+                              int mode, long long n, int* miss, bool all_miss, hipStream_t st);
 hipError_t launch_tile_spread(int storage, int K, const TileArgs& t, const double* at,
                               const double* F, void* field, long long n, hipStream_t st);
 

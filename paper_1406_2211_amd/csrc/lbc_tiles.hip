@@ -177,103 +177,9 @@ struct TileT<LB_BF16> {
   using W = float;
 };
 
-// Interpolation lane groups: one lane per z-plane of stencil nodes, K planes
-// rounded up to a power of two (2 lanes for K = 2, 4 for K = 3, 4), so that a
-// 256-lane workgroup interpolates 64 markers at once and the group reduction
-// takes one or two butterfly levels.
-template <int K>
-struct RowLanes {
-  static constexpr int L = K == 2 ? 2 : 4;
-};
-
-// Weighted sum over the lane's plane of K x K nodes of the region moments (or
-// of gathered moments for a row with a node that was not staged), reduced
-// over the marker's lane group: u_p = sum_nodes W u(node),
-// W = phi(x) phi(y) phi(z).
-template <int S, int K>
-__device__ __forceinline__ void row_interp(const SiteArgs& s, const Region& r,
-                                           const typename TileT<S>::W* mu,
-                                           const uint32_t* rowm, const double X[3], int lane,
-                                           double up[3]) {
-  using W = typename TileT<S>::W;
-  constexpr int L = RowLanes<K>::L;
-  const int kz = lane;
-  int j0[3];
-  bool inside = true;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    j0[a] = first_node<K>(X[a]);
-    inside = inside && j0[a] - r.o[a] >= 0 && j0[a] - r.o[a] + K <= kReg;
-  }
-  W ux = 0, uy = 0, uz = 0;
-  if (kz < K) {
-    W wx[K], wy[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      wx[k] = phi_eval_t<W>(K, (W)((double)(j0[0] + k) - X[0]));
-      wy[k] = phi_eval_t<W>(K, (W)((double)(j0[1] + k) - X[1]));
-    }
-    const W wz = phi_eval_t<W>(K, (W)((double)(j0[2] + kz) - X[2]));
-    constexpr uint32_t km = (1u << K) - 1u;
-    uint32_t miss = 0;  // rows with a node that was not staged
-#pragma unroll
-    for (int ky = 0; ky < K; ++ky) {
-      const int jy = j0[1] + ky;
-      if (s.g.wall && (jy < 0 || jy >= s.g.ny)) continue;  // beyond a wall: no node
-      bool staged = inside;  // the row's K nodes must all have been staged
-      if (staged) {
-        const uint32_t bits = rowm[(j0[2] + kz - r.o[2]) * kReg + (jy - r.o[1])];
-        staged = ((bits >> (j0[0] - r.o[0])) & km) == km;
-      }
-      if (!staged) {
-        miss |= 1u << ky;
-        continue;
-      }
-      const W* row = mu + ((j0[2] + kz - r.o[2]) * kReg + (jy - r.o[1])) * kReg + (j0[0] - r.o[0]);
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const W Wt = wx[k] * (wy[ky] * wz);
-        if (Wt == W(0)) continue;
-        ux += Wt * row[k];
-        uy += Wt * row[kRegSites + k];
-        uz += Wt * row[2 * kRegSites + k];
-      }
-    }
-    // direct path (rare): gather the missing rows' nodes from global memory,
-    // weights recomputed so that no array is indexed at run time
-#pragma unroll 1
-    for (int ky = 0; miss != 0u && ky < K; ++ky) {
-      const int jy = j0[1] + ky;
-      if (!((miss >> ky) & 1u)) continue;
-      const W wyz = phi_eval_t<W>(K, (W)((double)jy - X[1])) * wz;
-      const int y = s.g.wall ? jy : wrap_idx(jy, s.g.ny), z = wrap_idx(j0[2] + kz, s.g.nz);
-#pragma unroll 1
-      for (int k = 0; k < K; ++k) {
-        const W Wt = phi_eval_t<W>(K, (W)((double)(j0[0] + k) - X[0])) * wyz;
-        if (Wt == W(0)) continue;
-        W drho, j[3];
-        site_phys_r_seq<S, W>(s, wrap_idx(j0[0] + k, s.g.nx), y, z, drho, j);
-        const W rr = W(s.rho0) + drho;
-        ux += Wt * (j[0] / rr);
-        uy += Wt * (j[1] / rr);
-        uz += Wt * (j[2] / rr);
-      }
-    }
-  }
-  up[0] = (double)group_sum_t<L, W>(ux);
-  up[1] = (double)group_sum_t<L, W>(uy);
-  up[2] = (double)group_sum_t<L, W>(uz);
-}
-
-// Interpolation and spreading workgroups are small (256 lanes) so that the
-// occupied tiles of a dense marker set are worked on nearly all at once: the
-// grid holds four per CU.  In FP32 four interpolation workgroups are resident
-// per CU (128 registers, which the rolled direct-path gather keeps within
-// reach; the staged velocities, one marker chunk and the staging lists take
-// 38 KB of LDS) and three spreading ones (40 KB of LDS each).
-constexpr int kInterpLanes = 256;
-constexpr int kInterpWgPerCu = 4;
-constexpr int kInterpChunk = 128;
+// Spreading workgroups are small (256 lanes) so that the occupied tiles of a
+// dense marker set are worked on nearly all at once: the grid holds four per
+// CU; in FP32 three are resident per CU (40 KB of LDS each).
 constexpr int kSpreadLanes = 256;
 constexpr int kSpreadWgPerCu = 4;
 constexpr int kSpreadChunk = 128;
@@ -290,14 +196,10 @@ struct MarkerLds {
   double Y[C][3];  // second vector: pos (interpolation) or force (spreading)
 };
 
-// Which region slots the interpolation stages.  Only the slots inside some
-// marker's stencil are read, about a quarter of the region for markers on a
-// surface, so the workgroup first marks the stencils of its markers (at the
-// positions it knows, widened by kMarkDelta for the drifts of the pass) in a
-// bitmap with one kReg-bit x mask per (y, z) row, then lists the marked slots
-// and stages only those.  A stencil row with an unstaged node takes the
-// direct path, so the bitmap decides speed, not results.
-constexpr double kMarkDelta = 0.05;
+// The region slots the spreading accumulates: the workgroup marks the
+// stencils of its markers in a bitmap with one kReg-bit x mask per (y, z)
+// row, then lists the marked slots (about a quarter of the region for markers
+// on a surface).
 constexpr int kRows = kReg * kReg;
 constexpr int kListWaves = (kRegSites + 63) / 64;
 static_assert(kListWaves <= 64, "segment offsets are scanned by one wavefront");
@@ -370,149 +272,334 @@ __device__ __forceinline__ void list_marked(StageLds* sg, unsigned short* idx) {
   __syncthreads();
 }
 
-// ------------------------------------------------------------- interpolation
-// mode 0: IB predictor       aux = wrap(pos + h/2 u(pos))
-// mode 1: IB advection       pos = wrap(pos + h/2 u(aux))
-// mode 2: both, in that order, from one staged region (at = pos); the first
-//         advection only needs the state before the lattice pass, like the
-//         predictor, so both read the same LDS moments.
-// mode 3: mode 1 of one step followed by mode 2 of the next (at = aux): the
-//         final advection of a step and the predictor and first advection of
-//         the next read the same fluid state, so one staging serves all three.
-// A marker whose stencil leaves the region gathers its nodes from global
-// memory instead (same arithmetic per node).  Workgroups loop over the
-// occupied tiles (persistent grid).
-template <int S, int K>
-__global__ __launch_bounds__(kInterpLanes) void k_tile_interp(TileArgs t, SiteArgs s,
-                                                              const double* at, double* pos,
-                                                              double* aux, int mode) {
-  constexpr int L = RowLanes<K>::L;
-  constexpr int G = 16;  // lanes per marker while marking
+// ------------------------------------------------ interpolation, flagged sites
+// The sites whose force-mask bit is set after the lattice pass are those where
+// the pending immersed-boundary field is nonzero: the stencil sites of the
+// last spread, at the predictor positions X~.  The markers interpolate at X~
+// (the final advection of the previous step) and at points that have drifted
+// by a fraction of a site from there, so nearly all of their stencil nodes
+// are flagged.  k_flag_vel computes the physical velocity (pull gather plus
+// pending half force, the redefined velocity of Sec. 4) of every flagged site
+// once into a dense field U, each entry stamped with the number of the call;
+// k_marker_interp interpolates each marker from U alone, and a marker that
+// meets a node without the current stamp is listed and redone by
+// k_marker_slow, which gathers such nodes from the populations (same
+// arithmetic).  So the flags decide speed, not results.
+
+// Stamp of a velocity entry, kept in its fourth component as raw bits.
+__device__ __forceinline__ float stamp_value(float, uint32_t st) { return __uint_as_float(st); }
+__device__ __forceinline__ double stamp_value(double, uint32_t st) {
+  return __longlong_as_double((long long)st);
+}
+__device__ __forceinline__ bool stamped(float w, uint32_t st) { return __float_as_uint(w) == st; }
+__device__ __forceinline__ bool stamped(double w, uint32_t st) {
+  return __double_as_longlong(w) == (long long)st;
+}
+
+// j mod n for a stencil node: one compare-and-add for a node within a box
+// length of the box, the division otherwise.
+__device__ __forceinline__ int wrap_near(int j, int n) {
+  const int r = j < 0 ? j + n : (j >= n ? j - n : j);
+  return (unsigned)r < (unsigned)n ? r : wrap_idx(j, n);
+}
+
+// Position of the n-th set bit (n < popcount) of v.
+__device__ __forceinline__ int nth_set_bit(uint64_t v, int n) {
+  int pos = 0;
+#pragma unroll
+  for (int half = 32; half > 0; half >>= 1) {
+    const int c = __popcll(v & ((1ull << half) - 1ull));
+    if (n >= c) {
+      n -= c;
+      v >>= half;
+      pos += half;
+    }
+  }
+  return pos;
+}
+
+// Each wavefront reads kFlagWords mask words and hands their flagged sites
+// out one per lane (a scan of the words' bit counts and a binary search in
+// it), so that one round of 19 gathers serves up to 64 flagged sites.
+constexpr int kFlagWords = 16;
+
+template <int S>
+__global__ __launch_bounds__(256) void k_flag_vel(SiteArgs s, const uint64_t* __restrict__ mask,
+                                                  long long nwords, void* Uv, uint32_t stamp) {
   using W = typename TileT<S>::W;
-  using MK = MarkerLds<kInterpChunk>;
-  constexpr int kChunk = MK::kChunk;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  W* mu = (W*)lds_raw;                                                // 3 * kRegSites
-  MK* mk = (MK*)(lds_raw + sizeof(W) * 3 * kRegSites);                // one chunk
-  StageLds* sg = (StageLds*)(lds_raw + sizeof(W) * 3 * kRegSites + sizeof(MK));
-  const int lane = threadIdx.x % L;
-  const int nocc = t.nocc[0];
-  const bool two = mode == 1 || mode == 3;  // pos is read as well as at
-  auto load_chunk = [&](int c0, int nc) {
-    for (int i = threadIdx.x; i < nc; i += blockDim.x) {
-      const int p = t.sorted[c0 + i];
-      mk->p[i] = p;
-      for (int a = 0; a < 3; ++a) {
-        mk->X[i][a] = at[3 * (long long)p + a];
-        mk->Y[i][a] = two ? pos[3 * (long long)p + a] : 0.0;
-      }
+  using V4 = typename Store<S>::V4;
+  const int lane = (int)threadIdx.x & 63;
+  const long long chunk = (long long)kFlagWords * gridDim.x * (blockDim.x / 64);
+  for (long long base = (long long)kFlagWords * (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
+       base < nwords; base += chunk) {
+    const long long w = base + lane;
+    const uint64_t word = (lane < kFlagWords && w < nwords) ? mask[w] : 0ull;
+    const int c = __popcll(word);
+    int incl = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int u = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += u;
     }
-  };
-  for (int ot = blockIdx.x; ot < nocc; ot += gridDim.x) {
-    const int tl = t.occ[ot];
-    const Region r = region_of(t, tl);
-    const int b0 = t.start[tl], b1 = t.start[tl + 1];
-    // first marker chunk, and a cleared bitmap
-    load_chunk(b0, min(kChunk, b1 - b0));
-    for (int k = threadIdx.x; k < kRows; k += blockDim.x) sg->rowm[k] = 0u;
-    __syncthreads();
-    // mark the stencils the pass will read: at at and, where it is also
-    // interpolated from, at pos (mode 3: the final advection starts there)
-    for (int i = (int)threadIdx.x / G; i < b1 - b0; i += (int)blockDim.x / G) {
-      double X[3], Y[3];
-      if (i < kChunk) {
-        for (int a = 0; a < 3; ++a) {
-          X[a] = mk->X[i][a];
-          Y[a] = mk->Y[i][a];
-        }
-      } else {
-        const long long p = t.sorted[b0 + i];
-        for (int a = 0; a < 3; ++a) {
-          X[a] = at[3 * p + a];
-          Y[a] = two ? pos[3 * p + a] : 0.0;
-        }
+    const int excl = incl - c;
+    const int total = __shfl(incl, 63, 64);
+    for (int k0 = 0; k0 < total; k0 += 64) {
+      const int k = k0 + lane;
+      int lo = 0;  // the last word whose first flagged site is at or before k
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1) {
+        const int mid = lo + step;
+        if (__shfl(excl, mid, 64) <= k) lo = mid;
       }
-      mark_stencil<K>(r, X, kMarkDelta, sg->rowm, (int)threadIdx.x % G, G);
-      if (mode == 3) mark_stencil<K>(r, Y, kMarkDelta, sg->rowm, (int)threadIdx.x % G, G);
-    }
-    __syncthreads();
-    list_marked(sg, nullptr);
-    const int nlist = sg->nlist;
-    for (int i = threadIdx.x; i < nlist; i += blockDim.x) {
-      const int k = sg->list[i];
-      const int ix = k % kReg, iy = (k / kReg) % kReg, iz = k / (kReg * kReg);
+      const uint64_t wl = __shfl(word, lo, 64);
+      const int nth = k - __shfl(excl, lo, 64);
+      if (k >= total) continue;
+      const int bit = nth_set_bit(wl, nth);
+      const long long wi = base + lo;
       int x, y, z;
-      W u0 = W(0), u1 = W(0), u2 = W(0);  // beyond a wall: never read
-      if (slot_site(s.g, r, ix, iy, iz, x, y, z)) {
-        W drho, j[3];
-        site_phys_r<S, W>(s, x, y, z, drho, j);
-        const W rr = W(s.rho0) + drho;
-        u0 = j[0] / rr;
-        u1 = j[1] / rr;
-        u2 = j[2] / rr;
+      if (s.g.wpr) {
+        const long long row = wi / s.g.wpr;
+        x = (int)(wi % s.g.wpr) * 64 + bit;
+        y = (int)(row % s.g.ny);
+        z = (int)(row / s.g.ny);
+      } else {
+        const long long site = wi * 64 + bit;
+        x = (int)(site % s.g.nx);
+        y = (int)((site / s.g.nx) % s.g.ny);
+        z = (int)(site / ((long long)s.g.nx * s.g.ny));
       }
-      mu[k] = u0;
-      mu[kRegSites + k] = u1;
-      mu[2 * kRegSites + k] = u2;
+      W drho, j[3];
+      site_phys_r<S, W>(s, x, y, z, drho, j);
+      const W rr = W(s.rho0) + drho;
+      V4 u;
+      u.x = j[0] / rr;
+      u.y = j[1] / rr;
+      u.z = j[2] / rr;
+      u.w = stamp_value(W(0), stamp);
+      ((V4*)Uv)[site_index(s.g, x, y, z)] = u;
     }
-    auto interp_at = [&](const double X[3], double up[3]) {
-      row_interp<S, K>(s, r, mu, sg->rowm, X, lane, up);
-    };
-    auto half_drift = [&](const double from[3], const double u[3], double to[3]) {
-      for (int a = 0; a < 3; ++a) to[a] = from[a] + 0.5 * u[a];
-      to[0] = wrap_pos(to[0], (double)s.g.nx);
-      if (!s.g.wall) to[1] = wrap_pos(to[1], (double)s.g.ny);
-      to[2] = wrap_pos(to[2], (double)s.g.nz);
-    };
-    for (int c0 = b0; c0 < b1; c0 += kChunk) {
-      const int nc = min(kChunk, b1 - c0);
-      if (c0 != b0) {
-        __syncthreads();  // previous chunk done with mk
-        load_chunk(c0, nc);
-      }
-      __syncthreads();  // staged moments (first chunk) or the new chunk ready
-      for (int i = (int)threadIdx.x / L; i < nc; i += (int)blockDim.x / L) {  // groups leave together
-        const long long p = mk->p[i];
-        const double X[3] = {mk->X[i][0], mk->X[i][1], mk->X[i][2]};
-        const double P[3] = {mk->Y[i][0], mk->Y[i][1], mk->Y[i][2]};
-        // Interpolation points in order (one call site, so the interpolation
-        // is compiled once): mode 0, 1: X; mode 2: X, then X~ = X + h/2 u(X);
-        // mode 3: X (= X~ of the previous step), then Xs = P + h/2 u(X), then
-        // X~ = Xs + h/2 u(Xs).  Xs is the point the last half drift starts from.
-        const int nint = mode == 3 ? 3 : (mode == 2 ? 2 : 1);
-        double q[3] = {X[0], X[1], X[2]}, Xs[3] = {X[0], X[1], X[2]}, u[3], Y[3];
-#pragma unroll 1
-        for (int it = 0; it < nint; ++it) {
-          interp_at(q, u);
-          if (it + 1 == nint) break;
-          if (mode == 3 && it == 0) {
-            half_drift(P, u, Xs);
-            for (int a = 0; a < 3; ++a) q[a] = Xs[a];
-          } else {
-            half_drift(Xs, u, q);
-          }
-        }
-        if (mode == 0) {  // predictor only
-          half_drift(X, u, Y);
-          if (lane == 0)
-            for (int a = 0; a < 3; ++a) aux[3 * p + a] = Y[a];
-        } else if (mode == 1) {  // advection with the velocity at X~ = at
-          half_drift(P, u, Y);
-          if (lane == 0)
-            for (int a = 0; a < 3; ++a) pos[3 * p + a] = Y[a];
-        } else {  // X~ = q, and X <- Xs + h/2 u(X~)
-          half_drift(Xs, u, Y);
-          if (lane == 0)
-            for (int a = 0; a < 3; ++a) {
-              aux[3 * p + a] = q[a];
-              pos[3 * p + a] = Y[a];
-            }
-        }
-      }
-    }
-    __syncthreads();  // region moments and bitmap are overwritten by the next tile
   }
 }
+
+// One axis of a K-point stencil (Appendix A kernels) in closed form: the
+// first node j0 and two parameters t, q from which each of the K weights
+// follows in two operations (the K = 4 and K = 3 weights share one square
+// root).  K = 4: t = X - floor(X), j0 = floor(X) - 1, q = sqrt(1 + 4t - 4t^2),
+//   weights (3 - 2t - q, 3 - 2t + q, 1 + 2t + q, 1 + 2t - q) / 8;
+// K = 3: t = X - round(X), j0 = round(X) - 1, q = sqrt(1 - 3t^2),
+//   weights ((2 - 3t - q) / 6, (1 + q) / 3, (2 + 3t - q) / 6);
+// K = 2: t = X - floor(X), j0 = floor(X), weights (1 - t, t).
+// These are the piecewise definitions evaluated at the node distances
+// -1 - t, -t, 1 - t, 2 - t (K = 4) and -1 - t, -t, 1 - t (K = 3, 2).  The
+// position is clamped as in safe_floor, so any X gives an in-range node.
+template <int K, typename W>
+__device__ __forceinline__ void stencil_t(double X, int& j0, W& t, W& q) {
+  const double f = floor(fmin(fmax(K == 3 ? X + 0.5 : X, -1073741824.0), 1073741824.0));
+  j0 = (int)f - (K == 2 ? 0 : 1);
+  t = (W)(X - f);
+  q = K == 4 ? sqrt(W(1) + W(4) * t - W(4) * t * t) : (K == 3 ? sqrt(W(1) - W(3) * t * t) : W(0));
+}
+template <int K, typename W>
+__device__ __forceinline__ W node_weight(int k, W t, W q) {
+  if (K == 4) {
+    const W a = k < 2 ? W(3) : W(1), b = k < 2 ? W(-2) : W(2), c = (k == 1 || k == 2) ? W(1) : W(-1);
+    return (a + b * t + c * q) * W(0.125);
+  }
+  if (K == 3) {
+    if (k == 1) return (W(1) + q) * (W(1) / W(3));
+    return (W(2) + (k == 0 ? W(-3) : W(3)) * t - q) * (W(1) / W(6));
+  }
+  return k == 0 ? W(1) - t : t;
+}
+
+// Sum over an aligned group of G = 4 or 16 lanes with DPP moves (every lane
+// gets the sum): pairs and quads by quad permutations, then the two quads of
+// each 8-lane half by a half-row mirror and the two halves by a row mirror.
+template <int ctrl>
+__device__ __forceinline__ float dpp_add(float v) {
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xf, 0xf, false));
+}
+template <int ctrl>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, ctrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xf, 0xf, false);
+  return v + __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int G, typename T>
+__device__ __forceinline__ T group_sum_dpp(T v) {
+  static_assert(G == 4 || G == 16, "DPP group sums cover 4 or 16 lanes");
+  v = dpp_add<0xB1>(v);  // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E>(v);  // quad_perm [2,3,0,1]
+  if (G == 16) {
+    v = dpp_add<0x141>(v);  // row_half_mirror
+    v = dpp_add<0x140>(v);  // row_mirror
+  }
+  return v;
+}
+
+// Lanes per marker: one per (x, y) column of stencil nodes, K rounded up to a
+// power of two in x and y, so that in each z plane the lanes of a marker read
+// whole x rows of the velocity field.
+template <int K>
+struct ColGroup {
+  static constexpr int KP = K == 2 ? 2 : 4;
+  static constexpr int G = KP * KP;
+};
+
+// Interpolated velocity of one stencil (Eq. IBM-interpolation),
+// u_p = sum W u(node), W = phi(x) phi(y) phi(z): lane r takes the node column
+// (r % KP, r / KP) over the K z planes, and the marker's lanes sum.  FAST:
+// nodes are read from U only, and the return value (the same on every lane of
+// the group) tells whether each node carried the stamp; otherwise a node
+// without it is gathered from the populations and the return value is true.
+template <int S, int K, bool FAST>
+__device__ __forceinline__ bool marker_interp_at(const SiteArgs& s, const void* Uv,
+                                                 uint32_t stamp, const double X[3], int r,
+                                                 double up[3]) {
+  using W = typename TileT<S>::W;
+  using V4 = typename Store<S>::V4;
+  constexpr int KP = ColGroup<K>::KP, G = ColGroup<K>::G;
+  int j0[3];
+  W t[3], q[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) stencil_t<K, W>(X[a], j0[a], t[a], q[a]);
+  const int kx = r % KP, ky = r / KP;
+  const int jx = j0[0] + kx, jy = j0[1] + ky;
+  W ux = 0, uy = 0, uz = 0;
+  bool all = true;
+  if (kx < K && ky < K && !(s.g.wall && (jy < 0 || jy >= s.g.ny))) {
+    const W wxy = node_weight<K, W>(kx, t[0], q[0]) * node_weight<K, W>(ky, t[1], q[1]);
+    const uint32_t nx = (uint32_t)s.g.nx, ny = (uint32_t)s.g.ny;
+    const uint32_t x = (uint32_t)wrap_near(jx, s.g.nx);
+    const uint32_t y = (uint32_t)(s.g.wall ? jy : wrap_near(jy, s.g.ny));
+#pragma unroll
+    for (int kz = 0; kz < K; ++kz) {
+      const uint32_t z = (uint32_t)wrap_near(j0[2] + kz, s.g.nz);
+      const W Wt = wxy * node_weight<K, W>(kz, t[2], q[2]);
+      V4 u = ((const V4*)Uv)[(z * ny + y) * nx + x];  // fewer than 2^32 sites
+      const bool ok = stamped(u.w, stamp);
+      if (!FAST && !ok) {  // a node that was not flagged: gather it
+        W drho, j[3];
+        site_phys_r<S, W>(s, (int)x, (int)y, (int)z, drho, j);
+        const W rr = W(s.rho0) + drho;
+        u.x = j[0] / rr;
+        u.y = j[1] / rr;
+        u.z = j[2] / rr;
+      }
+      all = all && ok;
+      ux += Wt * u.x;
+      uy += Wt * u.y;
+      uz += Wt * u.z;
+    }
+  }
+  up[0] = (double)group_sum_dpp<G, W>(ux);
+  up[1] = (double)group_sum_dpp<G, W>(uy);
+  up[2] = (double)group_sum_dpp<G, W>(uz);
+  if (!FAST) return true;
+  const int lane = (int)threadIdx.x & 63;
+  const uint64_t miss = __ballot(!all);
+  const uint64_t gm = ((1ull << G) - 1ull) << (lane / G * G);
+  return (miss & gm) == 0ull;
+}
+
+// One marker's interpolations and half drifts.
+// mode 0: IB predictor       aux = wrap(pos + h/2 u(pos))
+// mode 1: IB advection       pos = wrap(pos + h/2 u(aux))
+// mode 2: both, in that order (at = pos); the first advection only needs the
+//         state before the lattice pass, like the predictor.
+// mode 3: mode 1 of one step followed by mode 2 of the next (at = aux): the
+//         final advection of a step and the predictor and first advection of
+//         the next read the same fluid state.
+// FAST stops, with nothing written, at the first stencil with a node outside
+// the velocity field's current stamp and returns false.
+template <int S, int K, bool FAST>
+__device__ __forceinline__ bool marker_run(const SiteArgs& s, const void* Uv, uint32_t stamp,
+                                           const double* at, double* pos, double* aux, int mode,
+                                           long long p, int r) {
+  const double X[3] = {at[3 * p], at[3 * p + 1], at[3 * p + 2]};
+  double P[3] = {0.0, 0.0, 0.0};
+  if (mode == 1 || mode == 3)
+    for (int a = 0; a < 3; ++a) P[a] = pos[3 * p + a];
+  auto half_drift = [&](const double from[3], const double u[3], double to[3]) {
+    for (int a = 0; a < 3; ++a) to[a] = from[a] + 0.5 * u[a];
+    to[0] = wrap_pos(to[0], (double)s.g.nx);
+    if (!s.g.wall) to[1] = wrap_pos(to[1], (double)s.g.ny);
+    to[2] = wrap_pos(to[2], (double)s.g.nz);
+  };
+  // Interpolation points in order: mode 0, 1: X; mode 2: X, then
+  // X~ = X + h/2 u(X); mode 3: X (= X~ of the previous step), then
+  // Xs = P + h/2 u(X), then X~ = Xs + h/2 u(Xs).
+  const int nint = mode == 3 ? 3 : (mode == 2 ? 2 : 1);
+  double q[3] = {X[0], X[1], X[2]}, Xs[3] = {X[0], X[1], X[2]}, u[3], Y[3];
+#pragma unroll 1
+  for (int it = 0; it < nint; ++it) {
+    if (!marker_interp_at<S, K, FAST>(s, Uv, stamp, q, r, u)) return false;
+    if (it + 1 == nint) break;
+    if (mode == 3 && it == 0) {
+      half_drift(P, u, Xs);
+      for (int a = 0; a < 3; ++a) q[a] = Xs[a];
+    } else {
+      half_drift(Xs, u, q);
+    }
+  }
+  if (mode == 0) {
+    half_drift(X, u, Y);
+    if (r == 0)
+      for (int a = 0; a < 3; ++a) aux[3 * p + a] = Y[a];
+  } else if (mode == 1) {
+    half_drift(P, u, Y);
+    if (r == 0)
+      for (int a = 0; a < 3; ++a) pos[3 * p + a] = Y[a];
+  } else {
+    half_drift(Xs, u, Y);
+    if (r == 0)
+      for (int a = 0; a < 3; ++a) {
+        aux[3 * p + a] = q[a];
+        pos[3 * p + a] = Y[a];
+      }
+  }
+  return true;
+}
+
+// One marker per group of G lanes, from the velocity field only.  A marker
+// that meets a node without the current stamp is listed: miss[stamp & 1]
+// counts, the list follows the two counters.  Six wavefronts per SIMD for
+// the 32-bit weights (80 registers, no spills); FP64 keeps its register
+// count.
+template <int S, int K>
+__global__ __launch_bounds__(256, S == LB_F64 ? 1 : 6) void k_marker_interp(
+    SiteArgs s, const void* Uv, uint32_t stamp, const double* at, double* pos, double* aux,
+    int mode, long long n, int* miss) {
+  constexpr int G = ColGroup<K>::G;
+  const long long p = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int r = (int)threadIdx.x % G;
+  if (p >= n) return;  // whole groups leave together
+  if (marker_run<S, K, true>(s, Uv, stamp, at, pos, aux, mode, p, r)) return;
+  if (r == 0) miss[2 + atomicAdd(miss + (stamp & 1u), 1)] = (int)p;
+}
+
+// The listed markers, with the nodes that lack the stamp gathered from the
+// populations (a grid-stride loop over the list); also clears the counter
+// that the next call uses.
+template <int S, int K>
+__global__ __launch_bounds__(256) void k_marker_slow(SiteArgs s, const void* Uv, uint32_t stamp,
+                                                     const double* at, double* pos, double* aux,
+                                                     int mode, int* miss) {
+  constexpr int G = ColGroup<K>::G;
+  const int cnt = miss[stamp & 1u];
+  const long long lanes = (long long)gridDim.x * blockDim.x;
+  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g / G < cnt; g += lanes)
+    marker_run<S, K, false>(s, Uv, stamp, at, pos, aux, mode, miss[2 + g / G], (int)(g % G));
+  if (blockIdx.x == 0 && threadIdx.x == 0) miss[(stamp + 1u) & 1u] = 0;
+}
+
+// Spreading lane groups: one lane per z-plane of stencil nodes, K planes
+// rounded up to a power of two (2 lanes for K = 2, 4 for K = 3, 4).
+template <int K>
+struct RowLanes {
+  static constexpr int L = K == 2 ? 2 : 4;
+};
 
 // ------------------------------------------------------------------ spreading
 // The accumulator is FP64 whatever the field precision: LDS atomic adds run
@@ -660,7 +747,7 @@ hipError_t launch_bin(const TileArgs& t, const double* pos, long long n, hipStre
 
 // Persistent grid over the occupied tiles (their number is only known on the
 // device): per_cu workgroups per CU, at most one per tile.
-static unsigned tile_grid(const TileArgs& t, int per_cu) {
+static int cu_count() {
   static int cus = 0;
   if (cus == 0) {
     int dev = 0;
@@ -669,7 +756,11 @@ static unsigned tile_grid(const TileArgs& t, int per_cu) {
               ? prop.multiProcessorCount
               : 256;
   }
-  return (unsigned)std::min(t.ntiles, per_cu * cus);
+  return cus;
+}
+
+static unsigned tile_grid(const TileArgs& t, int per_cu) {
+  return (unsigned)std::min(t.ntiles, per_cu * cu_count());
 }
 
 #define LBC_TILE_K_SWITCH(K, CALL)                        \
@@ -686,14 +777,23 @@ static unsigned tile_grid(const TileArgs& t, int per_cu) {
     default: { constexpr int SS = LB_BF16; CALL; } break;           \
   }
 
-hipError_t launch_tile_interp(int storage, int K, const TileArgs& t, const SiteArgs& s,
-                              const double* at, double* pos, double* aux, int mode, long long n,
-                              hipStream_t st) {
+hipError_t launch_flag_interp(int storage, int K, const SiteArgs& s, const uint64_t* mask,
+                              void* U, uint32_t stamp, const double* at, double* pos, double* aux,
+                              int mode, long long n, int* miss, bool all_miss, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  LBC_TILE_K_SWITCH(K, LBC_TILE_S_SWITCH(storage, (k_tile_interp<SS, KK>
-      <<<tile_grid(t, kInterpWgPerCu), kInterpLanes,
-         sizeof(typename TileT<SS>::W) * 3 * kRegSites + sizeof(MarkerLds<kInterpChunk>) +
-             sizeof(StageLds), st>>>(t, s, at, pos, aux, mode))));
+  const long long nwords = s.g.wpr ? (long long)s.g.ny * s.g.nz * s.g.wpr : (s.g.N + 63) / 64;
+  const long long per_wg = 4ll * kFlagWords;
+  const unsigned gv = (unsigned)std::min<long long>((nwords + per_wg - 1) / per_wg, 64ll * cu_count());
+  const long long lanes = n * (K == 2 ? 4 : 16);
+  const unsigned gi = (unsigned)((lanes + 255) / 256);
+  // The listed markers are few once the flags follow the markers; right after
+  // the fluid or the markers were set every marker is listed.
+  const unsigned gs = all_miss ? gi : 64u;
+  LBC_TILE_S_SWITCH(storage, (k_flag_vel<SS><<<gv, 256, 0, st>>>(s, mask, nwords, U, stamp)));
+  LBC_TILE_K_SWITCH(K, LBC_TILE_S_SWITCH(storage, (k_marker_interp<SS, KK><<<gi, 256, 0, st>>>(
+                                                      s, U, stamp, at, pos, aux, mode, n, miss))));
+  LBC_TILE_K_SWITCH(K, LBC_TILE_S_SWITCH(storage, (k_marker_slow<SS, KK><<<gs, 256, 0, st>>>(
+                                                      s, U, stamp, at, pos, aux, mode, miss))));
   return hipGetLastError();
 }
 
