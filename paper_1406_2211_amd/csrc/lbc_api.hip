@@ -141,6 +141,7 @@ bool check_params(const lb_grid* g, const lb_params* p, const lb_limits* lim, st
   if (p->f16_scale_log2 < -40 || p->f16_scale_log2 > 40)
     return err = "f16_scale_log2 out of range", false;
   if (p->mts_substeps < 0 || p->mts_substeps > 256) return err = "mts_substeps out of range", false;
+  if (p->ib_rebin < 0) return err = "ib_rebin must be >= 0", false;
   if (p->mts_substeps > 0 && p->coupling == LB_COUPLE_IB)
     return err = "multiple time stepping applies to force coupling only", false;
   if (p->mts_inside != 0 && p->mts_inside != 1) return err = "mts_inside must be 0 or 1", false;
@@ -169,7 +170,7 @@ bool check_params(const lb_grid* g, const lb_params* p, const lb_limits* lim, st
 }
 
 // Steps between two binnings of IB markers into tiles.
-constexpr int64_t kRebin = 8;
+constexpr int64_t kRebin = 8;  // default steps between two marker binnings
 
 }  // namespace
 
@@ -642,7 +643,8 @@ static lb_status step_once(lb_ctx* c) {
     // a marker whose stencil has left its tile's region adds to the field
     // directly, so results do not depend on how fresh the binning is.
     // Markers move far less than a site per step: rebin every kRebin steps.
-    if (c->binned_at < 0 || c->steps - c->binned_at >= kRebin) {
+    const int64_t rebin = c->p.ib_rebin > 0 ? c->p.ib_rebin : kRebin;
+    if (c->binned_at < 0 || c->steps - c->binned_at >= rebin) {
       HIPCHK(c, launch_bin(t, c->L.pos, c->np, c->st));
       c->binned_at = c->steps;
     }

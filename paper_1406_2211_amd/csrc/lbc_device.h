@@ -197,9 +197,14 @@ __device__ __forceinline__ uint64_t* mask_word(uint64_t* m, const Geo& g, int x,
 }
 
 // Flag a site for the next lattice pass (after its force was added): a plain
-// load first, since in steady state the bit is usually set already.
+// load first, since in steady state the bit is usually set already.  The load
+// goes through the caches (an atomic load of device or system scope would
+// bypass them and take a memory round trip per site): bits are only set while
+// a kernel flags sites and cleared by the lattice pass, a kernel boundary
+// away, so a cached copy can at worst lack a bit set meanwhile by another
+// workgroup, which costs one redundant atomic.
 __device__ __forceinline__ void flag_site(uint64_t* mw, uint64_t bit) {
-  if (!(__atomic_load_n(mw, __ATOMIC_RELAXED) & bit)) atomicOr((unsigned long long*)mw, bit);
+  if (!(*mw & bit)) atomicOr((unsigned long long*)mw, bit);
 }
 
 // Quotient and remainder of n / d for 32-bit n and d >= 1, with rd = 1/d

@@ -435,13 +435,14 @@ __device__ __forceinline__ void group_interp(const PartArgs& a, const double X[3
 // The mask word of the lane's stencil node at X, loaded ahead of the
 // spreading so that its latency overlaps the gathers: bits are only set while
 // a coupling kernel runs (the lattice pass clears them between kernels), so a
-// bit seen set stays set, and one seen clear is set with an atomic.
+// bit seen set stays set, and one seen clear is set with an atomic.  A plain,
+// cached load (see flag_site).
 template <int K>
 __device__ __forceinline__ uint64_t mask_preload(const PartArgs& a, const double X[3], int lane) {
   const SiteSlot sl = slot_of<K>(a.s.g, X, lane);
   if (!sl.valid) return ~0ull;
   uint64_t bit;
-  return __atomic_load_n(mask_word(a.mask, a.s.g, sl.x, sl.y, sl.z, bit), __ATOMIC_RELAXED);
+  return *mask_word(a.mask, a.s.g, sl.x, sl.y, sl.z, bit);
 }
 
 // Spread W F to the lane's stencil node; pre: the node's mask word from

@@ -1,31 +1,21 @@
-// lbc_tiles.hip -- binned, LDS-staged interpolation and spreading for dense
-// Lagrangian markers (immersed-boundary shells).
+// lbc_tiles.hip -- interpolation and spreading for dense Lagrangian markers
+// (immersed-boundary shells).
 //
-// Markers are binned into 8x8x8 lattice tiles by the cell containing them
-// (counting sort: count, single-block scan that also lists the occupied tiles
-// in increasing order, scatter).  Workgroups loop over the occupied tiles;
-// for each they work on a region of 13^3 sites: the tile, two sites below it
-// and three above.  That covers the 2-, 3- and 4-point stencils of every
-// marker binned into the tile, also after it has moved by up to one lattice
-// spacing in any direction since the binning (the 4-point stencil reaches one
-// node below the marker's cell and two above it).  A marker whose stencil
-// leaves the region (it moved further, or across a periodic seam) takes the
-// direct path that gathers from global memory.  The markers of a tile are
-// staged in LDS too, in chunks.
-//
-//   interpolation (Eq. IBM-interpolation): the region sites that some marker
-//   stencil covers are marked in an LDS bitmap and listed; their physical
-//   velocities u are computed once (pull gather + pending half force) into
-//   LDS (FP64 with FP64 storage, FP32 otherwise); each marker then sums K^3
-//   weighted LDS entries, one lane per z-plane of stencil nodes and a butterfly
-//   reduction over the lane group.
-//   spreading (Eq. IBM-spreading): the stencil sites are listed the same way;
-//   markers add W F into an FP64 LDS accumulator of the listed sites (LDS
-//   atomics, one lane per z-plane of stencil nodes); the workgroup then adds
-//   every nonzero listed site to the global force field once and flags it for
-//   the lattice pass.
-// Workgroups have 256 lanes, four per CU in the grid, so that nearly every
-// tile of a dense marker set is worked on at once.
+//   interpolation (Eq. IBM-interpolation): from the velocity of the sites the
+//   last spread flagged, computed once per step (see "interpolation, flagged
+//   sites" below); no binning needed.
+//   spreading (Eq. IBM-spreading): markers are binned into 8x8x8 lattice
+//   tiles by the cell containing them (counting sort: count, single-block
+//   scan that also lists the occupied tiles in increasing order, scatter).
+//   Workgroups loop over the occupied tiles; each sums its markers' stencil
+//   contributions over a region of 11^3 sites (the tile, one site below it
+//   and two above) in LDS and adds the region to the field once.  The region
+//   is the union of the 2-, 3- and 4-point stencils of the tile's cells (the
+//   4-point stencil reaches one node below a marker's cell and two above
+//   it); a node outside it (the marker has crossed a cell face out of the
+//   tile since the binning, or a periodic seam) is added to the field
+//   directly.  On the shell channel (128x128x256, 41 088 markers, binning
+//   every 8 steps) that is about 20 of 2.6 million nodes per step.
 #include <algorithm>
 
 #include "lbc_device.h"
@@ -34,8 +24,8 @@
 namespace lbc {
 
 constexpr int kTile = 8;
-constexpr int kLo = 2;     // region starts two sites below the tile
-constexpr int kReg = 13;   // region edge: tile + 2 below + 3 above
+constexpr int kLo = 1;     // region starts one site below the tile
+constexpr int kReg = 11;   // region edge: tile + 1 below + 2 above
 constexpr int kRegSites = kReg * kReg * kReg;
 
 __device__ __forceinline__ int tile_of(const TileArgs& t, const double X[3], int c[3]) {
@@ -176,101 +166,6 @@ template <>
 struct TileT<LB_BF16> {
   using W = float;
 };
-
-// Spreading workgroups are small (256 lanes) so that the occupied tiles of a
-// dense marker set are worked on nearly all at once: the grid holds four per
-// CU; in FP32 three are resident per CU (40 KB of LDS each).
-constexpr int kSpreadLanes = 256;
-constexpr int kSpreadWgPerCu = 4;
-constexpr int kSpreadChunk = 128;
-constexpr int kSpreadCap = 1024;  // accumulated sites per tile
-
-// Markers of the tile being processed, staged in LDS in chunks of C
-// (index and the positions and forces the kernel reads), so that the marker
-// loops never wait on dependent global loads.
-template <int C>
-struct MarkerLds {
-  static constexpr int kChunk = C;
-  int p[C];
-  double X[C][3];  // position the stencil is built at
-  double Y[C][3];  // second vector: pos (interpolation) or force (spreading)
-};
-
-// The region slots the spreading accumulates: the workgroup marks the
-// stencils of its markers in a bitmap with one kReg-bit x mask per (y, z)
-// row, then lists the marked slots (about a quarter of the region for markers
-// on a surface).
-constexpr int kRows = kReg * kReg;
-constexpr int kListWaves = (kRegSites + 63) / 64;
-static_assert(kListWaves <= 64, "segment offsets are scanned by one wavefront");
-
-struct StageLds {
-  uint32_t rowm[kRows];         // x mask of marked slots per (y, z) row
-  int cnt[kListWaves];          // marked slots per 64-slot segment, then their offsets
-  unsigned short list[kRegSites];  // marked slots, increasing
-  int nlist;
-};
-
-// Mark the slots of the K-point stencils of X - d .. X + d (per axis),
-// clipped to the region; lanes g of a group of G cover the rows.
-template <int K>
-__device__ __forceinline__ void mark_stencil(const Region& r, const double X[3], double d,
-                                             uint32_t* rowm, int g, int G) {
-  int lo[3], hi[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = max(first_node<K>(X[a] - d) - r.o[a], 0);
-    hi[a] = min(first_node<K>(X[a] + d) + K - 1 - r.o[a], kReg - 1);
-  }
-  if (lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2]) return;
-  const uint32_t xb = ((1u << (hi[0] - lo[0] + 1)) - 1u) << lo[0];
-  const int ny = hi[1] - lo[1] + 1, nrow = ny * (hi[2] - lo[2] + 1);
-  for (int q = g; q < nrow; q += G)
-    atomicOr(rowm + (lo[2] + q / ny) * kReg + lo[1] + q % ny, xb);
-}
-
-// List the slots marked in sg->rowm in increasing order: per 64-slot segment
-// a wave ballot counts them, one wavefront scans the counts into offsets, and
-// every marked slot writes itself at its offset plus its rank in the ballot.
-// idx (optional) receives each listed slot's list position.  Called after a
-// barrier that follows the marking; ends with a barrier.
-__device__ __forceinline__ void list_marked(StageLds* sg, unsigned short* idx) {
-  const int wv = (int)threadIdx.x / 64;
-  for (int k0 = 0; k0 < kRegSites; k0 += (int)blockDim.x) {
-    const int seg = k0 / 64 + wv, k = k0 + (int)threadIdx.x;  // wave wv: slots 64 seg ..
-    if (seg >= kListWaves) continue;  // (uniform over the wave)
-    const bool on = k < kRegSites && ((sg->rowm[k / kReg] >> (k % kReg)) & 1u);
-    const uint64_t b = __ballot(on);
-    if (threadIdx.x % 64 == 0) sg->cnt[seg] = (int)__popcll(b);
-  }
-  __syncthreads();
-  if (threadIdx.x < 64) {  // segment counts -> exclusive offsets (one wave)
-    const int l = (int)threadIdx.x, v = l < kListWaves ? sg->cnt[l] : 0;
-    int incl = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int u = __shfl_up(incl, d, 64);
-      if (l >= d) incl += u;
-    }
-    if (l < kListWaves) sg->cnt[l] = incl - v;
-    if (l == 63) sg->nlist = incl;
-  }
-  __syncthreads();
-  for (int k0 = 0; k0 < kRegSites; k0 += (int)blockDim.x) {
-    const int seg = k0 / 64 + wv, k = k0 + (int)threadIdx.x;
-    if (seg >= kListWaves) continue;
-    const bool on = k < kRegSites && ((sg->rowm[k / kReg] >> (k % kReg)) & 1u);
-    const uint64_t b = __ballot(on);
-    const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
-                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-    if (on) {
-      const int at = sg->cnt[seg] + below;
-      sg->list[at] = (unsigned short)k;
-      if (idx) idx[k] = (unsigned short)at;
-    }
-  }
-  __syncthreads();
-}
 
 // ------------------------------------------------ interpolation, flagged sites
 // The sites whose force-mask bit is set after the lattice pass are those where
@@ -594,53 +489,40 @@ __global__ __launch_bounds__(256) void k_marker_slow(SiteArgs s, const void* Uv,
   if (blockIdx.x == 0 && threadIdx.x == 0) miss[(stamp + 1u) & 1u] = 0;
 }
 
-// Spreading lane groups: one lane per z-plane of stencil nodes, K planes
-// rounded up to a power of two (2 lanes for K = 2, 4 for K = 3, 4).
-template <int K>
-struct RowLanes {
-  static constexpr int L = K == 2 ? 2 : 4;
-};
-
 // ------------------------------------------------------------------ spreading
-// The accumulator is FP64 whatever the field precision: LDS atomic adds run
-// several times faster in FP64 than in FP32 on this device.  It holds only
-// the region sites the tile's stencils cover (listed as in the
-// interpolation, at most kSpreadCap of them; a node listed beyond that adds
-// to the global field directly), so that the workgroup's LDS stays small.
-// Global adds go through atomics: the regions of neighbouring tiles overlap.
+// One workgroup per occupied tile (Eq. IBM-spreading, F(x) = sum_p W(x - X_p)
+// F_p, the adjoint of the interpolation, with the same closed-form weights):
+// the tile's markers are staged in LDS, their stencil contributions are
+// summed in a dense FP64 LDS accumulator over the tile's region, and every
+// nonzero region site is then added to the global field once, with an
+// atomic (the regions of neighbouring tiles overlap).  The accumulator is
+// FP64 whatever the field precision: LDS atomic adds measured about three
+// times faster in FP64 than in FP32 on this device (c3 spreading 31 against
+// 100 us).  The flags for the lattice pass are collected per region row in
+// LDS and set with one cached load and at most one atomic per mask word of
+// the row, instead of a dependent load per site.
+constexpr int kSpreadChunk = 128;  // markers staged per round
+constexpr int kRegRows = kReg * kReg;
+
 template <typename E, int K>
-__global__ __launch_bounds__(kSpreadLanes) void k_tile_spread(TileArgs t, const double* at,
-                                                              const double* F, void* field) {
-  constexpr int L = RowLanes<K>::L;
-  constexpr int G = 16;  // lanes per marker while marking
-  using MK = MarkerLds<kSpreadChunk>;
-  constexpr int kChunk = MK::kChunk;
+__global__ __launch_bounds__(256) void k_tile_spread(TileArgs t, const double* at, const double* F,
+                                                     void* field) {
+  constexpr int KP = ColGroup<K>::KP, G = ColGroup<K>::G;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double* acc = (double*)lds_raw;                                    // 3 * kSpreadCap
-  MK* mk = (MK*)(lds_raw + sizeof(double) * 3 * kSpreadCap);        // one chunk
-  StageLds* sg = (StageLds*)((unsigned char*)mk + sizeof(MK));
-  unsigned short* idx = (unsigned short*)((unsigned char*)sg + sizeof(StageLds));  // kRegSites
+  double* acc = (double*)lds_raw;                 // [3][kRegSites]
+  double* mx = acc + 3 * kRegSites;               // [chunk][6]: position, force
+  uint32_t* rowbits = (uint32_t*)(mx + 6 * kSpreadChunk);  // [kRegRows]: nonzero x slots
+  static_assert(kReg <= 32, "a region row's slots fit one 32-bit mask");
   E* Fd = (E*)field;
-  const int lane = threadIdx.x % L;
   const int nocc = t.nocc[0];
-  auto load_chunk = [&](int c0, int nc) {
-    for (int i = threadIdx.x; i < nc; i += blockDim.x) {
-      const int p = t.sorted[c0 + i];
-      mk->p[i] = p;
-      for (int a = 0; a < 3; ++a) {
-        mk->X[i][a] = at[3 * (long long)p + a];
-        mk->Y[i][a] = F[3 * (long long)p + a];
-      }
-    }
-  };
-  auto global_add = [&](int jx, int jy, int jz, double f0, double f1, double f2) {
+  auto global_add = [&](int jx, int jy, int jz, E f0, E f1, E f2) {
     const int j[3] = {jx, jy, jz};
     int x, y, z;
     if (!node_site(t.g, j, x, y, z)) return;  // beyond a wall
     const long long sidx = site_index(t.g, x, y, z);
-    unsafeAtomicAdd(Fd + 4 * sidx + 0, (E)f0);
-    unsafeAtomicAdd(Fd + 4 * sidx + 1, (E)f1);
-    unsafeAtomicAdd(Fd + 4 * sidx + 2, (E)f2);
+    unsafeAtomicAdd(Fd + 4 * sidx + 0, f0);
+    unsafeAtomicAdd(Fd + 4 * sidx + 1, f1);
+    unsafeAtomicAdd(Fd + 4 * sidx + 2, f2);
     uint64_t bit;
     flag_site(mask_word(t.mask, t.g, x, y, z, bit), bit);
   };
@@ -648,90 +530,84 @@ __global__ __launch_bounds__(kSpreadLanes) void k_tile_spread(TileArgs t, const 
     const int tl = t.occ[ot];
     const Region r = region_of(t, tl);
     const int b0 = t.start[tl], b1 = t.start[tl + 1];
-    load_chunk(b0, min(kChunk, b1 - b0));
-    for (int k = threadIdx.x; k < kRows; k += blockDim.x) sg->rowm[k] = 0u;
-    __syncthreads();
-    for (int i = (int)threadIdx.x / G; i < b1 - b0; i += (int)blockDim.x / G) {
-      double X[3];
-      if (i < kChunk) {
-        for (int a = 0; a < 3; ++a) X[a] = mk->X[i][a];
-      } else {
-        const long long p = t.sorted[b0 + i];
-        for (int a = 0; a < 3; ++a) X[a] = at[3 * p + a];
-      }
-      mark_stencil<K>(r, X, 0.0, sg->rowm, (int)threadIdx.x % G, G);
-    }
-    __syncthreads();
-    list_marked(sg, idx);
-    const int nacc = min(sg->nlist, kSpreadCap);
-    for (int k = threadIdx.x; k < 3 * nacc; k += blockDim.x) acc[k] = 0.0;
-    for (int c0 = b0; c0 < b1; c0 += kChunk) {
-      const int nc = min(kChunk, b1 - c0);
-      if (c0 != b0) {
-        __syncthreads();  // previous chunk done with mk
-        load_chunk(c0, nc);
-      }
-      __syncthreads();  // accumulator cleared (first chunk) or the new chunk ready
-      for (int i = (int)threadIdx.x / L; i < nc; i += (int)blockDim.x / L) {
-        const int kz = lane;
-        if (kz >= K) continue;
-        const double X[3] = {mk->X[i][0], mk->X[i][1], mk->X[i][2]};
-        const double Fp[3] = {mk->Y[i][0], mk->Y[i][1], mk->Y[i][2]};
-        int j0[3];
-        bool inside = true;
-#pragma unroll
+    for (int k = threadIdx.x; k < 3 * kRegSites; k += blockDim.x) acc[k] = 0.0;
+    for (int k = threadIdx.x; k < kRegRows; k += blockDim.x) rowbits[k] = 0u;
+    for (int c0 = b0; c0 < b1; c0 += kSpreadChunk) {
+      const int nc = min(kSpreadChunk, b1 - c0);
+      __syncthreads();  // accumulator cleared, or the previous chunk done with mx
+      for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+        const long long p = t.sorted[c0 + i];
         for (int a = 0; a < 3; ++a) {
-          j0[a] = first_node<K>(X[a]);
-          inside = inside && j0[a] - r.o[a] >= 0 && j0[a] - r.o[a] + K <= kReg;
+          mx[6 * i + a] = at[3 * p + a];
+          mx[6 * i + 3 + a] = F[3 * p + a];
         }
-        E wx[K], wy[K];  // weights in the field precision
+      }
+      __syncthreads();
+      // one lane per (x, y) column of a marker's stencil, over its z nodes
+      for (int i = (int)threadIdx.x / G; i < nc; i += (int)blockDim.x / G) {
+        const int rr = (int)threadIdx.x % G, kx = rr % KP, ky = rr / KP;
+        if (kx >= K || ky >= K) continue;
+        const double* m = mx + 6 * i;
+        int j0[3];
+        E tt[3], qq[3];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          wx[k] = phi_eval_t<E>(K, (E)((double)(j0[0] + k) - X[0]));
-          wy[k] = phi_eval_t<E>(K, (E)((double)(j0[1] + k) - X[1]));
-        }
-        const E wz = phi_eval_t<E>(K, (E)((double)(j0[2] + kz) - X[2]));
+        for (int a = 0; a < 3; ++a) stencil_t<K, E>(m[a], j0[a], tt[a], qq[a]);
+        const int jx = j0[0] + kx, jy = j0[1] + ky;
+        if (t.g.wall && (jy < 0 || jy >= t.g.ny)) continue;  // beyond a wall: no node
+        const E wxy = node_weight<K, E>(kx, tt[0], qq[0]) * node_weight<K, E>(ky, tt[1], qq[1]);
+        const int ix = jx - r.o[0], iy = jy - r.o[1];
+        const bool in_xy = ix >= 0 && ix < kReg && iy >= 0 && iy < kReg;
 #pragma unroll
-        for (int ky = 0; ky < K; ++ky) {
-          const int jy = j0[1] + ky;
-          if (t.g.wall && (jy < 0 || jy >= t.g.ny)) continue;  // beyond a wall
-          const int rowslot = inside ? ((j0[2] + kz - r.o[2]) * kReg + (jy - r.o[1])) * kReg +
-                                           (j0[0] - r.o[0])
-                                     : 0;
-#pragma unroll
-          for (int k = 0; k < K; ++k) {
-            const double W = (double)(wx[k] * wy[ky] * wz);
-            if (W == 0.0) continue;
-            const double f0 = W * Fp[0], f1 = W * Fp[1], f2 = W * Fp[2];
-            const int q = inside ? (int)idx[rowslot + k] : kSpreadCap;
-            if (q < kSpreadCap) {
-              double* a = acc + 3 * q;
-              atomicAdd(a + 0, f0);
-              atomicAdd(a + 1, f1);
-              atomicAdd(a + 2, f2);
-            } else {
-              global_add(j0[0] + k, jy, j0[2] + kz, f0, f1, f2);
-            }
+        for (int kz = 0; kz < K; ++kz) {
+          const double W = (double)(wxy * node_weight<K, E>(kz, tt[2], qq[2]));
+          const double f0 = W * m[3], f1 = W * m[4], f2 = W * m[5];
+          const int jz = j0[2] + kz, iz = jz - r.o[2];
+          if (in_xy && iz >= 0 && iz < kReg) {
+            double* a = acc + (iz * kReg + iy) * kReg + ix;
+            atomicAdd(a, f0);
+            atomicAdd(a + kRegSites, f1);
+            atomicAdd(a + 2 * kRegSites, f2);
+          } else {
+            global_add(jx, jy, jz, (E)f0, (E)f1, (E)f2);
           }
         }
       }
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < nacc; q += blockDim.x) {
-      const E a0 = (E)acc[3 * q], a1 = (E)acc[3 * q + 1], a2 = (E)acc[3 * q + 2];
+    for (int k = threadIdx.x; k < kRegSites; k += blockDim.x) {
+      const E a0 = (E)acc[k], a1 = (E)acc[kRegSites + k], a2 = (E)acc[2 * kRegSites + k];
       if (a0 == E(0) && a1 == E(0) && a2 == E(0)) continue;
-      const int k = sg->list[q];
-      const int ix = k % kReg, iy = (k / kReg) % kReg, iz = k / (kReg * kReg);
       int x, y, z;
-      if (!slot_site(t.g, r, ix, iy, iz, x, y, z)) continue;
+      if (!slot_site(t.g, r, k % kReg, (k / kReg) % kReg, k / (kReg * kReg), x, y, z)) continue;
       const long long sidx = site_index(t.g, x, y, z);
       unsafeAtomicAdd(Fd + 4 * sidx + 0, a0);
       unsafeAtomicAdd(Fd + 4 * sidx + 1, a1);
       unsafeAtomicAdd(Fd + 4 * sidx + 2, a2);
-      uint64_t bit;
-      flag_site(mask_word(t.mask, t.g, x, y, z, bit), bit);
+      atomicOr(rowbits + k / kReg, 1u << (k % kReg));
     }
-    __syncthreads();  // accumulator, lists and chunk are reused by the next tile
+    __syncthreads();
+    // flags: per region row, runs of slots in the same mask word
+    for (int row = threadIdx.x; row < kRegRows; row += blockDim.x) {
+      uint32_t bits = rowbits[row];
+      uint64_t* cur = nullptr;
+      uint64_t acc_bits = 0;
+      while (bits) {
+        const int ix = __ffs(bits) - 1;
+        bits &= bits - 1u;
+        int x, y, z;
+        slot_site(t.g, r, ix, row % kReg, row / kReg, x, y, z);  // (a wall row has no bits)
+        uint64_t bit;
+        uint64_t* mw = mask_word(t.mask, t.g, x, y, z, bit);
+        if (mw != cur) {
+          if (cur && (*cur & acc_bits) != acc_bits) atomicOr((unsigned long long*)cur, acc_bits);
+          cur = mw;
+          acc_bits = 0;
+        }
+        acc_bits |= bit;
+      }
+      if (cur && (*cur & acc_bits) != acc_bits) atomicOr((unsigned long long*)cur, acc_bits);
+    }
+    __syncthreads();  // the accumulator and the row masks are cleared for the next tile
   }
 }
 
@@ -800,13 +676,14 @@ hipError_t launch_flag_interp(int storage, int K, const SiteArgs& s, const uint6
 hipError_t launch_tile_spread(int storage, int K, const TileArgs& t, const double* at,
                               const double* F, void* field, long long n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const size_t lds = sizeof(double) * 3 * kSpreadCap + sizeof(MarkerLds<kSpreadChunk>) +
-                     sizeof(StageLds) + sizeof(unsigned short) * kRegSites;
-  const unsigned gr = tile_grid(t, kSpreadWgPerCu);
+  // 38 KB of LDS: four workgroups per CU, so that the occupied tiles of a
+  // dense marker set are worked on at once.
+  const size_t lds = sizeof(double) * (3 * kRegSites + 6 * kSpreadChunk) + 4 * kRegRows;
+  const unsigned gr = tile_grid(t, 4);
   if (storage == LB_F64) {
-    LBC_TILE_K_SWITCH(K, (k_tile_spread<double, KK><<<gr, kSpreadLanes, lds, st>>>(t, at, F, field)));
+    LBC_TILE_K_SWITCH(K, (k_tile_spread<double, KK><<<gr, 256, lds, st>>>(t, at, F, field)));
   } else {
-    LBC_TILE_K_SWITCH(K, (k_tile_spread<float, KK><<<gr, kSpreadLanes, lds, st>>>(t, at, F, field)));
+    LBC_TILE_K_SWITCH(K, (k_tile_spread<float, KK><<<gr, 256, lds, st>>>(t, at, F, field)));
   }
   return hipGetLastError();
 }

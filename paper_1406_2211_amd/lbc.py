@@ -43,7 +43,8 @@ class lb_params(C.Structure):
                 ("storage", C.c_int32), ("f16_scale_log2", C.c_int32),
                 ("mts_substeps", C.c_int32), ("deterministic", C.c_int32),
                 ("comoving", C.c_int32), ("csc", C.c_int32), ("mts_inside", C.c_int32),
-                ("kT", C.c_double), ("seed", C.c_uint64), ("mrt_rates", C.c_double * 5)]
+                ("kT", C.c_double), ("seed", C.c_uint64), ("mrt_rates", C.c_double * 5),
+                ("ib_rebin", C.c_int32)]
 
 
 class lb_limits(C.Structure):
@@ -132,7 +133,7 @@ def lattice_velocities():
 def make_params(tau, rho0=1.0, body_force=(0.0, 0.0, 0.0), collision=LB_BGK, trt_magic=3.0 / 16.0,
                 coupling=LB_COUPLE_NONE, gamma=0.0, kernel=LB_PHI2, storage=LB_F64,
                 f16_scale_log2=0, mts_substeps=0, comoving=0, csc=0, mts_inside=0, kT=0.0,
-                seed=0, mrt_rates=(1.0, 1.0, 1.0, 1.0, 1.0), deterministic=0):
+                seed=0, mrt_rates=(1.0, 1.0, 1.0, 1.0, 1.0), deterministic=0, ib_rebin=0):
     p = lb_params()
     p.tau, p.rho0 = float(tau), float(rho0)
     for a in range(3):
@@ -145,6 +146,7 @@ def make_params(tau, rho0=1.0, body_force=(0.0, 0.0, 0.0), collision=LB_BGK, trt
     p.kT, p.seed = float(kT), int(seed)
     for k in range(5):
         p.mrt_rates[k] = float(mrt_rates[k])
+    p.ib_rebin = int(ib_rebin)
     return p
 
 

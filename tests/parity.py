@@ -117,7 +117,8 @@ def make_gpu(c: Case):
                     mts_inside=c.extra.get("mts_inside", 0), rho0=c.extra.get("rho0", 1.0),
                     kT=c.extra.get("kT", 0.0), seed=c.extra.get("seed", 0),
                     mrt_rates=c.extra.get("mrt_rates", (1.0,) * 5),
-                    deterministic=c.extra.get("deterministic", 0))
+                    deterministic=c.extra.get("deterministic", 0),
+                    ib_rebin=c.extra.get("ib_rebin", 0))
     rho, u = initial_fields(c)
     lat.lb_init_fluid(None if rho is None else torch.from_numpy(rho),
                       None if u is None else torch.from_numpy(np.ascontiguousarray(u)))

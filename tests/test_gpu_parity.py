@@ -325,6 +325,36 @@ def test_ib_markers_crossing_tiles_and_seam(kernel):
     check(c, TOL64)
 
 
+@pytest.mark.parametrize("kernel,rebin,steps", [(4, 0, 30), (3, 0, 30), (4, 100000, 110)])
+def test_ib_markers_spread_over_many_tiles(kernel, rebin, steps):
+    """IB markers (bonded in pairs) scattered over a 40x32x48 channel (5 x 4 x 6
+    spreading tiles, y walls) and at its periodic seams, carried by a uniform
+    flow.  With the default binning every tile gathers from its neighbouring
+    bins; binned only once (rebin 100000), the markers travel more than six
+    sites from their bins, and the spreads after that take the fallback."""
+    rng = np.random.default_rng(33)
+    n = 60
+    a = rng.uniform(0.0, 1.0, (n, 3)) * np.array([40.0, 30.0, 48.0]) + np.array([0.0, 1.0, 0.0])
+    a[:6, 0] = [0.0002, 39.9998, 7.9999, 8.0, 31.9999, 24.0001]
+    a[6:12, 2] = [0.0003, 47.9997, 15.9999, 16.0, 39.9999, 40.0]
+    b = a + rng.uniform(-0.5, 0.5, (n, 3))
+    b[:, 1] = np.clip(b[:, 1], 1.0, 30.0)
+    pos = np.vstack([a, b]) % np.array([40.0, 32.0, 48.0])
+    bonds = np.array([[i, i + n] for i in range(n)])
+    c = Case(name=f"ib_many_tiles_k{kernel}_r{rebin}", nx=40, ny=32, nz=48, tau=0.7, steps=steps,
+             wall_y=1, coupling=3, kernel=kernel, u_noise=0.0, pos=pos, bonds=bonds, bond_k=0.05,
+             bond_r0=0.5, fext=(1e-6, 0.0, -1e-6))
+    c.extra["u0"] = np.array([0.07, 0.0, -0.06])
+    c.extra["ib_rebin"] = rebin
+    g = run_gpu(c)
+    o = run_oracle(c)
+    compare(c, g, o, TOL64)
+    if rebin:
+        d = o["pos"] - pos
+        d -= np.array([40.0, 32.0, 48.0]) * np.round(d / np.array([40.0, 32.0, 48.0]))
+        assert np.abs(d[:, 0]).max() > 7.0, "the markers did not leave their bins' neighbourhood"
+
+
 @pytest.mark.parametrize("kernel,storage", [(4, 0), (3, 0), (4, 1)])
 def test_ib_dense_tile_overflows_spread_accumulator(kernel, storage):
     """400 IB markers (bonded in pairs) packed into one 8^3 tile: their
