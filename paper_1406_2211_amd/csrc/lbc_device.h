@@ -821,6 +821,45 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+// Sum over an aligned group of G = 4 or 16 lanes with DPP moves (every lane
+// gets the sum): pairs and quads by quad permutations, then the two quads of
+// each 8-lane half by a half-row mirror and the two halves by a row mirror.
+template <int ctrl>
+__device__ __forceinline__ float dpp_add(float v) {
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xf, 0xf, false));
+}
+template <int ctrl>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, ctrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xf, 0xf, false);
+  return v + __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int G, typename T>
+__device__ __forceinline__ T group_sum_dpp(T v) {
+  static_assert(G == 4 || G == 16, "DPP group sums cover 4 or 16 lanes");
+  v = dpp_add<0xB1>(v);  // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E>(v);  // quad_perm [2,3,0,1]
+  if (G == 16) {
+    v = dpp_add<0x141>(v);  // row_half_mirror
+    v = dpp_add<0x140>(v);  // row_mirror
+  }
+  return v;
+}
+
+// Sum over the 64 lanes of a wavefront, every lane getting it: the DPP sum of
+// each 16-lane row, then the four row sums read from lanes 0, 16, 32, 48.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v = group_sum_dpp<16, double>(v);
+  auto lane_value = [&](int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  };
+  return (lane_value(0) + lane_value(16)) + (lane_value(32) + lane_value(48));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

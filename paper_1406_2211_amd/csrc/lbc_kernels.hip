@@ -1091,47 +1091,90 @@ __device__ __forceinline__ bool quat_top(const double A[4][4], double q[4]) {
   return res <= 1e-12 * sqrt(fro2);
 }
 
+// Sum of N values over the workgroup, every lane getting the sums: DPP wave
+// sums, one LDS slot per wavefront, then each lane adds the slots.
+template <int N>
+__device__ __forceinline__ void block_sum_n(double v[N], double* lds /*[N * 16]*/) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = wave_sum_dpp(v[k]);
+  if (lane == 0)
+    for (int k = 0; k < N; ++k) lds[N * wv + k] = v[k];
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    double t = 0;
+    for (int w = 0; w < nw; ++w) t += lds[N * w + k];
+    v[k] = t;
+  }
+  __syncthreads();  // lds is reused by the next sum
+}
+
+// A shell of up to kShellPerLane * 256 markers keeps each lane's unwrapped
+// positions and template vectors in registers across the three passes
+// (centre, cross-covariance, forces), so every marker is loaded once.
+constexpr int kShellPerLane = 4;
+
 __global__ __launch_bounds__(256) void k_shell_forces(ShellArgs sa) {
-  __shared__ double red[16 * 4];
-  __shared__ double sh_c[3], sh_R[9];
+  __shared__ double red[16 * 9];
+  __shared__ double sh_R[9];
   const int M = sa.M;
   const long long base = (long long)blockIdx.x * M;
   const double* X = sa.pos + 3 * base;
   const double X0[3] = {X[0], X[1], X[2]};
+  const double L[3] = {(double)sa.g.nx, (double)sa.g.ny, (double)sa.g.nz};
+  const double rL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
+  // minimum image around the first marker (a shell spans less than half a box)
   auto unwrap = [&](int j, double y[3]) {
-    for (int k = 0; k < 3; ++k) y[k] = X[3 * j + k] - X0[k];
-    y[0] -= sa.g.nx * floor(y[0] / sa.g.nx + 0.5);
-    if (!sa.g.wall) y[1] -= sa.g.ny * floor(y[1] / sa.g.ny + 0.5);
-    y[2] -= sa.g.nz * floor(y[2] / sa.g.nz + 0.5);
-    for (int k = 0; k < 3; ++k) y[k] += X0[k];
+    for (int k = 0; k < 3; ++k) {
+      y[k] = X[3 * j + k] - X0[k];
+      if (k != 1 || !sa.g.wall) y[k] -= L[k] * floor(y[k] * rL[k] + 0.5);
+      y[k] += X0[k];
+    }
   };
-  double acc[4] = {0, 0, 0, 0};
-  for (int j = threadIdx.x; j < M; j += blockDim.x) {
-    double y[3];
-    unwrap(j, y);
-    for (int k = 0; k < 3; ++k) acc[k] += y[k];
+  const bool held = M <= kShellPerLane * (int)blockDim.x;
+  double yh[kShellPerLane][3], th[kShellPerLane][3];
+  if (held) {
+#pragma unroll
+    for (int q = 0; q < kShellPerLane; ++q) {
+      const int j = (int)threadIdx.x + q * (int)blockDim.x;
+      if (j < M) {
+        unwrap(j, yh[q]);
+        for (int a = 0; a < 3; ++a) th[q][a] = sa.tmpl[3 * j + a];
+      }
+    }
   }
-  block_sum4(acc, red);
-  if (threadIdx.x == 0)
-    for (int k = 0; k < 3; ++k) sh_c[k] = acc[k] / M;
-  __syncthreads();
-  const double c[3] = {sh_c[0], sh_c[1], sh_c[2]};
+  // each lane's markers: from registers, or loaded again for a larger shell
+  auto for_markers = [&](auto&& fn) {
+    if (held) {
+#pragma unroll
+      for (int q = 0; q < kShellPerLane; ++q) {
+        const int j = (int)threadIdx.x + q * (int)blockDim.x;
+        if (j < M) fn(j, yh[q], th[q]);
+      }
+    } else {
+      for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        double y[3], t[3];
+        unwrap(j, y);
+        for (int a = 0; a < 3; ++a) t[a] = sa.tmpl[3 * j + a];
+        fn(j, y, t);
+      }
+    }
+  };
+  double c[3] = {0, 0, 0};
+  for_markers([&](int, const double* y, const double*) {
+    for (int k = 0; k < 3; ++k) c[k] += y[k];
+  });
+  block_sum_n<3>(c, red);
+  for (int k = 0; k < 3; ++k) c[k] /= M;
   double S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int j = threadIdx.x; j < M; j += blockDim.x) {
-    double y[3];
-    unwrap(j, y);
-    const double* t = sa.tmpl + 3 * j;
+  for_markers([&](int, const double* y, const double* t) {
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) S[3 * a + b] += t[a] * (y[b] - c[b]);
-  }
-  double s0[4] = {S[0], S[1], S[2], S[3]}, s1[4] = {S[4], S[5], S[6], S[7]},
-         s2[4] = {S[8], 0, 0, 0};
-  block_sum4(s0, red);
-  block_sum4(s1, red);
-  block_sum4(s2, red);
+  });
+  block_sum_n<9>(S, red);
   if (threadIdx.x == 0) {
-    const double Sxx = s0[0], Sxy = s0[1], Sxz = s0[2], Syx = s0[3], Syy = s1[0], Syz = s1[1],
-                 Szx = s1[2], Szy = s1[3], Szz = s2[0];
+    const double Sxx = S[0], Sxy = S[1], Sxz = S[2], Syx = S[3], Syy = S[4], Syz = S[5],
+                 Szx = S[6], Szy = S[7], Szz = S[8];
     double A[4][4] = {{Sxx + Syy + Szz, Syz - Szy, Szx - Sxz, Sxy - Syx},
                       {Syz - Szy, Sxx - Syy - Szz, Sxy + Syx, Szx + Sxz},
                       {Szx - Sxz, Sxy + Syx, -Sxx + Syy - Szz, Syz + Szy},
@@ -1152,15 +1195,12 @@ __global__ __launch_bounds__(256) void k_shell_forces(ShellArgs sa) {
       for (int k = 0; k < 9; ++k) sa.rot[9 * blockIdx.x + k] = sh_R[k];
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < M; j += blockDim.x) {
-    double y[3];
-    unwrap(j, y);
-    const double* t = sa.tmpl + 3 * j;
+  for_markers([&](int j, const double* y, const double* t) {
     for (int a = 0; a < 3; ++a) {
       const double tgt = sh_R[3 * a] * t[0] + sh_R[3 * a + 1] * t[1] + sh_R[3 * a + 2] * t[2];
       sa.fint[3 * (base + j) + a] = -sa.k * (y[a] - c[a] - tgt);
     }
-  }
+  });
 }
 
 // ======================================================================

@@ -307,32 +307,6 @@ __device__ __forceinline__ W node_weight(int k, W t, W q) {
   return k == 0 ? W(1) - t : t;
 }
 
-// Sum over an aligned group of G = 4 or 16 lanes with DPP moves (every lane
-// gets the sum): pairs and quads by quad permutations, then the two quads of
-// each 8-lane half by a half-row mirror and the two halves by a row mirror.
-template <int ctrl>
-__device__ __forceinline__ float dpp_add(float v) {
-  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xf, 0xf, false));
-}
-template <int ctrl>
-__device__ __forceinline__ double dpp_add(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, ctrl, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xf, 0xf, false);
-  return v + __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-template <int G, typename T>
-__device__ __forceinline__ T group_sum_dpp(T v) {
-  static_assert(G == 4 || G == 16, "DPP group sums cover 4 or 16 lanes");
-  v = dpp_add<0xB1>(v);  // quad_perm [1,0,3,2]
-  v = dpp_add<0x4E>(v);  // quad_perm [2,3,0,1]
-  if (G == 16) {
-    v = dpp_add<0x141>(v);  // row_half_mirror
-    v = dpp_add<0x140>(v);  // row_mirror
-  }
-  return v;
-}
-
 // Lanes per marker: one per (x, y) column of stencil nodes, K rounded up to a
 // power of two in x and y, so that in each z plane the lanes of a marker read
 // whole x rows of the velocity field.
