@@ -473,13 +473,18 @@ static lb_status lattice_pass(lb_ctx* c, int bond_nsub = 0, double bond_dt = 0.0
   // of the 19 population streams open at once, which raised the streaming
   // rate of the deterministic pass: 20 waves per CU for FP32 (256^3: 452 ->
   // 435 us; 250^3 on the linear-site pass: 427 -> 408 us), 24 for 16-bit
-  // storage (256^3 FP16: 229 -> 225 us).  The cap is an unused dynamic LDS
-  // reservation per workgroup.  Not for FP64 (no gain measured) nor with
-  // thermal noise (its arithmetic needs the occupancy).
+  // storage (256^3 FP16: 229 -> 225 us).  Narrow rows stream best with fewer
+  // still (FP32, 2^22 sites): 12 waves for 128-wide rows (122.4 -> 116.7 us
+  // per step) and 8 for 64-wide rows (122.2 -> 114.6 us); 256-wide rows lose
+  // 8 % below 20.  The cap is an unused dynamic LDS reservation per
+  // workgroup.  Not for FP64 (no gain measured) nor with thermal noise (its
+  // arithmetic needs the occupancy).
   a.occ_lds = 0;
   if (c->lds_cu > 0 && c->p.kT == 0.0 && c->p.storage != LB_F64) {
-    const int waves_cu = c->p.storage == LB_F32 ? 20 : 24;
     const int bx = c->geo.wpr == 0 ? 256 : std::min(256, (c->geo.nx + 63) / 64 * 64);
+    int waves_cu = c->p.storage == LB_F32 ? 20 : 24;
+    if (c->p.storage == LB_F32 && bx == 64) waves_cu = 8;
+    if (c->p.storage == LB_F32 && bx == 128) waves_cu = 12;
     const int groups = std::max(1, waves_cu / (bx / 64));
     a.occ_lds = (c->lds_cu / groups) & ~1023;
   }
