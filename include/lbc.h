@@ -359,8 +359,10 @@ lb_status lb_ensemble_query(lb_ensemble* e, int32_t slot, int64_t* steps_done, i
 lb_status lb_ensemble_retire(lb_ensemble* e, int32_t slot);
 
 /* Times steps_per_candidate real steps of the live mix under each candidate
- * persistent-grid shape of the batched launches, keeps the fastest and
- * returns it.  The tuning steps count against the boxes' budgets. */
+ * persistent-grid shape of the batched particle launches, keeps the fastest
+ * and returns it (lat_grid: the lattice launch, one block per 256-site work
+ * item, reported as it is).  The tuning steps count against the boxes'
+ * budgets. */
 lb_status lb_ensemble_autotune(lb_ensemble* e, int32_t steps_per_candidate, int32_t* lat_grid,
                                int32_t* part_grid);
 
