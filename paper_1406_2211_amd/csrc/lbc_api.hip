@@ -1172,6 +1172,7 @@ struct lb_ensemble {
   bool dirty = true;
   int cus = 256;
   int lat_grid = 0, part_grid = 512;  // lattice: one block per item (ens_refresh)
+  int part_items = 1024;  // particle work items, rounded up (an autotuner candidate)
   hipGraphExec_t exec[2] = {nullptr, nullptr};  // kGraphSteps steps, one step
   bool graphs_ok = false;
   std::string err;
@@ -1290,6 +1291,7 @@ static lb_status ens_refresh(lb_ensemble* e) {
     e->lat_grid = cap;
     ens_drop_graphs(e);
   }
+  e->part_items = std::max(1024, ((int)pi.size() + 1023) / 1024 * 1024);
   EHIPCHK(e, hipMemcpy(e->d_slots, hs.data(), hs.size() * sizeof(EnsSlot), hipMemcpyHostToDevice));
   if (!li.empty())
     EHIPCHK(e, hipMemcpy(e->d_litems, li.data(), li.size() * sizeof(int2), hipMemcpyHostToDevice));
@@ -1529,7 +1531,7 @@ lb_status lb_ensemble_autotune(lb_ensemble* e, int32_t steps_per_candidate, int3
   if (e->dirty && (s = ens_refresh(e)) != LB_OK) return s;
   const int cus = e->cus;
   const int lat_c[] = {e->lat_grid};
-  const int part_c[] = {cus, cus * 2, cus * 4};
+  const int part_c[] = {cus, cus * 2, cus * 4, e->part_items};
   hipEvent_t t0, t1;
   EHIPCHK(e, hipEventCreate(&t0));
   EHIPCHK(e, hipEventCreate(&t1));
