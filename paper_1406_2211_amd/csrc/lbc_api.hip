@@ -49,6 +49,11 @@ struct Layout {
   uint64_t* det;  // fixed-point spreading accumulator [N][3][2] (deterministic mode)
   void* U;        // velocity at the flagged sites [N][4] (binned immersed boundary)
   int* miss;      // markers left to the gathering interpolation: 2 counters, then the list
+  // coupling-inside sub-steps: second state buffer pair and the lattice-force
+  // fields of the sub-steps before a fold
+  double *pos2, *vel2;
+  int4* pn;  // packed bond partners (SubArgs::pn)
+  void* G[kMtsFields];
   size_t bytes;
 };
 
@@ -105,6 +110,13 @@ Layout carve(const lb_grid& g, const lb_params& p, const lb_limits& lim, void* b
   const bool binned = p.coupling == LB_COUPLE_IB && p.kernel >= 3;
   L.U = c.take<void>(binned ? (size_t)N * 4 * (p.storage == LB_F64 ? 8 : 4) : 64);
   L.miss = c.take<int>(binned ? (np + 2) * 4 : 64);
+  const bool sub = p.mts_inside && p.mts_substeps > 0 && !p.deterministic;
+  const int nf = sub ? std::min(p.mts_substeps - 1, kMtsFields) : 0;
+  L.pos2 = c.take<double>(sub ? np * 24 : 64);
+  L.vel2 = c.take<double>(sub ? np * 24 : 64);
+  L.pn = c.take<int4>(sub ? np * 16 : 64);
+  for (int f = 0; f < kMtsFields; ++f)
+    L.G[f] = f < nf ? c.take<void>((size_t)N * force_vec_bytes(p.storage)) : nullptr;
   L.bytes = c.off;
   return L;
 }
@@ -364,6 +376,7 @@ static lb_status build_groups(lb_ctx* c) {
   if (maxc > 1024) return fail(c, LB_EINVAL, "a bonded cluster has more than 1024 particles");
   const int gcap = std::max(128, ((maxc + 63) / 64) * 64);
   std::vector<int32_t> perm, loc(n), goff{0};
+  std::vector<int4> pn;
   int fillg = 0;
   for (auto& cl : clusters) {
     if (fillg + cl.second > gcap) {
@@ -386,6 +399,15 @@ static lb_status build_groups(lb_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(c->L.goff, goff.data(), goff.size() * 4, hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->L.bstart, start.data(), (n + 1) * 4, hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->L.bnbr, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice, c->st));
+    if (c->p.mts_inside && !c->p.deterministic) {  // the first partners in list order
+      pn.assign(n, int4{0, 0, 0, 0});
+      for (int64_t p = 0; p < n; ++p) {
+        int32_t q[kSubPartners] = {0, 0, 0};
+        for (int k = 0; k < kSubPartners && k < deg[p]; ++k) q[k] = nbr[start[p] + k];
+        pn[p] = int4{q[0], q[1], q[2], deg[p]};
+      }
+      HIPCHK(c, hipMemcpyAsync(c->L.pn, pn.data(), n * 16, hipMemcpyHostToDevice, c->st));
+    }
     HIPCHK(c, hipStreamSynchronize(c->st));
   }
   c->groups_dirty = false;
@@ -588,9 +610,68 @@ static lb_status spread_fint_det(lb_ctx* c) {
 // velocity a sub-step sees is that of the populations with every force
 // applied so far: the pending fields of the earlier sub-steps and k dt of the
 // body force; after the pass the first sub-step sees the post-stream velocity
-// (as the second half of Alg. 3).  A sub-step that reads the field it writes
-// stores its forces and spreads them in a second launch.
+// (as the second half of Alg. 3).  Each sub-step is one launch (SubArgs):
+// the first of a side spreads into the side's field, the later ones into
+// fields of their own that the next interpolations add, folded into the
+// side's field when kMtsFields are in use and at the end of the side.  The
+// deterministic mode takes step_mts_inside_det.
+static lb_status step_mts_inside_det(lb_ctx* c);
+
 static lb_status step_mts_inside(lb_ctx* c) {
+  if (c->p.deterministic) return step_mts_inside_det(c);
+  const int n = c->p.mts_substeps;
+  const double dt = 1.0 / (2.0 * n);
+  double* const P[2] = {c->L.pos, c->L.pos2};
+  double* const V[2] = {c->L.vel, c->L.vel2};
+  lb_status s;
+  for (int side = 0; side < 2; ++side) {
+    if (side == 1 && (s = lattice_pass(c)) != LB_OK) return s;
+    SubArgs u{};
+    u.bonds = c->nbond > 0 ? 1 : 0;
+    u.pn = c->L.pn;
+    u.b = bond_args(c, c->L.pos);
+    int used = 0;  // sub-step fields written since the last fold
+    PartArgs a;
+    for (int k = 0; k < n; ++k) {
+      a = part_args(c);
+      a.hh = dt;
+      a.hd = 0.5 * dt;
+      a.sw = 2.0 * dt;
+      a.jc = side * n + k;
+      a.use_fint = u.bonds;
+      a.target = side;
+      const double ext = (side == 0 ? c->pend : 0) + 2.0 * k * dt;  // body force applied, x h/2
+      a.s.pfx = ext * c->p.body_force[0];
+      a.s.pfy = ext * c->p.body_force[1];
+      a.s.pfz = ext * c->p.body_force[2];
+      a.phys = (side == 0 || k > 0) ? 1 : 0;  // side 1, k > 0: FB holds the earlier sub-steps
+      a.fa_rd = (side == 0 && k > 0) ? 1 : 0;
+      a.cache_fill = (side == 1 && k == 0) ? 1 : 0;
+      a.cache_use = (side == 1 && k > 0) || (side == 0 && c->mvalid) ? 1 : 0;
+      if (k > 0 && used == kMtsFields) {
+        HIPCHK(c, launch_mts_fold(c->p.storage, a, u, used, c->st));
+        used = 0;
+      }
+      const int i = side * n + k;  // 2n sub-steps: the state ends where it started
+      u.pin = P[i & 1];
+      u.vin = V[i & 1];
+      u.pout = P[(i + 1) & 1];
+      u.vout = V[(i + 1) & 1];
+      for (int f = 0; f < kMtsFields; ++f) u.gin[f] = c->L.G[f];
+      u.ngin = used;
+      u.gout = k > 0 ? c->L.G[used] : nullptr;
+      HIPCHK(c, launch_mts_substep(c->p.storage, a, u, c->st));
+      if (k > 0) ++used;
+    }
+    if (used > 0) HIPCHK(c, launch_mts_fold(c->p.storage, a, u, used, c->st));
+  }
+  c->mvalid = true;
+  return LB_OK;
+}
+
+// The deterministic mode: each sub-step as a launch of the bond forces, a
+// coupling launch and the fixed-point spread of the lattice forces.
+static lb_status step_mts_inside_det(lb_ctx* c) {
   const int n = c->p.mts_substeps;
   const double dt = 1.0 / (2.0 * n);
   const bool fint = c->nshell > 0 || c->nbond > 0;
@@ -617,15 +698,7 @@ static lb_status step_mts_inside(lb_ctx* c) {
       a.fa_rd = (side == 0 && k > 0) ? 1 : 0;
       a.cache_fill = (side == 1 && k == 0) ? 1 : 0;
       a.cache_use = (side == 1 && k > 0) || (side == 0 && c->mvalid) ? 1 : 0;
-      if (k == 0 || c->p.deterministic) {  // (the deterministic spread is a launch of its own)
-        if ((s = couple(c, a)) != LB_OK) return s;
-      } else {  // spread and closing drift in a second launch, from the midpoint positions
-        a.defer = c->L.aux;
-        PartArgs b = a;
-        b.drift_after = 0;
-        HIPCHK(c, launch_couple_half(c->p.storage, b, c->st));
-        HIPCHK(c, launch_spread_deferred(c->p.storage, a, c->st));
-      }
+      if ((s = couple(c, a)) != LB_OK) return s;
     }
   }
   c->mvalid = true;
@@ -843,6 +916,8 @@ lb_status lb_init_fluid(lb_ctx* c, const double* d_rho, const double* d_u) {
   HIPCHK(c, launch_zero(c->L.FA, vb, c->st));
   HIPCHK(c, launch_zero(c->L.FB, vb, c->st));
   HIPCHK(c, launch_zero(c->L.mask, mask_words(c->g) * 8, c->st));
+  for (int f = 0; f < kMtsFields; ++f)
+    if (c->L.G[f]) HIPCHK(c, launch_zero(c->L.G[f], vb, c->st));
   if (c->p.deterministic) HIPCHK(c, launch_zero(c->L.det, (size_t)c->geo.N * 48, c->st));
   if (c->tiled) {
     HIPCHK(c, launch_zero(c->L.U, (size_t)c->geo.N * 4 * (c->p.storage == LB_F64 ? 8 : 4), c->st));

@@ -866,4 +866,80 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Position of the n-th set bit (n < popcount) of v.
+__device__ __forceinline__ int nth_set_bit(uint64_t v, int n) {
+  int pos = 0;
+#pragma unroll
+  for (int half = 32; half > 0; half >>= 1) {
+    const int c = __popcll(v & ((1ull << half) - 1ull));
+    if (n >= c) {
+      n -= c;
+      v >>= half;
+      pos += half;
+    }
+  }
+  return pos;
+}
+
+// Each wavefront reads WORDS (at most 64) words of the force mask and hands
+// their flagged sites out one per lane (a scan of the words' bit counts and a
+// binary search in it); f(x, y, z) runs once for every flagged site, up to 64
+// sites at a time per wavefront.  Few words per wavefront suit a densely
+// flagged mask, 64 a sparse one.
+constexpr int kFlagWords = 16;
+
+template <int WORDS = kFlagWords, typename F>
+__device__ __forceinline__ void for_flagged_sites(const Geo& g, const uint64_t* __restrict__ mask,
+                                                  long long nwords, F&& f) {
+  static_assert(WORDS >= 1 && WORDS <= 64, "one word per lane at most");
+  const int lane = (int)threadIdx.x & 63;
+  const long long chunk = (long long)WORDS * gridDim.x * (blockDim.x / 64);
+  for (long long base = (long long)WORDS * (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
+       base < nwords; base += chunk) {
+    const long long w = base + lane;
+    const uint64_t word = (lane < WORDS && w < nwords) ? mask[w] : 0ull;
+    const int c = __popcll(word);
+    int incl = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int u = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += u;
+    }
+    const int excl = incl - c;
+    const int total = __shfl(incl, 63, 64);
+    for (int k0 = 0; k0 < total; k0 += 64) {
+      const int k = k0 + lane;
+      int lo = 0;  // the last word whose first flagged site is at or before k
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1) {
+        const int mid = lo + step;
+        if (__shfl(excl, mid, 64) <= k) lo = mid;
+      }
+      const uint64_t wl = __shfl(word, lo, 64);
+      const int nth = k - __shfl(excl, lo, 64);
+      if (k >= total) continue;
+      const int bit = nth_set_bit(wl, nth);
+      const long long wi = base + lo;
+      int x, y, z;
+      if (g.wpr) {
+        const long long row = wi / g.wpr;
+        x = (int)(wi % g.wpr) * 64 + bit;
+        y = (int)(row % g.ny);
+        z = (int)(row / g.ny);
+      } else {
+        const long long site = wi * 64 + bit;
+        x = (int)(site % g.nx);
+        y = (int)((site / g.nx) % g.ny);
+        z = (int)(site / ((long long)g.nx * g.ny));
+      }
+      f(x, y, z);
+    }
+  }
+}
+
+// Mask words of a box: rows of 64-site words, or a linear bit array.
+__host__ __device__ inline long long mask_nwords(const Geo& g) {
+  return g.wpr ? (long long)g.ny * g.nz * g.wpr : (g.N + 63) / 64;
+}
+
 }  // namespace lbc

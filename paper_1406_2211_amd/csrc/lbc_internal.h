@@ -131,9 +131,8 @@ struct PartArgs {
   double hd;         // length of drift_before / drift_after
   int fa_rd;         // the interpolated momentum also takes (h/2) FA (earlier sub-steps)
   double sw;         // scale of the lattice force written: 1, or 2 hh for sub-steps
-  double* defer;     // non-null: store the lattice force per particle [n][3] here; a
-                     // separate launch spreads it (the interpolation of a sub-step must
-                     // not see the spreads of the same sub-step)
+  double* defer;     // non-null: store the lattice force per particle [n][3] here for a
+                     // separate (deterministic) spread
   // Moment cache: the second coupling half stores, per particle and stencil
   // node, the moments it gathered; the next step's first half reads the same
   // populations (no lattice pass in between) and reuses them when the
@@ -142,6 +141,32 @@ struct PartArgs {
   int4* mbase;      // [n] first stencil node (x, y, z) of the cached entries
   int cache_use;    // first half: cached entries are current
   int cache_fill;   // second half: store the gathered moments
+};
+
+// A coupled sub-step of the multiple time-step split with the coupling inside
+// (Eq. multistep) as one launch.  The particle state is read from one buffer
+// pair and written to the other, so that a particle takes its bond partners'
+// midpoint positions from their start-of-sub-step state while they advance.
+// The lattice force of a sub-step that later sub-steps of the same side read
+// goes into a field of its own (gout), and the interpolation adds the target
+// field and the fields of the earlier sub-steps (gin): a sub-step never sees
+// its own spreads.  A fold launch moves those fields into the target field
+// at the flagged sites.
+constexpr int kMtsFields = 4;  // sub-step fields held before a fold
+constexpr int kSubPartners = 3;  // bond partners a sub-step holds in registers
+
+struct SubArgs {
+  const double* pin;
+  const double* vin;
+  double* pout;
+  double* vout;
+  const void* gin[kMtsFields];  // fields of the earlier sub-steps of this side
+  int ngin;
+  void* gout;    // null: spread into the target field
+  int bonds;     // F_int from the bond partners at the midpoints
+  const int4* pn;  // per particle: up to kSubPartners partners (x, y, z) and the
+                   // partner count (w); more partners: the CSR list in b
+  BondArgs b;
 };
 
 struct ShellArgs {
@@ -240,7 +265,11 @@ hipError_t launch_wrap(const Geo& g, long long n, double* pos, hipStream_t st);
 // Zeroes bytes (a multiple of 8) at p with a fill kernel.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_couple_half(int storage, const PartArgs& a, hipStream_t st);
-hipError_t launch_spread_deferred(int storage, const PartArgs& a, hipStream_t st);
+// One coupled sub-step (SubArgs); and the fold: the nf fields u.gin moved
+// into the target field of a (a.target) at the flagged sites and left zero.
+hipError_t launch_mts_substep(int storage, const PartArgs& a, const SubArgs& u, hipStream_t st);
+hipError_t launch_mts_fold(int storage, const PartArgs& a, const SubArgs& u, int nf,
+                           hipStream_t st);
 // Deterministic spreading: W F of every particle (positions X, lattice forces
 // F [n][3]) into the 128-bit fixed-point accumulator acc [N][3][2], flagging
 // the sites (and the closing drift if a.drift_after); then field += the sums

@@ -392,20 +392,23 @@ __device__ __forceinline__ SiteSlot slot_of(const Geo& g, const double X[3], int
 // pending half force is added exactly as the gather would add it.
 template <int S, int K>
 __device__ __forceinline__ void group_interp(const PartArgs& a, const double X[3], bool phys,
-                                             int lane, double& rp, double up[3], long long p) {
+                                             int lane, double& rp, double up[3], long long p,
+                                             const void* const* gin = nullptr, int ngin = 0,
+                                             const int4* pre_base = nullptr,
+                                             const double4* pre_m = nullptr) {
   constexpr int L = Lanes<K>::L;
   const SiteSlot sl = slot_of<K>(a.s.g, X, lane);
   const bool fill = a.cache_fill != 0 && !phys;
   bool hit = false;
-  if (a.cache_use) {
-    const int4 b = a.mbase[p];
+  if (a.cache_use) {  // (pre_base, pre_m: the entries, loaded by the caller)
+    const int4 b = pre_base ? *pre_base : a.mbase[p];
     hit = b.x == sl.j0[0] && b.y == sl.j0[1] && b.z == sl.j0[2];
   }
   double r = 0, ux = 0, uy = 0, uz = 0;
   if (sl.site && (sl.valid || fill)) {
     double drho, j[3];
     if (hit) {
-      const double4 m = a.mcache[p * L + lane];
+      const double4 m = pre_m ? *pre_m : a.mcache[p * L + lane];
       drho = m.x;
       j[0] = m.y;
       j[1] = m.z;
@@ -417,6 +420,7 @@ __device__ __forceinline__ void group_interp(const PartArgs& a, const double X[3
       if (fill) a.mcache[p * L + lane] = make_double4(drho, j[0], j[1], j[2]);
     }
     if (phys && a.fa_rd) add_field<S>(a.FA, site_index(a.s.g, sl.x, sl.y, sl.z), j);
+    for (int f = 0; f < ngin; ++f) add_field<S>(gin[f], site_index(a.s.g, sl.x, sl.y, sl.z), j);
     if (sl.valid) {
       const double rr = a.s.rho0 + drho;
       r = sl.W * rr;
@@ -477,46 +481,55 @@ __device__ __forceinline__ void group_spread(const PartArgs& a, const double X[3
 // predecessor to the predecessor's lane for that node, which adds it in FP64;
 // only nodes that are not handed on issue the three float atomics.  The sum at
 // a site is the same set of terms as with one atomic per contribution (the
-// order of atomic additions is unspecified either way).  pre: the node's mask
-// word from mask_preload.
+// order of atomic additions is unspecified either way).
+//
+// Which lanes pair up follows from the particles' first nodes alone (read
+// from lanes 8q into scalars): the predecessor's node k' is the successor's
+// node k' - d, d the difference of their first nodes, and a pair counts when
+// both lanes carry weight (a ballot).  Only the contributions themselves move
+// between lanes, one shuffle round per particle.  pre: the node's mask word
+// from mask_preload.
 template <typename E>
 __device__ __forceinline__ void group_spread_k2(const PartArgs& a, const double X[3],
                                                 const double F[3], void* field, int lane,
                                                 long long p, uint64_t pre) {
   const SiteSlot sl = slot_of<2>(a.s.g, X, lane);
-  long long sidx = sl.valid ? site_index(a.s.g, sl.x, sl.y, sl.z) : -1;
+  const long long sidx = sl.valid ? site_index(a.s.g, sl.x, sl.y, sl.z) : -1;
   double c0 = sl.valid ? sl.W * F[0] : 0.0, c1 = sl.valid ? sl.W * F[1] : 0.0,
          c2 = sl.valid ? sl.W * F[2] : 0.0;
   const int wl = (int)(threadIdx.x & 63), qi = wl >> 3;
   const int kx = lane & 1, ky = (lane >> 1) & 1, kz = lane >> 2;
-#pragma unroll 1
+  const uint64_t live = __ballot(sidx >= 0);  // lanes that carry weight
+  const bool next = p + 1 < a.n;              // particle qi + 1 exists
+  bool issue = sidx >= 0;
+  int jx[8], jy[8], jz[8];  // first node of each particle of the wavefront
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    jx[q] = __builtin_amdgcn_readlane(sl.j0[0], 8 * q);
+    jy[q] = __builtin_amdgcn_readlane(sl.j0[1], 8 * q);
+    jz[q] = __builtin_amdgcn_readlane(sl.j0[2], 8 * q);
+  }
+#pragma unroll
   for (int i = 7; i >= 1; --i) {
-    // first node of particle i and of particle i - 1 (uniform over each group)
-    const int ax = __shfl(sl.j0[0], 8 * i, 64), ay = __shfl(sl.j0[1], 8 * i, 64),
-              az = __shfl(sl.j0[2], 8 * i, 64);
-    const int bx = __shfl(sl.j0[0], 8 * (i - 1), 64), by = __shfl(sl.j0[1], 8 * (i - 1), 64),
-              bz = __shfl(sl.j0[2], 8 * (i - 1), 64);
-    const int dx = ax - bx, dy = ay - by, dz = az - bz;
+    const int dx = jx[i] - jx[i - 1], dy = jy[i] - jy[i - 1], dz = jz[i] - jz[i - 1];
     // receiver (particle i - 1, node k'): its node k' - d of particle i
     const int sx = kx - dx, sy = ky - dy, sz = kz - dz;
-    const bool rin = qi == i - 1 && p + 1 < a.n && sx >= 0 && sx <= 1 && sy >= 0 && sy <= 1 &&
+    const bool rin = qi == i - 1 && next && sx >= 0 && sx <= 1 && sy >= 0 && sy <= 1 &&
                      sz >= 0 && sz <= 1;
     const int src = rin ? 8 * i + sx + 2 * sy + 4 * sz : wl;
     // donor (particle i, node k): the receiver's node k + d of particle i - 1
     const int tx = kx + dx, ty = ky + dy, tz = kz + dz;
     const bool din = qi == i && tx >= 0 && tx <= 1 && ty >= 0 && ty <= 1 && tz >= 0 && tz <= 1;
-    const int dst = din ? 8 * (i - 1) + tx + 2 * ty + 4 * tz : wl;
-    const long long s_src = __shfl(sidx, src, 64);
+    const int dst = 8 * (i - 1) + tx + 2 * ty + 4 * tz;
     const double g0 = __shfl(c0, src, 64), g1 = __shfl(c1, src, 64), g2 = __shfl(c2, src, 64);
-    const long long s_dst = __shfl(sidx, dst, 64);
-    if (rin && sidx >= 0 && s_src == sidx) {
+    if (rin && sidx >= 0 && ((live >> src) & 1)) {
       c0 += g0;
       c1 += g1;
       c2 += g2;
     }
-    if (din && sidx >= 0 && s_dst == sidx) sidx = -1;  // handed on to particle i - 1
+    if (din && sidx >= 0 && ((live >> dst) & 1)) issue = false;  // handed on to particle i - 1
   }
-  if (sidx < 0) return;
+  if (!issue) return;
   E* Fd = (E*)field;
   unsafeAtomicAdd(Fd + 4 * sidx + 0, (E)c0);
   unsafeAtomicAdd(Fd + 4 * sidx + 1, (E)c1);
@@ -550,34 +563,13 @@ __global__ void k_wrap(Geo g, long long n, double* pos) {
   for (int k = 0; k < 3; ++k) pos[3 * p + k] = r[k];
 }
 
-// One coupling step for FC / modified EBF: interpolate rho_p, u_p at r,
-// compute F^h over h' = a.hh (h/2 for the half steps of Alg. 3, h/2n for the
-// sub-steps of Eq. multistep), kick v, optionally drift, and spread -F^h
-// (scaled by a.sw) or store it for k_spread_deferred.
-template <int S, int K>
-__global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
-  using E = typename Store<S>::R;
-  constexpr int L = Lanes<K>::L;
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long p = gid / L;
-  const int lane = (int)(gid % L);
-  if (p >= a.n) return;  // whole groups leave together
-  double r[3], v[3], Fi[3] = {0, 0, 0};
-  for (int k = 0; k < 3; ++k) {
-    r[k] = a.pos[3 * p + k];
-    v[k] = a.vel[3 * p + k];
-    if (a.use_fint) Fi[k] = a.fint[3 * p + k];
-  }
-  if (a.drift_before) {  // P^1/2: r <- wrap(r + (h/2) v), as k_drift does
-    for (int k = 0; k < 3; ++k) r[k] += a.hd * v[k];
-    wrap3(a.s.g, r);
-  }
-  const uint64_t mpre = a.defer ? ~0ull : mask_preload<K>(a, r, lane);
-  const double m = a.mass[p];
-  double rp, up[3];
-  group_interp<S, K>(a, r, a.phys != 0, lane, rp, up, p);
+// F^h over the coupling step a.hh from the interpolated rho_p, u_p, and the
+// kick of v: the Crank-Nicolson solution of Eq. fc-vel (Eq. modified-force)
+// for force coupling, Eq. modified-ebf for the modified EBF.
+__device__ __forceinline__ void couple_update(const PartArgs& a, long long p, double m, double rp,
+                                              const double up[3], const double Fi[3], double v[3],
+                                              double Fh[3]) {
   const double hh = a.hh, al = a.gamma * hh / m, be = a.gamma * hh / rp;
-  double Fh[3];
   if (a.coupling == LB_COUPLE_FC) {
     const double den = 1.0 + 0.5 * al + 0.5 * be;
     double zeta[4] = {0, 0, 0, 0};
@@ -605,6 +597,36 @@ __global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
       v[k] = v[k] - al / sm * d + (hh / m) * (be / sm) * Fi[k];
     }
   }
+}
+
+// One coupling step for FC / modified EBF: interpolate rho_p, u_p at r,
+// compute F^h over h' = a.hh (h/2 for the half steps of Alg. 3, h/2n for the
+// sub-steps of Eq. multistep), kick v, optionally drift, and spread -F^h
+// (scaled by a.sw) or store it for the deterministic spread.
+template <int S, int K>
+__global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
+  using E = typename Store<S>::R;
+  constexpr int L = Lanes<K>::L;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long p = gid / L;
+  const int lane = (int)(gid % L);
+  if (p >= a.n) return;  // whole groups leave together
+  double r[3], v[3], Fi[3] = {0, 0, 0};
+  for (int k = 0; k < 3; ++k) {
+    r[k] = a.pos[3 * p + k];
+    v[k] = a.vel[3 * p + k];
+    if (a.use_fint) Fi[k] = a.fint[3 * p + k];
+  }
+  if (a.drift_before) {  // P^1/2: r <- wrap(r + (h/2) v), as k_drift does
+    for (int k = 0; k < 3; ++k) r[k] += a.hd * v[k];
+    wrap3(a.s.g, r);
+  }
+  const uint64_t mpre = a.defer ? ~0ull : mask_preload<K>(a, r, lane);
+  const double m = a.mass[p];
+  double rp, up[3];
+  group_interp<S, K>(a, r, a.phys != 0, lane, rp, up, p);
+  double Fh[3];
+  couple_update(a, p, m, rp, up, Fi, v, Fh);
   const double Ff[3] = {-a.sw * Fh[0], -a.sw * Fh[1], -a.sw * Fh[2]};
   if (a.defer) {
     if (lane == 0)
@@ -623,36 +645,6 @@ __global__ __launch_bounds__(256) void k_couple_half(PartArgs a) {
     if (a.drift_after || a.drift_before)
       for (int k = 0; k < 3; ++k) a.pos[3 * p + k] = r[k];
     for (int k = 0; k < 3; ++k) a.vel[3 * p + k] = v[k];
-  }
-}
-
-// Spread of the lattice forces a deferred coupling step stored, then the
-// closing drift of the sub-step (Eq. multistep: the interpolation of every
-// particle in a sub-step sees the spreads of the earlier sub-steps and none
-// of its own, so the spread runs as a launch of its own).
-template <int S, int K>
-__global__ __launch_bounds__(256) void k_spread_deferred(PartArgs a) {
-  using E = typename Store<S>::R;
-  constexpr int L = Lanes<K>::L;
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long p = gid / L;
-  const int lane = (int)(gid % L);
-  if (p >= a.n) return;  // whole groups leave together
-  double r[3], F[3];
-  for (int k = 0; k < 3; ++k) {
-    r[k] = a.pos[3 * p + k];
-    F[k] = a.defer[3 * p + k];
-  }
-  if constexpr (K == 2) {  // contributions of consecutive beads combined before the atomics
-    const uint64_t mpre = mask_preload<K>(a, r, lane);
-    group_spread_k2<E>(a, r, F, a.target ? a.FB : a.FA, lane, p, mpre);
-  } else {
-    group_spread<E, K>(a, r, F, a.target ? a.FB : a.FA, lane);
-  }
-  if (lane == 0 && a.drift_after) {
-    for (int k = 0; k < 3; ++k) r[k] += a.hd * a.vel[3 * p + k];
-    wrap3(a.s.g, r);
-    for (int k = 0; k < 3; ++k) a.pos[3 * p + k] = r[k];
   }
 }
 
@@ -935,6 +927,120 @@ __device__ __forceinline__ void bond_group(const BondArgs& b, int grp, int mode,
 __global__ void k_bond_groups(BondArgs b, int mode, int acc, int nsub, double dt) {
   extern __shared__ double lds[];
   bond_group(b, blockIdx.x, mode, acc, nsub, dt, lds);
+}
+
+// One coupled sub-step of Eq. multistep in one launch (SubArgs): drift dt/2 to
+// the midpoint, F_int there (each particle advances its bond partners itself,
+// with the same arithmetic as their own drift), interpolation of the fluid
+// that every earlier sub-step has forced, F^h and kick over dt, spread of the
+// lattice force at the midpoint, drift dt/2.  Everything that depends only on
+// the particle index (its state, partner list and cached moments) is loaded
+// first, and the partners' state is loaded before the interpolation's gathers
+// but used after them, so that the launch waits on about three memory round
+// trips: state, gathers, spreading atomics.
+template <int S, int K>
+__global__ __launch_bounds__(256) void k_mts_substep(PartArgs a, SubArgs u) {
+  using E = typename Store<S>::R;
+  constexpr int L = Lanes<K>::L;
+  constexpr int NP = kSubPartners;
+  static_assert(NP == 3, "the packed partner entry holds three partners");
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long p = gid / L;
+  const int lane = (int)(gid % L);
+  if (p >= a.n) return;  // whole groups leave together
+  double pi[3], v[3];
+  for (int k = 0; k < 3; ++k) {
+    pi[k] = u.pin[3 * p + k];
+    v[k] = u.vin[3 * p + k];
+  }
+  const int4 pn = u.bonds ? u.pn[p] : make_int4(0, 0, 0, 0);
+  const double m = a.mass[p];
+  int4 mb = make_int4(0, 0, 0, 0);
+  double4 mc = make_double4(0, 0, 0, 0);
+  if (a.cache_use) {
+    mb = a.mbase[p];
+    mc = a.mcache[p * L + lane];
+  }
+  double r[3];
+  for (int k = 0; k < 3; ++k) r[k] = pi[k] + a.hd * v[k];
+  wrap3(a.s.g, r);
+  // the partners' start-of-sub-step state (pn.w <= NP: partners in pn.x..z)
+  const int qs[3] = {pn.x, pn.y, pn.z};
+  double pq[NP][3], vq[NP][3];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    const long long q = j < pn.w ? qs[j] : p;
+    for (int k = 0; k < 3; ++k) {
+      pq[j][k] = u.pin[3 * q + k];
+      vq[j][k] = u.vin[3 * q + k];
+    }
+  }
+  const uint64_t mpre = mask_preload<K>(a, r, lane);
+  double rp, up[3];
+  group_interp<S, K>(a, r, a.phys != 0, lane, rp, up, p, u.gin, u.ngin, &mb, &mc);
+  double Fi[3] = {0, 0, 0};
+  if (pn.w <= NP) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      if (j < pn.w) {
+        double rq[3];
+        for (int k = 0; k < 3; ++k) rq[k] = pq[j][k] + a.hd * vq[j][k];
+        wrap3(a.s.g, rq);
+        bond_pair(u.b, r, rq, Fi);
+      }
+    }
+  } else {  // more partners than held in registers: the CSR list
+    for (int e = u.b.start[p]; e < u.b.start[p + 1]; ++e) {
+      const long long q = u.b.nbr[e];
+      double rq[3];
+      for (int k = 0; k < 3; ++k) rq[k] = u.pin[3 * q + k] + a.hd * u.vin[3 * q + k];
+      wrap3(a.s.g, rq);
+      bond_pair(u.b, r, rq, Fi);
+    }
+  }
+  double Fh[3];
+  couple_update(a, p, m, rp, up, Fi, v, Fh);
+  const double Ff[3] = {-a.sw * Fh[0], -a.sw * Fh[1], -a.sw * Fh[2]};
+  void* field = u.gout ? u.gout : (a.target ? a.FB : a.FA);
+  if constexpr (K == 2)
+    group_spread_k2<E>(a, r, Ff, field, lane, p, mpre);
+  else
+    group_spread<E, K>(a, r, Ff, field, lane, &mpre);
+  if (lane == 0) {
+    for (int k = 0; k < 3; ++k) r[k] += a.hd * v[k];
+    wrap3(a.s.g, r);
+    for (int k = 0; k < 3; ++k) {
+      u.pout[3 * p + k] = r[k];
+      u.vout[3 * p + k] = v[k];
+    }
+  }
+}
+
+// The sub-step fields into the target field at every flagged site (every
+// nonzero entry of a field lies on a site its spread flagged), one lane per
+// site: no two lanes share a site, so plain loads and stores suffice.  The
+// fields are left zero.
+template <int S>
+__global__ __launch_bounds__(256) void k_mts_fold(Geo g, const uint64_t* __restrict__ mask,
+                                                  long long nwords, SubArgs u, int nf, void* T) {
+  using V4 = typename Store<S>::V4;
+  for_flagged_sites<64>(g, mask, nwords, [&](int x, int y, int z) {
+    const long long s = site_index(g, x, y, z);
+    V4 t = ((const V4*)T)[s];
+    bool any = false;
+    for (int f = 0; f < nf; ++f) {
+      V4* G = (V4*)u.gin[f];
+      const V4 w = G[s];
+      if (w.x != 0 || w.y != 0 || w.z != 0) {
+        t.x += w.x;
+        t.y += w.y;
+        t.z += w.z;
+        G[s] = V4{0, 0, 0, 0};
+        any = true;
+      }
+    }
+    if (any) ((V4*)T)[s] = t;
+  });
 }
 
 // Rigid-shell tethers: block per shell.  Markers are unwrapped around the
@@ -1365,10 +1471,25 @@ hipError_t launch_couple_half(int storage, const PartArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_spread_deferred(int storage, const PartArgs& a, hipStream_t st) {
+hipError_t launch_mts_substep(int storage, const PartArgs& a, const SubArgs& u, hipStream_t st) {
   if (a.n > 0)
-    LBC_KERNEL_SWITCH(a.K, LBC_STORAGE_SWITCH(storage, (k_spread_deferred<SS, KK>
-                                                        <<<gblocks(a.n, KK), 256, 0, st>>>(a))));
+    LBC_KERNEL_SWITCH(a.K, LBC_STORAGE_SWITCH(storage, (k_mts_substep<SS, KK>
+                                                        <<<gblocks(a.n, KK), 256, 0, st>>>(a, u))));
+  return hipGetLastError();
+}
+
+hipError_t launch_mts_fold(int storage, const PartArgs& a, const SubArgs& u, int nf,
+                           hipStream_t st) {
+  if (nf <= 0) return hipSuccess;
+  const Geo& g = a.s.g;
+  const long long nwords = mask_nwords(g);
+  const long long per_wg = 4ll * 64;  // 64 words per wavefront: the mask is sparse here
+  const unsigned gr = (unsigned)std::min<long long>((nwords + per_wg - 1) / per_wg, 16384ll);
+  void* T = a.target ? a.FB : a.FA;
+  if (storage == LB_F64)
+    k_mts_fold<LB_F64><<<gr, 256, 0, st>>>(g, a.mask, nwords, u, nf, T);
+  else
+    k_mts_fold<LB_F32><<<gr, 256, 0, st>>>(g, a.mask, nwords, u, nf, T);
   return hipGetLastError();
 }
 

@@ -198,82 +198,22 @@ __device__ __forceinline__ int wrap_near(int j, int n) {
   return (unsigned)r < (unsigned)n ? r : wrap_idx(j, n);
 }
 
-// Position of the n-th set bit (n < popcount) of v.
-__device__ __forceinline__ int nth_set_bit(uint64_t v, int n) {
-  int pos = 0;
-#pragma unroll
-  for (int half = 32; half > 0; half >>= 1) {
-    const int c = __popcll(v & ((1ull << half) - 1ull));
-    if (n >= c) {
-      n -= c;
-      v >>= half;
-      pos += half;
-    }
-  }
-  return pos;
-}
-
-// Each wavefront reads kFlagWords mask words and hands their flagged sites
-// out one per lane (a scan of the words' bit counts and a binary search in
-// it), so that one round of 19 gathers serves up to 64 flagged sites.
-constexpr int kFlagWords = 16;
-
 template <int S>
 __global__ __launch_bounds__(256) void k_flag_vel(SiteArgs s, const uint64_t* __restrict__ mask,
                                                   long long nwords, void* Uv, uint32_t stamp) {
   using W = typename TileT<S>::W;
   using V4 = typename Store<S>::V4;
-  const int lane = (int)threadIdx.x & 63;
-  const long long chunk = (long long)kFlagWords * gridDim.x * (blockDim.x / 64);
-  for (long long base = (long long)kFlagWords * (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
-       base < nwords; base += chunk) {
-    const long long w = base + lane;
-    const uint64_t word = (lane < kFlagWords && w < nwords) ? mask[w] : 0ull;
-    const int c = __popcll(word);
-    int incl = c;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int u = __shfl_up(incl, d, 64);
-      if (lane >= d) incl += u;
-    }
-    const int excl = incl - c;
-    const int total = __shfl(incl, 63, 64);
-    for (int k0 = 0; k0 < total; k0 += 64) {
-      const int k = k0 + lane;
-      int lo = 0;  // the last word whose first flagged site is at or before k
-#pragma unroll
-      for (int step = 32; step > 0; step >>= 1) {
-        const int mid = lo + step;
-        if (__shfl(excl, mid, 64) <= k) lo = mid;
-      }
-      const uint64_t wl = __shfl(word, lo, 64);
-      const int nth = k - __shfl(excl, lo, 64);
-      if (k >= total) continue;
-      const int bit = nth_set_bit(wl, nth);
-      const long long wi = base + lo;
-      int x, y, z;
-      if (s.g.wpr) {
-        const long long row = wi / s.g.wpr;
-        x = (int)(wi % s.g.wpr) * 64 + bit;
-        y = (int)(row % s.g.ny);
-        z = (int)(row / s.g.ny);
-      } else {
-        const long long site = wi * 64 + bit;
-        x = (int)(site % s.g.nx);
-        y = (int)((site / s.g.nx) % s.g.ny);
-        z = (int)(site / ((long long)s.g.nx * s.g.ny));
-      }
-      W drho, j[3];
-      site_phys_r<S, W>(s, x, y, z, drho, j);
-      const W rr = W(s.rho0) + drho;
-      V4 u;
-      u.x = j[0] / rr;
-      u.y = j[1] / rr;
-      u.z = j[2] / rr;
-      u.w = stamp_value(W(0), stamp);
-      ((V4*)Uv)[site_index(s.g, x, y, z)] = u;
-    }
-  }
+  for_flagged_sites(s.g, mask, nwords, [&](int x, int y, int z) {
+    W drho, j[3];
+    site_phys_r<S, W>(s, x, y, z, drho, j);
+    const W rr = W(s.rho0) + drho;
+    V4 u;
+    u.x = j[0] / rr;
+    u.y = j[1] / rr;
+    u.z = j[2] / rr;
+    u.w = stamp_value(W(0), stamp);
+    ((V4*)Uv)[site_index(s.g, x, y, z)] = u;
+  });
 }
 
 // One axis of a K-point stencil (Appendix A kernels) in closed form: the
@@ -631,7 +571,7 @@ hipError_t launch_flag_interp(int storage, int K, const SiteArgs& s, const uint6
                               void* U, uint32_t stamp, const double* at, double* pos, double* aux,
                               int mode, long long n, int* miss, bool all_miss, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const long long nwords = s.g.wpr ? (long long)s.g.ny * s.g.nz * s.g.wpr : (s.g.N + 63) / 64;
+  const long long nwords = mask_nwords(s.g);
   const long long per_wg = 4ll * kFlagWords;
   const unsigned gv = (unsigned)std::min<long long>((nwords + per_wg - 1) / per_wg, 64ll * cu_count());
   const long long lanes = n * (K == 2 ? 4 : 16);

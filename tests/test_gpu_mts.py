@@ -32,8 +32,10 @@ def _check(c, tol):
     return compare(c, run_gpu(c), o, tol, sens=sens)
 
 
-@pytest.mark.parametrize("n", [1, 3])
+@pytest.mark.parametrize("n", [1, 3, 7])
 def test_soft_chains_fc_fp64(n):
+    """n = 7: six sub-steps per side write fields of their own, more than are
+    held before a fold, so each side folds twice."""
     _check(_chains(f"in_soft_n{n}", 24, 2, 12, 30, n), TOL64)
 
 
@@ -82,3 +84,8 @@ def test_one_site_lattice_pair():
 
 def test_soft_chains_fc_fp32():
     _check(_chains("in_soft32", 32, 3, 16, 60, 3, storage=1), TOL32)
+
+
+def test_many_substeps_phi4_fp32():
+    """Ten sub-steps per side (three folds each), 4-point kernel, FP32."""
+    _check(_chains("in_many32", 24, 2, 10, 20, 10, storage=1, kernel=4), TOL32)
