@@ -89,3 +89,24 @@ def test_soft_chains_fc_fp32():
 def test_many_substeps_phi4_fp32():
     """Ten sub-steps per side (three folds each), 4-point kernel, FP32."""
     _check(_chains("in_many32", 24, 2, 10, 20, 10, storage=1, kernel=4), TOL32)
+
+
+def test_crossing_chains_row_mask_fp64():
+    """Two chains laid side by side half a site apart, so beads of different
+    chains (far apart in index) share stencil nodes; 64-site rows, so the
+    force mask is kept as one word per row and the fold walks that layout;
+    n = 6 puts five sub-steps per side into fields of their own, one more
+    than are held before a fold."""
+    nb = 20
+    x = 20.3 + np.arange(nb, dtype=np.float64)
+    a = np.stack([x, np.full(nb, 7.2), np.full(nb, 8.4)], axis=1)
+    b = np.stack([x[::-1] + 0.45, np.full(nb, 7.7), np.full(nb, 8.9)], axis=1)
+    pos = np.vstack([a, b])
+    idx = np.arange(2 * nb).reshape(2, nb)
+    bonds = np.stack([idx[:, :-1].ravel(), idx[:, 1:].ravel()], axis=1).astype(np.int32)
+    vel = np.random.default_rng(5).normal(0.0, 1e-3, pos.shape)
+    c = Case(name="in_cross_rows", nx=64, ny=16, nz=16, tau=0.7, steps=20, collision=1,
+             coupling=1, gamma=2.0, kernel=2, storage=0, mts=6, u_noise=1e-4, pos=pos, vel=vel,
+             mass=np.full(len(pos), 0.9), bonds=bonds, bond_k=2.0, bond_r0=1.0)
+    c.extra["mts_inside"] = 1
+    _check(c, TOL64)
