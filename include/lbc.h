@@ -104,7 +104,10 @@ typedef struct lb_params {
                             [P F_int P]^n F_h^1/2); 1 the coupling inside every sub-step
                             (Eq. multistep: [P^(1/4n) F^(1/2n) P^(1/4n)]^n (C S) [...]^n, F
                             holding every force; 2n coupling evaluations per step).
-                            LB_EINVAL without sub-steps. */
+                            LB_EINVAL without sub-steps.  Unless deterministic is set, the
+                            workspace also holds min(n - 1, 4) extra force fields (16 B per
+                            site each, 32 B in FP64) and a second copy of the particle
+                            state. */
   double kT;             /* thermal energy k_B T (lattice units); 0: deterministic.  > 0: the
                             fluctuating collision of Eq. mrt-fluct (noise sqrt(rho) phi_k r_k
                             on every non-conserved moment, phi_k = sqrt(mu b_k lambda_k
