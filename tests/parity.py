@@ -58,7 +58,11 @@ def initial_fields(c: Case):
     return rho, u
 
 
-def run_oracle(c: Case):
+def run_oracle(c: Case, progress=None):
+    """The oracle run of a case.  progress(msg): the steps run in chunks of 10
+    with a line after each (a long silent run looks hung to a watchdog); a
+    chunked run is bit-identical to one call, since the state between steps is
+    (df, pos, vel) and the index of the step in the random streams."""
     o = O.Oracle(nx=c.nx, ny=c.ny, nz=c.nz, tau=c.tau, wall_y=c.wall_y, fext=c.fext,
                  collision=c.collision, coupling=COUPLING_TO_ORACLE[c.coupling], gamma=c.gamma,
                  kernel=c.kernel, mts_n=c.mts, bonds=c.bonds, bond_k=c.bond_k, bond_r0=c.bond_r0,
@@ -73,7 +77,15 @@ def run_oracle(c: Case):
     vel = None
     if pos is not None:
         vel = np.zeros_like(pos) if c.vel is None else np.array(c.vel, dtype=np.float64, copy=True)
-    o.run(df, c.steps, pos, vel, c.mass)
+    chunk = 10 if progress else max(c.steps, 1)
+    done = 0
+    while done < c.steps:
+        k = min(chunk, c.steps - done)
+        o.run(df, k, pos, vel, c.mass)
+        o.cfg.step0 += k
+        done += k
+        if progress:
+            progress(f"[oracle] {c.name}: {done}/{c.steps} steps")
     rho_o, u_o = o.moments(df)
     out = dict(df=df, rho=rho_o, u=u_o, pos=pos, vel=vel, totals=o.totals(df, vel, c.mass))
     if c.extra.get("stress"):
@@ -196,7 +208,7 @@ def errors(c: Case, g, o):
     return errs
 
 
-def ulp_sensitivity(c: Case, o):
+def ulp_sensitivity(c: Case, o, progress=None):
     """The oracle's own response to a one-ulp change of every particle
     position: the round-off floor of a trajectory comparison.  Stiff bonds
     amplify position round-off into velocity and fluid differences far above
@@ -206,7 +218,7 @@ def ulp_sensitivity(c: Case, o):
         return 0.0
     c2 = copy.copy(c)
     c2.pos = np.nextafter(np.asarray(c.pos, np.float64), np.inf)
-    o2 = run_oracle(c2)
+    o2 = run_oracle(c2, progress)
     o2["oracle_order"] = True
     return max(errors(c, o2, o).values())
 

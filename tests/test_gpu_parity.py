@@ -38,11 +38,12 @@ def _ib_case(name, kernel, storage=0, steps=30):
                 pos=X, nshell=2, template=T, tether_k=0.05)
 
 
-def check(c, tol, ptol=None, conditioned=False):
+def check(c, tol, ptol=None, conditioned=False, progress=None):
     """conditioned=True: the trajectory is ill-conditioned (stiff bonds), so the
-    bound is raised to 20x the oracle's own one-ulp sensitivity if larger."""
-    o = run_oracle(c)
-    sens = ulp_sensitivity(c, o) if conditioned else 0.0
+    bound is raised to 20x the oracle's own one-ulp sensitivity if larger.
+    progress: see run_oracle."""
+    o = run_oracle(c, progress)
+    sens = ulp_sensitivity(c, o, progress) if conditioned else 0.0
     g = run_gpu(c)
     return compare(c, g, o, tol, ptol, sens=sens)
 
@@ -213,14 +214,19 @@ def test_empty_particle_set():
     check(c, TOL64)
 
 
-def test_full_size_force_coupling_fp64():
+def test_full_size_force_coupling_fp64(capsys):
     """The benchmark workload at full size with FP64 storage (the reference of
     the precision study): 256^3 two-rate MRT, 10^4 bonded particles with the
     multiple time-step split, 100 steps against the oracle.  The stiff bonds
     make the trajectory ill-conditioned, so the bound follows the oracle's own
-    one-ulp sensitivity where that exceeds 1e-12."""
+    one-ulp sensitivity where that exceeds 1e-12.  The two oracle runs take
+    minutes: their progress goes to the terminal past the output capture."""
+    def progress(msg):
+        with capsys.disabled():
+            print(msg, flush=True)
+
     c = _chains_case("c2_full_fp64", 256, 100, 100, 100, storage=0)
-    check(c, TOL64, conditioned=True)
+    check(c, TOL64, conditioned=True, progress=progress)
 
 
 # ------------------------------------------------------------------- FP32
