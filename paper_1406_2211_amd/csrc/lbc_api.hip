@@ -414,10 +414,11 @@ static lb_status build_groups(lb_ctx* c) {
   return LB_OK;
 }
 
-// F_int at the given positions: shell tethers and bonds.
-static lb_status enqueue_fint(lb_ctx* c, double* pos, bool& any) {
-  any = false;
-  if (c->nshell > 0) {
+// F_int at the given positions: shell tethers and bonds (shells_done: the
+// tether forces are already in fint).
+static lb_status enqueue_fint(lb_ctx* c, double* pos, bool& any, bool shells_done = false) {
+  any = shells_done;
+  if (c->nshell > 0 && !shells_done) {
     const int64_t nm = (int64_t)c->nshell * c->shell_size;
     if (nm < c->np)
       HIPCHK(c, launch_zero(c->L.fint + 3 * nm, (size_t)(c->np - nm) * 24, c->st));
@@ -549,14 +550,35 @@ static lb_status lattice_pass(lb_ctx* c, int bond_nsub = 0, double bond_dt = 0.0
 // velocity pass over the flagged sites under a new stamp, then the markers.
 // The field is cleared before a stamp is reused (every 2^32 - 1 calls), so
 // that an entry carries the current stamp only if this call wrote it.
-static lb_status flag_interp(lb_ctx* c, const double* at, double* pos, double* aux, int mode) {
+// redo = false: the listed markers are left to shell_forces_redo, which must
+// follow with the same call's arguments.
+static lb_status flag_interp(lb_ctx* c, const double* at, double* pos, double* aux, int mode,
+                             bool redo = true) {
   if (++c->ustamp == 0xffffffffu) {
     HIPCHK(c, launch_zero(c->L.U, (size_t)c->geo.N * 4 * (c->p.storage == LB_F64 ? 8 : 4), c->st));
     c->ustamp = 1;
   }
   HIPCHK(c, launch_flag_interp(c->p.storage, c->p.kernel, site_args(c), c->L.mask, c->L.U,
                                c->ustamp, at, pos, aux, mode, c->np, c->L.miss, !c->flags_follow,
-                               c->st));
+                               redo, c->st));
+  return LB_OK;
+}
+
+// Whether the markers listed by a flag_interp call of the tiled path can be
+// redone by the shells' workgroups: the markers are whole shells and the
+// flags follow them (right after the fluid or the markers were set every
+// marker is listed, which the grid of k_marker_slow handles better).
+static bool redo_in_shells(const lb_ctx* c) {
+  return c->nshell > 0 && (int64_t)c->nshell * c->shell_size == c->np && c->flags_follow;
+}
+
+// The listed markers of the last flag_interp call (same arguments) redone,
+// then the tether forces at the positions pos_f (launch_shell_redo_forces).
+static lb_status shell_forces_redo(lb_ctx* c, const double* at, double* pos, double* aux,
+                                   int mode, double* pos_f) {
+  ShellArgs s{c->geo, pos_f, c->L.tmpl, c->L.fint, c->L.rot, c->shell_size, c->k_tether};
+  HIPCHK(c, launch_shell_redo_forces(c->p.storage, c->p.kernel, s, c->nshell, site_args(c),
+                                     c->L.U, c->ustamp, at, pos, aux, mode, c->L.miss, c->st));
   return LB_OK;
 }
 
@@ -729,13 +751,16 @@ static lb_status step_once(lb_ctx* c) {
     // X~ = X + h/2 I[X]u(t), then X <- X + h/2 I[X~]u(t), from one velocity
     // pass.  The final advection of the previous step, X <- X + h/2 I[X~]u(t),
     // reads the same state and is done first (mode 3).
-    if (c->adv_pending)
-      s = flag_interp(c, c->L.aux, c->L.pos, c->L.aux, 3);
-    else
-      s = flag_interp(c, c->L.pos, c->L.pos, c->L.aux, 2);
-    if (s != LB_OK) return s;
+    // Markers listed by the interpolation are redone by their shells'
+    // workgroups in the tether-force launch where the markers are whole shells.
+    const bool fused = redo_in_shells(c);
+    const double* at = c->adv_pending ? c->L.aux : c->L.pos;
+    const int mode = c->adv_pending ? 3 : 2;
+    if ((s = flag_interp(c, at, c->L.pos, c->L.aux, mode, !fused)) != LB_OK) return s;
+    if (fused && (s = shell_forces_redo(c, at, c->L.pos, c->L.aux, mode, c->L.aux)) != LB_OK)
+      return s;
     bool any;
-    if ((s = enqueue_fint(c, c->L.aux, any)) != LB_OK) return s;
+    if ((s = enqueue_fint(c, c->L.aux, any, fused)) != LB_OK) return s;
     if (!any) HIPCHK(c, launch_zero(c->L.fint, (size_t)c->np * 24, c->st));
     if (c->p.deterministic) {
       if ((s = spread_fint_det(c)) != LB_OK) return s;

@@ -195,9 +195,17 @@ struct TileArgs {
 };
 
 hipError_t launch_bin(const TileArgs& t, const double* pos, long long n, hipStream_t st);
+// Interpolation from the velocity of the flagged sites; redo = false leaves
+// the listed markers to launch_shell_redo_forces (a marker set of whole
+// shells), which redoes them and then computes the tether forces.
 hipError_t launch_flag_interp(int storage, int K, const SiteArgs& s, const uint64_t* mask,
                               void* U, uint32_t stamp, const double* at, double* pos, double* aux,
-                              int mode, long long n, int* miss, bool all_miss, hipStream_t st);
+                              int mode, long long n, int* miss, bool all_miss, bool redo,
+                              hipStream_t st);
+hipError_t launch_shell_redo_forces(int storage, int K, const ShellArgs& sa, int nshell,
+                                    const SiteArgs& s, const void* U, uint32_t stamp,
+                                    const double* at, double* pos, double* aux, int mode,
+                                    int* miss, hipStream_t st);
 hipError_t launch_tile_spread(int storage, int K, const TileArgs& t, const double* at,
                               const double* F, void* field, long long n, hipStream_t st);
 

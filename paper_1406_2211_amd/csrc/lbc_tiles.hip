@@ -525,6 +525,319 @@ __global__ __launch_bounds__(256) void k_tile_spread(TileArgs t, const double* a
   }
 }
 
+// ------------------------------------------------------------------ shells
+// Rigid-shell tethers: block per shell.  Markers are unwrapped around the
+// first marker, centred, the least-squares rotation of the template onto
+// them is found from the dominant eigenvector of Horn's symmetric 4x4
+// quaternion matrix (cyclic Jacobi), and F_j = -k (y_j - c - R t_j).
+// Every index below is a compile-time constant after unrolling, so A and V
+// stay in registers (indexed at run time they went to scratch memory).
+__device__ __forceinline__ void sym4_eig_max(double A[4][4], double q[4]) {
+  double V[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+  for (int it = 0; it < 50; ++it) {
+    double off = 0, dia = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) (i == j ? dia : off) += A[i][j] * A[i][j];
+    if (off == 0.0 || off < 1e-32 * dia) break;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int r = p + 1; r < 4; ++r) {
+        const double apr = A[p][r];
+        if (apr == 0.0) continue;
+        const double theta = 0.5 * (A[r][r] - A[p][p]) / apr;
+        const double t = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = rsqrt(t * t + 1.0), s = t * c;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double x = A[k][p], y = A[k][r];
+          A[k][p] = c * x - s * y;
+          A[k][r] = s * x + c * y;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double x = A[p][k], y = A[r][k];
+          A[p][k] = c * x - s * y;
+          A[r][k] = s * x + c * y;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double x = V[k][p], y = V[k][r];
+          V[k][p] = c * x - s * y;
+          V[k][r] = s * x + c * y;
+        }
+      }
+  }
+  double bv = A[0][0];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] = V[k][0];
+#pragma unroll
+  for (int j = 1; j < 4; ++j)
+    if (A[j][j] > bv) {
+      bv = A[j][j];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) q[k] = V[k][j];
+    }
+}
+
+// Dominant eigenvector of Horn's traceless symmetric 4x4 matrix A without an
+// iterative eigen-solve: the largest root of the characteristic polynomial
+// p(l) = l^4 - (tr A^2 / 2) l^2 - (tr A^3 / 3) l + det A by Newton's method
+// from the upper bound ||A||_F (p is convex above its largest root, so the
+// iterates decrease monotonically onto it; the same idea as Theobald's
+// quaternion characteristic polynomial method), then the column of
+// adj(A - l I) with the largest diagonal entry, which is proportional to the
+// eigenvector of a simple root.  Returns false when the eigen-residual is not
+// at rounding level (a near-degenerate top eigenvalue); the caller then uses
+// the Jacobi solve.  Every index is a compile-time constant after unrolling.
+__device__ __forceinline__ int skip_idx(int i, int k) { return k < i ? k : k + 1; }
+
+__device__ __forceinline__ bool quat_top(const double A[4][4], double q[4]) {
+  double fro2 = 0, tr3 = 0;
+  double B[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      fro2 += A[i][j] * A[i][j];
+      double b = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) b += A[i][k] * A[k][j];
+      B[i][j] = b;
+    }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tr3 += B[i][j] * A[j][i];
+  if (!(fro2 > 0.0)) {  // A = 0: any rotation fits; the identity, as the Jacobi solve gives
+    q[0] = 1.0;
+    q[1] = q[2] = q[3] = 0.0;
+    return true;
+  }
+  // det A by cofactors along row 0
+  double det = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c0 = skip_idx(j, 0), c1 = skip_idx(j, 1), c2 = skip_idx(j, 2);
+    const double m = A[1][c0] * (A[2][c1] * A[3][c2] - A[2][c2] * A[3][c1]) -
+                     A[1][c1] * (A[2][c0] * A[3][c2] - A[2][c2] * A[3][c0]) +
+                     A[1][c2] * (A[2][c0] * A[3][c1] - A[2][c1] * A[3][c0]);
+    det += ((j & 1) ? -1.0 : 1.0) * A[0][j] * m;
+  }
+  const double a2 = 0.5 * fro2, a1 = tr3 / 3.0;
+  double l = sqrt(fro2);
+  for (int it = 0; it < 60; ++it) {
+    const double l2 = l * l;
+    const double p = (l2 - a2) * l2 - a1 * l + det;
+    const double dp = (4.0 * l2 - 2.0 * a2) * l - a1;
+    if (!(dp > 0.0)) break;
+    const double dl = p / dp;
+    l -= dl;
+    if (fabs(dl) <= 1e-15 * fabs(l)) break;
+  }
+  // adjugate of M = A - l I: adj[i][j] = (-1)^(i+j) det(M without row j, column i)
+  double M[4][4], best = -1.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) M[i][j] = A[i][j] - (i == j ? l : 0.0);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double col[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r0 = skip_idx(c, 0), r1 = skip_idx(c, 1), r2 = skip_idx(c, 2);
+      const int k0 = skip_idx(i, 0), k1 = skip_idx(i, 1), k2 = skip_idx(i, 2);
+      const double m = M[r0][k0] * (M[r1][k1] * M[r2][k2] - M[r1][k2] * M[r2][k1]) -
+                       M[r0][k1] * (M[r1][k0] * M[r2][k2] - M[r1][k2] * M[r2][k0]) +
+                       M[r0][k2] * (M[r1][k0] * M[r2][k1] - M[r1][k1] * M[r2][k0]);
+      col[i] = (((i + c) & 1) ? -1.0 : 1.0) * m;
+    }
+    if (fabs(col[c]) > best) {
+      best = fabs(col[c]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) q[i] = col[i];
+    }
+  }
+  const double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  if (!(nq > 0.0)) return false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) q[i] /= nq;
+  double res = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double r = -l * q[i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r += A[i][j] * q[j];
+    res = fmax(res, fabs(r));
+  }
+  return res <= 1e-12 * sqrt(fro2);
+}
+
+// Sum of N values over the workgroup, every lane getting the sums: DPP wave
+// sums, one LDS slot per wavefront, then each lane adds the slots.
+template <int N>
+__device__ __forceinline__ void block_sum_n(double v[N], double* lds /*[N * 16]*/) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = wave_sum_dpp(v[k]);
+  if (lane == 0)
+    for (int k = 0; k < N; ++k) lds[N * wv + k] = v[k];
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    double t = 0;
+    for (int w = 0; w < nw; ++w) t += lds[N * w + k];
+    v[k] = t;
+  }
+  __syncthreads();  // lds is reused by the next sum
+}
+
+// A shell of up to kShellPerLane * 256 markers keeps each lane's unwrapped
+// positions and template vectors in registers across the three passes
+// (centre, cross-covariance, forces), so every marker is loaded once.
+constexpr int kShellPerLane = 4;
+
+// The tether forces of one shell, computed by the whole workgroup; red
+// [16 * 9] and sh_R [9] are LDS.
+__device__ __forceinline__ void shell_block(const ShellArgs& sa, int shell, double* red,
+                                            double* sh_R) {
+  const int M = sa.M;
+  const long long base = (long long)shell * M;
+  const double* X = sa.pos + 3 * base;
+  const double X0[3] = {X[0], X[1], X[2]};
+  const double L[3] = {(double)sa.g.nx, (double)sa.g.ny, (double)sa.g.nz};
+  const double rL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
+  // minimum image around the first marker (a shell spans less than half a box)
+  auto unwrap = [&](int j, double y[3]) {
+    for (int k = 0; k < 3; ++k) {
+      y[k] = X[3 * j + k] - X0[k];
+      if (k != 1 || !sa.g.wall) y[k] -= L[k] * floor(y[k] * rL[k] + 0.5);
+      y[k] += X0[k];
+    }
+  };
+  const bool held = M <= kShellPerLane * (int)blockDim.x;
+  double yh[kShellPerLane][3], th[kShellPerLane][3];
+  if (held) {
+#pragma unroll
+    for (int q = 0; q < kShellPerLane; ++q) {
+      const int j = (int)threadIdx.x + q * (int)blockDim.x;
+      if (j < M) {
+        unwrap(j, yh[q]);
+        for (int a = 0; a < 3; ++a) th[q][a] = sa.tmpl[3 * j + a];
+      }
+    }
+  }
+  // each lane's markers: from registers, or loaded again for a larger shell
+  auto for_markers = [&](auto&& fn) {
+    if (held) {
+#pragma unroll
+      for (int q = 0; q < kShellPerLane; ++q) {
+        const int j = (int)threadIdx.x + q * (int)blockDim.x;
+        if (j < M) fn(j, yh[q], th[q]);
+      }
+    } else {
+      for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        double y[3], t[3];
+        unwrap(j, y);
+        for (int a = 0; a < 3; ++a) t[a] = sa.tmpl[3 * j + a];
+        fn(j, y, t);
+      }
+    }
+  };
+  double c[3] = {0, 0, 0};
+  for_markers([&](int, const double* y, const double*) {
+    for (int k = 0; k < 3; ++k) c[k] += y[k];
+  });
+  block_sum_n<3>(c, red);
+  for (int k = 0; k < 3; ++k) c[k] /= M;
+  double S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for_markers([&](int, const double* y, const double* t) {
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) S[3 * a + b] += t[a] * (y[b] - c[b]);
+  });
+  block_sum_n<9>(S, red);
+  if (threadIdx.x == 0) {
+    const double Sxx = S[0], Sxy = S[1], Sxz = S[2], Syx = S[3], Syy = S[4], Syz = S[5],
+                 Szx = S[6], Szy = S[7], Szz = S[8];
+    double A[4][4] = {{Sxx + Syy + Szz, Syz - Szy, Szx - Sxz, Sxy - Syx},
+                      {Syz - Szy, Sxx - Syy - Szz, Sxy + Syx, Szx + Sxz},
+                      {Szx - Sxz, Sxy + Syx, -Sxx + Syy - Szz, Syz + Szy},
+                      {Sxy - Syx, Szx + Sxz, Syz + Szy, -Sxx - Syy + Szz}};
+    double q[4];
+    if (!quat_top(A, q)) sym4_eig_max(A, q);
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    sh_R[0] = w * w + x * x - y * y - z * z;
+    sh_R[1] = 2 * (x * y - w * z);
+    sh_R[2] = 2 * (x * z + w * y);
+    sh_R[3] = 2 * (x * y + w * z);
+    sh_R[4] = w * w - x * x + y * y - z * z;
+    sh_R[5] = 2 * (y * z - w * x);
+    sh_R[6] = 2 * (x * z - w * y);
+    sh_R[7] = 2 * (y * z + w * x);
+    sh_R[8] = w * w - x * x - y * y + z * z;
+    if (sa.rot)
+      for (int k = 0; k < 9; ++k) sa.rot[9 * shell + k] = sh_R[k];
+  }
+  __syncthreads();
+  for_markers([&](int j, const double* y, const double* t) {
+    for (int a = 0; a < 3; ++a) {
+      const double tgt = sh_R[3 * a] * t[0] + sh_R[3 * a + 1] * t[1] + sh_R[3 * a + 2] * t[2];
+      sa.fint[3 * (base + j) + a] = -sa.k * (y[a] - c[a] - tgt);
+    }
+  });
+}
+
+__global__ __launch_bounds__(256) void k_shell_forces(ShellArgs sa) {
+  __shared__ double red[16 * 9];
+  __shared__ double sh_R[9];
+  shell_block(sa, blockIdx.x, red, sh_R);
+}
+
+// The listed markers redone, then the tether forces, in one launch for a
+// marker set made of whole shells: each shell's workgroup takes the markers
+// of its shell from the list that the interpolation left (a stencil node
+// without the current stamp), redoes them with gathers exactly as
+// k_marker_slow does, and computes the shell's forces from the positions of
+// all its markers (the fast interpolation wrote the others before this
+// launch).  Takes the place of k_marker_slow followed by k_shell_forces.
+template <int S, int K>
+__global__ __launch_bounds__(256) void k_shell_redo_forces(ShellArgs sa, SiteArgs s,
+                                                           const void* Uv, uint32_t stamp,
+                                                           const double* at, double* pos,
+                                                           double* aux, int mode, int* miss) {
+  constexpr int G = ColGroup<K>::G;
+  constexpr int kScan = 1024;  // list entries scanned per round (so at most as many are the shell's)
+  __shared__ int mine[kScan];
+  __shared__ int nmine;
+  __shared__ double red[16 * 9];
+  __shared__ double sh_R[9];
+  const int shell = (int)blockIdx.x;
+  const int cnt = miss[stamp & 1u];
+  const long long lo = (long long)shell * sa.M, hi = lo + sa.M;
+  for (int b0 = 0; b0 < cnt; b0 += kScan) {
+    if (threadIdx.x == 0) nmine = 0;
+    __syncthreads();
+    const int b1 = min(cnt, b0 + kScan);
+    for (int j = b0 + (int)threadIdx.x; j < b1; j += (int)blockDim.x) {
+      const int p = miss[2 + j];
+      if (p >= lo && p < hi) mine[atomicAdd(&nmine, 1)] = p;
+    }
+    __syncthreads();
+    const int nm = nmine;
+    for (int g = (int)threadIdx.x; g / G < nm; g += (int)blockDim.x)  // whole groups leave together
+      marker_run<S, K, false>(s, Uv, stamp, at, pos, aux, mode, mine[g / G], g % G);
+    __syncthreads();  // the redone positions are visible to the workgroup; nmine is free
+  }
+  if (shell == 0 && threadIdx.x == 0) miss[(stamp + 1u) & 1u] = 0;  // the next call's counter
+  shell_block(sa, shell, red, sh_R);
+}
+
 // ------------------------------------------------------------------ launchers
 hipError_t launch_bin(const TileArgs& t, const double* pos, long long n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
@@ -569,7 +882,8 @@ static unsigned tile_grid(const TileArgs& t, int per_cu) {
 
 hipError_t launch_flag_interp(int storage, int K, const SiteArgs& s, const uint64_t* mask,
                               void* U, uint32_t stamp, const double* at, double* pos, double* aux,
-                              int mode, long long n, int* miss, bool all_miss, hipStream_t st) {
+                              int mode, long long n, int* miss, bool all_miss, bool redo,
+                              hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const long long nwords = mask_nwords(s.g);
   const long long per_wg = 4ll * kFlagWords;
@@ -582,8 +896,24 @@ hipError_t launch_flag_interp(int storage, int K, const SiteArgs& s, const uint6
   LBC_TILE_S_SWITCH(storage, (k_flag_vel<SS><<<gv, 256, 0, st>>>(s, mask, nwords, U, stamp)));
   LBC_TILE_K_SWITCH(K, LBC_TILE_S_SWITCH(storage, (k_marker_interp<SS, KK><<<gi, 256, 0, st>>>(
                                                       s, U, stamp, at, pos, aux, mode, n, miss))));
-  LBC_TILE_K_SWITCH(K, LBC_TILE_S_SWITCH(storage, (k_marker_slow<SS, KK><<<gs, 256, 0, st>>>(
-                                                      s, U, stamp, at, pos, aux, mode, miss))));
+  if (redo)
+    LBC_TILE_K_SWITCH(K, LBC_TILE_S_SWITCH(storage, (k_marker_slow<SS, KK><<<gs, 256, 0, st>>>(
+                                                        s, U, stamp, at, pos, aux, mode, miss))));
+  return hipGetLastError();
+}
+
+hipError_t launch_shell_redo_forces(int storage, int K, const ShellArgs& sa, int nshell,
+                                    const SiteArgs& s, const void* U, uint32_t stamp,
+                                    const double* at, double* pos, double* aux, int mode,
+                                    int* miss, hipStream_t st) {
+  if (nshell <= 0) return hipSuccess;
+  LBC_TILE_K_SWITCH(K, LBC_TILE_S_SWITCH(storage, (k_shell_redo_forces<SS, KK><<<nshell, 256, 0, st>>>(
+                                                      sa, s, U, stamp, at, pos, aux, mode, miss))));
+  return hipGetLastError();
+}
+
+hipError_t launch_shell_forces(const ShellArgs& s, int nshell, hipStream_t st) {
+  if (nshell > 0) k_shell_forces<<<nshell, 256, 0, st>>>(s);
   return hipGetLastError();
 }
 

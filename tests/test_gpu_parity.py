@@ -286,6 +286,21 @@ def test_ib_shells_fp32():
     check(_ib_case("ib32", 4, storage=1), TOL32)
 
 
+@pytest.mark.parametrize("kernel", [2, 4])
+def test_ib_shells_carried_across_nodes_fp64(kernel):
+    """Shells carried by a uniform flow of 0.05 sites per step: each step some
+    markers' stencils move onto nodes the previous spread did not flag, so the
+    interpolation lists them and the shells' workgroups redo them in the
+    tether-force launch before the forces are taken."""
+    T = I.icosphere(1, 3.0)
+    cen = np.array([[6.3, 7.1, 8.2], [17.6, 15.4, 19.9]])
+    X = np.vstack([c + T for c in cen])
+    c = Case(name=f"ib_carried_k{kernel}", nx=24, ny=24, nz=28, tau=0.8, steps=40, coupling=3,
+             kernel=kernel, u_noise=0.0, pos=X, nshell=2, template=T, tether_k=0.05)
+    c.extra["u0"] = np.array([0.05, -0.02, 0.04])
+    check(c, TOL64)
+
+
 # ------------------------------------------------------------- totals
 def test_totals_match_oracle():
     c = _soft_alg3_case("totals", 20)
