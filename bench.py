@@ -264,7 +264,7 @@ def main():
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
