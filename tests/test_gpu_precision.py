@@ -94,3 +94,24 @@ def test_16bit_storage_ib_tiles_error_reported(storage, scale, limit):
           ", ".join(f"{k}={v:.3e}" for k, v in e.items()), flush=True)
     assert np.all(np.isfinite(g["u"])) and np.all(np.isfinite(g["pos"]))
     assert e["u"] < limit and e["pos"] < 1e-6
+
+
+@pytest.mark.parametrize("storage,scale,limit", [(2, 20, 5e-3), (3, 0, 5e-2)])
+def test_16bit_storage_coupling_inside_substeps_error_reported(storage, scale, limit):
+    """Bonded chains with the coupling inside every sub-step (n = 6: the
+    sub-step fields and a fold inside each side) on 16-bit storage, against the
+    FP64 oracle; the bound catches a broken 16-bit sub-step or fold path, the
+    measured errors are printed."""
+    pos, vel, bonds = I.chains(2, 12, (24, 24, 24), 1.0, 1e-3, 2)
+    c = Case(name=f"mts16_s{storage}", nx=24, ny=24, nz=24, tau=0.7, steps=30, collision=1,
+             coupling=1, gamma=2.0, kernel=2, storage=storage, mts=6, u_noise=1e-4, pos=pos,
+             vel=vel, mass=np.full(len(pos), 0.9), bonds=bonds, bond_k=2.0, bond_r0=1.0,
+             f16_scale_log2=scale)
+    c.extra["mts_inside"] = 1
+    o = run_oracle(c)
+    g = run_gpu(c)
+    e = errors(c, g, o)
+    print(f"[precision] coupling inside, storage={storage} scale=2^{scale}: " +
+          ", ".join(f"{k}={v:.3e}" for k, v in e.items()), flush=True)
+    assert np.all(np.isfinite(g["u"])) and np.all(np.isfinite(g["pos"]))
+    assert e["u"] < limit and e["pos"] < 1e-6
