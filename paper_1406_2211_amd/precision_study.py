@@ -3,8 +3,8 @@ workload (256^3 two-rate MRT, 10^4 bonded particles, multiple time steps):
 the run is repeated with FP32, FP16 (scaled) and BF16 storage, all with FP32
 compute and FP64 particles, and the physical velocity field is compared with
 the FP64-storage run (itself checked against the CPU oracle at this size over
-100 steps in the GPU parity tests) at
-the requested step counts.  Prints one JSON line per precision and step.
+100 steps by test_full_size_force_coupling_fp64 in tests/test_gpu_parity.py)
+at the requested step counts.  Prints one JSON line per precision and step.
 
     python -m paper_1406_2211_amd.precision_study --steps 100 1000 5000
 """
