@@ -110,3 +110,16 @@ def test_crossing_chains_row_mask_fp64():
              mass=np.full(len(pos), 0.9), bonds=bonds, bond_k=2.0, bond_r0=1.0)
     c.extra["mts_inside"] = 1
     _check(c, TOL64)
+
+
+def test_benchmark_chains_at_64_cubed_fp64():
+    """The coupling-inside form of the force-coupling workload at a reduced
+    size: 64^3 two-rate MRT, tau = 0.6, 10 chains of 100 beads (k = 30, m = 1),
+    n = 5 sub-steps per side, 40 steps, against the oracle (bound: 1e-12 or 20x
+    the oracle's one-ulp sensitivity of these stiff chains)."""
+    pos, vel, bonds = I.chains(10, 100, (64, 64, 64), 1.0, 1e-3, 2)
+    c = Case(name="in_c2_64", nx=64, ny=64, nz=64, tau=0.6, steps=40, collision=1, coupling=1,
+             gamma=2.0, kernel=2, storage=0, mts=5, u_noise=0.0, pos=pos, vel=vel,
+             mass=np.ones(len(pos)), bonds=bonds, bond_k=30.0, bond_r0=1.0)
+    c.extra["mts_inside"] = 1
+    _check(c, TOL64)
