@@ -127,7 +127,7 @@ typedef struct lb_params {
                             (2c^2 - 3)(cy^2 - cz^2).  The shear stress relaxes at 1/tau.  Not
                             with csc or comoving, nor in ensembles (LB_EINVAL). */
   int32_t ib_rebin;      /* LB_COUPLE_IB with LB_PHI3/LB_PHI4 (markers binned into 8^3 tiles
-                            for spreading): steps between two binnings, 0 for the default 16.
+                            for spreading): steps between two binnings, 0 for the default 32.
                             Any value gives the same results: a marker whose stencil leaves
                             its bin's neighbourhood switches that spread to a slower path. */
 } lb_params;

@@ -182,7 +182,7 @@ bool check_params(const lb_grid* g, const lb_params* p, const lb_limits* lim, st
 }
 
 // Steps between two binnings of IB markers into tiles.
-constexpr int64_t kRebin = 16;  // default steps between two marker binnings
+constexpr int64_t kRebin = 32;  // default steps between two marker binnings
 
 }  // namespace
 
