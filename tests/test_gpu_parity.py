@@ -346,13 +346,15 @@ def test_ib_markers_crossing_tiles_and_seam(kernel):
     check(c, TOL64)
 
 
-@pytest.mark.parametrize("kernel,rebin,steps", [(4, 0, 30), (3, 0, 30), (4, 100000, 110)])
+@pytest.mark.parametrize("kernel,rebin,steps",
+                         [(4, 0, 30), (3, 0, 30), (4, 8, 30), (4, 100000, 110)])
 def test_ib_markers_spread_over_many_tiles(kernel, rebin, steps):
     """IB markers (bonded in pairs) scattered over a 40x32x48 channel (5 x 4 x 6
     spreading tiles, y walls) and at its periodic seams, carried by a uniform
     flow.  With the default binning every tile gathers from its neighbouring
-    bins; binned only once (rebin 100000), the markers travel more than six
-    sites from their bins, and the spreads after that take the fallback."""
+    bins; rebinned every 8 steps, four binnings in the run; binned only once
+    (rebin 100000), the markers travel more than six sites from their bins,
+    and the spreads after that take the fallback."""
     rng = np.random.default_rng(33)
     n = 60
     a = rng.uniform(0.0, 1.0, (n, 3)) * np.array([40.0, 30.0, 48.0]) + np.array([0.0, 1.0, 0.0])
