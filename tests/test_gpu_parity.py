@@ -372,7 +372,7 @@ def test_ib_markers_spread_over_many_tiles(kernel, rebin, steps):
     g = run_gpu(c)
     o = run_oracle(c)
     compare(c, g, o, TOL64)
-    if rebin:
+    if rebin > steps:  # binned once: the markers must have left their bins' neighbourhood
         d = o["pos"] - pos
         d -= np.array([40.0, 32.0, 48.0]) * np.round(d / np.array([40.0, 32.0, 48.0]))
         assert np.abs(d[:, 0]).max() > 7.0, "the markers did not leave their bins' neighbourhood"
