@@ -54,6 +54,26 @@ def test_workspace_size_scales_with_storage():
     assert sizes[1] >= 2 * 19 * N * 4
 
 
+@pytest.mark.parametrize("storage,vec", [(L.LB_F32, 16), (L.LB_F64, 32)])
+def test_workspace_of_coupling_inside_substeps(storage, vec):
+    """The coupling inside the sub-steps holds min(n - 1, 4) force fields of
+    its own and a second copy of the particle state; the deterministic mode,
+    which keeps three launches per sub-step, holds neither."""
+    g, N, npart = _g(32, 32, 32), 32 ** 3, 100
+    base = dict(coupling=L.LB_COUPLE_FC, gamma=1.0, storage=storage, mts_substeps=1)
+
+    def size(**kw):
+        return L.workspace_size(g, L.make_params(0.8, **dict(base, **kw)), _lim(n=npart, nb=99))
+
+    outside = size()
+    for n, fields in ((1, 0), (2, 1), (5, 4), (9, 4)):
+        extra = size(mts_substeps=n, mts_inside=1) - size(mts_substeps=n)
+        assert fields * N * vec <= extra < fields * N * vec + 64 * 1024, (n, extra)
+    assert size(mts_substeps=5, mts_inside=1, deterministic=1) - size(
+        mts_substeps=5, deterministic=1) < 64 * 1024
+    assert outside > 0
+
+
 @pytest.mark.parametrize("bad", [
     dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(tau=0.8, rho0=0.0),
     dict(tau=0.8, collision=7), dict(tau=0.8, coupling=9), dict(tau=0.8, kernel=5),
