@@ -11,13 +11,13 @@ from paper_1406_2211_amd import lbc as L
 pytestmark = pytest.mark.gpu
 
 
-def _run(n, steps, static):
+def _run(n, steps, static, **kw):
     import torch
     pos = I.uniform_positions(3, (n, n, n), 7)
     vel = 1e-3 * np.random.default_rng(3).standard_normal((3, 3))
     lat = L.Lattice(n, n, n, max_particles=3, static_workspace=static, tau=0.8,
                     body_force=(1e-6, 0.0, -2e-6), coupling=L.LB_COUPLE_FC, gamma=1.0,
-                    kernel=L.LB_PHI3, storage=L.LB_F64)
+                    kernel=L.LB_PHI3, storage=L.LB_F64, **kw)
     lat.lb_init_fluid(None, torch.from_numpy(I.noise_velocity(lat.shape, 1e-4, 5)))
     lat.lb_set_particles(torch.from_numpy(pos), torch.from_numpy(vel), torch.ones(3, dtype=torch.float64))
     print(f"[gpu] no-alloc case n={n} steps={steps} static={static}", flush=True)
@@ -41,6 +41,14 @@ def _same(a, b):
 def test_static_workspace_matches_caller_workspace():
     for n, steps in ((24, 40), (12, 25)):  # the second call on a smaller box
         _same(_run(n, steps, True), _run(n, steps, False))
+
+
+def test_static_workspace_coupling_inside_substeps():
+    """The coupling inside every sub-step (its sub-step fields and second state
+    buffer in the static array too), two contexts in a row."""
+    for n, steps in ((16, 20), (10, 12)):
+        kw = dict(mts_substeps=3, mts_inside=1)
+        _same(_run(n, steps, True, **kw), _run(n, steps, False, **kw))
 
 
 def test_static_workspace_limits():
